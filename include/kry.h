@@ -1,0 +1,173 @@
+/*
+ * kry.h -- C ABI of the exponential-Krylov multi-frequency Maxwell solver.
+ *
+ * The library computes, for the semi-discrete Maxwell system
+ *
+ *     y'(t) = -A y(t) + Im(e^{i w t}) b,   y(0) = 0,               (1)
+ *
+ * (the ODE of the paper's Section 2.1, equation (ode), with the sinusoidal
+ * source of equation (src) written for an angular frequency w), the field
+ * y(T) through the time-harmonic / transient split of Corollary 3,
+ * equation (split1):
+ *
+ *     y(T) = Im(e^{i w T} z) - e^{-T A} Im z,   z = (A + i w I)^{-1} b.
+ *
+ * A = M^{-1} (S + K) is the 3D Yee operator: K = [[0, C], [-C^T, 0]] with C
+ * the discrete curl E -> H, S the per-cell conductivity on all six
+ * components, M = diag(mu on H, eps on E) (the block form of the operator
+ * after equation (ode)).  All Krylov bases are built by Arnoldi in the
+ * energy inner product <x, y>_M = x^T M y, in which A is dissipative.
+ *
+ * Layout.  A state vector has n = 6 * nx * ny * nz entries: six planes
+ * [Hx, Hy, Hz, Ex, Ey, Ez], each an nz x ny x nx array in C order (x
+ * fastest).  Cell (i, j, k) owns Ex(i+1/2, j, k), Ey(i, j+1/2, k),
+ * Ez(i, j, k+1/2), Hx(i, j+1/2, k+1/2), Hy(i+1/2, j, k+1/2),
+ * Hz(i+1/2, j+1/2, k).  Stencil reads outside the grid are zero.
+ * Several vectors ("columns") are stored one after another, column c at
+ * offset c * n (c * 2n doubles for complex, interleaved re/im).
+ *
+ * Memory and streams.  Every pointer documented as "device" is a device
+ * pointer owned by the caller; the library never frees it.  The context
+ * owns its workspaces (Krylov basis, reduction buffers).  All work is
+ * enqueued on the stream given in kry_opts; calls that return host data
+ * (H matrices, statistics) synchronise that stream before returning.
+ * A context is not thread-safe.
+ *
+ * Errors.  Every int-returning function returns 0 on success or one of the
+ * negative KRY_E* codes; kry_last_error() then describes the failure.
+ * No C++ exception crosses this interface.
+ */
+#ifndef KRY_H
+#define KRY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KRY_OK 0
+#define KRY_EINVAL (-1)  /* invalid argument: sizes, NaN/Inf, eps <= 0, ... */
+#define KRY_ENOMEM (-2)  /* device allocation failed or size out of range     */
+#define KRY_EHIP (-3)    /* a HIP runtime call failed (message kept)          */
+#define KRY_ENOCONV (-4) /* restart limit reached; outputs hold best estimate */
+
+typedef struct kry_ctx kry_ctx;
+
+typedef struct {
+  int32_t nx, ny, nz; /* cells per axis, each >= 1                       */
+  int32_t boundary;   /* 0: zero ghost values outside the grid (only mode) */
+} kry_grid;
+
+typedef struct {
+  int32_t storage;      /* 0: FP64 fields and bases; 1: FP32 storage with
+                           FP32 stencil, FP64 dots/norms/small dense       */
+  int32_t krylov_dim;   /* Arnoldi steps per restart cycle m, 1..1024      */
+  int32_t max_restarts; /* cap on restart cycles per solve (0: 100000)     */
+  double tol;           /* relative accuracy target of each output column  */
+  int32_t block_width;  /* reserved for the batched form (0: automatic)    */
+  int32_t use_graph;    /* reserved: capture restart cycles in HIP graphs  */
+  int32_t inner_product;/* 0: energy inner product (the only mode)         */
+  void* stream;         /* hipStream_t; NULL = the null stream             */
+  int32_t timing;       /* 1: time every launch of the main kernel classes
+                           with HIP events on the stream (adds a little
+                           overhead); results in kry_stats.kernel_*        */
+} kry_opts;
+
+/* Kernel classes reported by the per-kernel timing. */
+#define KRY_K_STENCIL 0 /* operator fused with the first Gram-Schmidt dots */
+#define KRY_K_UPDATE 1  /* w -= V h (multi-vector update), two per step    */
+#define KRY_K_DOTS 2    /* second Gram-Schmidt dot pass                    */
+#define KRY_K_COMBINE 3 /* basis combinations V Y                          */
+#define KRY_K_CLASSES 4
+
+typedef struct {
+  int64_t matvecs_stationary; /* operator applications, shifted solves     */
+  int64_t matvecs_transient;  /* operator applications, exponential part   */
+  int64_t cycles_stationary;  /* restart cycles of the shifted solves      */
+  int64_t steps_transient;    /* restarts in time of the exponential part  */
+  double max_residual;        /* largest final relative shifted residual   */
+  double max_err_estimate;    /* largest transient error bound / |y|_M     */
+  double ms_stationary;       /* wall time of the phases (host clock)      */
+  double ms_transient;
+  double ms_total;
+  int32_t converged;          /* 1 if every column met its target          */
+  /* filled when kry_opts.timing = 1 (else zero), per kernel class:
+     summed HIP-event durations, launches, and algorithmic bytes (each
+     vector read or written once, materials once per cell)              */
+  double kernel_ms[KRY_K_CLASSES];
+  int64_t kernel_launches[KRY_K_CLASSES];
+  double kernel_bytes[KRY_K_CLASSES];
+} kry_stats;
+
+/* Create a context for the grid and per-cell materials.
+ * eps, mu, sigma: device arrays of nx*ny*nz doubles (C order, x fastest).
+ * mu may be NULL (mu = 1 everywhere), sigma may be NULL (sigma = 0).
+ * eps > 0, mu > 0, sigma >= 0 and all finite, else KRY_EINVAL.
+ * The arrays are copied into the context; the caller may free them after.
+ * opts is copied.  On success *out holds the new context. */
+int kry_create(const kry_grid* grid, const double* eps, const double* mu,
+               const double* sigma, const kry_opts* opts, kry_ctx** out);
+
+/* Free the context and all of its device memory. NULL is allowed. */
+void kry_destroy(kry_ctx* ctx);
+
+/* Message of the last failure on this context (or of the last failed
+ * kry_create when ctx is NULL).  Valid until the next call on ctx. */
+const char* kry_last_error(const kry_ctx* ctx);
+
+/* Problem size n = 6 nx ny nz. */
+int64_t kry_size(const kry_ctx* ctx);
+
+/* w = A v for ncols columns (operator of equation (ode)); v, w device,
+ * FP64, n x ncols.  v and w must not overlap. */
+int kry_apply(kry_ctx* ctx, const double* v, double* w, int32_t ncols);
+
+/* As kry_apply with FP32 vectors and FP32 arithmetic (the stencil of the
+ * FP32-storage form). */
+int kry_apply_f32(kry_ctx* ctx, const float* v, float* w, int32_t ncols);
+
+/* m steps of Arnoldi in the energy inner product from the start vector v
+ * (device, FP64, length n): V_{m+1} with V^T M V = I and the (m+1) x m
+ * upper-Hessenberg H with A V_m = V_{m+1} H (equation (Arn), regular
+ * Krylov, with v_1 = v / |v|_M as in equation (Krylov)).
+ * V_out: device, (m+1) x n in the context's storage type (double or
+ * float), column j at offset j*n.  H_out: host, (m+1) x m doubles,
+ * column-major.  beta_out: host, |v|_M.  Returns the number of steps taken
+ * (< m on an exact invariant subspace, h_{j+1,j} = 0), or a KRY_E* code. */
+int kry_arnoldi(kry_ctx* ctx, const double* v, int32_t m, void* V_out,
+                double* H_out, double* beta_out);
+
+/* y = e^{-t A} v for ncols columns (equation (y_homo)), by restarts in time
+ * with the residual of Lemma 1 (g = 0) bounding the error of each step.
+ * v, y: device FP64, n x ncols (may alias). Target: |err|_M <= tol |v|_M. */
+int kry_expv(kry_ctx* ctx, double t, const double* v, double* y,
+             int32_t ncols, kry_stats* stats);
+
+/* y(T) of problem (1) for every (w, source) pair, by Corollary 3.
+ * omegas: host, n_omega angular frequencies (w >= 0).
+ * b: device, complex interleaved (re, im) FP64 sources.  If b_per_omega is
+ *    0, b holds n_src columns shared by every w; otherwise n_omega*n_src
+ *    columns, column (w, s) at index w*n_src + s.
+ * yT: device FP64, n x (n_omega*n_src), column (w, s) at w*n_src + s.
+ * The shifted systems of all w that share a source are solved in one real
+ * Krylov sequence (restarted multi-shift FOM, residuals collinear across
+ * shifts, cf. Corollaries 1 and 2); the transients are then integrated per
+ * column.  stats: host, may be NULL. */
+int kry_solve_multifreq(kry_ctx* ctx, const double* omegas, int32_t n_omega,
+                        int32_t n_src, const double* b, int32_t b_per_omega,
+                        double T, double* yT, kry_stats* stats);
+
+/* Time-harmonic fields only: z_w = (A + i w I)^{-1} b for every column, the
+ * vector z_stat of Corollary 3.  Same argument conventions as
+ * kry_solve_multifreq; z: device, complex interleaved FP64,
+ * n x (n_omega*n_src).  Target: shifted residual <= tol |b|_M. */
+int kry_stationary(kry_ctx* ctx, const double* omegas, int32_t n_omega,
+                   int32_t n_src, const double* b, int32_t b_per_omega,
+                   double* z, kry_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRY_H */

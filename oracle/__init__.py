@@ -27,4 +27,4 @@ Readings of the paper where it is silent or 2D-only (3D Yee staggering,
 zero-ghost boundary, damping scaling sigma/eps, angular omega, minus sign of
 the split) are listed in the design notes and restated in each docstring.
 """
-from . import operator, solve, grad  # noqa: F401
+from . import operator, solve, grad, krylov  # noqa: F401

@@ -65,9 +65,9 @@ def curl_H(Hx, Hy, Hz):
 
 
 def apply_A(eps, mu, sigma, y):
-    """w = A y, matrix-free.  ``y`` may be real or complex, length 6 N^3."""
-    N = eps.shape[0]
-    Y = y.reshape(6, N, N, N)
+    """w = A y, matrix-free.  ``y`` may be real or complex, length 6 nz ny nx
+    (materials of shape (nz, ny, nx); cubes and general boxes alike)."""
+    Y = y.reshape((6,) + eps.shape)
     Hx, Hy, Hz, Ex, Ey, Ez = Y
     ce = curl_E(Ex, Ey, Ez)
     ch = curl_H(Hx, Hy, Hz)
@@ -83,26 +83,27 @@ def diff_1d(N):
     return sp.diags([-np.ones(N), np.ones(N - 1)], [0, 1], format="csr")
 
 
-def curl_matrix(N):
-    """Sparse C (3 N^3 x 3 N^3): rows (C E)_x,y,z, columns Ex, Ey, Ez.
+def curl_matrix(nx, ny=None, nz=None):
+    """Sparse C (3 N3 x 3 N3): rows (C E)_x,y,z, columns Ex, Ey, Ez.
 
-    With D the 1D forward difference and flattening [k][j][i] (i fastest):
-    Dx = I (x) I (x) D, Dy = I (x) D (x) I, Dz = D (x) I (x) I and
-    C = [[0, -Dz, Dy], [Dz, 0, -Dx], [-Dy, Dx, 0]].
+    With D_a the 1D forward difference of length a and flattening [k][j][i]
+    (i fastest): Dx = I_nz (x) I_ny (x) D_nx, Dy = I_nz (x) D_ny (x) I_nx,
+    Dz = D_nz (x) I_ny (x) I_nx and C = [[0, -Dz, Dy], [Dz, 0, -Dx], [-Dy, Dx, 0]].
     """
-    D = diff_1d(N)
-    I = sp.identity(N, format="csr")
-    Dx = sp.kron(I, sp.kron(I, D))
-    Dy = sp.kron(I, sp.kron(D, I))
-    Dz = sp.kron(D, sp.kron(I, I))
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    I = lambda a: sp.identity(a, format="csr")
+    Dx = sp.kron(I(nz), sp.kron(I(ny), diff_1d(nx)))
+    Dy = sp.kron(I(nz), sp.kron(diff_1d(ny), I(nx)))
+    Dz = sp.kron(diff_1d(nz), sp.kron(I(ny), I(nx)))
     return sp.bmat([[None, -Dz, Dy], [Dz, None, -Dx], [-Dy, Dx, None]],
                    format="csr")
 
 
 def assemble_A(eps, mu, sigma):
     """Sparse A = diag(1/m) (diag(sigma_own) + [[0, C], [-C^T, 0]])."""
-    N = eps.shape[0]
-    C = curl_matrix(N)
+    nz, ny, nx = eps.shape
+    C = curl_matrix(nx, ny, nz)
     K = sp.bmat([[None, C], [-C.T, None]], format="csr")
     s6 = np.tile(sigma.reshape(-1), 6)
     m6 = material_weights(eps, mu)

@@ -1,0 +1,269 @@
+"""Python binding of libkry: argument marshalling only.
+
+Every numerical step runs in the HIP library (libkry.so, built in-tree by
+``paper_1707_00023_amd.build``).  PyTorch supplies device memory and the
+current stream; this module only converts tensors to raw pointers, checks
+shapes and dtypes, and turns status codes into exceptions.  There is no
+fallback: if the library is missing, loading fails with an error.
+
+Vector layout: a state vector has n = 6 nx ny nz entries, six planes
+[Hx, Hy, Hz, Ex, Ey, Ez] each nz x ny x nx in C order.  Several vectors are
+passed as a contiguous tensor of shape (ncols, n).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkry.so")
+
+KRY_OK, KRY_EINVAL, KRY_ENOMEM, KRY_EHIP, KRY_ENOCONV = 0, -1, -2, -3, -4
+_CODES = {KRY_EINVAL: "KRY_EINVAL", KRY_ENOMEM: "KRY_ENOMEM", KRY_EHIP: "KRY_EHIP",
+          KRY_ENOCONV: "KRY_ENOCONV"}
+
+EXPORTED = ("kry_create", "kry_destroy", "kry_last_error", "kry_size", "kry_apply",
+            "kry_apply_f32", "kry_arnoldi", "kry_expv", "kry_solve_multifreq",
+            "kry_stationary")
+
+
+class KryGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("boundary", ctypes.c_int32)]
+
+
+class KryOpts(ctypes.Structure):
+    _fields_ = [("storage", ctypes.c_int32), ("krylov_dim", ctypes.c_int32),
+                ("max_restarts", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("block_width", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("inner_product", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("timing", ctypes.c_int32)]
+
+
+class KryStats(ctypes.Structure):
+    _fields_ = [("matvecs_stationary", ctypes.c_int64), ("matvecs_transient", ctypes.c_int64),
+                ("cycles_stationary", ctypes.c_int64), ("steps_transient", ctypes.c_int64),
+                ("max_residual", ctypes.c_double), ("max_err_estimate", ctypes.c_double),
+                ("ms_stationary", ctypes.c_double), ("ms_transient", ctypes.c_double),
+                ("ms_total", ctypes.c_double), ("converged", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_int64 * 4),
+                ("kernel_bytes", ctypes.c_double * 4)]
+
+    def as_dict(self):
+        out = {}
+        for f, _ in self._fields_:
+            v = getattr(self, f)
+            out[f] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+
+KERNEL_CLASSES = ("stencil_dots", "gs_update", "gs_dots", "combine")
+
+
+class KryError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libkry.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libkry.so not found at {path}; build it with "
+                           f"`python -m paper_1707_00023_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.kry_create.argtypes = [ctypes.POINTER(KryGrid), P, P, P, ctypes.POINTER(KryOpts),
+                               ctypes.POINTER(P)]
+    lib.kry_create.restype = ctypes.c_int
+    lib.kry_destroy.argtypes = [P]
+    lib.kry_destroy.restype = None
+    lib.kry_last_error.argtypes = [P]
+    lib.kry_last_error.restype = ctypes.c_char_p
+    lib.kry_size.argtypes = [P]
+    lib.kry_size.restype = ctypes.c_int64
+    lib.kry_apply.argtypes = [P, P, P, I32]
+    lib.kry_apply_f32.argtypes = [P, P, P, I32]
+    lib.kry_arnoldi.argtypes = [P, P, I32, P, P, ctypes.POINTER(D)]
+    lib.kry_expv.argtypes = [P, D, P, P, I32, ctypes.POINTER(KryStats)]
+    lib.kry_solve_multifreq.argtypes = [P, P, I32, I32, P, I32, D, P, ctypes.POINTER(KryStats)]
+    lib.kry_stationary.argtypes = [P, P, I32, I32, P, I32, P, ctypes.POINTER(KryStats)]
+    for name in ("kry_apply", "kry_apply_f32", "kry_arnoldi", "kry_expv",
+                 "kry_solve_multifreq", "kry_stationary"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Options:
+    storage: str = "f64"        # "f64" or "f32"
+    krylov_dim: int = 30
+    max_restarts: int = 0
+    tol: float = 1e-8
+    timing: bool = False
+
+
+class Solver:
+    """One libkry context: a grid with its materials on the current device."""
+
+    def __init__(self, eps, mu=None, sigma=None, opts: Optional[Options] = None):
+        import torch
+        lib = load_library()
+        opts = opts or Options()
+        if eps.dim() != 3:
+            raise ValueError("eps must be (nz, ny, nx)")
+        nz, ny, nx = eps.shape
+        dev = eps.device
+        if dev.type != "cuda":
+            raise ValueError("materials must be device tensors")
+        keep = []
+        def prep(t):
+            if t is None:
+                return None
+            if tuple(t.shape) != (nz, ny, nx):
+                raise ValueError("material shapes differ")
+            t = t.to(device=dev, dtype=torch.float64).contiguous()
+            keep.append(t)
+            return t
+        e, m, s = prep(eps), prep(mu), prep(sigma)
+        self.grid = KryGrid(nx, ny, nz, 0)
+        self.opts = KryOpts(1 if opts.storage == "f32" else 0, opts.krylov_dim,
+                            opts.max_restarts, opts.tol, 0, 0, 0, _stream_ptr().value,
+                            int(bool(opts.timing)))
+        self.storage = opts.storage
+        ctx = ctypes.c_void_p()
+        rc = lib.kry_create(ctypes.byref(self.grid), _ptr(e),
+                            _ptr(m) if m is not None else None,
+                            _ptr(s) if s is not None else None,
+                            ctypes.byref(self.opts), ctypes.byref(ctx))
+        if rc != KRY_OK:
+            raise KryError(rc, lib.kry_last_error(None).decode())
+        self._ctx = ctx
+        self._lib = lib
+        self.n = int(lib.kry_size(ctx))
+        self.device = dev
+        self.last_stats = None
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.kry_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow_noconv=False):
+        if rc == KRY_OK or (allow_noconv and rc == KRY_ENOCONV):
+            return rc
+        raise KryError(rc, self._lib.kry_last_error(self._ctx).decode())
+
+    def _vecs(self, x, dtype):
+        import torch
+        if x.dim() == 1:
+            x = x.unsqueeze(0)
+        if x.shape[-1] != self.n:
+            raise ValueError(f"expected vectors of length {self.n}")
+        if x.device != self.device:
+            raise ValueError("tensor on the wrong device")
+        return x.to(dtype).contiguous()
+
+    def apply(self, v):
+        """w = A v; v: (ncols, n) or (n,) float64 (float32 via apply_f32)."""
+        import torch
+        v = self._vecs(v, torch.float64)
+        w = torch.empty_like(v)
+        self._check(self._lib.kry_apply(self._ctx, _ptr(v), _ptr(w), v.shape[0]))
+        return w
+
+    def apply_f32(self, v):
+        import torch
+        v = self._vecs(v, torch.float32)
+        w = torch.empty_like(v)
+        self._check(self._lib.kry_apply_f32(self._ctx, _ptr(v), _ptr(w), v.shape[0]))
+        return w
+
+    def arnoldi(self, v, m: int):
+        """(V (m+1, n), H (m+1, m) numpy, beta, steps) of m Arnoldi steps from v."""
+        import numpy as np
+        import torch
+        v = self._vecs(v, torch.float64)[0]
+        dt = torch.float32 if self.storage == "f32" else torch.float64
+        V = torch.empty((m + 1, self.n), dtype=dt, device=self.device)
+        H = np.zeros((m, m + 1))  # column-major (m+1) x m
+        beta = ctypes.c_double()
+        rc = self._lib.kry_arnoldi(self._ctx, _ptr(v), m, _ptr(V),
+                                   H.ctypes.data_as(ctypes.c_void_p), ctypes.byref(beta))
+        if rc < 0:
+            self._check(rc)
+        return V, H.T.copy(), beta.value, rc
+
+    def expv(self, t: float, v):
+        """e^{-tA} v for each row of v."""
+        import torch
+        v = self._vecs(v, torch.float64)
+        y = torch.empty_like(v)
+        st = KryStats()
+        rc = self._lib.kry_expv(self._ctx, float(t), _ptr(v), _ptr(y), v.shape[0], ctypes.byref(st))
+        self._check(rc, allow_noconv=True)
+        self.last_stats = st.as_dict()
+        return y
+
+    def _omega_b(self, omegas, b, b_per_omega):
+        import numpy as np
+        import torch
+        om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64).reshape(-1))
+        b = self._vecs(b, torch.complex128)
+        nw = om.size
+        if b_per_omega:
+            if b.shape[0] % nw:
+                raise ValueError("b rows must be n_omega * n_src")
+            nsrc = b.shape[0] // nw
+        else:
+            nsrc = b.shape[0]
+        return om, b, nw, nsrc
+
+    def stationary(self, omegas: Sequence[float], b, b_per_omega: bool = False):
+        """z = (A + i w I)^-1 b; returns complex128 (n_omega * n_src, n)."""
+        import torch
+        om, b, nw, nsrc = self._omega_b(omegas, b, b_per_omega)
+        z = torch.empty((nw * nsrc, self.n), dtype=torch.complex128, device=self.device)
+        st = KryStats()
+        rc = self._lib.kry_stationary(self._ctx, om.ctypes.data_as(ctypes.c_void_p), nw, nsrc,
+                                      _ptr(b), int(bool(b_per_omega)), _ptr(z), ctypes.byref(st))
+        self._check(rc, allow_noconv=True)
+        self.last_stats = st.as_dict()
+        return z
+
+    def solve_multifreq(self, omegas: Sequence[float], b, T: float, b_per_omega: bool = False):
+        """y(T) for every (omega, source) column; float64 (n_omega * n_src, n)."""
+        import torch
+        om, b, nw, nsrc = self._omega_b(omegas, b, b_per_omega)
+        y = torch.empty((nw * nsrc, self.n), dtype=torch.float64, device=self.device)
+        st = KryStats()
+        rc = self._lib.kry_solve_multifreq(self._ctx, om.ctypes.data_as(ctypes.c_void_p), nw, nsrc,
+                                           _ptr(b), int(bool(b_per_omega)), float(T), _ptr(y),
+                                           ctypes.byref(st))
+        self._check(rc, allow_noconv=True)
+        self.last_stats = st.as_dict()
+        return y

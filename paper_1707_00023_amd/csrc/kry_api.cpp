@@ -1,0 +1,871 @@
+// C-ABI driver: context, workspaces, Arnoldi cycles, restarted multi-shift
+// shifted solves, time-restarted exponential, split assembly.
+#include "../../include/kry.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kry_dense.h"
+#include "kry_internal.h"
+
+using kry::cplx;
+
+struct kry_ctx {
+  kry::DevGrid g{};
+  long long n = 0;    // 6 N3
+  long long ldv = 0;  // padded vector stride (elements)
+  kry::Storage st = kry::F64;
+  size_t esz = 8;
+  kry_opts opts{};
+  hipStream_t stream = nullptr;
+
+  double* d_mat = nullptr;  // one allocation holding the derived material arrays
+  kry::DevMats mats{};
+
+  // Krylov workspace: slots 0..mcap hold the basis, slot mcap+1 the work vector.
+  int mcap = 0;
+  void* V = nullptr;
+  double* partials = nullptr;
+  double* d_red1 = nullptr;
+  double* d_red2 = nullptr;
+  double* d_scal = nullptr;
+  double* d_H = nullptr;
+  double* d_Y = nullptr;
+  int* d_colmap = nullptr;
+  int ycap = 0;   // columns of d_Y
+  int yrows = 0;  // rows of d_Y
+  double* h_H = nullptr;     // pinned (mcap+1) x mcap
+  double* h_scal = nullptr;  // pinned, 4 doubles
+
+  void* Z = nullptr;  // 2 * zcap columns (Re, Im per solution column)
+  int zcap = 0;
+
+  // optional per-kernel-class timing with HIP events
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Pending> pending;
+  double k_ms[KRY_K_CLASSES] = {};
+  long long k_launch[KRY_K_CLASSES] = {};
+  double k_bytes[KRY_K_CLASSES] = {};
+
+  std::string err;
+};
+
+namespace {
+
+std::string g_create_err;
+
+int fail(kry_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg; else g_create_err = msg;
+  return code;
+}
+
+#define KRY_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(c, KRY_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+template <typename F>
+struct Defer {
+  F f;
+  ~Defer() { f(); }
+};
+
+hipEvent_t take_event(kry_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Record the start event of a timed launch (no-op unless timing is on).
+hipEvent_t tbeg(kry_ctx* c) {
+  if (!c->opts.timing) return nullptr;
+  hipEvent_t a = take_event(c);
+  if (a) hipEventRecord(a, c->stream);
+  return a;
+}
+
+void tend(kry_ctx* c, hipEvent_t a, int cls, double bytes) {
+  if (!a) return;
+  hipEvent_t b = take_event(c);
+  if (!b) return;
+  hipEventRecord(b, c->stream);
+  c->pending.push_back({cls, a, b, bytes});
+}
+
+// Fold completed event pairs into the per-class totals (after a stream sync).
+void tresolve(kry_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->k_ms[p.cls] += ms;
+      c->k_launch[p.cls] += 1;
+      c->k_bytes[p.cls] += p.bytes;
+    }
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+void treset(kry_ctx* c) {
+  for (int k = 0; k < KRY_K_CLASSES; ++k) c->k_ms[k] = c->k_bytes[k] = 0.0, c->k_launch[k] = 0;
+}
+
+void texport(kry_ctx* c, kry_stats* st) {
+  if (!st) return;
+  tresolve(c);
+  for (int k = 0; k < KRY_K_CLASSES; ++k) {
+    st->kernel_ms[k] = c->k_ms[k];
+    st->kernel_launches[k] = c->k_launch[k];
+    st->kernel_bytes[k] = c->k_bytes[k];
+  }
+}
+
+// Algorithmic bytes: every vector entry read or written once; materials once
+// per cell (inv_eps, sigma, plus the eps weight of the dots; mu adds two).
+double vbytes(kry_ctx* c) { return 6.0 * c->g.N3 * c->esz; }
+double mbytes(kry_ctx* c, bool stencil) {
+  const double per = stencil ? (c->mats.inv_mu ? 40.0 : 24.0) : (c->mats.inv_mu ? 16.0 : 8.0);
+  return per * c->g.N3;
+}
+
+void* slot(kry_ctx* c, int i) { return (char*)c->V + (size_t)i * c->ldv * c->esz; }
+void* zcol(kry_ctx* c, int col) { return (char*)c->Z + (size_t)col * c->ldv * c->esz; }
+
+int ensure_basis(kry_ctx* c, int m) {
+  if (m <= c->mcap && c->V) return KRY_OK;
+  if (m + 2 > kry::kMaxCoef) return fail(c, KRY_ENOMEM, "krylov_dim too large");
+  hipFree(c->V);
+  hipFree(c->partials);
+  hipFree(c->d_red1);
+  hipFree(c->d_red2);
+  hipFree(c->d_H);
+  hipHostFree(c->h_H);
+  c->V = nullptr;
+  c->partials = nullptr;
+  c->d_red1 = c->d_red2 = c->d_H = c->h_H = nullptr;
+  c->mcap = 0;
+  const size_t vbytes = (size_t)(m + 2) * c->ldv * c->esz;
+  if (hipMalloc(&c->V, vbytes) != hipSuccess) {
+    c->V = nullptr;
+    (void)hipGetLastError();
+    return fail(c, KRY_ENOMEM, "cannot allocate Krylov basis of " + std::to_string(vbytes) + " bytes");
+  }
+  const size_t nparts = (size_t)kry::cell_blocks(c->g.N3);
+  KRY_HIP(hipMalloc(&c->partials, sizeof(double) * nparts * (size_t)(m + 3)));
+  KRY_HIP(hipMalloc(&c->d_red1, sizeof(double) * (m + 3)));
+  KRY_HIP(hipMalloc(&c->d_red2, sizeof(double) * (m + 3)));
+  KRY_HIP(hipMalloc(&c->d_H, sizeof(double) * (size_t)(m + 1) * m));
+  KRY_HIP(hipHostMalloc(&c->h_H, sizeof(double) * (size_t)(m + 1) * m, hipHostMallocDefault));
+  c->mcap = m;
+  return KRY_OK;
+}
+
+int ensure_y(kry_ctx* c, int m, int ncol) {
+  if (c->d_Y && ncol <= c->ycap && m <= c->yrows) return KRY_OK;
+  hipFree(c->d_Y);
+  hipFree(c->d_colmap);
+  c->d_Y = nullptr;
+  c->d_colmap = nullptr;
+  const int cap = std::max(ncol, 8);
+  KRY_HIP(hipMalloc(&c->d_Y, sizeof(double) * (size_t)std::max(m, 1) * cap));
+  KRY_HIP(hipMalloc(&c->d_colmap, sizeof(int) * cap));
+  c->ycap = cap;
+  c->yrows = std::max(m, 1);
+  return KRY_OK;
+}
+
+int ensure_z(kry_ctx* c, int ncols) {
+  if (c->Z && ncols <= c->zcap) return KRY_OK;
+  hipFree(c->Z);
+  c->Z = nullptr;
+  c->zcap = 0;
+  const size_t bytes = (size_t)2 * ncols * c->ldv * c->esz;
+  if (hipMalloc(&c->Z, bytes) != hipSuccess) {
+    c->Z = nullptr;
+    (void)hipGetLastError();
+    return fail(c, KRY_ENOMEM, "cannot allocate solution workspace of " + std::to_string(bytes) + " bytes");
+  }
+  c->zcap = ncols;
+  return KRY_OK;
+}
+
+// |x|_M^2 and <x, y_i>_M for i < cnt (y_i = slots of a contiguous array with
+// stride ldv), returned on the host (synchronises the stream).
+int host_dots(kry_ctx* c, const void* x, const void* Y, int cnt, std::vector<double>& out) {
+  const int nparts = kry::cell_blocks(c->g.N3);
+  KRY_HIP(kry::launch_dots(c->st, x, Y, c->ldv, cnt, c->g, c->mats, c->partials, c->stream));
+  KRY_HIP(kry::launch_reduce(c->partials, nparts, cnt + 1, cnt + 1, c->d_red1, c->stream));
+  out.assign(cnt + 1, 0.0);
+  KRY_HIP(hipMemcpyAsync(out.data(), c->d_red1, sizeof(double) * (cnt + 1), hipMemcpyDeviceToHost,
+                         c->stream));
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  return KRY_OK;
+}
+
+// Arnoldi in the energy inner product (regular Krylov, equation (Arn)):
+// the start vector sits unnormalised in slot 0; on return slots 0..m hold
+// V_{m+1}, h_H holds H ((m+1) x m, column-major), *beta = |start|_M and
+// *m_eff the steps before an exact invariant subspace (h_{j+1,j} = 0).
+// Each step: w = A v_j fused with the dots of pass 1, then
+// w -= V h1, dots of pass 2 (classical Gram-Schmidt twice), then
+// v_{j+1} = (w - V h2) / nu.
+int arnoldi(kry_ctx* c, int m, double* beta, int* m_eff) {
+  const int nparts = kry::cell_blocks(c->g.N3);
+  hipStream_t s = c->stream;
+  const long long ldv = c->ldv;
+  KRY_HIP(hipMemsetAsync(c->d_H, 0, sizeof(double) * (size_t)(m + 1) * m, s));
+  // normalise the start vector
+  KRY_HIP(kry::launch_dots(c->st, slot(c, 0), nullptr, ldv, 0, c->g, c->mats, c->partials, s));
+  KRY_HIP(kry::launch_reduce(c->partials, nparts, 1, 1, c->d_red1, s));
+  KRY_HIP(kry::launch_fin_start(c->d_red1, c->d_scal + 2, s));  // scal[2] = 1/beta, scal[3] = beta
+  KRY_HIP(kry::launch_scale(c->st, slot(c, 0), c->d_scal + 2, slot(c, 0), c->n, s));
+  void* W = slot(c, c->mcap + 1);
+  for (int j = 0; j < m; ++j) {
+    const int cnt = j + 1;
+    const double vb = vbytes(c);
+    hipEvent_t e = tbeg(c);
+    KRY_HIP(kry::launch_stencil(c->st, slot(c, j), W, c->V, ldv, cnt, c->g, c->mats, c->partials, s));
+    tend(c, e, KRY_K_STENCIL, vb * (cnt + 2) + mbytes(c, true));
+    KRY_HIP(kry::launch_reduce(c->partials, nparts, cnt + 1, cnt + 1, c->d_red1, s));
+    e = tbeg(c);
+    KRY_HIP(kry::launch_update(c->st, W, c->V, ldv, cnt, c->d_red1, nullptr, W, c->g, s));
+    tend(c, e, KRY_K_UPDATE, vb * (cnt + 2));
+    e = tbeg(c);
+    KRY_HIP(kry::launch_dots(c->st, W, c->V, ldv, cnt, c->g, c->mats, c->partials, s));
+    tend(c, e, KRY_K_DOTS, vb * (cnt + 1) + mbytes(c, false));
+    KRY_HIP(kry::launch_reduce(c->partials, nparts, cnt + 1, cnt + 1, c->d_red2, s));
+    KRY_HIP(kry::launch_fin_step(c->d_red1, c->d_red2, j, c->d_H, m + 1, c->d_scal, s));
+    e = tbeg(c);
+    KRY_HIP(kry::launch_update(c->st, W, c->V, ldv, cnt, c->d_red2, c->d_scal, slot(c, j + 1), c->g, s));
+    tend(c, e, KRY_K_UPDATE, vb * (cnt + 2));
+  }
+  KRY_HIP(hipMemcpyAsync(c->h_H, c->d_H, sizeof(double) * (size_t)(m + 1) * m, hipMemcpyDeviceToHost, s));
+  KRY_HIP(hipMemcpyAsync(c->h_scal, c->d_scal, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
+  KRY_HIP(hipStreamSynchronize(s));
+  tresolve(c);
+  *beta = c->h_scal[3];
+  int me = m;
+  for (int j = 0; j < m; ++j) {
+    if (c->h_H[j + 1 + (size_t)j * (m + 1)] == 0.0) { me = j + 1; break; }
+  }
+  if (*beta == 0.0) me = 0;
+  *m_eff = me;
+  return KRY_OK;
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Restarted multi-shift solve of (A + i w_k I) z_k = coef_k * s for all k
+// at once, with s (real) in slot 0.  All shifts share one real Krylov
+// sequence (a Krylov space is shift invariant); a restart must then leave
+// every shift's residual on one common real vector.  FOM does that with
+// v_{m+1} (Lemma 1 with a constant source: the residual is a multiple of
+// v_{m+1}, the collinearity behind Corollaries 1 and 2), but restarted FOM
+// can diverge on these indefinite systems.  Here the common direction is
+// instead chosen per cycle as the real unit vector w in span(V_{m+1}) that
+// minimises the residual of the worst shift (the "seed"): with q the left
+// null vector of the seed's (m+1) x m projected matrix, the residual for a
+// restart direction w is |q^H g| |w| / |q^H w|, maximised over real w by
+// the top eigenvector of Re q Re q^T + Im q Im q^T (within sqrt 2 of the
+// unconstrained GMRES minimum).  Every shift then solves the bordered
+// Hessenberg system [Hbar_k, -w] [y_k; rho_k] = coef_k beta e_1, so its new
+// residual is -rho_k V_{m+1} w.
+// Z columns zre_k = 2 * zcol_k, zim_k = 2 * zcol_k + 1 accumulate V_m y_k.
+int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> coef,
+               const std::vector<int>& zcolk, double bnorm, double tol, kry_stats* st,
+               double* max_res) {
+  const int nw = (int)omegas.size();
+  const int m = c->opts.krylov_dim;
+  int rc = ensure_basis(c, m);
+  if (rc) return rc;
+  rc = ensure_y(c, m + 1, 2 * nw + 1);
+  if (rc) return rc;
+  std::vector<char> active(nw, 1);
+  std::vector<double> Yh((size_t)(m + 1) * (2 * nw + 1));
+  std::vector<int> cmap(2 * nw);
+  const int maxcyc = c->opts.max_restarts > 0 ? c->opts.max_restarts : 100000;
+  double worst = 0.0;
+  const int M1 = m + 1;
+  std::vector<cplx> Mb((size_t)M1 * M1), g(M1), sol(M1), q(M1), Hs((size_t)m * m), rhs(m);
+  std::vector<double> wt(M1);
+  for (int cyc = 0; cyc < maxcyc; ++cyc) {
+    double beta = 0.0;
+    int me = 0;
+    rc = arnoldi(c, m, &beta, &me);
+    if (rc) return rc;
+    if (st) { st->matvecs_stationary += m; st->cycles_stationary += 1; }
+    if (me == 0) {  // zero start vector: nothing left to solve
+      worst = 0.0;
+      break;
+    }
+    const int ldh = m + 1;
+    const double* H = c->h_H;
+    const bool exact = me < m;  // invariant subspace: projected solve is exact
+    if (!exact) {
+      // seed: the active shift with the largest residual
+      int k0 = -1;
+      for (int k = 0; k < nw; ++k)
+        if (active[k] && (k0 < 0 || std::abs(coef[k]) > std::abs(coef[k0]))) k0 = k;
+      // left null vector of the seed's Hbar: (H + i w I)^H q[:m] = -h e_m, q[m] = 1
+      const double hnext = H[m + (size_t)(m - 1) * ldh];
+      for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) {
+          // (H + i w I)^H entry (i, j) = conj(H(j, i) + i w delta_ij)
+          cplx v = (j <= i + 1) ? cplx(H[j + (size_t)i * ldh], 0.0) : cplx(0.0);
+          if (i == j) v += cplx(0.0, omegas[k0]);
+          Hs[i + (size_t)j * m] = std::conj(v);
+        }
+      std::fill(rhs.begin(), rhs.end(), cplx(0.0));
+      rhs[m - 1] = -hnext;
+      bool okq = kry::dense_solve(m, Hs.data(), rhs.data(), q.data());
+      q[m] = 1.0;
+      if (okq) {
+        kry::best_real_direction(M1, q.data(), wt.data());
+      } else {  // singular seed projection: fall back to the FOM direction
+        std::fill(wt.begin(), wt.end(), 0.0);
+        wt[m] = 1.0;
+      }
+    }
+    int ncol = 0;
+    worst = 0.0;
+    for (int k = 0; k < nw; ++k) {
+      if (!active[k]) continue;
+      cplx rho = 0.0;
+      if (exact) {
+        std::fill(rhs.begin(), rhs.end(), cplx(0.0));
+        rhs[0] = coef[k] * beta;
+        if (!kry::hess_shift_solve(me, H, ldh, cplx(0.0, omegas[k]), rhs.data(), sol.data()))
+          return fail(c, KRY_ENOCONV, "singular projected shifted system");
+      } else {
+        // bordered upper-Hessenberg system [Hbar + i w Ibar, -wt]
+        for (int j = 0; j < m; ++j)
+          for (int i = 0; i < M1; ++i) {
+            cplx v = (i <= j + 1) ? cplx(H[i + (size_t)j * ldh], 0.0) : cplx(0.0);
+            if (i == j) v += cplx(0.0, omegas[k]);
+            Mb[i + (size_t)j * M1] = v;
+          }
+        for (int i = 0; i < M1; ++i) Mb[i + (size_t)m * M1] = -wt[i];
+        std::fill(g.begin(), g.end(), cplx(0.0));
+        g[0] = coef[k] * beta;
+        if (!kry::hess_solve(M1, Mb.data(), g.data(), sol.data()))
+          return fail(c, KRY_ENOCONV, "singular projected shifted system");
+        rho = sol[m];
+      }
+      for (int i = 0; i < me; ++i) {
+        Yh[i + (size_t)(2 * ncol) * me] = sol[i].real();
+        Yh[i + (size_t)(2 * ncol + 1) * me] = sol[i].imag();
+      }
+      cmap[2 * ncol] = 2 * zcolk[k];
+      cmap[2 * ncol + 1] = 2 * zcolk[k] + 1;
+      ++ncol;
+      coef[k] = exact ? cplx(0.0) : -rho;  // new residual: coef_k * (V_{m+1} w), |V w|_M = 1
+      const double res = std::abs(coef[k]) / bnorm;
+      worst = std::max(worst, res);
+      if (res <= tol) active[k] = 0;
+    }
+    if (ncol > 0) {
+      KRY_HIP(hipMemcpyAsync(c->d_Y, Yh.data(), sizeof(double) * (size_t)me * 2 * ncol,
+                             hipMemcpyHostToDevice, c->stream));
+      KRY_HIP(hipMemcpyAsync(c->d_colmap, cmap.data(), sizeof(int) * 2 * ncol, hipMemcpyHostToDevice,
+                             c->stream));
+      hipEvent_t e = tbeg(c);
+      KRY_HIP(kry::launch_combine(c->st, c->V, c->ldv, me, c->d_Y, 2 * ncol, c->Z, c->ldv,
+                                  c->d_colmap, 1, c->g, c->stream));
+      tend(c, e, KRY_K_COMBINE, vbytes(c) * (me + 4.0 * ncol));
+    }
+    bool any = false;
+    for (int k = 0; k < nw; ++k) any |= active[k] != 0;
+    if (!any || exact) {
+      KRY_HIP(hipStreamSynchronize(c->stream));
+      break;
+    }
+    if (cyc + 1 == maxcyc) {
+      KRY_HIP(hipStreamSynchronize(c->stream));
+      *max_res = std::max(*max_res, worst);
+      return KRY_ENOCONV;
+    }
+    // next start vector s = V_{m+1} w (overwrites slot 0 after the Z update read it)
+    double* Yw = c->d_Y + (size_t)me * 2 * ncol;
+    KRY_HIP(hipMemcpyAsync(Yw, wt.data(), sizeof(double) * M1, hipMemcpyHostToDevice, c->stream));
+    hipEvent_t e = tbeg(c);
+    KRY_HIP(kry::launch_combine(c->st, c->V, c->ldv, M1, Yw, 1, slot(c, 0), c->ldv, nullptr, 0,
+                                c->g, c->stream));
+    tend(c, e, KRY_K_COMBINE, vbytes(c) * (M1 + 1.0));
+    // the host arrays are reused next cycle: wait for the copies
+    KRY_HIP(hipStreamSynchronize(c->stream));
+  }
+  *max_res = std::max(*max_res, worst);
+  return KRY_OK;
+}
+
+// e^{-T A} x for the vector in slot 0, by restarts in time; the result is
+// left in slot 0.  Each step picks tau so that the Lemma 1 residual
+// h_{m+1,m} |e_m^T u(s)| stays below rate = abstol / T on [0, tau]: the
+// error of the step is then at most rate * tau in the energy norm (A is
+// dissipative in that norm, so e^{-sA} does not amplify it), and the total
+// stays below abstol.  Once |y_hat(t)|_M <= drop the remainder is dropped
+// (e^{-(T-t)A} cannot increase it).
+int expv_slot0(kry_ctx* c, double T, double abstol, double drop, kry_stats* st, double* err_est) {
+  const int m = c->opts.krylov_dim;
+  int rc = ensure_basis(c, m);
+  if (rc) return rc;
+  rc = ensure_y(c, m, 1);
+  if (rc) return rc;
+  const int ldh = m + 1;
+  double t = 0.0;
+  double tau_try = T;
+  double err = 0.0;
+  const double rate = abstol / std::max(T, 1e-300);
+  const int maxsteps = c->opts.max_restarts > 0 ? c->opts.max_restarts : 100000;
+  std::vector<double> u(m), Hc((size_t)m * m);
+  int steps = 0;
+  while (t < T) {
+    if (steps >= maxsteps) { *err_est = err; return KRY_ENOCONV; }
+    double beta = 0.0;
+    int me = 0;
+    rc = arnoldi(c, m, &beta, &me);
+    if (rc) return rc;
+    ++steps;
+    if (st) { st->matvecs_transient += m; st->steps_transient += 1; }
+    if (me == 0) break;  // y_hat(t) = 0
+    if (beta <= drop) {  // remainder below the drop threshold
+      KRY_HIP(hipMemsetAsync(slot(c, 0), 0, c->ldv * c->esz, c->stream));
+      err += beta;
+      break;
+    }
+    const double tmax = T - t;
+    double tau = 0.0;
+    double step_err = 0.0;
+    if (me < m) {
+      // exact invariant subspace: the projected exponential is exact
+      for (int j = 0; j < me; ++j)
+        for (int i = 0; i < me; ++i) Hc[i + (size_t)j * me] = -tmax * c->h_H[i + (size_t)j * ldh];
+      std::vector<double> E((size_t)me * me);
+      kry::expm(me, Hc.data(), E.data());
+      for (int i = 0; i < me; ++i) u[i] = beta * E[i];
+      tau = tmax;
+    } else {
+      const double hnext = c->h_H[m + (size_t)(m - 1) * ldh];
+      double trial = std::min(tau_try, tmax);
+      for (int attempt = 0; attempt < 60 && tau == 0.0; ++attempt) {
+        tau = kry::choose_step(m, c->h_H, ldh, hnext, beta, trial, rate, 16, u.data(), &step_err);
+        if (tau == 0.0) trial /= 16.0;
+      }
+      if (tau == 0.0) return fail(c, KRY_ENOCONV, "time step underflow in the restarted exponential");
+      tau_try = (tau >= trial * (1.0 - 1e-12)) ? 2.0 * trial : 1.25 * tau;
+      if (t + tau > T * (1.0 - 1e-15)) tau = tmax;
+    }
+    err += step_err;
+    KRY_HIP(hipMemcpyAsync(c->d_Y, u.data(), sizeof(double) * me, hipMemcpyHostToDevice, c->stream));
+    hipEvent_t e = tbeg(c);
+    KRY_HIP(kry::launch_combine(c->st, c->V, c->ldv, me, c->d_Y, 1, slot(c, 0), c->ldv, nullptr, 0,
+                                c->g, c->stream));
+    tend(c, e, KRY_K_COMBINE, vbytes(c) * (me + 1.0));
+    KRY_HIP(hipStreamSynchronize(c->stream));
+    t += tau;
+  }
+  *err_est = err;
+  return KRY_OK;
+}
+
+bool finite_all(const std::vector<double>& a) {
+  for (double v : a)
+    if (!std::isfinite(v)) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kry_create(const kry_grid* grid, const double* eps, const double* mu, const double* sigma,
+               const kry_opts* opts, kry_ctx** out) {
+  kry_ctx* c = nullptr;
+  if (!grid || !eps || !opts || !out) return fail(nullptr, KRY_EINVAL, "null argument");
+  *out = nullptr;
+  if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || grid->boundary != 0)
+    return fail(nullptr, KRY_EINVAL, "invalid grid");
+  const long long N3 = (long long)grid->nx * grid->ny * grid->nz;
+  if (N3 > (1LL << 30) / 6) return fail(nullptr, KRY_EINVAL, "grid too large");
+  if (opts->storage != 0 && opts->storage != 1) return fail(nullptr, KRY_EINVAL, "invalid storage");
+  if (opts->krylov_dim < 1 || opts->krylov_dim + 2 > kry::kMaxCoef)
+    return fail(nullptr, KRY_EINVAL, "krylov_dim out of range");
+  if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) return fail(nullptr, KRY_EINVAL, "invalid tol");
+  if (opts->inner_product != 0) return fail(nullptr, KRY_EINVAL, "only the energy inner product is supported");
+  std::vector<double> he(N3), hm, hs(N3, 0.0);
+  if (hipMemcpy(he.data(), eps, sizeof(double) * N3, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(nullptr, KRY_EINVAL, "eps is not a readable device array");
+  if (mu) {
+    hm.resize(N3);
+    if (hipMemcpy(hm.data(), mu, sizeof(double) * N3, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(nullptr, KRY_EINVAL, "mu is not a readable device array");
+  }
+  if (sigma && hipMemcpy(hs.data(), sigma, sizeof(double) * N3, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(nullptr, KRY_EINVAL, "sigma is not a readable device array");
+  if (!finite_all(he) || !finite_all(hm) || !finite_all(hs))
+    return fail(nullptr, KRY_EINVAL, "non-finite material value");
+  for (long long i = 0; i < N3; ++i) {
+    if (!(he[i] > 0.0)) return fail(nullptr, KRY_EINVAL, "eps must be > 0");
+    if (mu && !(hm[i] > 0.0)) return fail(nullptr, KRY_EINVAL, "mu must be > 0");
+    if (hs[i] < 0.0) return fail(nullptr, KRY_EINVAL, "sigma must be >= 0");
+  }
+  c = new (std::nothrow) kry_ctx();
+  if (!c) return fail(nullptr, KRY_ENOMEM, "host allocation failed");
+  c->g.nx = grid->nx;
+  c->g.ny = grid->ny;
+  c->g.nz = grid->nz;
+  c->g.N3 = N3;
+  c->n = 6 * N3;
+  c->ldv = (c->n + 63) / 64 * 64;
+  c->st = opts->storage == 1 ? kry::F32 : kry::F64;
+  c->esz = opts->storage == 1 ? 4 : 8;
+  c->opts = *opts;
+  c->stream = (hipStream_t)opts->stream;
+  // derived arrays: inv_eps, sigma (or sigma/mu), eps, [inv_mu, mu]
+  const int narr = mu ? 5 : 3;
+  std::vector<double> host((size_t)narr * N3);
+  for (long long i = 0; i < N3; ++i) {
+    host[i] = 1.0 / he[i];
+    host[N3 + i] = mu ? hs[i] / hm[i] : hs[i];
+    host[2 * N3 + i] = he[i];
+    if (mu) {
+      host[3 * N3 + i] = 1.0 / hm[i];
+      host[4 * N3 + i] = hm[i];
+    }
+  }
+  if (hipMalloc(&c->d_mat, sizeof(double) * host.size()) != hipSuccess) {
+    delete c;
+    return fail(nullptr, KRY_ENOMEM, "cannot allocate material arrays");
+  }
+  if (hipMemcpy(c->d_mat, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMalloc(&c->d_scal, sizeof(double) * 4) != hipSuccess ||
+      hipHostMalloc(&c->h_scal, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess) {
+    kry_destroy(c);
+    return fail(nullptr, KRY_EHIP, "device setup failed");
+  }
+  c->mats.inv_eps = c->d_mat;
+  c->mats.sigma = c->d_mat + N3;
+  c->mats.eps = c->d_mat + 2 * N3;
+  c->mats.inv_mu = mu ? c->d_mat + 3 * N3 : nullptr;
+  c->mats.mu = mu ? c->d_mat + 4 * N3 : nullptr;
+  *out = c;
+  return KRY_OK;
+}
+
+void kry_destroy(kry_ctx* c) {
+  if (!c) return;
+  hipFree(c->d_mat);
+  hipFree(c->V);
+  hipFree(c->partials);
+  hipFree(c->d_red1);
+  hipFree(c->d_red2);
+  hipFree(c->d_scal);
+  hipFree(c->d_H);
+  hipFree(c->d_Y);
+  hipFree(c->d_colmap);
+  hipFree(c->Z);
+  for (auto& p : c->pending) {
+    hipEventDestroy(p.a);
+    hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+  if (c->h_H) hipHostFree(c->h_H);
+  if (c->h_scal) hipHostFree(c->h_scal);
+  delete c;
+}
+
+const char* kry_last_error(const kry_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+int64_t kry_size(const kry_ctx* c) { return c ? c->n : 0; }
+
+int kry_apply(kry_ctx* c, const double* v, double* w, int32_t ncols) {
+  if (!c || !v || !w || ncols < 0) return fail(c, KRY_EINVAL, "invalid argument");
+  for (int k = 0; k < ncols; ++k)
+    KRY_HIP(kry::launch_stencil(kry::F64, v + (size_t)k * c->n, w + (size_t)k * c->n, nullptr, 0, 0,
+                                c->g, c->mats, nullptr, c->stream));
+  return KRY_OK;
+}
+
+int kry_apply_f32(kry_ctx* c, const float* v, float* w, int32_t ncols) {
+  if (!c || !v || !w || ncols < 0) return fail(c, KRY_EINVAL, "invalid argument");
+  for (int k = 0; k < ncols; ++k)
+    KRY_HIP(kry::launch_stencil(kry::F32, v + (size_t)k * c->n, w + (size_t)k * c->n, nullptr, 0, 0,
+                                c->g, c->mats, nullptr, c->stream));
+  return KRY_OK;
+}
+
+int kry_arnoldi(kry_ctx* c, const double* v, int32_t m, void* V_out, double* H_out, double* beta_out) {
+  if (!c || !v || !V_out || !H_out || !beta_out) return fail(c, KRY_EINVAL, "null argument");
+  if (m < 1 || m + 2 > kry::kMaxCoef) return fail(c, KRY_EINVAL, "invalid m");
+  int rc = ensure_basis(c, std::max(m, c->opts.krylov_dim));
+  if (rc) return rc;
+  KRY_HIP(kry::launch_load_real(c->st, v, slot(c, 0), c->n, c->stream));
+  double beta = 0.0;
+  int me = 0;
+  rc = arnoldi(c, m, &beta, &me);
+  if (rc) return rc;
+  std::memcpy(H_out, c->h_H, sizeof(double) * (size_t)(m + 1) * m);
+  *beta_out = beta;
+  for (int j = 0; j <= m; ++j)
+    KRY_HIP(hipMemcpyAsync((char*)V_out + (size_t)j * c->n * c->esz, slot(c, j), c->n * c->esz,
+                           hipMemcpyDeviceToDevice, c->stream));
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  return me;
+}
+
+int kry_expv(kry_ctx* c, double t, const double* v, double* y, int32_t ncols, kry_stats* st) {
+  if (!c || !v || !y || ncols < 0) return fail(c, KRY_EINVAL, "invalid argument");
+  if (!(t >= 0.0) || !std::isfinite(t)) return fail(c, KRY_EINVAL, "invalid time");
+  if (st) std::memset(st, 0, sizeof(*st));
+  treset(c);
+  const double t0 = now_ms();
+  int rc = ensure_basis(c, c->opts.krylov_dim);
+  if (rc) return rc;
+  int status = KRY_OK;
+  double worst = 0.0;
+  for (int k = 0; k < ncols; ++k) {
+    KRY_HIP(kry::launch_load_real(c->st, v + (size_t)k * c->n, slot(c, 0), c->n, c->stream));
+    std::vector<double> d;
+    rc = host_dots(c, slot(c, 0), nullptr, 0, d);
+    if (rc) return rc;
+    const double vn = std::sqrt(std::max(d[0], 0.0));
+    double err = 0.0;
+    if (t > 0.0 && vn > 0.0) {
+      rc = expv_slot0(c, t, 0.5 * c->opts.tol * vn, 0.25 * c->opts.tol * vn, st, &err);
+      if (rc == KRY_ENOCONV) status = KRY_ENOCONV;
+      else if (rc) return rc;
+    }
+    worst = std::max(worst, vn > 0.0 ? err / vn : 0.0);
+    KRY_HIP(kry::launch_store_real(c->st, slot(c, 0), y + (size_t)k * c->n, c->n, c->stream));
+  }
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  if (st) {
+    st->max_err_estimate = worst;
+    st->ms_transient = st->ms_total = now_ms() - t0;
+    st->converged = status == KRY_OK;
+    texport(c, st);
+  }
+  return status;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Shifted solves for a group of columns sharing one complex source (slot
+// data from b_col): z_k = (A + i w_k)^{-1} b for the listed shifts, stored
+// in Z columns 2*zcolk[k] (Re) and 2*zcolk[k]+1 (Im).
+int stationary_group(kry_ctx* c, const double* b_col, const std::vector<double>& omegas,
+                     const std::vector<int>& zcolk, double tol_rel, kry_stats* st, double* max_res,
+                     double* bnorm_out) {
+  const int nw = (int)omegas.size();
+  for (int k = 0; k < nw; ++k) {
+    KRY_HIP(hipMemsetAsync(zcol(c, 2 * zcolk[k]), 0, 2 * c->ldv * c->esz, c->stream));
+  }
+  // norms of Re b and Im b
+  std::vector<double> d;
+  KRY_HIP(kry::launch_load_complex(c->st, b_col, 1, slot(c, 0), c->n, c->stream));
+  int rc = host_dots(c, slot(c, 0), nullptr, 0, d);
+  if (rc) return rc;
+  const double nim2 = d[0];
+  KRY_HIP(kry::launch_load_complex(c->st, b_col, 0, slot(c, 0), c->n, c->stream));
+  rc = host_dots(c, slot(c, 0), nullptr, 0, d);
+  if (rc) return rc;
+  const double nre2 = d[0];
+  const double bnorm = std::sqrt(nre2 + nim2);
+  *bnorm_out = bnorm;
+  if (bnorm == 0.0) return KRY_OK;
+  int status = KRY_OK;
+  const double tol_part = tol_rel / ((nre2 > 0 && nim2 > 0) ? std::sqrt(2.0) : 1.0);
+  if (nre2 > 0.0) {  // slot 0 holds Re b
+    rc = multishift(c, omegas, std::vector<cplx>(nw, cplx(1.0, 0.0)), zcolk, bnorm, tol_part, st, max_res);
+    if (rc == KRY_ENOCONV) status = rc;
+    else if (rc) return rc;
+  }
+  if (nim2 > 0.0) {
+    KRY_HIP(kry::launch_load_complex(c->st, b_col, 1, slot(c, 0), c->n, c->stream));
+    rc = multishift(c, omegas, std::vector<cplx>(nw, cplx(0.0, 1.0)), zcolk, bnorm, tol_part, st, max_res);
+    if (rc == KRY_ENOCONV) status = rc;
+    else if (rc) return rc;
+  }
+  return status;
+}
+
+int check_multifreq_args(kry_ctx* c, const double* omegas, int n_omega, int n_src, const double* b) {
+  if (!c) return KRY_EINVAL;
+  if (!omegas || !b || n_omega < 1 || n_src < 1) return fail(c, KRY_EINVAL, "invalid argument");
+  for (int k = 0; k < n_omega; ++k)
+    if (!std::isfinite(omegas[k]) || omegas[k] < 0.0) return fail(c, KRY_EINVAL, "invalid omega");
+  return KRY_OK;
+}
+
+// Runs the shifted solves for every output column; calls `each(col, omega)`
+// once the Z columns of a group are ready.  Groups: one per source when the
+// sources are shared by all omegas, one per column otherwise.
+template <typename F>
+int for_each_group(kry_ctx* c, const double* omegas, int n_omega, int n_src, const double* b,
+                   int b_per_omega, double tol_s, kry_stats* st, double* max_res, F each) {
+  int status = KRY_OK;
+  {
+    int rc0 = ensure_basis(c, c->opts.krylov_dim);
+    if (rc0) return rc0;
+  }
+  if (!b_per_omega) {
+    int rc = ensure_z(c, n_omega);
+    if (rc) return rc;
+    std::vector<double> om(omegas, omegas + n_omega);
+    std::vector<int> zc(n_omega);
+    for (int k = 0; k < n_omega; ++k) zc[k] = k;
+    for (int s = 0; s < n_src; ++s) {
+      double bn = 0.0;
+      rc = stationary_group(c, b + (size_t)s * 2 * c->n, om, zc, tol_s, st, max_res, &bn);
+      if (rc == KRY_ENOCONV) status = rc;
+      else if (rc) return rc;
+      for (int k = 0; k < n_omega; ++k) {
+        rc = each(k * n_src + s, omegas[k], k, bn);
+        if (rc == KRY_ENOCONV) status = rc;
+        else if (rc) return rc;
+      }
+    }
+  } else {
+    int rc = ensure_z(c, 1);
+    if (rc) return rc;
+    for (int k = 0; k < n_omega; ++k) {
+      for (int s = 0; s < n_src; ++s) {
+        const int col = k * n_src + s;
+        double bn = 0.0;
+        rc = stationary_group(c, b + (size_t)col * 2 * c->n, std::vector<double>{omegas[k]},
+                              std::vector<int>{0}, tol_s, st, max_res, &bn);
+        if (rc == KRY_ENOCONV) status = rc;
+        else if (rc) return rc;
+        rc = each(col, omegas[k], 0, bn);
+        if (rc == KRY_ENOCONV) status = rc;
+        else if (rc) return rc;
+      }
+    }
+  }
+  return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kry_stationary(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src, const double* b,
+                   int32_t b_per_omega, double* z, kry_stats* st) {
+  int rc = check_multifreq_args(c, omegas, n_omega, n_src, b);
+  if (rc) return rc;
+  if (!z) return fail(c, KRY_EINVAL, "null output");
+  if (st) std::memset(st, 0, sizeof(*st));
+  treset(c);
+  const double t0 = now_ms();
+  double max_res = 0.0;
+  rc = for_each_group(c, omegas, n_omega, n_src, b, b_per_omega, c->opts.tol, st, &max_res,
+                      [&](int col, double, int zk, double) -> int {
+                        KRY_HIP(kry::launch_store_complex(c->st, zcol(c, 2 * zk), zcol(c, 2 * zk + 1),
+                                                          z + (size_t)col * 2 * c->n, c->n, c->stream));
+                        return KRY_OK;
+                      });
+  if (rc && rc != KRY_ENOCONV) return rc;
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  if (st) {
+    st->max_residual = max_res;
+    st->ms_stationary = st->ms_total = now_ms() - t0;
+    st->converged = rc == KRY_OK;
+    texport(c, st);
+  }
+  return rc;
+}
+
+int kry_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src,
+                        const double* b, int32_t b_per_omega, double T, double* yT, kry_stats* st) {
+  int rc = check_multifreq_args(c, omegas, n_omega, n_src, b);
+  if (rc) return rc;
+  if (!yT) return fail(c, KRY_EINVAL, "null output");
+  if (!(T >= 0.0) || !std::isfinite(T)) return fail(c, KRY_EINVAL, "invalid T");
+  if (st) std::memset(st, 0, sizeof(*st));
+  treset(c);
+  const double t0 = now_ms();
+  double max_res = 0.0, max_err = 0.0;
+  double t_trans = 0.0;
+  // error budget (relative to |y(T)|_M): shifted residual 0.05 tol,
+  // transient steps 0.15 tol, dropped remainder 0.15 tol
+  const double tol = c->opts.tol;
+  rc = for_each_group(
+      c, omegas, n_omega, n_src, b, b_per_omega, 0.05 * tol, st, &max_res,
+      [&](int col, double w, int zk, double bnorm) -> int {
+        const double t1 = now_ms();
+        const double sn = std::sin(w * T), cs = std::cos(w * T);
+        void* zre = zcol(c, 2 * zk);
+        void* zim = zcol(c, 2 * zk + 1);
+        double* out = yT + (size_t)col * c->n;
+        if (bnorm == 0.0) {
+          KRY_HIP(hipMemsetAsync(out, 0, sizeof(double) * c->n, c->stream));
+          return KRY_OK;
+        }
+        // |Im(e^{iwT} z)|_M from <re,re>, <re,im>, <im,im>
+        std::vector<double> d1, d2;
+        int r = host_dots(c, zre, zre, 2, d1);  // <re,re>, <re,im>, |re|^2
+        if (r) return r;
+        const double nre = d1[2], xri = d1[1];
+        r = host_dots(c, zim, nullptr, 0, d2);
+        if (r) return r;
+        const double nim = d2[0];
+        const double yt2 = sn * sn * nre + cs * cs * nim + 2.0 * sn * cs * xri;
+        const double ynorm = std::sqrt(std::max(yt2, 0.0));
+        const double scale = std::max(ynorm, 1e-300);
+        // transient: y_hat(0) = Im z
+        KRY_HIP(hipMemcpyAsync(slot(c, 0), zim, c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
+        double err = 0.0;
+        int status = KRY_OK;
+        if (T > 0.0) {
+          r = expv_slot0(c, T, 0.15 * tol * scale, 0.15 * tol * scale, st, &err);
+          if (r == KRY_ENOCONV) status = r;
+          else if (r) return r;
+        }
+        max_err = std::max(max_err, err / scale);
+        KRY_HIP(kry::launch_assemble(c->st, zre, zim, slot(c, 0), sn, cs, out, c->n, c->stream));
+        KRY_HIP(hipStreamSynchronize(c->stream));
+        t_trans += now_ms() - t1;
+        return status;
+      });
+  if (rc && rc != KRY_ENOCONV) return rc;
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  if (st) {
+    st->max_residual = max_res;
+    st->max_err_estimate = max_err;
+    st->ms_total = now_ms() - t0;
+    st->ms_transient = t_trans;
+    st->ms_stationary = st->ms_total - t_trans;
+    st->converged = rc == KRY_OK;
+    texport(c, st);
+  }
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal interface between the C-ABI driver and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kry {
+
+enum Storage : int { F64 = 0, F32 = 1 };
+
+struct DevGrid {
+  int nx, ny, nz;
+  long long N3;  // cells
+};
+
+// Per-cell material data derived at context creation (all FP64, N3 each).
+struct DevMats {
+  const double* inv_eps;  // 1 / eps
+  const double* sigma;    // sigma (sigma/mu when mu is given)
+  const double* inv_mu;   // 1 / mu, or nullptr when mu == 1
+  const double* eps;      // eps: energy weight of the E planes
+  const double* mu;       // mu: energy weight of the H planes, or nullptr
+};
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kChunk = 16;       // basis vectors per dot-product chunk
+constexpr int kMaxCoef = 1026;   // max coefficients staged by an update (m <= 1024)
+
+// Number of workgroups the cell-parallel kernels use, and cells per thread.
+int cells_per_thread(long long N3);
+int cell_blocks(long long N3);
+
+// w = A v (single column).  If V != nullptr also writes per-workgroup
+// partial sums of <w, V_i>_M for i < cnt and |w|_M^2 (slot cnt) into
+// partials[blk * (cnt + 1) + q].
+hipError_t launch_stencil(Storage st, const void* v, void* w, const void* V, long long ldv,
+                          int cnt, const DevGrid& g, const DevMats& m, double* partials,
+                          hipStream_t s);
+
+// Partial sums of <x, V_i>_M (i < cnt) and |x|_M^2 (slot cnt).
+hipError_t launch_dots(Storage st, const void* x, const void* V, long long ldv, int cnt,
+                       const DevGrid& g, const DevMats& m, double* partials, hipStream_t s);
+
+// out = (w - sum_i coef[i] V_i) * (*scale or 1); out may alias w.
+hipError_t launch_update(Storage st, const void* w, const void* V, long long ldv, int cnt,
+                         const double* coef, const double* scale, void* out,
+                         const DevGrid& g, hipStream_t s);
+
+// out[q] = sum_p partials[p * stride + q] for q < cnt, fixed order.
+hipError_t launch_reduce(const double* partials, int nparts, int stride, int cnt, double* out,
+                         hipStream_t s);
+
+// scal[1] = sqrt(red[0]), scal[0] = 1/scal[1] (0 if scal[1] == 0).
+hipError_t launch_fin_start(const double* red, double* scal, hipStream_t s);
+
+// Arnoldi column j after two Gram-Schmidt passes: H[:, j] = red1 + red2,
+// H[j+1, j] = nu = sqrt(|w1|^2 - |red2|^2) (0 on breakdown), scal[0] = 1/nu.
+hipError_t launch_fin_step(const double* red1, const double* red2, int j, double* H, int ldh,
+                           double* scal, hipStream_t s);
+
+// out = x * (*scale).
+hipError_t launch_scale(Storage st, const void* x, const double* scale, void* out, long long n,
+                        hipStream_t s);
+
+// out_c (= or +=) sum_{i<m} V_i Y[i + c*m] for c < ncol; column c goes to
+// out + colmap[c] * ldo (colmap may be nullptr: identity).
+hipError_t launch_combine(Storage st, const void* V, long long ldv, int m, const double* Y,
+                          int ncol, void* out, long long ldo, const int* colmap, int accumulate,
+                          const DevGrid& g, hipStream_t s);
+
+// Conversions between caller FP64 buffers and storage-type vectors.
+hipError_t launch_load_complex(Storage st, const double* b, int part, void* out, long long n,
+                               hipStream_t s);
+hipError_t launch_load_real(Storage st, const double* src, void* out, long long n, hipStream_t s);
+hipError_t launch_store_real(Storage st, const void* src, double* out, long long n, hipStream_t s);
+hipError_t launch_store_complex(Storage st, const void* re, const void* im, double* out,
+                                long long n, hipStream_t s);
+
+// out = sn * re + cs * im - yhat  (yhat may be nullptr): Im(e^{iwT} z) - y_hat(T).
+hipError_t launch_assemble(Storage st, const void* re, const void* im, const void* yhat,
+                           double sn, double cs, double* out, long long n, hipStream_t s);
+
+}  // namespace kry

@@ -1,0 +1,590 @@
+// HIP kernels for gfx950 (CDNA4): Yee operator, Arnoldi Gram-Schmidt in the
+// energy inner product, basis combinations and conversions.
+//
+// Every streaming kernel is cell-parallel: a thread owns whole cells and
+// touches the six planes [Hx, Hy, Hz, Ex, Ey, Ez] of each, so plane offsets
+// are p * N3 and no 64-bit division is needed; consecutive threads own
+// consecutive cells, so every plane access is coalesced.  Reductions are
+// two-stage (per-workgroup partial sums, then a fixed-order sum), so the
+// results are bitwise reproducible run to run.
+#include "kry_internal.h"
+
+namespace kry {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum CH per-thread values over the workgroup; thread q < valid stores the
+// q-th total to dst[q].
+template <int CH>
+__device__ __forceinline__ void block_sum_store(const double (&acc)[CH], int valid, double* dst) {
+  __shared__ double sh[CH][kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < CH; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) sh[q][wid] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < valid) {
+    const int q = threadIdx.x;
+    dst[q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+  }
+  __syncthreads();
+}
+
+// Logical block index with consecutive logical blocks kept on one XCD: the
+// dispatcher places block b on XCD (b mod 8), so remap b -> (b mod 8) *
+// (nblk / 8) + b / 8 over the largest multiple of 8, keeping neighbouring
+// z-slabs of the stencil in the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+  const int full = nblk & ~7;
+  if (b >= full) return b;
+  const int per = full >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+template <typename T>
+__device__ __forceinline__ T ld(const T* p) { return *p; }
+
+// ---------------------------------------------------------------------------
+// Yee operator, optionally fused with the first Gram-Schmidt dot pass.
+//   (A y)_H = sigma/mu H + (C E)/mu,   (A y)_E = (sigma E - C^T H)/eps
+//   (C E)x = dEz/dy - dEy/dz with forward differences (zero beyond N-1),
+//   (C^T H)x = dHz/dy - dHy/dz with backward differences (zero below 0),
+//   and cyclically.
+// Arithmetic is in the storage type T (FP32 storage computes the stencil in
+// FP32); dot products accumulate in FP64.
+template <typename T, bool HAS_MU, int CPT, bool DOTS>
+__global__ __launch_bounds__(kBlock) void k_stencil(const T* __restrict__ v, T* __restrict__ w,
+                                                    const T* __restrict__ V, long long ldv, int cnt,
+                                                    DevGrid g, DevMats mt,
+                                                    double* __restrict__ partials) {
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const long long N3 = g.N3;
+  const long long sy = nx, sz = (long long)nx * ny;
+  const T* Hx = v;
+  const T* Hy = v + N3;
+  const T* Hz = v + 2 * N3;
+  const T* Ex = v + 3 * N3;
+  const T* Ey = v + 4 * N3;
+  const T* Ez = v + 5 * N3;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+
+  double wm[CPT][6];  // weight * output, for the dots
+  long long cellq[CPT];
+  bool okq[CPT];
+  double nrm = 0.0;
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const long long c = ((long long)lb * CPT + q) * kBlock + threadIdx.x;
+    okq[q] = c < N3;
+    cellq[q] = okq[q] ? c : 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) wm[q][p] = 0.0;
+    if (!okq[q]) continue;
+    const int ci = (int)c;
+    const int i = ci % nx;
+    const int t = ci / nx;
+    const int j = t % ny;
+    const int k = t / ny;
+    const T z0 = T(0);
+    const T ex = Ex[c], ey = Ey[c], ez = Ez[c];
+    const T ex_j = (j + 1 < ny) ? Ex[c + sy] : z0;
+    const T ex_k = (k + 1 < nz) ? Ex[c + sz] : z0;
+    const T ey_i = (i + 1 < nx) ? Ey[c + 1] : z0;
+    const T ey_k = (k + 1 < nz) ? Ey[c + sz] : z0;
+    const T ez_i = (i + 1 < nx) ? Ez[c + 1] : z0;
+    const T ez_j = (j + 1 < ny) ? Ez[c + sy] : z0;
+    const T cex = (ez_j - ez) - (ey_k - ey);
+    const T cey = (ex_k - ex) - (ez_i - ez);
+    const T cez = (ey_i - ey) - (ex_j - ex);
+    const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
+    const T hx_j = (j > 0) ? Hx[c - sy] : z0;
+    const T hx_k = (k > 0) ? Hx[c - sz] : z0;
+    const T hy_i = (i > 0) ? Hy[c - 1] : z0;
+    const T hy_k = (k > 0) ? Hy[c - sz] : z0;
+    const T hz_i = (i > 0) ? Hz[c - 1] : z0;
+    const T hz_j = (j > 0) ? Hz[c - sy] : z0;
+    const T chx = (hz - hz_j) - (hy - hy_k);
+    const T chy = (hx - hx_k) - (hz - hz_i);
+    const T chz = (hy - hy_i) - (hx - hx_j);
+    const T ie = T(mt.inv_eps[c]);
+    const T sg = T(mt.sigma[c]);
+    T o[6];
+    if (HAS_MU) {
+      const T im = T(mt.inv_mu[c]);
+      o[0] = sg * hx + im * cex;
+      o[1] = sg * hy + im * cey;
+      o[2] = sg * hz + im * cez;
+      o[3] = ie * (T(mt.sigma[c] * mt.mu[c]) * ex - chx);
+      o[4] = ie * (T(mt.sigma[c] * mt.mu[c]) * ey - chy);
+      o[5] = ie * (T(mt.sigma[c] * mt.mu[c]) * ez - chz);
+    } else {
+      o[0] = sg * hx + cex;
+      o[1] = sg * hy + cey;
+      o[2] = sg * hz + cez;
+      o[3] = ie * (sg * ex - chx);
+      o[4] = ie * (sg * ey - chy);
+      o[5] = ie * (sg * ez - chz);
+    }
+#pragma unroll
+    for (int p = 0; p < 6; ++p) w[p * N3 + c] = o[p];
+    if (DOTS) {
+      const double we = mt.eps[c];
+      const double wh = HAS_MU ? mt.mu[c] : 1.0;
+#pragma unroll
+      for (int p = 0; p < 6; ++p) {
+        const double ov = (double)o[p];
+        wm[q][p] = (p < 3 ? wh : we) * ov;
+        nrm += wm[q][p] * ov;
+      }
+    }
+  }
+  if (!DOTS) return;
+  for (int i0 = 0; i0 < cnt; i0 += kChunk) {
+    double acc[kChunk];
+#pragma unroll
+    for (int r = 0; r < kChunk; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int r = 0; r < kChunk; ++r) {
+      if (i0 + r < cnt) {
+        const T* vi = V + (long long)(i0 + r) * ldv;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          if (!okq[q]) continue;
+#pragma unroll
+          for (int p = 0; p < 6; ++p) acc[r] += wm[q][p] * (double)vi[p * N3 + cellq[q]];
+        }
+      }
+    }
+    const int valid = min(kChunk, cnt - i0);
+    block_sum_store<kChunk>(acc, valid, partials + (long long)lb * (cnt + 1) + i0);
+  }
+  const double a1[1] = {nrm};
+  block_sum_store<1>(a1, 1, partials + (long long)lb * (cnt + 1) + cnt);
+}
+
+// Partial sums of <x, V_i>_M and |x|_M^2.
+template <typename T, bool HAS_MU, int CPT>
+__global__ __launch_bounds__(kBlock) void k_dots(const T* __restrict__ x, const T* __restrict__ V,
+                                                 long long ldv, int cnt, DevGrid g, DevMats mt,
+                                                 double* __restrict__ partials) {
+  const long long N3 = g.N3;
+  double xm[CPT][6];
+  long long cellq[CPT];
+  bool okq[CPT];
+  double nrm = 0.0;
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const long long c = ((long long)blockIdx.x * CPT + q) * kBlock + threadIdx.x;
+    okq[q] = c < N3;
+    cellq[q] = okq[q] ? c : 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) xm[q][p] = 0.0;
+    if (!okq[q]) continue;
+    const double we = mt.eps[c];
+    const double wh = HAS_MU ? mt.mu[c] : 1.0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const double xv = (double)x[p * N3 + c];
+      xm[q][p] = (p < 3 ? wh : we) * xv;
+      nrm += xm[q][p] * xv;
+    }
+  }
+  for (int i0 = 0; i0 < cnt; i0 += kChunk) {
+    double acc[kChunk];
+#pragma unroll
+    for (int r = 0; r < kChunk; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int r = 0; r < kChunk; ++r) {
+      if (i0 + r < cnt) {
+        const T* vi = V + (long long)(i0 + r) * ldv;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          if (!okq[q]) continue;
+#pragma unroll
+          for (int p = 0; p < 6; ++p) acc[r] += xm[q][p] * (double)vi[p * N3 + cellq[q]];
+        }
+      }
+    }
+    const int valid = min(kChunk, cnt - i0);
+    block_sum_store<kChunk>(acc, valid, partials + (long long)blockIdx.x * (cnt + 1) + i0);
+  }
+  const double a1[1] = {nrm};
+  block_sum_store<1>(a1, 1, partials + (long long)blockIdx.x * (cnt + 1) + cnt);
+}
+
+// out = (w - sum_i coef[i] V_i) * scale; out may alias w (each element is
+// read before it is written by the same thread).
+template <typename T, int CPT>
+__global__ __launch_bounds__(kBlock) void k_update(const T* w, const T* __restrict__ V,
+                                                   long long ldv, int cnt,
+                                                   const double* __restrict__ coef,
+                                                   const double* __restrict__ scale, T* out,
+                                                   long long N3) {
+  __shared__ double sc[kMaxCoef];
+  for (int t = threadIdx.x; t < cnt; t += kBlock) sc[t] = coef[t];
+  __syncthreads();
+  const double s = scale ? *scale : 1.0;
+  double acc[CPT][6];
+  long long cellq[CPT];
+  bool okq[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const long long c = ((long long)blockIdx.x * CPT + q) * kBlock + threadIdx.x;
+    okq[q] = c < N3;
+    cellq[q] = okq[q] ? c : 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) acc[q][p] = okq[q] ? (double)w[p * N3 + c] : 0.0;
+  }
+  for (int i = 0; i < cnt; ++i) {
+    const double h = sc[i];
+    const T* vi = V + (long long)i * ldv;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      if (!okq[q]) continue;
+#pragma unroll
+      for (int p = 0; p < 6; ++p) acc[q][p] -= h * (double)vi[p * N3 + cellq[q]];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    if (!okq[q]) continue;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) out[p * N3 + cellq[q]] = T(acc[q][p] * s);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ partials, int nparts,
+                                                   int stride, double* __restrict__ out) {
+  const int q = blockIdx.x;
+  double acc = 0.0;
+  for (int p = threadIdx.x; p < nparts; p += kBlock) acc += partials[(long long)p * stride + q];
+  const double a1[1] = {acc};
+  block_sum_store<1>(a1, 1, out + q);
+}
+
+__global__ void k_fin_start(const double* __restrict__ red, double* __restrict__ scal) {
+  if (threadIdx.x == 0) {
+    const double b = sqrt(fmax(red[0], 0.0));
+    scal[1] = b;
+    scal[0] = b > 0.0 ? 1.0 / b : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_step(const double* __restrict__ red1,
+                                                     const double* __restrict__ red2, int j,
+                                                     double* __restrict__ H, int ldh,
+                                                     double* __restrict__ scal) {
+  double ss = 0.0;
+  for (int i = threadIdx.x; i <= j; i += kBlock) {
+    H[i + (long long)j * ldh] = red1[i] + red2[i];
+    ss += red2[i] * red2[i];
+  }
+  __shared__ double tot[1];
+  const double a1[1] = {ss};
+  block_sum_store<1>(a1, 1, tot);
+  if (threadIdx.x == 0) {
+    const double wnorm = sqrt(fmax(red1[j + 1], 0.0));  // |A v_j|_M before projection
+    const double nu2 = red2[j + 1] - tot[0];
+    double nu = sqrt(fmax(nu2, 0.0));
+    if (!(nu > 1e-12 * wnorm)) nu = 0.0;  // exact invariant subspace (or A v_j = 0)
+    H[j + 1 + (long long)j * ldh] = nu;
+    scal[0] = nu > 0.0 ? 1.0 / nu : 0.0;
+  }
+}
+
+template <typename T>
+__global__ void k_scale(const T* __restrict__ x, const double* __restrict__ s, T* out, long long n) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) out[e] = T((double)x[e] * (*s));
+}
+
+// out_c (=|+=) sum_{i<m} V_i Y[i + c*m]; columns processed CC at a time.
+template <typename T, int CC>
+__global__ __launch_bounds__(kBlock) void k_combine(const T* V, long long ldv, int m,
+                                                    const double* __restrict__ Y, int ncol,
+                                                    T* out, long long ldo,
+                                                    const int* __restrict__ colmap, int accumulate,
+                                                    long long N3) {
+  extern __shared__ double sY[];  // m * CC
+  const int c0 = blockIdx.y * CC;
+  const int nc = min(CC, ncol - c0);
+  for (int t = threadIdx.x; t < m * CC; t += kBlock) {
+    const int i = t / CC, cc = t % CC;
+    sY[t] = (cc < nc) ? Y[i + (long long)(c0 + cc) * m] : 0.0;
+  }
+  __syncthreads();
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= N3) return;
+  double acc[CC][6];
+#pragma unroll
+  for (int cc = 0; cc < CC; ++cc)
+#pragma unroll
+    for (int p = 0; p < 6; ++p) acc[cc][p] = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const T* vi = V + (long long)i * ldv;
+    double vv[6];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) vv[p] = (double)vi[p * N3 + c];
+#pragma unroll
+    for (int cc = 0; cc < CC; ++cc) {
+      const double y = sY[i * CC + cc];
+#pragma unroll
+      for (int p = 0; p < 6; ++p) acc[cc][p] += vv[p] * y;
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < CC; ++cc) {
+    if (cc >= nc) break;
+    const int col = colmap ? colmap[c0 + cc] : (c0 + cc);
+    T* o = out + (long long)col * ldo;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const long long e = p * N3 + c;
+      const double prev = accumulate ? (double)o[e] : 0.0;
+      o[e] = T(prev + acc[cc][p]);
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_load_complex(const double* __restrict__ b, int part, T* __restrict__ out,
+                               long long n) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) out[e] = T(b[2 * e + part]);
+}
+
+template <typename T>
+__global__ void k_load_real(const double* __restrict__ src, T* __restrict__ out, long long n) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) out[e] = T(src[e]);
+}
+
+template <typename T>
+__global__ void k_store_real(const T* __restrict__ src, double* __restrict__ out, long long n) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) out[e] = (double)src[e];
+}
+
+template <typename T>
+__global__ void k_store_complex(const T* __restrict__ re, const T* __restrict__ im,
+                                double* __restrict__ out, long long n) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) {
+    out[2 * e] = (double)re[e];
+    out[2 * e + 1] = (double)im[e];
+  }
+}
+
+template <typename T>
+__global__ void k_assemble(const T* __restrict__ re, const T* __restrict__ im,
+                           const T* __restrict__ yhat, double sn, double cs,
+                           double* __restrict__ out, long long n) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) {
+    double v = sn * (double)re[e] + cs * (double)im[e];
+    if (yhat) v -= (double)yhat[e];
+    out[e] = v;
+  }
+}
+
+inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+int cells_per_thread(long long N3) { return N3 >= (long long)kBlock * 4 * 1024 ? 4 : 1; }
+int cell_blocks(long long N3) {
+  const long long per = (long long)kBlock * cells_per_thread(N3);
+  return (int)((N3 + per - 1) / per);
+}
+
+template <typename T>
+static hipError_t stencil_t(const void* v, void* w, const void* V, long long ldv, int cnt,
+                            const DevGrid& g, const DevMats& m, double* partials, hipStream_t s) {
+  const int cpt = cells_per_thread(g.N3);
+  const dim3 grid(cell_blocks(g.N3)), blk(kBlock);
+  const T* vv = (const T*)v;
+  T* ww = (T*)w;
+  const T* VV = (const T*)V;
+  const bool dots = V != nullptr;
+  const bool mu = m.inv_mu != nullptr;
+#define KRY_STENCIL(C, M, D) \
+  hipLaunchKernelGGL((k_stencil<T, M, C, D>), grid, blk, 0, s, vv, ww, VV, ldv, cnt, g, m, partials)
+  if (cpt == 4) {
+    if (mu) { if (dots) KRY_STENCIL(4, true, true); else KRY_STENCIL(4, true, false); }
+    else { if (dots) KRY_STENCIL(4, false, true); else KRY_STENCIL(4, false, false); }
+  } else {
+    if (mu) { if (dots) KRY_STENCIL(1, true, true); else KRY_STENCIL(1, true, false); }
+    else { if (dots) KRY_STENCIL(1, false, true); else KRY_STENCIL(1, false, false); }
+  }
+#undef KRY_STENCIL
+  return hipGetLastError();
+}
+
+hipError_t launch_stencil(Storage st, const void* v, void* w, const void* V, long long ldv, int cnt,
+                          const DevGrid& g, const DevMats& m, double* partials, hipStream_t s) {
+  return st == F64 ? stencil_t<double>(v, w, V, ldv, cnt, g, m, partials, s)
+                   : stencil_t<float>(v, w, V, ldv, cnt, g, m, partials, s);
+}
+
+template <typename T>
+static hipError_t dots_t(const void* x, const void* V, long long ldv, int cnt, const DevGrid& g,
+                         const DevMats& m, double* partials, hipStream_t s) {
+  const int cpt = cells_per_thread(g.N3);
+  const dim3 grid(cell_blocks(g.N3)), blk(kBlock);
+  const bool mu = m.inv_mu != nullptr;
+  const T* xx = (const T*)x;
+  const T* VV = (const T*)V;
+  if (cpt == 4) {
+    if (mu) hipLaunchKernelGGL((k_dots<T, true, 4>), grid, blk, 0, s, xx, VV, ldv, cnt, g, m, partials);
+    else hipLaunchKernelGGL((k_dots<T, false, 4>), grid, blk, 0, s, xx, VV, ldv, cnt, g, m, partials);
+  } else {
+    if (mu) hipLaunchKernelGGL((k_dots<T, true, 1>), grid, blk, 0, s, xx, VV, ldv, cnt, g, m, partials);
+    else hipLaunchKernelGGL((k_dots<T, false, 1>), grid, blk, 0, s, xx, VV, ldv, cnt, g, m, partials);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dots(Storage st, const void* x, const void* V, long long ldv, int cnt,
+                       const DevGrid& g, const DevMats& m, double* partials, hipStream_t s) {
+  return st == F64 ? dots_t<double>(x, V, ldv, cnt, g, m, partials, s)
+                   : dots_t<float>(x, V, ldv, cnt, g, m, partials, s);
+}
+
+template <typename T>
+static hipError_t update_t(const void* w, const void* V, long long ldv, int cnt, const double* coef,
+                           const double* scale, void* out, const DevGrid& g, hipStream_t s) {
+  if (cnt > kMaxCoef) return hipErrorInvalidValue;
+  const int cpt = cells_per_thread(g.N3);
+  const dim3 grid(cell_blocks(g.N3)), blk(kBlock);
+  if (cpt == 4)
+    hipLaunchKernelGGL((k_update<T, 4>), grid, blk, 0, s, (const T*)w, (const T*)V, ldv, cnt, coef,
+                       scale, (T*)out, g.N3);
+  else
+    hipLaunchKernelGGL((k_update<T, 1>), grid, blk, 0, s, (const T*)w, (const T*)V, ldv, cnt, coef,
+                       scale, (T*)out, g.N3);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(Storage st, const void* w, const void* V, long long ldv, int cnt,
+                         const double* coef, const double* scale, void* out, const DevGrid& g,
+                         hipStream_t s) {
+  return st == F64 ? update_t<double>(w, V, ldv, cnt, coef, scale, out, g, s)
+                   : update_t<float>(w, V, ldv, cnt, coef, scale, out, g, s);
+}
+
+hipError_t launch_reduce(const double* partials, int nparts, int stride, int cnt, double* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(cnt), dim3(kBlock), 0, s, partials, nparts, stride, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fin_start(const double* red, double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(64), 0, s, red, scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_fin_step(const double* red1, const double* red2, int j, double* H, int ldh,
+                           double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(kBlock), 0, s, red1, red2, j, H, ldh, scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(Storage st, const void* x, const double* scale, void* out, long long n,
+                        hipStream_t s) {
+  if (st == F64)
+    hipLaunchKernelGGL(k_scale<double>, dim3(blocks_for(n)), dim3(kBlock), 0, s, (const double*)x,
+                       scale, (double*)out, n);
+  else
+    hipLaunchKernelGGL(k_scale<float>, dim3(blocks_for(n)), dim3(kBlock), 0, s, (const float*)x,
+                       scale, (float*)out, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t combine_t(const void* V, long long ldv, int m, const double* Y, int ncol, void* out,
+                            long long ldo, const int* colmap, int accumulate, const DevGrid& g,
+                            hipStream_t s) {
+  if (m <= 0 || ncol <= 0) return hipSuccess;
+  const unsigned gx = blocks_for(g.N3);
+  if (ncol == 1) {
+    const size_t shm = sizeof(double) * (size_t)m;
+    hipLaunchKernelGGL((k_combine<T, 1>), dim3(gx, 1), dim3(kBlock), shm, s, (const T*)V, ldv, m, Y,
+                       ncol, (T*)out, ldo, colmap, accumulate, g.N3);
+  } else {
+    constexpr int CC = 8;
+    const size_t shm = sizeof(double) * (size_t)m * CC;
+    hipLaunchKernelGGL((k_combine<T, CC>), dim3(gx, (ncol + CC - 1) / CC), dim3(kBlock), shm, s,
+                       (const T*)V, ldv, m, Y, ncol, (T*)out, ldo, colmap, accumulate, g.N3);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(Storage st, const void* V, long long ldv, int m, const double* Y, int ncol,
+                          void* out, long long ldo, const int* colmap, int accumulate,
+                          const DevGrid& g, hipStream_t s) {
+  return st == F64 ? combine_t<double>(V, ldv, m, Y, ncol, out, ldo, colmap, accumulate, g, s)
+                   : combine_t<float>(V, ldv, m, Y, ncol, out, ldo, colmap, accumulate, g, s);
+}
+
+hipError_t launch_load_complex(Storage st, const double* b, int part, void* out, long long n,
+                               hipStream_t s) {
+  if (st == F64)
+    hipLaunchKernelGGL(k_load_complex<double>, dim3(blocks_for(n)), dim3(kBlock), 0, s, b, part,
+                       (double*)out, n);
+  else
+    hipLaunchKernelGGL(k_load_complex<float>, dim3(blocks_for(n)), dim3(kBlock), 0, s, b, part,
+                       (float*)out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_real(Storage st, const double* src, void* out, long long n, hipStream_t s) {
+  if (st == F64)
+    hipLaunchKernelGGL(k_load_real<double>, dim3(blocks_for(n)), dim3(kBlock), 0, s, src,
+                       (double*)out, n);
+  else
+    hipLaunchKernelGGL(k_load_real<float>, dim3(blocks_for(n)), dim3(kBlock), 0, s, src,
+                       (float*)out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_real(Storage st, const void* src, double* out, long long n, hipStream_t s) {
+  if (st == F64)
+    hipLaunchKernelGGL(k_store_real<double>, dim3(blocks_for(n)), dim3(kBlock), 0, s,
+                       (const double*)src, out, n);
+  else
+    hipLaunchKernelGGL(k_store_real<float>, dim3(blocks_for(n)), dim3(kBlock), 0, s,
+                       (const float*)src, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_complex(Storage st, const void* re, const void* im, double* out,
+                                long long n, hipStream_t s) {
+  if (st == F64)
+    hipLaunchKernelGGL(k_store_complex<double>, dim3(blocks_for(n)), dim3(kBlock), 0, s,
+                       (const double*)re, (const double*)im, out, n);
+  else
+    hipLaunchKernelGGL(k_store_complex<float>, dim3(blocks_for(n)), dim3(kBlock), 0, s,
+                       (const float*)re, (const float*)im, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(Storage st, const void* re, const void* im, const void* yhat, double sn,
+                           double cs, double* out, long long n, hipStream_t s) {
+  if (st == F64)
+    hipLaunchKernelGGL(k_assemble<double>, dim3(blocks_for(n)), dim3(kBlock), 0, s,
+                       (const double*)re, (const double*)im, (const double*)yhat, sn, cs, out, n);
+  else
+    hipLaunchKernelGGL(k_assemble<float>, dim3(blocks_for(n)), dim3(kBlock), 0, s,
+                       (const float*)re, (const float*)im, (const float*)yhat, sn, cs, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace kry

@@ -1,0 +1,70 @@
+"""Write sampled oracle results for the large workloads (calls only the oracle).
+
+The full-size workloads are too large for the oracle to finish inside a test,
+so this script runs it once and stores what a test can compare against:
+the 2-norm of y(T), its values at seeded random indices, and its projections
+on seeded random vectors.  y(T) is evaluated by the variation-of-constants
+route (one exponential action of the augmented matrix), which needs no
+shifted solve and does not use Corollary 3.
+
+    python tests/golden/make_golden.py c2        # ~1 h on one CPU core
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import workloads as wk  # noqa: E402
+from oracle import operator as op  # noqa: E402
+from oracle import solve as osv  # noqa: E402
+
+N_SAMPLES = 4096
+N_PROJ = 4
+SAMPLE_SEED = 20170630
+
+
+def sample_spec(n):
+    rng = np.random.default_rng(SAMPLE_SEED)
+    idx = np.sort(rng.choice(n, size=min(N_SAMPLES, n), replace=False))
+    return idx
+
+
+def projection_vector(n, k):
+    return np.random.default_rng(SAMPLE_SEED + 1 + k).standard_normal(n)
+
+
+def main(cfg_name: str):
+    wl = wk.CONFIGS[cfg_name]
+    inp = wk.generate(wl)
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    out = {"workload": wl.name, "n": wl.n, "T": wl.T, "columns": [],
+           "route": "augmented-matrix exponential action (expm_multiply)"}
+    idx = sample_spec(wl.n)
+    out["indices"] = idx.tolist()
+    for wi, omega in enumerate(wl.omegas):
+        for ti, theta in enumerate(inp.thetas):
+            b = wk.source_vector(wl, omega, float(theta))
+            t0 = time.time()
+            y = osv.augmented_solution(A, b, omega, wl.T)
+            dt = time.time() - t0
+            col = {"omega_index": wi, "theta_index": ti, "omega": omega,
+                   "theta": float(theta), "norm2": float(np.linalg.norm(y)),
+                   "values": y[idx].tolist(),
+                   "projections": [float(projection_vector(wl.n, k) @ y)
+                                   for k in range(N_PROJ)],
+                   "oracle_seconds": dt}
+            out["columns"].append(col)
+            print(f"{cfg_name} col ({wi},{ti}) |y|={col['norm2']:.6e} {dt:.1f}s", flush=True)
+    with open(os.path.join(HERE, f"{cfg_name}_yT_samples.json"), "w") as f:
+        json.dump(out, f)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1])

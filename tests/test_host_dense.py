@@ -1,0 +1,116 @@
+"""Host-side small dense routines of the library (built with g++, no GPU)."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib(tmp_path_factory):
+    out = tmp_path_factory.mktemp("dense") / "libdense_shim.so"
+    srcs = [os.path.join(ROOT, "tests", "native", "dense_shim.cpp"),
+            os.path.join(ROOT, "paper_1707_00023_amd", "csrc", "kry_dense.cpp")]
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", str(out)] + srcs,
+                   check=True)
+    L = ctypes.CDLL(str(out))
+    L.t_choose_step.restype = ctypes.c_double
+    return L
+
+
+def P(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@pytest.mark.parametrize("m,scale", [(1, 0.3), (5, 0.01), (12, 1.0), (30, 25.0), (64, 400.0)])
+def test_expm_matches_scipy(lib, m, scale):
+    rng = np.random.default_rng(m)
+    A = scale * rng.standard_normal((m, m)) / np.sqrt(m)
+    E = np.zeros((m, m), order="F")
+    Af = np.asfortranarray(A)
+    lib.t_expm(m, P(Af), P(E))
+    ref = sla.expm(A)
+    assert np.abs(E - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_expm_skew_is_orthogonal(lib):
+    rng = np.random.default_rng(3)
+    S = rng.standard_normal((20, 20))
+    S = 30.0 * (S - S.T)
+    E = np.zeros((20, 20), order="F")
+    lib.t_expm(20, P(np.asfortranarray(S)), P(E))
+    assert np.abs(E.T @ E - np.eye(20)).max() < 1e-11
+
+
+def _hess(rng, N, cplx=True):
+    M = rng.standard_normal((N, N)) + (1j * rng.standard_normal((N, N)) if cplx else 0)
+    return np.triu(M, -1).astype(np.complex128)
+
+
+def test_hess_solve_and_bordered_matrix(lib):
+    rng = np.random.default_rng(4)
+    for N in (1, 2, 7, 33):
+        M = _hess(rng, N)
+        M[:, -1] = rng.standard_normal(N)   # dense last column (bordered form)
+        b = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        y = np.zeros(N, np.complex128)
+        assert lib.t_hess_solve(N, P(np.asfortranarray(M)), P(b), P(y)) == 1
+        assert np.abs(M @ y - b).max() <= 1e-11 * np.abs(b).max() * np.linalg.cond(M)
+
+
+def test_hess_shift_and_dense_solve(lib):
+    rng = np.random.default_rng(5)
+    m = 17
+    H = np.triu(rng.standard_normal((m + 1, m)), -1)
+    Hf = np.asfortranarray(H)
+    b = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    y = np.zeros(m, np.complex128)
+    assert lib.t_hess_shift_solve(m, P(Hf), m + 1, ctypes.c_double(0.0), ctypes.c_double(0.7),
+                                  P(b), P(y)) == 1
+    ref = np.linalg.solve(H[:m] + 0.7j * np.eye(m), b)
+    assert np.abs(y - ref).max() <= 1e-10 * np.abs(ref).max()
+    A = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    y2 = np.zeros(m, np.complex128)
+    assert lib.t_dense_solve(m, P(np.asfortranarray(A)), P(b), P(y2)) == 1
+    assert np.abs(y2 - np.linalg.solve(A, b)).max() <= 1e-10 * np.abs(y2).max()
+
+
+def test_best_real_direction_is_optimal(lib):
+    rng = np.random.default_rng(6)
+    for n in (2, 5, 40):
+        q = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        w = np.zeros(n)
+        lib.t_best_real_direction(n, P(q), P(w))
+        assert abs(np.linalg.norm(w) - 1) < 1e-14
+        best = abs(np.vdot(q, w))
+        # brute force over the plane spanned by Re q, Im q
+        Q, _ = np.linalg.qr(np.stack([q.real, q.imag], 1))
+        ang = np.linspace(0, np.pi, 20001)
+        cand = np.abs(np.stack([np.cos(ang), np.sin(ang)], 1) @ (Q.T @ q.conj()))
+        assert best >= cand.max() * (1 - 1e-8)
+        assert best >= np.linalg.norm(q) / np.sqrt(2) * (1 - 1e-14)
+
+
+def test_choose_step_respects_residual_rate(lib):
+    rng = np.random.default_rng(7)
+    m = 12
+    S = rng.standard_normal((m, m))
+    H = np.triu(0.5 * (S - S.T) + 0.05 * np.eye(m), -1)
+    Hbar = np.zeros((m + 1, m))
+    Hbar[:m] = H
+    hnext, beta, rate = 0.8, 2.0, 1e-6
+    u = np.zeros(m)
+    err = ctypes.c_double()
+    tau = lib.t_choose_step(m, P(np.asfortranarray(Hbar)), m + 1, ctypes.c_double(hnext),
+                            ctypes.c_double(beta), ctypes.c_double(5.0), ctypes.c_double(rate),
+                            16, P(u), ctypes.byref(err))
+    assert 0 < tau <= 5.0
+    ref = beta * sla.expm(-tau * H)[:, 0]
+    assert np.abs(u - ref).max() <= 1e-12 * beta
+    ts = np.linspace(0, tau, 200)
+    rho = [abs(hnext * (beta * sla.expm(-t * H)[:, 0])[-1]) for t in ts]
+    assert max(rho) <= 1.05 * rate

@@ -90,6 +90,20 @@ def test_matrix_free_equals_assembled_and_skew():
     assert np.abs(K + K.T).max() < 1e-14
 
 
+def test_matrix_free_equals_assembled_on_a_box():
+    rng = np.random.default_rng(6)
+    shape = (5, 3, 4)   # (nz, ny, nx)
+    eps = 1 + 2 * rng.random(shape)
+    mu = 1 + rng.random(shape)
+    sig = 0.3 * rng.random(shape)
+    A = op.assemble_A(eps, mu, sig)
+    y = rng.standard_normal(6 * eps.size)
+    assert np.allclose(A @ y, op.apply_A(eps, mu, sig, y), rtol=0, atol=1e-13)
+    # single-cell-thick box: each axis of length 1 reduces to the hand case
+    one = np.ones((1, 1, 1))
+    assert np.array_equal(op.curl_matrix(1, 1, 1).toarray(), op.curl_matrix(1).toarray())
+
+
 # --- P4: separable modes reduce the problem to a 6 x 6 closed form ---------
 
 def _mode(N, q):
@@ -277,3 +291,25 @@ def test_adjoint_gradient_matches_fd_every_cell():
     fd = og.fd_grad(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, kf, cells, h=1e-5)
     gv = np.array([g[k, j, i] for (i, j, k) in cells])
     assert np.linalg.norm(gv - fd) <= 1e-6 * np.linalg.norm(fd)
+
+
+# --- Krylov basis by definition: properties the definition fixes ----------
+
+def test_krylov_basis_definition_properties():
+    from oracle import krylov as okr
+    wl, inp = _medium(5, seed=13)
+    v = wk.random_state(wl.n, 4)
+    m = 5
+    V, H, beta = okr.krylov_basis(inp.eps, inp.mu, inp.sigma, v, m)
+    w = op.material_weights(inp.eps, inp.mu)
+    assert np.abs(V.T @ (w[:, None] * V) - np.eye(m + 1)).max() < 1e-12
+    assert np.allclose(V[:, 0] * beta, v, atol=1e-12 * np.abs(v).max())
+    # upper Hessenberg with positive subdiagonal
+    assert np.abs(np.tril(H, -2)).max() < 1e-10
+    assert all(H[j + 1, j] > 0 for j in range(m))
+    # Arnoldi relation A V_m = V_{m+1} H
+    AV = np.stack([op.apply_A(inp.eps, inp.mu, inp.sigma, V[:, j]) for j in range(m)], axis=1)
+    assert np.abs(AV - V @ H).max() < 1e-10
+    # energy dissipativity carries to the projection: the symmetric part of
+    # H (an orthogonal projection in the energy product) is positive semidefinite
+    assert np.linalg.eigvalsh(0.5 * (H[:m] + H[:m].T)).min() > -1e-12
