@@ -72,6 +72,10 @@ typedef struct {
   int32_t timing;       /* 1: time every launch of the main kernel classes
                            with HIP events on the stream (adds a little
                            overhead); results in kry_stats.kernel_*        */
+  int32_t orth;         /* Gram-Schmidt: 0 = classical twice with the second
+                           projection delayed by one step (two basis sweeps
+                           per step, default); 1 = classical twice, both
+                           projections in the step (four sweeps)          */
 } kry_opts;
 
 /* Kernel classes reported by the per-kernel timing. */

@@ -39,7 +39,7 @@ class KryOpts(ctypes.Structure):
                 ("max_restarts", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("block_width", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("inner_product", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("timing", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("orth", ctypes.c_int32)]
 
 
 class KryStats(ctypes.Structure):
@@ -119,6 +119,7 @@ class Options:
     max_restarts: int = 0
     tol: float = 1e-8
     timing: bool = False
+    orth: str = "delayed"       # "delayed" (two basis sweeps per step) or "cgs2"
 
 
 class Solver:
@@ -147,7 +148,7 @@ class Solver:
         self.grid = KryGrid(nx, ny, nz, 0)
         self.opts = KryOpts(1 if opts.storage == "f32" else 0, opts.krylov_dim,
                             opts.max_restarts, opts.tol, 0, 0, 0, _stream_ptr().value,
-                            int(bool(opts.timing)))
+                            int(bool(opts.timing)), 1 if opts.orth == "cgs2" else 0)
         self.storage = opts.storage
         ctx = ctypes.c_void_p()
         rc = lib.kry_create(ctypes.byref(self.grid), _ptr(e),

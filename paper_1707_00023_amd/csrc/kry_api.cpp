@@ -38,6 +38,7 @@ struct kry_ctx {
   double* d_red1 = nullptr;
   double* d_red2 = nullptr;
   double* d_scal = nullptr;
+  double* d_co = nullptr;  // pass-B coefficients of the delayed scheme
   double* d_H = nullptr;
   double* d_Y = nullptr;
   int* d_colmap = nullptr;
@@ -160,22 +161,25 @@ int ensure_basis(kry_ctx* c, int m) {
   hipFree(c->partials);
   hipFree(c->d_red1);
   hipFree(c->d_red2);
+  hipFree(c->d_co);
   hipFree(c->d_H);
   hipHostFree(c->h_H);
   c->V = nullptr;
   c->partials = nullptr;
-  c->d_red1 = c->d_red2 = c->d_H = c->h_H = nullptr;
+  c->d_red1 = c->d_red2 = c->d_co = c->d_H = c->h_H = nullptr;
   c->mcap = 0;
-  const size_t vbytes = (size_t)(m + 2) * c->ldv * c->esz;
+  // slots 0..m: basis; m+1: candidate / work vector; m+2: operator output
+  const size_t vbytes = (size_t)(m + 3) * c->ldv * c->esz;
   if (hipMalloc(&c->V, vbytes) != hipSuccess) {
     c->V = nullptr;
     (void)hipGetLastError();
     return fail(c, KRY_ENOMEM, "cannot allocate Krylov basis of " + std::to_string(vbytes) + " bytes");
   }
   const size_t nparts = (size_t)kry::cell_blocks(c->g.N3);
-  KRY_HIP(hipMalloc(&c->partials, sizeof(double) * nparts * (size_t)(m + 3)));
-  KRY_HIP(hipMalloc(&c->d_red1, sizeof(double) * (m + 3)));
-  KRY_HIP(hipMalloc(&c->d_red2, sizeof(double) * (m + 3)));
+  KRY_HIP(hipMalloc(&c->partials, sizeof(double) * nparts * (size_t)(2 * m + 4)));
+  KRY_HIP(hipMalloc(&c->d_red1, sizeof(double) * (2 * m + 4)));
+  KRY_HIP(hipMalloc(&c->d_red2, sizeof(double) * (2 * m + 4)));
+  KRY_HIP(hipMalloc(&c->d_co, sizeof(double) * (2 * m + 4)));
   KRY_HIP(hipMalloc(&c->d_H, sizeof(double) * (size_t)(m + 1) * m));
   KRY_HIP(hipHostMalloc(&c->h_H, sizeof(double) * (size_t)(m + 1) * m, hipHostMallocDefault));
   c->mcap = m;
@@ -231,7 +235,7 @@ int host_dots(kry_ctx* c, const void* x, const void* Y, int cnt, std::vector<dou
 // Each step: w = A v_j fused with the dots of pass 1, then
 // w -= V h1, dots of pass 2 (classical Gram-Schmidt twice), then
 // v_{j+1} = (w - V h2) / nu.
-int arnoldi(kry_ctx* c, int m, double* beta, int* m_eff) {
+int arnoldi_cgs2(kry_ctx* c, int m, double* beta, int* m_eff) {
   const int nparts = kry::cell_blocks(c->g.N3);
   hipStream_t s = c->stream;
   const long long ldv = c->ldv;
@@ -273,6 +277,64 @@ int arnoldi(kry_ctx* c, int m, double* beta, int* m_eff) {
   if (*beta == 0.0) me = 0;
   *m_eff = me;
   return KRY_OK;
+}
+
+// Arnoldi with the second Gram-Schmidt projection delayed by one step (two
+// sweeps over the basis per step instead of four).  Step j applies A to
+// the candidate u_j (projected once, not yet reorthogonalised or
+// normalised): pass A computes x = A u_j with <x, v_i>, <u_j, v_i>, |u_j|^2
+// and <u_j, x>; the small step (k_lag_fin) completes column j-1 (second
+// projection of u_j and its norm), rebuilds A v_j from x through the
+// Arnoldi relation A V_{j-1} = V_j Hbar_{j-1}, and its first projection;
+// pass B sweeps the basis once to write v_j and the next candidate u_{j+1}.
+// After m steps the last candidate is reorthogonalised and normalised.
+// Same contract as arnoldi_cgs2 (start vector unnormalised in slot 0).
+int arnoldi_lag(kry_ctx* c, int m, double* beta, int* m_eff) {
+  const int nparts = kry::cell_blocks(c->g.N3);
+  hipStream_t s = c->stream;
+  const long long ldv = c->ldv;
+  const int ldh = m + 1;
+  KRY_HIP(hipMemsetAsync(c->d_H, 0, sizeof(double) * (size_t)(m + 1) * m, s));
+  void* U = slot(c, c->mcap + 1);
+  void* X = slot(c, c->mcap + 2);
+  const double vb = vbytes(c);
+  for (int j = 0; j < m; ++j) {
+    const int cnt = j;
+    void* uj = (j == 0) ? slot(c, 0) : U;
+    hipEvent_t e = tbeg(c);
+    KRY_HIP(kry::launch_stencil_lag(c->st, uj, X, c->V, ldv, cnt, c->g, c->mats, c->partials, s));
+    tend(c, e, KRY_K_STENCIL, vb * (cnt + 2) + mbytes(c, true));
+    KRY_HIP(kry::launch_reduce(c->partials, nparts, 2 * cnt + 2, 2 * cnt + 2, c->d_red1, s));
+    KRY_HIP(kry::launch_lag_fin(c->d_red1, j, c->d_H, ldh, c->d_co, c->d_scal, s));
+    e = tbeg(c);
+    KRY_HIP(kry::launch_lag_update(c->st, uj, X, c->V, ldv, cnt, c->d_co, slot(c, j), U, c->g, s));
+    tend(c, e, KRY_K_UPDATE, vb * (cnt + 4));
+  }
+  // last candidate: second projection and normalisation -> v_m
+  hipEvent_t e = tbeg(c);
+  KRY_HIP(kry::launch_dots(c->st, U, c->V, ldv, m, c->g, c->mats, c->partials, s));
+  tend(c, e, KRY_K_DOTS, vb * (m + 1) + mbytes(c, false));
+  KRY_HIP(kry::launch_reduce(c->partials, nparts, m + 1, m + 1, c->d_red1, s));
+  KRY_HIP(kry::launch_lag_final(c->d_red1, m, c->d_H, ldh, c->d_scal, s));
+  e = tbeg(c);
+  KRY_HIP(kry::launch_update(c->st, U, c->V, ldv, m, c->d_red1, c->d_scal, slot(c, m), c->g, s));
+  tend(c, e, KRY_K_UPDATE, vb * (m + 2));
+  KRY_HIP(hipMemcpyAsync(c->h_H, c->d_H, sizeof(double) * (size_t)(m + 1) * m, hipMemcpyDeviceToHost, s));
+  KRY_HIP(hipMemcpyAsync(c->h_scal, c->d_scal, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
+  KRY_HIP(hipStreamSynchronize(s));
+  tresolve(c);
+  *beta = c->h_scal[1];
+  int me = m;
+  for (int j = 0; j < m; ++j) {
+    if (c->h_H[j + 1 + (size_t)j * ldh] == 0.0) { me = j + 1; break; }
+  }
+  if (*beta == 0.0) me = 0;
+  *m_eff = me;
+  return KRY_OK;
+}
+
+int arnoldi(kry_ctx* c, int m, double* beta, int* m_eff) {
+  return c->opts.orth == 1 ? arnoldi_cgs2(c, m, beta, m_eff) : arnoldi_lag(c, m, beta, m_eff);
 }
 
 double now_ms() {
@@ -517,6 +579,7 @@ int kry_create(const kry_grid* grid, const double* eps, const double* mu, const 
     return fail(nullptr, KRY_EINVAL, "krylov_dim out of range");
   if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) return fail(nullptr, KRY_EINVAL, "invalid tol");
   if (opts->inner_product != 0) return fail(nullptr, KRY_EINVAL, "only the energy inner product is supported");
+  if (opts->orth != 0 && opts->orth != 1) return fail(nullptr, KRY_EINVAL, "invalid orth");
   std::vector<double> he(N3), hm, hs(N3, 0.0);
   if (hipMemcpy(he.data(), eps, sizeof(double) * N3, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(nullptr, KRY_EINVAL, "eps is not a readable device array");
@@ -585,6 +648,7 @@ void kry_destroy(kry_ctx* c) {
   hipFree(c->d_red1);
   hipFree(c->d_red2);
   hipFree(c->d_scal);
+  hipFree(c->d_co);
   hipFree(c->d_H);
   hipFree(c->d_Y);
   hipFree(c->d_colmap);

@@ -37,6 +37,27 @@ hipError_t launch_stencil(Storage st, const void* v, void* w, const void* V, lon
                           int cnt, const DevGrid& g, const DevMats& m, double* partials,
                           hipStream_t s);
 
+// Pass A of a delayed-reorthogonalisation Arnoldi step: x = A u and partial
+// sums of [<x,V_i>_M (cnt), <u,V_i>_M (cnt), |u|_M^2, <u,x>_M] per workgroup
+// (stride 2 cnt + 2).
+hipError_t launch_stencil_lag(Storage st, const void* u, void* x, const void* V, long long ldv,
+                              int cnt, const DevGrid& g, const DevMats& m, double* partials,
+                              hipStream_t s);
+
+// Pass B: vnew = u co[2cnt] - sum co[i] V_i, unext = x co[2cnt] -
+// co[2cnt+1] u - sum co[cnt+i] V_i (unext may alias u).
+hipError_t launch_lag_update(Storage st, const void* u, const void* x, const void* V, long long ldv,
+                             int cnt, const double* co, void* vnew, void* unext, const DevGrid& g,
+                             hipStream_t s);
+
+// Small step between the passes of Arnoldi step j (see the kernel).
+hipError_t launch_lag_fin(const double* red, int j, double* H, int ldh, double* co, double* scal,
+                          hipStream_t s);
+
+// Completes the last column of a cycle from red = [<u_m, V_i>_M (m), |u_m|_M^2].
+hipError_t launch_lag_final(const double* red, int m, double* H, int ldh, double* scal,
+                            hipStream_t s);
+
 // Partial sums of <x, V_i>_M (i < cnt) and |x|_M^2 (slot cnt).
 hipError_t launch_dots(Storage st, const void* x, const void* V, long long ldv, int cnt,
                        const DevGrid& g, const DevMats& m, double* partials, hipStream_t s);

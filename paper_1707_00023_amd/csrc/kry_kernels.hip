@@ -38,6 +38,28 @@ __device__ __forceinline__ void block_sum_store(const double (&acc)[CH], int val
   __syncthreads();
 }
 
+// As block_sum_store for 2*CH values: totals q < valid go to dstA[q],
+// totals CH + q (q < valid) to dstB[q].
+template <int CH>
+__device__ __forceinline__ void block_sum_store_split(const double (&acc)[2 * CH], int valid,
+                                                      double* dstA, double* dstB) {
+  __shared__ double sh[2 * CH][kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 2 * CH; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) sh[q][wid] = v;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 2 * CH && (t % CH) < valid) {
+    const double v = (sh[t][0] + sh[t][1]) + (sh[t][2] + sh[t][3]);
+    if (t < CH) dstA[t] = v;
+    else dstB[t - CH] = v;
+  }
+  __syncthreads();
+}
+
 // Logical block index with consecutive logical blocks kept on one XCD: the
 // dispatcher places block b on XCD (b mod 8), so remap b -> (b mod 8) *
 // (nblk / 8) + b / 8 over the largest multiple of 8, keeping neighbouring
@@ -49,22 +71,18 @@ __device__ __forceinline__ int xcd_block(int b, int nblk) {
   return (b & 7) * per + (b >> 3);
 }
 
-template <typename T>
-__device__ __forceinline__ T ld(const T* p) { return *p; }
-
 // ---------------------------------------------------------------------------
-// Yee operator, optionally fused with the first Gram-Schmidt dot pass.
+// Yee operator at one cell:
 //   (A y)_H = sigma/mu H + (C E)/mu,   (A y)_E = (sigma E - C^T H)/eps
-//   (C E)x = dEz/dy - dEy/dz with forward differences (zero beyond N-1),
-//   (C^T H)x = dHz/dy - dHy/dz with backward differences (zero below 0),
-//   and cyclically.
+//   (C E)x = dEz/dy - dEy/dz with forward differences (zero beyond the last
+//   cell), (C^T H)x = dHz/dy - dHy/dz with backward differences (zero before
+//   the first cell), and cyclically.
+// o receives the six outputs, ctr the six input values at the cell itself.
 // Arithmetic is in the storage type T (FP32 storage computes the stencil in
-// FP32); dot products accumulate in FP64.
-template <typename T, bool HAS_MU, int CPT, bool DOTS>
-__global__ __launch_bounds__(kBlock) void k_stencil(const T* __restrict__ v, T* __restrict__ w,
-                                                    const T* __restrict__ V, long long ldv, int cnt,
-                                                    DevGrid g, DevMats mt,
-                                                    double* __restrict__ partials) {
+// FP32).
+template <typename T, bool HAS_MU>
+__device__ __forceinline__ void yee_cell(const T* __restrict__ v, long long c, const DevGrid& g,
+                                         const DevMats& mt, T (&o)[6], T (&ctr)[6]) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const long long N3 = g.N3;
   const long long sy = nx, sz = (long long)nx * ny;
@@ -74,8 +92,64 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const T* __restrict__ v, T* 
   const T* Ex = v + 3 * N3;
   const T* Ey = v + 4 * N3;
   const T* Ez = v + 5 * N3;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int ci = (int)c;
+  const int i = ci % nx;
+  const int t = ci / nx;
+  const int j = t % ny;
+  const int k = t / ny;
+  const T z0 = T(0);
+  const T ex = Ex[c], ey = Ey[c], ez = Ez[c];
+  const T ex_j = (j + 1 < ny) ? Ex[c + sy] : z0;
+  const T ex_k = (k + 1 < nz) ? Ex[c + sz] : z0;
+  const T ey_i = (i + 1 < nx) ? Ey[c + 1] : z0;
+  const T ey_k = (k + 1 < nz) ? Ey[c + sz] : z0;
+  const T ez_i = (i + 1 < nx) ? Ez[c + 1] : z0;
+  const T ez_j = (j + 1 < ny) ? Ez[c + sy] : z0;
+  const T cex = (ez_j - ez) - (ey_k - ey);
+  const T cey = (ex_k - ex) - (ez_i - ez);
+  const T cez = (ey_i - ey) - (ex_j - ex);
+  const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
+  const T hx_j = (j > 0) ? Hx[c - sy] : z0;
+  const T hx_k = (k > 0) ? Hx[c - sz] : z0;
+  const T hy_i = (i > 0) ? Hy[c - 1] : z0;
+  const T hy_k = (k > 0) ? Hy[c - sz] : z0;
+  const T hz_i = (i > 0) ? Hz[c - 1] : z0;
+  const T hz_j = (j > 0) ? Hz[c - sy] : z0;
+  const T chx = (hz - hz_j) - (hy - hy_k);
+  const T chy = (hx - hx_k) - (hz - hz_i);
+  const T chz = (hy - hy_i) - (hx - hx_j);
+  const T ie = T(mt.inv_eps[c]);
+  const T sg = T(mt.sigma[c]);
+  if (HAS_MU) {
+    const T im = T(mt.inv_mu[c]);
+    const T se = T(mt.sigma[c] * mt.mu[c]);
+    o[0] = sg * hx + im * cex;
+    o[1] = sg * hy + im * cey;
+    o[2] = sg * hz + im * cez;
+    o[3] = ie * (se * ex - chx);
+    o[4] = ie * (se * ey - chy);
+    o[5] = ie * (se * ez - chz);
+  } else {
+    o[0] = sg * hx + cex;
+    o[1] = sg * hy + cey;
+    o[2] = sg * hz + cez;
+    o[3] = ie * (sg * ex - chx);
+    o[4] = ie * (sg * ey - chy);
+    o[5] = ie * (sg * ez - chz);
+  }
+  ctr[0] = hx; ctr[1] = hy; ctr[2] = hz;
+  ctr[3] = ex; ctr[4] = ey; ctr[5] = ez;
+}
 
+// w = A v, optionally fused with the first classical Gram-Schmidt dot pass:
+// partial sums of <w, V_i>_M for i < cnt and |w|_M^2 (slot cnt).
+template <typename T, bool HAS_MU, int CPT, bool DOTS>
+__global__ __launch_bounds__(kBlock) void k_stencil(const T* __restrict__ v, T* __restrict__ w,
+                                                    const T* __restrict__ V, long long ldv, int cnt,
+                                                    DevGrid g, DevMats mt,
+                                                    double* __restrict__ partials) {
+  const long long N3 = g.N3;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
   double wm[CPT][6];  // weight * output, for the dots
   long long cellq[CPT];
   bool okq[CPT];
@@ -88,51 +162,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const T* __restrict__ v, T* 
 #pragma unroll
     for (int p = 0; p < 6; ++p) wm[q][p] = 0.0;
     if (!okq[q]) continue;
-    const int ci = (int)c;
-    const int i = ci % nx;
-    const int t = ci / nx;
-    const int j = t % ny;
-    const int k = t / ny;
-    const T z0 = T(0);
-    const T ex = Ex[c], ey = Ey[c], ez = Ez[c];
-    const T ex_j = (j + 1 < ny) ? Ex[c + sy] : z0;
-    const T ex_k = (k + 1 < nz) ? Ex[c + sz] : z0;
-    const T ey_i = (i + 1 < nx) ? Ey[c + 1] : z0;
-    const T ey_k = (k + 1 < nz) ? Ey[c + sz] : z0;
-    const T ez_i = (i + 1 < nx) ? Ez[c + 1] : z0;
-    const T ez_j = (j + 1 < ny) ? Ez[c + sy] : z0;
-    const T cex = (ez_j - ez) - (ey_k - ey);
-    const T cey = (ex_k - ex) - (ez_i - ez);
-    const T cez = (ey_i - ey) - (ex_j - ex);
-    const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
-    const T hx_j = (j > 0) ? Hx[c - sy] : z0;
-    const T hx_k = (k > 0) ? Hx[c - sz] : z0;
-    const T hy_i = (i > 0) ? Hy[c - 1] : z0;
-    const T hy_k = (k > 0) ? Hy[c - sz] : z0;
-    const T hz_i = (i > 0) ? Hz[c - 1] : z0;
-    const T hz_j = (j > 0) ? Hz[c - sy] : z0;
-    const T chx = (hz - hz_j) - (hy - hy_k);
-    const T chy = (hx - hx_k) - (hz - hz_i);
-    const T chz = (hy - hy_i) - (hx - hx_j);
-    const T ie = T(mt.inv_eps[c]);
-    const T sg = T(mt.sigma[c]);
-    T o[6];
-    if (HAS_MU) {
-      const T im = T(mt.inv_mu[c]);
-      o[0] = sg * hx + im * cex;
-      o[1] = sg * hy + im * cey;
-      o[2] = sg * hz + im * cez;
-      o[3] = ie * (T(mt.sigma[c] * mt.mu[c]) * ex - chx);
-      o[4] = ie * (T(mt.sigma[c] * mt.mu[c]) * ey - chy);
-      o[5] = ie * (T(mt.sigma[c] * mt.mu[c]) * ez - chz);
-    } else {
-      o[0] = sg * hx + cex;
-      o[1] = sg * hy + cey;
-      o[2] = sg * hz + cez;
-      o[3] = ie * (sg * ex - chx);
-      o[4] = ie * (sg * ey - chy);
-      o[5] = ie * (sg * ez - chz);
-    }
+    T o[6], ctr[6];
+    yee_cell<T, HAS_MU>(v, c, g, mt, o, ctr);
 #pragma unroll
     for (int p = 0; p < 6; ++p) w[p * N3 + c] = o[p];
     if (DOTS) {
@@ -168,6 +199,243 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const T* __restrict__ v, T* 
   }
   const double a1[1] = {nrm};
   block_sum_store<1>(a1, 1, partials + (long long)lb * (cnt + 1) + cnt);
+}
+
+// Pass A of a delayed-reorthogonalisation Arnoldi step.  For the candidate
+// u (orthogonalised once against V_0..cnt-1, neither reorthogonalised nor
+// normalised): x = A u, and in the same sweep the partial sums of
+// a_i = <x, V_i>_M, b_i = <u, V_i>_M (i < cnt), alpha = |u|_M^2 and
+// beta = <u, x>_M, stored at partials[blk * (2 cnt + 2) + {i, cnt + i,
+// 2 cnt, 2 cnt + 1}].
+template <typename T, bool HAS_MU, int CPT, int CH>
+__global__ __launch_bounds__(kBlock) void k_stencil_lag(const T* __restrict__ u, T* __restrict__ x,
+                                                        const T* __restrict__ V, long long ldv,
+                                                        int cnt, DevGrid g, DevMats mt,
+                                                        double* __restrict__ partials) {
+  const long long N3 = g.N3;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const long long stride = 2 * cnt + 2;
+  double xm[CPT][6];  // weight * x
+  double um[CPT][6];  // weight * u
+  long long cellq[CPT];
+  bool okq[CPT];
+  double alpha = 0.0, beta = 0.0;
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const long long c = ((long long)lb * CPT + q) * kBlock + threadIdx.x;
+    okq[q] = c < N3;
+    cellq[q] = okq[q] ? c : 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) xm[q][p] = um[q][p] = 0.0;
+    if (!okq[q]) continue;
+    T o[6], ctr[6];
+    yee_cell<T, HAS_MU>(u, c, g, mt, o, ctr);
+#pragma unroll
+    for (int p = 0; p < 6; ++p) x[p * N3 + c] = o[p];
+    const double we = mt.eps[c];
+    const double wh = HAS_MU ? mt.mu[c] : 1.0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const double w8 = p < 3 ? wh : we;
+      const double ov = (double)o[p], uu = (double)ctr[p];
+      xm[q][p] = w8 * ov;
+      um[q][p] = w8 * uu;
+      alpha += um[q][p] * uu;
+      beta += um[q][p] * ov;
+    }
+  }
+  double* dst = partials + (long long)lb * stride;
+  for (int i0 = 0; i0 < cnt; i0 += CH) {
+    double acc[2 * CH];
+#pragma unroll
+    for (int r = 0; r < 2 * CH; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int r = 0; r < CH; ++r) {
+      if (i0 + r < cnt) {
+        const T* vi = V + (long long)(i0 + r) * ldv;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          if (!okq[q]) continue;
+#pragma unroll
+          for (int p = 0; p < 6; ++p) {
+            const double vv = (double)vi[p * N3 + cellq[q]];
+            acc[r] += xm[q][p] * vv;
+            acc[CH + r] += um[q][p] * vv;
+          }
+        }
+      }
+    }
+    block_sum_store_split<CH>(acc, min(CH, cnt - i0), dst + i0, dst + cnt + i0);
+  }
+  const double a2[2] = {alpha, beta};
+  block_sum_store<2>(a2, 2, dst + 2 * cnt);
+}
+
+// Pass B of a delayed-reorthogonalisation Arnoldi step, one sweep over
+// V_0..cnt-1: v_new = u * co[2cnt] - sum_i co[i] V_i (the reorthogonalised,
+// normalised u) and u_next = x * co[2cnt] - co[2cnt+1] u - sum_i co[cnt+i]
+// V_i (the next candidate).  u_next may alias u (read before written).
+template <typename T, int CPT>
+__global__ __launch_bounds__(kBlock) void k_lag_update(const T* u, const T* __restrict__ x,
+                                                       const T* __restrict__ V, long long ldv,
+                                                       int cnt, const double* __restrict__ co,
+                                                       T* vnew, T* unext,
+                                                       long long N3) {
+  __shared__ double sb[kMaxCoef];
+  __shared__ double sd[kMaxCoef];
+  for (int t = threadIdx.x; t < cnt; t += kBlock) {
+    sb[t] = co[t];
+    sd[t] = co[cnt + t];
+  }
+  __syncthreads();
+  const double inv_nu = co[2 * cnt];
+  const double kappa = co[2 * cnt + 1];
+  double av[CPT][6], au[CPT][6];
+  long long cellq[CPT];
+  bool okq[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const long long c = ((long long)blockIdx.x * CPT + q) * kBlock + threadIdx.x;
+    okq[q] = c < N3;
+    cellq[q] = okq[q] ? c : 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const double uu = okq[q] ? (double)u[p * N3 + c] : 0.0;
+      const double xx = okq[q] ? (double)x[p * N3 + c] : 0.0;
+      av[q][p] = uu * inv_nu;
+      au[q][p] = xx * inv_nu - kappa * uu;
+    }
+  }
+  for (int i = 0; i < cnt; ++i) {
+    const double b = sb[i], d = sd[i];
+    const T* vi = V + (long long)i * ldv;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      if (!okq[q]) continue;
+#pragma unroll
+      for (int p = 0; p < 6; ++p) {
+        const double vv = (double)vi[p * N3 + cellq[q]];
+        av[q][p] -= b * vv;
+        au[q][p] -= d * vv;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    if (!okq[q]) continue;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      vnew[p * N3 + cellq[q]] = T(av[q][p]);
+      unext[p * N3 + cellq[q]] = T(au[q][p]);
+    }
+  }
+}
+
+// Small step between pass A and pass B of step j (one workgroup).  With
+// red = [a (j), b (j), alpha, beta] from pass A and H the Hessenberg matrix
+// (leading dimension ldh) holding columns < j:
+//   nu = sqrt(alpha - |b|^2): norm of u after its second projection;
+//   H[:j, j-1] += b, H[j, j-1] = nu (column j-1 completed; for j = 0, nu is
+//   the start-vector norm, kept in scal[1]);
+//   c = Hbar_{j-1} b (length j+1), so A v_j = (x - V_j c) / nu by the Arnoldi
+//   relation A V_{j-1} = V_j Hbar_{j-1};
+//   h1_i = (a_i - c_i) / nu (i < j), h1_j = (beta - a.b - nu c_j) / nu^2:
+//   the first projection of A v_j, stored as H[:j+1, j];
+//   co = [b / nu, d, 1 / nu, kappa] for pass B, with kappa = (c_j/nu + h1_j)/nu
+//   and d_i = c_i / nu + h1_i - kappa b_i.
+// A vanishing nu (relative to the column it completes) is an exact
+// invariant subspace: nu and every coefficient are set to zero.
+__global__ __launch_bounds__(kBlock) void k_lag_fin(const double* __restrict__ red, int j,
+                                                    double* __restrict__ H, int ldh,
+                                                    double* __restrict__ co,
+                                                    double* __restrict__ scal) {
+  __shared__ double sc[kMaxCoef + 1];
+  __shared__ double s_nu[1], s_ab[1], s_hj[1];
+  const double* a = red;
+  const double* b = red + j;
+  const double alpha = red[2 * j], beta = red[2 * j + 1];
+  double bb = 0.0, ab = 0.0, col = 0.0;
+  for (int i = threadIdx.x; i < j; i += kBlock) {
+    bb += b[i] * b[i];
+    ab += a[i] * b[i];
+    const double hv = H[i + (long long)(j - 1) * ldh];
+    col += hv * hv;
+  }
+  __shared__ double t3[3];
+  {
+    const double v3[3] = {bb, ab, col};
+    block_sum_store<3>(v3, 3, t3);
+  }
+  if (threadIdx.x == 0) {
+    const double nu2 = alpha - t3[0];
+    double nu = sqrt(fmax(nu2, 0.0));
+    const double scale = sqrt(fmax(t3[2] + alpha, 0.0));
+    if (!(nu > 1e-12 * scale)) nu = 0.0;
+    s_nu[0] = nu;
+    s_ab[0] = t3[1];
+    if (j == 0) scal[1] = nu;
+    else H[j + (long long)(j - 1) * ldh] = nu;
+  }
+  __syncthreads();
+  const double nu = s_nu[0];
+  // complete column j-1 and form c = Hbar_{j-1} b (needs the updated column)
+  for (int i = threadIdx.x; i < j; i += kBlock) H[i + (long long)(j - 1) * ldh] += b[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j; i += kBlock) {
+    double acc = 0.0;
+    for (int l = (i > 0 ? i - 1 : 0); l < j; ++l) acc += H[i + (long long)l * ldh] * b[l];
+    sc[i] = acc;
+  }
+  __syncthreads();
+  if (nu == 0.0) {
+    for (int i = threadIdx.x; i < 2 * j + 2; i += kBlock) co[i] = 0.0;
+    for (int i = threadIdx.x; i <= j; i += kBlock) H[i + (long long)j * ldh] = 0.0;
+    return;
+  }
+  const double inv = 1.0 / nu;
+  if (threadIdx.x == 0) {
+    const double hj = (beta - s_ab[0] - nu * sc[j]) * inv * inv;
+    s_hj[0] = hj;
+    H[j + (long long)j * ldh] = hj;
+    co[2 * j] = inv;
+    co[2 * j + 1] = (sc[j] * inv + hj) * inv;
+  }
+  __syncthreads();
+  const double kappa = (sc[j] * inv + s_hj[0]) * inv;
+  for (int i = threadIdx.x; i < j; i += kBlock) {
+    const double h1 = (a[i] - sc[i]) * inv;
+    H[i + (long long)j * ldh] = h1;
+    co[i] = b[i] * inv;
+    co[j + i] = sc[i] * inv + h1 - kappa * b[i];
+  }
+}
+
+// End of a cycle: complete the last column from red = [b (m), alpha] (the
+// dots of the last candidate u_m with V_0..m-1): H[:m, m-1] += b,
+// H[m, m-1] = nu, scal[0] = 1/nu (0 on an invariant subspace).
+__global__ __launch_bounds__(kBlock) void k_lag_final(const double* __restrict__ red, int m,
+                                                      double* __restrict__ H, int ldh,
+                                                      double* __restrict__ scal) {
+  double bb = 0.0, col = 0.0;
+  for (int i = threadIdx.x; i < m; i += kBlock) {
+    bb += red[i] * red[i];
+    const double hv = H[i + (long long)(m - 1) * ldh];
+    col += hv * hv;
+  }
+  __shared__ double t2[2];
+  const double v2[2] = {bb, col};
+  block_sum_store<2>(v2, 2, t2);
+  __shared__ double s_nu[1];
+  if (threadIdx.x == 0) {
+    const double alpha = red[m];
+    double nu = sqrt(fmax(alpha - t2[0], 0.0));
+    if (!(nu > 1e-12 * sqrt(fmax(t2[1] + alpha, 0.0)))) nu = 0.0;
+    H[m + (long long)(m - 1) * ldh] = nu;
+    scal[0] = nu > 0.0 ? 1.0 / nu : 0.0;
+    s_nu[0] = nu;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += kBlock) H[i + (long long)(m - 1) * ldh] += red[i];
 }
 
 // Partial sums of <x, V_i>_M and |x|_M^2.
@@ -432,6 +700,68 @@ hipError_t launch_stencil(Storage st, const void* v, void* w, const void* V, lon
                           const DevGrid& g, const DevMats& m, double* partials, hipStream_t s) {
   return st == F64 ? stencil_t<double>(v, w, V, ldv, cnt, g, m, partials, s)
                    : stencil_t<float>(v, w, V, ldv, cnt, g, m, partials, s);
+}
+
+template <typename T>
+static hipError_t stencil_lag_t(const void* u, void* x, const void* V, long long ldv, int cnt,
+                                const DevGrid& g, const DevMats& m, double* partials, hipStream_t s) {
+  const int cpt = cells_per_thread(g.N3);
+  const dim3 grid(cell_blocks(g.N3)), blk(kBlock);
+  const T* uu = (const T*)u;
+  T* xx = (T*)x;
+  const T* VV = (const T*)V;
+  const bool mu = m.inv_mu != nullptr;
+  constexpr int CH = 8;
+  if (cpt == 4) {
+    if (mu) hipLaunchKernelGGL((k_stencil_lag<T, true, 4, CH>), grid, blk, 0, s, uu, xx, VV, ldv, cnt, g, m, partials);
+    else hipLaunchKernelGGL((k_stencil_lag<T, false, 4, CH>), grid, blk, 0, s, uu, xx, VV, ldv, cnt, g, m, partials);
+  } else {
+    if (mu) hipLaunchKernelGGL((k_stencil_lag<T, true, 1, CH>), grid, blk, 0, s, uu, xx, VV, ldv, cnt, g, m, partials);
+    else hipLaunchKernelGGL((k_stencil_lag<T, false, 1, CH>), grid, blk, 0, s, uu, xx, VV, ldv, cnt, g, m, partials);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stencil_lag(Storage st, const void* u, void* x, const void* V, long long ldv, int cnt,
+                              const DevGrid& g, const DevMats& m, double* partials, hipStream_t s) {
+  return st == F64 ? stencil_lag_t<double>(u, x, V, ldv, cnt, g, m, partials, s)
+                   : stencil_lag_t<float>(u, x, V, ldv, cnt, g, m, partials, s);
+}
+
+template <typename T>
+static hipError_t lag_update_t(const void* u, const void* x, const void* V, long long ldv, int cnt,
+                               const double* co, void* vnew, void* unext, const DevGrid& g,
+                               hipStream_t s) {
+  if (cnt > kMaxCoef) return hipErrorInvalidValue;
+  const int cpt = cells_per_thread(g.N3);
+  const dim3 grid(cell_blocks(g.N3)), blk(kBlock);
+  if (cpt == 4)
+    hipLaunchKernelGGL((k_lag_update<T, 4>), grid, blk, 0, s, (const T*)u, (const T*)x, (const T*)V,
+                       ldv, cnt, co, (T*)vnew, (T*)unext, g.N3);
+  else
+    hipLaunchKernelGGL((k_lag_update<T, 1>), grid, blk, 0, s, (const T*)u, (const T*)x, (const T*)V,
+                       ldv, cnt, co, (T*)vnew, (T*)unext, g.N3);
+  return hipGetLastError();
+}
+
+hipError_t launch_lag_update(Storage st, const void* u, const void* x, const void* V, long long ldv,
+                             int cnt, const double* co, void* vnew, void* unext, const DevGrid& g,
+                             hipStream_t s) {
+  return st == F64 ? lag_update_t<double>(u, x, V, ldv, cnt, co, vnew, unext, g, s)
+                   : lag_update_t<float>(u, x, V, ldv, cnt, co, vnew, unext, g, s);
+}
+
+hipError_t launch_lag_fin(const double* red, int j, double* H, int ldh, double* co, double* scal,
+                          hipStream_t s) {
+  if (j + 1 > kMaxCoef) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lag_fin, dim3(1), dim3(kBlock), 0, s, red, j, H, ldh, co, scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_lag_final(const double* red, int m, double* H, int ldh, double* scal,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_lag_final, dim3(1), dim3(kBlock), 0, s, red, m, H, ldh, scal);
+  return hipGetLastError();
 }
 
 template <typename T>

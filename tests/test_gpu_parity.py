@@ -105,10 +105,11 @@ def test_apply_at_c2_materials():
 
 # ---------------------------------------------------------------- Arnoldi --
 
-def test_arnoldi_matches_definition_first_steps():
-    _announce("arnoldi vs definition")
+@pytest.mark.parametrize("orth", ["delayed", "cgs2"])
+def test_arnoldi_matches_definition_first_steps(orth):
+    _announce(f"arnoldi vs definition ({orth})")
     eps, mu, sig = _box((6, 6, 6), 8)
-    s = _solver(eps, mu, sig, krylov_dim=8)
+    s = _solver(eps, mu, sig, krylov_dim=8, orth=orth)
     v = np.random.default_rng(3).standard_normal(6 * eps.size)
     m = 5
     V, H, beta, steps = s.arnoldi(_t(v), m)
@@ -119,12 +120,12 @@ def test_arnoldi_matches_definition_first_steps():
     assert np.abs(V.cpu().numpy() - Vo.T).max() <= 1e-11 * np.abs(Vo).max()
 
 
-@pytest.mark.parametrize("m", [30, 64])
-def test_arnoldi_relation_and_orthogonality(m):
-    _announce(f"arnoldi relation m={m}")
+@pytest.mark.parametrize("m,orth", [(30, "delayed"), (64, "delayed"), (64, "cgs2")])
+def test_arnoldi_relation_and_orthogonality(m, orth):
+    _announce(f"arnoldi relation m={m} {orth}")
     wl = wk.small(12, seed=4, n_spheres=5)
     inp = wk.generate(wl)
-    s = _solver(inp.eps, None, inp.sigma, krylov_dim=m)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=m, orth=orth)
     v = wk.random_state(wl.n, 9)
     V, H, beta, steps = s.arnoldi(_t(v), m)
     V = V.cpu().numpy().T
@@ -146,8 +147,27 @@ def test_arnoldi_relation_and_orthogonality(m):
     assert abs(math.sqrt(r @ (w * r)) - est) <= 1e-10 * max(est, 1e-300) + 1e-13 * beta
 
 
-def test_arnoldi_happy_breakdown_on_separable_mode():
-    _announce("arnoldi breakdown")
+def test_delayed_equals_classical_twice():
+    _announce("arnoldi delayed vs cgs2")
+    wl = wk.C1
+    inp = wk.generate(wl)
+    b = wk.source_vector(wl, wl.omegas[0], 0.0).real
+    out = {}
+    for orth in ("delayed", "cgs2"):
+        s = _solver(inp.eps, None, inp.sigma, krylov_dim=40, orth=orth)
+        V, H, beta, steps = s.arnoldi(_t(b), 40)
+        out[orth] = (V.cpu().numpy(), H, beta, steps)
+    Vd, Hd, bd, sd = out["delayed"]
+    Vc, Hc, bc, sc = out["cgs2"]
+    assert sd == sc == 40
+    assert abs(bd - bc) <= 1e-14 * bc
+    assert np.abs(Hd - Hc).max() <= 1e-11 * np.abs(Hc).max()
+    assert np.abs(Vd - Vc).max() <= 1e-10 * np.abs(Vc).max()
+
+
+@pytest.mark.parametrize("orth", ["delayed", "cgs2"])
+def test_arnoldi_happy_breakdown_on_separable_mode(orth):
+    _announce(f"arnoldi breakdown ({orth})")
     N = 6
     ones = np.ones((N, N, N))
     D = np.diag(-np.ones(N)) + np.diag(np.ones(N - 1), 1)
@@ -157,9 +177,11 @@ def test_arnoldi_happy_breakdown_on_separable_mode():
     ex = np.einsum("k,j,i->kji", Vt[qz], Vt[qy], U[:, qx])
     v = np.zeros((6, N, N, N))
     v[3] = ex
-    s = _solver(2.0 * ones, None, 0.1 * ones, krylov_dim=20)
+    s = _solver(2.0 * ones, None, 0.1 * ones, krylov_dim=20, orth=orth)
     V, H, beta, steps = s.arnoldi(_t(v.reshape(-1)), 20)
     assert 1 <= steps <= 6
+    Vn = V.cpu().numpy()
+    assert np.all(np.isfinite(Vn)) and np.all(np.isfinite(H))
 
 
 # ------------------------------------------------------------ exponential --
