@@ -170,6 +170,26 @@ int kry_stationary(kry_ctx* ctx, const double* omegas, int32_t n_omega,
                    int32_t n_src, const double* b, int32_t b_per_omega,
                    double* z, kry_stats* stats);
 
+/* Transmitted power and its gradient w.r.t. per-cell permittivity.
+ * The loss is the period-averaged Poynting flux of the time-harmonic parts
+ * Im(e^{i w t} z_w) of Corollary 3 through the plane z = plane_k, summed over
+ * the frequencies:
+ *     L = sum_w 1/2 Re sum_{i,j} [z_Ex conj(Hy_bar) - z_Ey conj(Hx_bar)],
+ * Hbar = (z_H[plane_k - 1] + z_H[plane_k]) / 2 (the paper computes no
+ * gradients; this is the differentiation form of the solver).  dL/d eps is
+ * obtained with one adjoint shifted solve per frequency, (A^T + i w) lam =
+ * dL/dz, solved as (A + i w) x = P M^{-1} dL/dz through the identity
+ * A^T = M P A P M^{-1}, P = diag(I_H, -I_E); the forward fields z_w are the
+ * saved state of the forward pass.
+ * omegas: host, n_omega.  b: device complex interleaved FP64; one shared
+ * column (b_per_omega = 0) or n_omega columns.  1 <= plane_k <= nz - 1.
+ * loss: host, one double.  dL_deps: device, nx*ny*nz doubles (overwritten),
+ * or NULL to evaluate the loss only (no adjoint solves).
+ * Shifted residual target: opts.tol relative.  stats may be NULL. */
+int kry_grad(kry_ctx* ctx, const double* omegas, int32_t n_omega, const double* b,
+             int32_t b_per_omega, int32_t plane_k, double* loss, double* dL_deps,
+             kry_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

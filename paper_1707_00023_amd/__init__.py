@@ -26,7 +26,7 @@ _CODES = {KRY_EINVAL: "KRY_EINVAL", KRY_ENOMEM: "KRY_ENOMEM", KRY_EHIP: "KRY_EHI
 
 EXPORTED = ("kry_create", "kry_destroy", "kry_last_error", "kry_size", "kry_apply",
             "kry_apply_f32", "kry_arnoldi", "kry_expv", "kry_solve_multifreq",
-            "kry_stationary")
+            "kry_stationary", "kry_grad")
 
 
 class KryGrid(ctypes.Structure):
@@ -96,8 +96,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kry_expv.argtypes = [P, D, P, P, I32, ctypes.POINTER(KryStats)]
     lib.kry_solve_multifreq.argtypes = [P, P, I32, I32, P, I32, D, P, ctypes.POINTER(KryStats)]
     lib.kry_stationary.argtypes = [P, P, I32, I32, P, I32, P, ctypes.POINTER(KryStats)]
+    lib.kry_grad.argtypes = [P, P, I32, P, I32, I32, ctypes.POINTER(D), P,
+                             ctypes.POINTER(KryStats)]
     for name in ("kry_apply", "kry_apply_f32", "kry_arnoldi", "kry_expv",
-                 "kry_solve_multifreq", "kry_stationary"):
+                 "kry_solve_multifreq", "kry_stationary", "kry_grad"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -268,3 +270,54 @@ class Solver:
         self._check(rc, allow_noconv=True)
         self.last_stats = st.as_dict()
         return y
+
+    def grad(self, omegas: Sequence[float], b, plane_k: int, b_per_omega: bool = False,
+             loss_only: bool = False):
+        """(L, dL/d eps) of the period-averaged flux through plane z = plane_k.
+
+        b: complex128 (1, n) shared source or (n_omega, n) per-omega sources.
+        Returns the loss (float) and dL/d eps as a float64 (nz, ny, nx) tensor.
+        """
+        import torch
+        om, b, nw, nsrc = self._omega_b(omegas, b, b_per_omega)
+        if nsrc != 1:
+            raise ValueError("one source per frequency (or one shared source)")
+        g = None if loss_only else torch.empty((self.grid.nz, self.grid.ny, self.grid.nx),
+                                               dtype=torch.float64, device=self.device)
+        loss = ctypes.c_double()
+        st = KryStats()
+        rc = self._lib.kry_grad(self._ctx, om.ctypes.data_as(ctypes.c_void_p), nw, _ptr(b),
+                                int(bool(b_per_omega)), int(plane_k), ctypes.byref(loss),
+                                None if g is None else _ptr(g), ctypes.byref(st))
+        self._check(rc, allow_noconv=True)
+        self.last_stats = st.as_dict()
+        return loss.value, g
+
+
+def _flux_function():
+    import torch
+
+    class FluxLoss(torch.autograd.Function):
+        """L(eps) = transmitted period-averaged power; backward by the adjoint."""
+
+        @staticmethod
+        def forward(ctx, eps, sigma, b, omegas, plane_k, opts, b_per_omega):
+            solver = Solver(eps.detach(), None, sigma, opts)
+            L, g = solver.grad(omegas, b, plane_k, b_per_omega)
+            solver.close()
+            ctx.save_for_backward(g)
+            return torch.tensor(L, dtype=torch.float64, device=eps.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (g,) = ctx.saved_tensors
+            return grad_out * g, None, None, None, None, None, None
+
+    return FluxLoss
+
+
+def flux_loss(eps, sigma, b, omegas, plane_k, opts: Optional[Options] = None,
+              b_per_omega: bool = False):
+    """Differentiable transmitted power (torch.autograd) w.r.t. per-cell eps."""
+    return _flux_function().apply(eps, sigma, b, omegas, plane_k, opts or Options(),
+                                  b_per_omega)

@@ -10,6 +10,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -930,6 +931,93 @@ int kry_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
     texport(c, st);
   }
   return rc;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int kry_grad(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
+             int32_t b_per_omega, int32_t plane_k, double* loss, double* dL_deps, kry_stats* st) {
+  int rc = check_multifreq_args(c, omegas, n_omega, 1, b);
+  if (rc) return rc;
+  if (!loss) return fail(c, KRY_EINVAL, "null output");
+  if (plane_k < 1 || plane_k > c->g.nz - 1) return fail(c, KRY_EINVAL, "plane_k out of range");
+  if (st) std::memset(st, 0, sizeof(*st));
+  treset(c);
+  const double t0 = now_ms();
+  rc = ensure_basis(c, c->opts.krylov_dim);
+  if (rc) return rc;
+  rc = ensure_z(c, n_omega + 1);
+  if (rc) return rc;
+  const long long n = c->n, N3 = c->g.N3;
+  double* rhs = nullptr;
+  double* fpart = nullptr;
+  const long long N2 = (long long)c->g.nx * c->g.ny;
+  const int nfb = (int)((N2 + kry::kBlock - 1) / kry::kBlock);
+  if (hipMalloc(&rhs, sizeof(double) * 2 * n) != hipSuccess ||
+      hipMalloc(&fpart, sizeof(double) * nfb) != hipSuccess) {
+    hipFree(rhs);
+    (void)hipGetLastError();
+    return fail(c, KRY_ENOMEM, "cannot allocate adjoint workspace");
+  }
+  Defer<std::function<void()>> free_ws{[&]() {
+    hipFree(rhs);
+    hipFree(fpart);
+  }};
+  int status = KRY_OK;
+  double max_res = 0.0;
+  const double tol = c->opts.tol;
+  std::vector<double> om(omegas, omegas + n_omega);
+  // forward: z_w in Z columns 0..n_omega-1
+  if (!b_per_omega) {
+    std::vector<int> zc(n_omega);
+    for (int k = 0; k < n_omega; ++k) zc[k] = k;
+    double bn = 0.0;
+    rc = stationary_group(c, b, om, zc, tol, st, &max_res, &bn);
+    if (rc == KRY_ENOCONV) status = rc;
+    else if (rc) return rc;
+  } else {
+    for (int k = 0; k < n_omega; ++k) {
+      double bn = 0.0;
+      rc = stationary_group(c, b + (size_t)k * 2 * n, std::vector<double>{om[k]},
+                            std::vector<int>{k}, tol, st, &max_res, &bn);
+      if (rc == KRY_ENOCONV) status = rc;
+      else if (rc) return rc;
+    }
+  }
+  if (dL_deps) KRY_HIP(hipMemsetAsync(dL_deps, 0, sizeof(double) * N3, c->stream));
+  double L = 0.0;
+  std::vector<double> hp(nfb);
+  for (int k = 0; k < n_omega; ++k) {
+    void* zre = zcol(c, 2 * k);
+    void* zim = zcol(c, 2 * k + 1);
+    KRY_HIP(hipMemsetAsync(rhs, 0, sizeof(double) * 2 * n, c->stream));
+    int nb = 0;
+    KRY_HIP(kry::launch_flux_seed(c->st, zre, zim, plane_k, c->g, c->mats, fpart, rhs, &nb, c->stream));
+    KRY_HIP(hipMemcpyAsync(hp.data(), fpart, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
+    KRY_HIP(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < nb; ++i) L += hp[i];
+    if (!dL_deps) continue;  // loss only
+    // adjoint: (A + i w) x = P M^-1 a, x in Z column n_omega
+    double bn = 0.0;
+    rc = stationary_group(c, rhs, std::vector<double>{om[k]}, std::vector<int>{n_omega}, tol, st,
+                          &max_res, &bn);
+    if (rc == KRY_ENOCONV) status = rc;
+    else if (rc) return rc;
+    const double* bk = b_per_omega ? b + (size_t)k * 2 * n : b;
+    KRY_HIP(kry::launch_grad_acc(c->st, zre, zim, zcol(c, 2 * n_omega), zcol(c, 2 * n_omega + 1), bk,
+                                 om[k], dL_deps, N3, c->stream));
+  }
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  *loss = L;
+  if (st) {
+    st->max_residual = max_res;
+    st->ms_stationary = st->ms_total = now_ms() - t0;
+    st->converged = status == KRY_OK;
+    texport(c, st);
+  }
+  return status;
 }
 
 }  // extern "C"

@@ -101,4 +101,16 @@ hipError_t launch_store_complex(Storage st, const void* re, const void* im, doub
 hipError_t launch_assemble(Storage st, const void* re, const void* im, const void* yhat,
                            double sn, double cs, double* out, long long n, hipStream_t s);
 
+// Flux of z = zre + i zim through plane kf (per-block partials, *nblocks
+// of them) and, if rhs != nullptr, the adjoint right-hand side P M^-1 dP/dz
+// written into the complex interleaved rhs (zero elsewhere beforehand).
+hipError_t launch_flux_seed(Storage st, const void* zre, const void* zim, int kf, const DevGrid& g,
+                            const DevMats& m, double* partials, double* rhs, int* nblocks,
+                            hipStream_t s);
+
+// g[c] -= sum_{E planes} Re(x (b - i w z)) (the adjoint gradient term).
+hipError_t launch_grad_acc(Storage st, const void* zre, const void* zim, const void* xre,
+                           const void* xim, const double* b, double w, double* g, long long N3,
+                           hipStream_t s);
+
 }  // namespace kry

@@ -663,6 +663,91 @@ __global__ void k_assemble(const T* __restrict__ re, const T* __restrict__ im,
   }
 }
 
+// Period-averaged Poynting flux of the time-harmonic field z = zre + i zim
+// through the plane z = kf, and the adjoint right-hand side.  One thread per
+// (i, j) column of the plane:
+//   Hbar = (z_H[kf-1] + z_H[kf]) / 2,
+//   P += 1/2 Re(z_Ex conj(Hbar_y) - z_Ey conj(Hbar_x))   (block partials),
+// and with a = dP/dz (dP = Re(a^T dz)):
+//   a_Ex = conj(Hbar_y)/2, a_Ey = -conj(Hbar_x)/2,
+//   a_Hy[kf-1] = a_Hy[kf] = conj(z_Ex)/4, a_Hx[kf-1] = a_Hx[kf] = -conj(z_Ey)/4,
+// the adjoint system (A^T + i w) lam = a is solved as (A + i w) x = P M^-1 a
+// (A^T = M P A P M^-1 with P = diag(I_H, -I_E)), so rhs = P M^-1 a is
+// written (complex interleaved) at those entries; rhs must be zero elsewhere.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_flux_seed(const T* __restrict__ zre,
+                                                      const T* __restrict__ zim, int kf,
+                                                      DevGrid g, DevMats mt,
+                                                      double* __restrict__ partials,
+                                                      double* __restrict__ rhs) {
+  const long long N2 = (long long)g.nx * g.ny;
+  const long long N3 = g.N3;
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  double p = 0.0;
+  if (t < N2) {
+    const long long c1 = (long long)kf * N2 + t;  // cell at kf
+    const long long c0 = c1 - N2;                 // cell at kf - 1
+    auto Z = [&](int comp, long long c, double& re, double& im) {
+      re = (double)zre[comp * N3 + c];
+      im = (double)zim[comp * N3 + c];
+    };
+    double hx0r, hx0i, hx1r, hx1i, hy0r, hy0i, hy1r, hy1i, exr, exi, eyr, eyi;
+    Z(0, c0, hx0r, hx0i);
+    Z(0, c1, hx1r, hx1i);
+    Z(1, c0, hy0r, hy0i);
+    Z(1, c1, hy1r, hy1i);
+    Z(3, c1, exr, exi);
+    Z(4, c1, eyr, eyi);
+    const double hxr = 0.5 * (hx0r + hx1r), hxi = 0.5 * (hx0i + hx1i);
+    const double hyr = 0.5 * (hy0r + hy1r), hyi = 0.5 * (hy0i + hy1i);
+    // Re(u conj(v)) = ur vr + ui vi
+    p = 0.5 * ((exr * hyr + exi * hyi) - (eyr * hxr + eyi * hxi));
+    if (rhs) {
+      const double ie = mt.inv_eps[c1];
+      const double im0 = mt.inv_mu ? mt.inv_mu[c0] : 1.0;
+      const double im1 = mt.inv_mu ? mt.inv_mu[c1] : 1.0;
+      // E rows: -a_E / eps
+      rhs[2 * (3 * N3 + c1)] = -0.5 * hyr * ie;
+      rhs[2 * (3 * N3 + c1) + 1] = 0.5 * hyi * ie;
+      rhs[2 * (4 * N3 + c1)] = 0.5 * hxr * ie;
+      rhs[2 * (4 * N3 + c1) + 1] = -0.5 * hxi * ie;
+      // H rows: a_H / mu
+      rhs[2 * (1 * N3 + c0)] = 0.25 * exr * im0;
+      rhs[2 * (1 * N3 + c0) + 1] = -0.25 * exi * im0;
+      rhs[2 * (1 * N3 + c1)] = 0.25 * exr * im1;
+      rhs[2 * (1 * N3 + c1) + 1] = -0.25 * exi * im1;
+      rhs[2 * (0 * N3 + c0)] = -0.25 * eyr * im0;
+      rhs[2 * (0 * N3 + c0) + 1] = 0.25 * eyi * im0;
+      rhs[2 * (0 * N3 + c1)] = -0.25 * eyr * im1;
+      rhs[2 * (0 * N3 + c1) + 1] = 0.25 * eyi * im1;
+    }
+  }
+  const double a1[1] = {p};
+  block_sum_store<1>(a1, 1, partials + blockIdx.x);
+}
+
+// Gradient of the flux w.r.t. per-cell eps for one frequency, accumulated:
+// dL/d eps_c += sum_{E rows r of c} Re(lam_r (A z)_r) / eps_c with
+// lam = M P x (so lam_E = -eps x_E) and A z = b - i w z (the shifted
+// equation), i.e. g_c -= sum_{p in Ex,Ey,Ez} Re(x_p (b_p - i w z_p)).
+template <typename T>
+__global__ void k_grad_acc(const T* __restrict__ zre, const T* __restrict__ zim,
+                           const T* __restrict__ xre, const T* __restrict__ xim,
+                           const double* __restrict__ b, double w, double* __restrict__ g,
+                           long long N3) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= N3) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int p = 3; p < 6; ++p) {
+    const long long e = p * N3 + c;
+    const double azr = b[2 * e] + w * (double)zim[e];
+    const double azi = b[2 * e + 1] - w * (double)zre[e];
+    acc += (double)xre[e] * azr - (double)xim[e] * azi;
+  }
+  g[c] -= acc;
+}
+
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -903,6 +988,35 @@ hipError_t launch_store_complex(Storage st, const void* re, const void* im, doub
   else
     hipLaunchKernelGGL(k_store_complex<float>, dim3(blocks_for(n)), dim3(kBlock), 0, s,
                        (const float*)re, (const float*)im, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_seed(Storage st, const void* zre, const void* zim, int kf, const DevGrid& g,
+                            const DevMats& m, double* partials, double* rhs, int* nblocks,
+                            hipStream_t s) {
+  const long long N2 = (long long)g.nx * g.ny;
+  const unsigned nb = blocks_for(N2);
+  *nblocks = (int)nb;
+  if (st == F64)
+    hipLaunchKernelGGL(k_flux_seed<double>, dim3(nb), dim3(kBlock), 0, s, (const double*)zre,
+                       (const double*)zim, kf, g, m, partials, rhs);
+  else
+    hipLaunchKernelGGL(k_flux_seed<float>, dim3(nb), dim3(kBlock), 0, s, (const float*)zre,
+                       (const float*)zim, kf, g, m, partials, rhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_acc(Storage st, const void* zre, const void* zim, const void* xre,
+                           const void* xim, const double* b, double w, double* g, long long N3,
+                           hipStream_t s) {
+  if (st == F64)
+    hipLaunchKernelGGL(k_grad_acc<double>, dim3(blocks_for(N3)), dim3(kBlock), 0, s,
+                       (const double*)zre, (const double*)zim, (const double*)xre,
+                       (const double*)xim, b, w, g, N3);
+  else
+    hipLaunchKernelGGL(k_grad_acc<float>, dim3(blocks_for(N3)), dim3(kBlock), 0, s,
+                       (const float*)zre, (const float*)zim, (const float*)xre,
+                       (const float*)xim, b, w, g, N3);
   return hipGetLastError();
 }
 
