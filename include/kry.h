@@ -65,7 +65,10 @@ typedef struct {
   int32_t krylov_dim;   /* Arnoldi steps per restart cycle m, 1..1024      */
   int32_t max_restarts; /* cap on restart cycles per solve (0: 100000)     */
   double tol;           /* relative accuracy target of each output column  */
-  int32_t block_width;  /* reserved for the batched form (0: automatic)    */
+  int32_t block_width;  /* batched form: 0 or 1 = one column at a time; B > 1
+                           = columns processed in groups of B/2 sharing one
+                           block Krylov space (2 real columns per complex
+                           source), block Gram-Schmidt on matrix cores     */
   int32_t use_graph;    /* reserved: capture restart cycles in HIP graphs  */
   int32_t inner_product;/* 0: energy inner product (the only mode)         */
   void* stream;         /* hipStream_t; NULL = the null stream             */
@@ -141,6 +144,19 @@ int kry_apply_f32(kry_ctx* ctx, const float* v, float* w, int32_t ncols);
  * (< m on an exact invariant subspace, h_{j+1,j} = 0), or a KRY_E* code. */
 int kry_arnoldi(kry_ctx* ctx, const double* v, int32_t m, void* V_out,
                 double* H_out, double* beta_out);
+
+/* Block Arnoldi: mb block steps from the start block V0 (device, FP64, p
+ * columns of length n), the block form of equation (Arn) with p columns per
+ * block.  Block Gram-Schmidt in the energy inner product runs on FP64
+ * matrix cores (V^T M W and W - V C products), each new block is
+ * orthonormalised by rank-revealing Cholesky QR twice (dependent directions
+ * become zero columns).  V_out: device, (mb+1)*p columns of length n in the
+ * context's storage type (block 0 = orthonormalised V0).  H_out: host,
+ * ((mb+1) p) x (mb p) doubles, column-major, with A V_{mb} = V_{mb+1} H.
+ * Returns the number of block steps taken (< mb if the block space became
+ * invariant) or a KRY_E* code.  1 <= p <= 128. */
+int kry_block_arnoldi(kry_ctx* ctx, const double* V0, int32_t p, int32_t mb, void* V_out,
+                      double* H_out);
 
 /* y = e^{-t A} v for ncols columns (equation (y_homo)), by restarts in time
  * with the residual of Lemma 1 (g = 0) bounding the error of each step.

@@ -26,7 +26,7 @@ _CODES = {KRY_EINVAL: "KRY_EINVAL", KRY_ENOMEM: "KRY_ENOMEM", KRY_EHIP: "KRY_EHI
 
 EXPORTED = ("kry_create", "kry_destroy", "kry_last_error", "kry_size", "kry_apply",
             "kry_apply_f32", "kry_arnoldi", "kry_expv", "kry_solve_multifreq",
-            "kry_stationary", "kry_grad")
+            "kry_stationary", "kry_grad", "kry_block_arnoldi")
 
 
 class KryGrid(ctypes.Structure):
@@ -98,6 +98,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kry_stationary.argtypes = [P, P, I32, I32, P, I32, P, ctypes.POINTER(KryStats)]
     lib.kry_grad.argtypes = [P, P, I32, P, I32, I32, ctypes.POINTER(D), P,
                              ctypes.POINTER(KryStats)]
+    lib.kry_block_arnoldi.argtypes = [P, P, I32, I32, P, P]
+    lib.kry_block_arnoldi.restype = ctypes.c_int
     for name in ("kry_apply", "kry_apply_f32", "kry_arnoldi", "kry_expv",
                  "kry_solve_multifreq", "kry_stationary", "kry_grad"):
         getattr(lib, name).restype = ctypes.c_int
@@ -122,6 +124,7 @@ class Options:
     tol: float = 1e-8
     timing: bool = False
     orth: str = "delayed"       # "delayed" (two basis sweeps per step) or "cgs2"
+    block_width: int = 0        # > 1: batched form, groups of block_width/2 columns
 
 
 class Solver:
@@ -149,7 +152,8 @@ class Solver:
         e, m, s = prep(eps), prep(mu), prep(sigma)
         self.grid = KryGrid(nx, ny, nz, 0)
         self.opts = KryOpts(1 if opts.storage == "f32" else 0, opts.krylov_dim,
-                            opts.max_restarts, opts.tol, 0, 0, 0, _stream_ptr().value,
+                            opts.max_restarts, opts.tol, opts.block_width, 0, 0,
+                            _stream_ptr().value,
                             int(bool(opts.timing)), 1 if opts.orth == "cgs2" else 0)
         self.storage = opts.storage
         ctx = ctypes.c_void_p()
@@ -220,6 +224,21 @@ class Solver:
         if rc < 0:
             self._check(rc)
         return V, H.T.copy(), beta.value, rc
+
+    def block_arnoldi(self, V0, mb: int):
+        """(V ((mb+1) p, n), H ((mb+1) p, mb p) numpy, block steps) from the block V0 (p, n)."""
+        import numpy as np
+        import torch
+        V0 = self._vecs(V0, torch.float64)
+        p = V0.shape[0]
+        dt = torch.float32 if self.storage == "f32" else torch.float64
+        V = torch.empty(((mb + 1) * p, self.n), dtype=dt, device=self.device)
+        H = np.zeros((mb * p, (mb + 1) * p))  # column-major ((mb+1)p) x (mb p)
+        rc = self._lib.kry_block_arnoldi(self._ctx, _ptr(V0), p, mb, _ptr(V),
+                                         H.ctypes.data_as(ctypes.c_void_p))
+        if rc < 0:
+            self._check(rc)
+        return V, H.T.copy(), rc
 
     def expv(self, t: float, v):
         """e^{-tA} v for each row of v."""

@@ -51,6 +51,15 @@ struct kry_ctx {
   void* Z = nullptr;  // 2 * zcap columns (Re, Im per solution column)
   int zcap = 0;
 
+  // block (batched) form: basis slots, energy weights, Gram partials
+  void* BV = nullptr;
+  int bslots = 0;
+  double* d_w = nullptr;       // energy weight per entry (n)
+  double* d_gp = nullptr;      // Gram partials
+  size_t gp_cap = 0;
+  double* d_bc = nullptr;      // reduced Gram / coefficient matrices
+  size_t bc_cap = 0;
+
   // optional per-kernel-class timing with HIP events
   struct Pending {
     int cls;
@@ -581,6 +590,8 @@ int kry_create(const kry_grid* grid, const double* eps, const double* mu, const 
   if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) return fail(nullptr, KRY_EINVAL, "invalid tol");
   if (opts->inner_product != 0) return fail(nullptr, KRY_EINVAL, "only the energy inner product is supported");
   if (opts->orth != 0 && opts->orth != 1) return fail(nullptr, KRY_EINVAL, "invalid orth");
+  if (opts->block_width < 0 || opts->block_width > 256)
+    return fail(nullptr, KRY_EINVAL, "block_width out of range");
   std::vector<double> he(N3), hm, hs(N3, 0.0);
   if (hipMemcpy(he.data(), eps, sizeof(double) * N3, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(nullptr, KRY_EINVAL, "eps is not a readable device array");
@@ -839,6 +850,425 @@ int for_each_group(kry_ctx* c, const double* omegas, int n_omega, int n_src, con
 
 }  // namespace
 
+
+// ---------------------------------------------------------------------------
+// Block (batched) form.  Several columns share one real block Krylov space
+// K(A, [X]) (Corollaries 1 and 2: the space does not depend on the time
+// factor of the source; a Krylov space is also shift invariant, so columns
+// with different omega can share it).  Block Gram-Schmidt runs as
+// tall-skinny FP64 matrix-core products (V^T M W and W - V C), with
+// rank-revealing Cholesky QR (twice) for each new block.
+
+namespace {
+
+void* bslot(kry_ctx* c, int i) { return (char*)c->BV + (size_t)i * c->ldv * c->esz; }
+
+int ensure_block(kry_ctx* c, int slots) {
+  if (!c->d_w) {
+    KRY_HIP(hipMalloc(&c->d_w, sizeof(double) * c->ldv));
+    KRY_HIP(kry::launch_weights(c->mats.eps, c->mats.mu, c->d_w, c->g.N3, c->stream));
+  }
+  if (slots > c->bslots || !c->BV) {
+    hipFree(c->BV);
+    c->BV = nullptr;
+    c->bslots = 0;
+    const size_t bytes = (size_t)slots * c->ldv * c->esz;
+    if (hipMalloc(&c->BV, bytes) != hipSuccess) {
+      c->BV = nullptr;
+      (void)hipGetLastError();
+      return fail(c, KRY_ENOMEM, "cannot allocate block basis of " + std::to_string(bytes) + " bytes");
+    }
+    c->bslots = slots;
+  }
+  return KRY_OK;
+}
+
+int ensure_gp(kry_ctx* c, size_t doubles, size_t bc) {
+  if (doubles > c->gp_cap) {
+    hipFree(c->d_gp);
+    c->d_gp = nullptr;
+    KRY_HIP(hipMalloc(&c->d_gp, sizeof(double) * doubles));
+    c->gp_cap = doubles;
+  }
+  if (bc > c->bc_cap) {
+    hipFree(c->d_bc);
+    c->d_bc = nullptr;
+    KRY_HIP(hipMalloc(&c->d_bc, sizeof(double) * bc));
+    c->bc_cap = bc;
+  }
+  return KRY_OK;
+}
+
+// C (M x N, row-major, host) = X^T M Y for block columns X[:M], Y[:N]
+// (device pointers to the first column; stride ldv).  Synchronises.
+int block_gram_host(kry_ctx* c, const void* X, int M, const void* Y, int N, std::vector<double>& C) {
+  const int ns = kry::gram_splits(c->n, M, N);
+  int rc = ensure_gp(c, (size_t)ns * M * N, (size_t)M * N);
+  if (rc) return rc;
+  hipEvent_t e = tbeg(c);
+  KRY_HIP(kry::launch_gram(c->st, X, M, Y, N, c->ldv, c->d_w, c->n, c->d_gp, ns, c->stream));
+  tend(c, e, KRY_K_DOTS, vbytes(c) * (M + N) + 8.0 * c->n);
+  KRY_HIP(kry::launch_reduce(c->d_gp, ns, M * N, M * N, c->d_bc, c->stream));
+  C.resize((size_t)M * N);
+  KRY_HIP(hipMemcpyAsync(C.data(), c->d_bc, sizeof(double) * M * N, hipMemcpyDeviceToHost, c->stream));
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  return KRY_OK;
+}
+
+// Out[:N] (=|+=) alpha X[:M] C with C (M x N row-major) from the host.
+int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, int N, void* Out,
+               double alpha, int accumulate) {
+  int rc = ensure_gp(c, 0, (size_t)M * N);
+  if (rc) return rc;
+  KRY_HIP(hipMemcpyAsync(c->d_bc, C.data(), sizeof(double) * M * N, hipMemcpyHostToDevice, c->stream));
+  hipEvent_t e = tbeg(c);
+  KRY_HIP(kry::launch_gemm_nn(c->st, X, M, c->d_bc, N, Out, c->ldv, c->n, alpha, accumulate, c->stream));
+  tend(c, e, KRY_K_UPDATE, vbytes(c) * (M + (accumulate ? 2.0 : 1.0) * N));
+  // the host array may be reused by the caller right after
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  return KRY_OK;
+}
+
+// Rank-revealing Cholesky QR, twice: Out[:p] = M-orthonormal basis of W[:p]
+// (zero columns for dropped directions), W ~= Out Rf.  W and Out must not
+// overlap; T2 is scratch (p columns).
+int block_cholqr2(kry_ctx* c, void* W, int p, void* T2, void* Out, std::vector<double>& Rf, int* rank) {
+  std::vector<double> G, Cm((size_t)p * p), R1((size_t)p * p), Cm2((size_t)p * p), R2((size_t)p * p);
+  int rc = block_gram_host(c, W, p, W, p, G);
+  if (rc) return rc;
+  const int r1 = kry::cholqr_factor(p, G.data(), 1e-10, Cm.data(), R1.data());
+  rc = block_gemm(c, W, p, Cm, p, T2, 1.0, 0);
+  if (rc) return rc;
+  rc = block_gram_host(c, T2, p, T2, p, G);
+  if (rc) return rc;
+  const int r2 = kry::cholqr_factor(p, G.data(), 1e-10, Cm2.data(), R2.data());
+  rc = block_gemm(c, T2, p, Cm2, p, Out, 1.0, 0);
+  if (rc) return rc;
+  Rf.assign((size_t)p * p, 0.0);
+  for (int a = 0; a < p; ++a)
+    for (int b = 0; b < p; ++b) {
+      double acc = 0.0;
+      for (int k = 0; k < p; ++k) acc += R2[(size_t)a * p + k] * R1[(size_t)k * p + b];
+      Rf[(size_t)a * p + b] = acc;
+    }
+  *rank = std::min(r1, r2);
+  return KRY_OK;
+}
+
+// Block Arnoldi (classical Gram-Schmidt twice, block CholQR2): start block
+// V_0 already orthonormal in slots [0, p); fills slots up to (mb+1) p and
+// Hb ((mb+1) p x mb p, column-major).  Stops early (*mb_eff) when a new
+// block is entirely dependent (an invariant block Krylov space).  Work
+// slots: W at ws, T2 at ws + p.
+int block_arnoldi(kry_ctx* c, int p, int mb, int ws, std::vector<double>& Hb, int* mb_eff,
+                  kry_stats* st, bool transient) {
+  const int ldh = (mb + 1) * p;
+  Hb.assign((size_t)ldh * mb * p, 0.0);
+  void* W = bslot(c, ws);
+  void* T2 = bslot(c, ws + p);
+  std::vector<double> Cc, Rf;
+  *mb_eff = mb;
+  for (int j = 0; j < mb; ++j) {
+    hipEvent_t e = tbeg(c);
+    KRY_HIP(kry::launch_stencil_cols(c->st, bslot(c, j * p), W, c->ldv, p, c->g, c->mats, c->stream));
+    tend(c, e, KRY_K_STENCIL, vbytes(c) * 2.0 * p + mbytes(c, true) - 8.0 * c->g.N3);
+    if (st) (transient ? st->matvecs_transient : st->matvecs_stationary) += p;
+    const int M = (j + 1) * p;
+    for (int pass = 0; pass < 2; ++pass) {
+      int rc = block_gram_host(c, bslot(c, 0), M, W, p, Cc);
+      if (rc) return rc;
+      rc = block_gemm(c, bslot(c, 0), M, Cc, p, W, -1.0, 1);
+      if (rc) return rc;
+      for (int a = 0; a < M; ++a)
+        for (int b = 0; b < p; ++b) Hb[a + (size_t)(j * p + b) * ldh] += Cc[(size_t)a * p + b];
+    }
+    int rank = 0;
+    int rc = block_cholqr2(c, W, p, T2, bslot(c, (j + 1) * p), Rf, &rank);
+    if (rc) return rc;
+    for (int a = 0; a < p; ++a)
+      for (int b = 0; b < p; ++b) Hb[(j + 1) * p + a + (size_t)(j * p + b) * ldh] = Rf[(size_t)a * p + b];
+    if (rank == 0) {  // the block space is invariant: stop here
+      *mb_eff = j + 1;
+      break;
+    }
+  }
+  return KRY_OK;
+}
+
+// Stationary part for a group of g complex columns (b_k, w_k): block GMRES
+// with one shift per column in the shared real block space.  Each cycle
+// minimises every column's residual over its own shifted projection; the
+// next start block spans the real and imaginary parts of the residual
+// coefficient vectors of the unconverged columns.  Those coefficients are
+// known exactly on the host in the orthonormal basis, so the restart block
+// is orthonormalised there (pivoted Householder QR) and the restart is
+// exact.  z_k accumulates in Z columns 2k (Re), 2k+1 (Im).
+int block_stationary(kry_ctx* c, const std::vector<const double*>& bcols, const std::vector<double>& om,
+                     double tol, kry_stats* st, double* max_res, std::vector<double>& bnorm) {
+  const int g = (int)bcols.size();
+  const int pmax = 2 * g;
+  const int mb = std::max(2, c->opts.krylov_dim / pmax);
+  const int ws = (mb + 1) * pmax;  // work slots: W, T2, start block
+  int rc = ensure_block(c, ws + 3 * pmax);
+  if (rc) return rc;
+  rc = ensure_z(c, g);
+  if (rc) return rc;
+  for (int k = 0; k < g; ++k) KRY_HIP(hipMemsetAsync(zcol(c, 2 * k), 0, 2 * c->ldv * c->esz, c->stream));
+  void* X = bslot(c, ws + 2 * pmax);
+  for (int k = 0; k < g; ++k) {
+    KRY_HIP(kry::launch_load_complex(c->st, bcols[k], 0, bslot(c, ws + 2 * pmax + 2 * k), c->n, c->stream));
+    KRY_HIP(kry::launch_load_complex(c->st, bcols[k], 1, bslot(c, ws + 2 * pmax + 2 * k + 1), c->n, c->stream));
+  }
+  std::vector<double> G;
+  rc = block_gram_host(c, X, pmax, X, pmax, G);
+  if (rc) return rc;
+  bnorm.assign(g, 0.0);
+  std::vector<char> active(g, 1);
+  for (int k = 0; k < g; ++k) {
+    bnorm[k] = std::sqrt(G[(size_t)(2 * k) * pmax + 2 * k] + G[(size_t)(2 * k + 1) * pmax + 2 * k + 1]);
+    if (bnorm[k] == 0.0) active[k] = 0;
+  }
+  // first start block: V_0 R = [Re b_k, Im b_k]
+  std::vector<double> Rf;
+  int rank = 0;
+  rc = block_cholqr2(c, X, pmax, bslot(c, ws + pmax), bslot(c, 0), Rf, &rank);
+  if (rc) return rc;
+  int p = pmax;
+  // gk[k]: column k's residual in the current start block V_0 (length p)
+  std::vector<std::vector<cplx>> gk(g, std::vector<cplx>(p, 0.0));
+  for (int k = 0; k < g; ++k)
+    for (int a = 0; a < p; ++a)
+      gk[k][a] = cplx(Rf[(size_t)a * p + 2 * k], Rf[(size_t)a * p + 2 * k + 1]);
+  const int maxcyc = c->opts.max_restarts > 0 ? c->opts.max_restarts : 100000;
+  std::vector<double> Hb;
+  double worst = 0.0;
+  for (int cyc = 0; cyc < maxcyc; ++cyc) {
+    int nact = 0;
+    for (int k = 0; k < g; ++k) nact += active[k];
+    if (nact == 0) break;
+    int mbe = 0;
+    rc = block_arnoldi(c, p, mb, ws, Hb, &mbe, st, false);
+    if (rc) return rc;
+    if (st) st->cycles_stationary += 1;
+    const int ldh = (mb + 1) * p;
+    const int K = mbe * p;
+    const int R = K + p;
+    std::vector<double> Yz((size_t)K * 2 * g, 0.0);  // row-major K x 2g
+    std::vector<std::vector<cplx>> res(g);
+    worst = 0.0;
+    for (int k = 0; k < g; ++k) {
+      if (!active[k]) continue;
+      std::vector<cplx> rhs(R, 0.0), y(K), r(R);
+      for (int a = 0; a < p; ++a) rhs[a] = gk[k][a];
+      kry::block_shift_lsq(K, p, 2 * p - 1, Hb.data(), ldh, cplx(0.0, om[k]), rhs.data(), y.data(), r.data());
+      for (int i = 0; i < K; ++i) {
+        Yz[(size_t)i * 2 * g + 2 * k] = y[i].real();
+        Yz[(size_t)i * 2 * g + 2 * k + 1] = y[i].imag();
+      }
+      double rn = 0.0;
+      for (auto& v : r) rn += std::norm(v);
+      rn = std::sqrt(rn) / bnorm[k];
+      worst = std::max(worst, rn);
+      res[k] = r;
+      if (rn <= tol) active[k] = 0;
+    }
+    rc = block_gemm(c, bslot(c, 0), K, Yz, 2 * g, zcol(c, 0), 1.0, 1);
+    if (rc) return rc;
+    nact = 0;
+    for (int k = 0; k < g; ++k) nact += active[k];
+    if (nact == 0) break;
+    if (cyc + 1 == maxcyc) {
+      *max_res = std::max(*max_res, worst);
+      return KRY_ENOCONV;
+    }
+    // next start block: orthonormal basis of the real and imaginary parts of
+    // the active residual coefficients, S = Q Rq on the host, V_0 = V_R Q
+    const int q = 2 * nact;
+    std::vector<double> Sm((size_t)R * q, 0.0);  // column-major R x q
+    std::vector<int> idx;
+    for (int k = 0; k < g; ++k) {
+      if (!active[k]) continue;
+      const int a = (int)idx.size();
+      idx.push_back(k);
+      for (int i = 0; i < R; ++i) {
+        Sm[i + (size_t)(2 * a) * R] = res[k][i].real();
+        Sm[i + (size_t)(2 * a + 1) * R] = res[k][i].imag();
+      }
+    }
+    std::vector<double> Q((size_t)R * q), Rq((size_t)q * q);
+    kry::qr_pivoted(R, q, Sm.data(), 1e-15, Q.data(), Rq.data());
+    std::vector<double> Qr((size_t)R * q);  // row-major for the product kernel
+    for (int i = 0; i < R; ++i)
+      for (int j = 0; j < q; ++j) Qr[(size_t)i * q + j] = Q[i + (size_t)j * R];
+    rc = block_gemm(c, bslot(c, 0), R, Qr, q, X, 1.0, 0);
+    if (rc) return rc;
+    KRY_HIP(hipMemcpyAsync(bslot(c, 0), X, (size_t)q * c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
+    p = q;
+    for (int a = 0; a < nact; ++a) {
+      const int k = idx[a];
+      gk[k].assign(p, 0.0);
+      for (int b = 0; b < p; ++b) gk[k][b] = cplx(Rq[(size_t)b * q + 2 * a], Rq[(size_t)b * q + 2 * a + 1]);
+    }
+  }
+  *max_res = std::max(*max_res, worst);
+  return KRY_OK;
+}
+
+// Transients for a group of g columns: X (slots at xs, g columns) holds
+// Im z_k; e^{-T A} X by restarts in time with block Arnoldi, left in X.
+// rate[k] is the residual rate of column k (its error budget / T).  The
+// first start block is orthonormalised on the device (Cholesky QR twice);
+// later ones are X = V_K U with U known on the host, so V_0 = V_K Q from a
+// host QR of U, exactly.
+int block_transient(kry_ctx* c, int xs, int g, double T, const std::vector<double>& rate,
+                    kry_stats* st, std::vector<double>& err) {
+  const int p = g;
+  const int mb = std::max(2, c->opts.krylov_dim / p);
+  const int ws = (mb + 1) * p;
+  int rc = ensure_block(c, std::max(ws + 2 * p, xs + g));
+  if (rc) return rc;
+  if (xs < ws + 2 * p) return fail(c, KRY_EINVAL, "block transient slot overlap");
+  void* X = bslot(c, xs);
+  err.assign(g, 0.0);
+  double t = 0.0, tau_try = T;
+  std::vector<double> Hb, R0, U, e;
+  int rank = 0;
+  rc = block_cholqr2(c, X, p, bslot(c, ws), bslot(c, 0), R0, &rank);
+  if (rc) return rc;
+  if (rank == 0) return KRY_OK;  // every transient is zero
+  const int maxsteps = c->opts.max_restarts > 0 ? c->opts.max_restarts : 100000;
+  int steps = 0;
+  while (true) {
+    if (steps >= maxsteps) return KRY_ENOCONV;
+    int mbe = 0;
+    rc = block_arnoldi(c, p, mb, ws, Hb, &mbe, st, true);
+    if (rc) return rc;
+    ++steps;
+    if (st) st->steps_transient += 1;
+    const int ldh = (mb + 1) * p;
+    const int K = mbe * p;
+    std::vector<double> U0((size_t)K * g, 0.0);  // column-major K x g
+    for (int a = 0; a < p; ++a)
+      for (int k = 0; k < g; ++k) U0[a + (size_t)k * K] = R0[(size_t)a * p + k];
+    const double tmax = T - t;
+    double tau = 0.0;
+    U.assign((size_t)K * g, 0.0);
+    e.assign(g, 0.0);
+    if (mbe < mb) {  // invariant block space: exact projected exponential
+      std::vector<double> Hm((size_t)K * K), E((size_t)K * K);
+      for (int j = 0; j < K; ++j)
+        for (int i = 0; i < K; ++i) Hm[i + (size_t)j * K] = -tmax * Hb[i + (size_t)j * ldh];
+      kry::expm(K, Hm.data(), E.data());
+      for (int k = 0; k < g; ++k)
+        for (int i = 0; i < K; ++i) {
+          double acc = 0.0;
+          for (int l = 0; l < K; ++l) acc += E[i + (size_t)l * K] * U0[l + (size_t)k * K];
+          U[i + (size_t)k * K] = acc;
+        }
+      tau = tmax;
+    } else {
+      double trial = std::min(tau_try, tmax);
+      for (int attempt = 0; attempt < 60 && tau == 0.0; ++attempt) {
+        tau = kry::choose_step_block(K, p, g, Hb.data(), ldh, U0.data(), trial, rate.data(), 16,
+                                     U.data(), e.data());
+        if (tau == 0.0) trial /= 16.0;
+      }
+      if (tau == 0.0) return fail(c, KRY_ENOCONV, "time step underflow in the block exponential");
+      tau_try = (tau >= trial * (1.0 - 1e-12)) ? 2.0 * trial : 1.25 * tau;
+      if (t + tau > T * (1.0 - 1e-15)) tau = tmax;
+    }
+    for (int k = 0; k < g; ++k) err[k] += e[k];
+    t += tau;
+    if (t >= T) {
+      // X = V_K U
+      std::vector<double> Ur((size_t)K * g);
+      for (int i = 0; i < K; ++i)
+        for (int k = 0; k < g; ++k) Ur[(size_t)i * g + k] = U[i + (size_t)k * K];
+      return block_gemm(c, bslot(c, 0), K, Ur, g, X, 1.0, 0);
+    }
+    // next start block from U = Q R0 (host), V_0 = V_K Q
+    std::vector<double> Q((size_t)K * g), Rq((size_t)g * g);
+    const int r = kry::qr_pivoted(K, g, U.data(), 1e-15, Q.data(), Rq.data());
+    if (r == 0) {  // the transients vanished exactly
+      KRY_HIP(hipMemsetAsync(X, 0, (size_t)g * c->ldv * c->esz, c->stream));
+      return KRY_OK;
+    }
+    std::vector<double> Qr((size_t)K * g);
+    for (int i = 0; i < K; ++i)
+      for (int k = 0; k < g; ++k) Qr[(size_t)i * g + k] = Q[i + (size_t)k * K];
+    rc = block_gemm(c, bslot(c, 0), K, Qr, g, X, 1.0, 0);
+    if (rc) return rc;
+    KRY_HIP(hipMemcpyAsync(bslot(c, 0), X, (size_t)g * c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
+    R0 = Rq;
+  }
+}
+
+// Batched solve: columns in groups of block_width/2 complex columns.
+int solve_blocked(kry_ctx* c, const double* omegas, int n_omega, int n_src, const double* b,
+                  int b_per_omega, double T, double* yT, kry_stats* st, double* max_res,
+                  double* max_err, double* t_trans) {
+  const int ncols = n_omega * n_src;
+  const int g = std::max(1, c->opts.block_width / 2);
+  const double tol = c->opts.tol;
+  int status = KRY_OK;
+  for (int c0 = 0; c0 < ncols; c0 += g) {
+    const int gg = std::min(g, ncols - c0);
+    std::vector<const double*> bc(gg);
+    std::vector<double> om(gg);
+    for (int k = 0; k < gg; ++k) {
+      const int col = c0 + k;
+      const int w = col / n_src, s = col % n_src;
+      bc[k] = b + (size_t)(b_per_omega ? col : s) * 2 * c->n;
+      om[k] = omegas[w];
+    }
+    std::vector<double> bnorm;
+    int rc = block_stationary(c, bc, om, 0.05 * tol, st, max_res, bnorm);
+    if (rc == KRY_ENOCONV) status = rc;
+    else if (rc) return rc;
+    const double t1 = now_ms();
+    // |Im(e^{iwT} z_k)|_M for the budgets
+    std::vector<double> Gz;
+    rc = block_gram_host(c, zcol(c, 0), 2 * gg, zcol(c, 0), 2 * gg, Gz);
+    if (rc) return rc;
+    std::vector<double> rate(gg), ynorm(gg);
+    for (int k = 0; k < gg; ++k) {
+      const double sn = std::sin(om[k] * T), cs = std::cos(om[k] * T);
+      const int P = 2 * gg;
+      const double rr = Gz[(size_t)(2 * k) * P + 2 * k], ii = Gz[(size_t)(2 * k + 1) * P + 2 * k + 1];
+      const double ri = Gz[(size_t)(2 * k) * P + 2 * k + 1];
+      ynorm[k] = std::sqrt(std::max(sn * sn * rr + cs * cs * ii + 2 * sn * cs * ri, 0.0));
+      rate[k] = 0.15 * tol * std::max(ynorm[k], 1e-300) / std::max(T, 1e-300);
+    }
+    // transient block: X = Im z_k, in slots after the transient workspace
+    const int mbt = std::max(2, c->opts.krylov_dim / gg);
+    const int xs = (mbt + 1) * gg + 2 * gg;
+    rc = ensure_block(c, xs + gg);
+    if (rc) return rc;
+    for (int k = 0; k < gg; ++k)
+      KRY_HIP(hipMemcpyAsync(bslot(c, xs + k), zcol(c, 2 * k + 1), c->ldv * c->esz,
+                             hipMemcpyDeviceToDevice, c->stream));
+    std::vector<double> err;
+    if (T > 0.0) {
+      rc = block_transient(c, xs, gg, T, rate, st, err);
+      if (rc == KRY_ENOCONV) status = rc;
+      else if (rc) return rc;
+    } else {
+      err.assign(gg, 0.0);
+    }
+    for (int k = 0; k < gg; ++k) {
+      const double sn = std::sin(om[k] * T), cs = std::cos(om[k] * T);
+      *max_err = std::max(*max_err, err[k] / std::max(ynorm[k], 1e-300));
+      KRY_HIP(kry::launch_assemble(c->st, zcol(c, 2 * k), zcol(c, 2 * k + 1), bslot(c, xs + k), sn, cs,
+                                   yT + (size_t)(c0 + k) * c->n, c->n, c->stream));
+    }
+    KRY_HIP(hipStreamSynchronize(c->stream));
+    *t_trans += now_ms() - t1;
+  }
+  return status;
+}
+
+}  // namespace
+
 extern "C" {
 
 int kry_stationary(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src, const double* b,
@@ -850,6 +1280,37 @@ int kry_stationary(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_
   treset(c);
   const double t0 = now_ms();
   double max_res = 0.0;
+  if (c->opts.block_width > 1) {
+    const int ncols = n_omega * n_src;
+    const int g = std::max(1, c->opts.block_width / 2);
+    int status = KRY_OK;
+    rc = ensure_basis(c, c->opts.krylov_dim);
+    if (rc) return rc;
+    for (int c0 = 0; c0 < ncols; c0 += g) {
+      const int gg = std::min(g, ncols - c0);
+      std::vector<const double*> bc(gg);
+      std::vector<double> om(gg), bn;
+      for (int k = 0; k < gg; ++k) {
+        const int col = c0 + k;
+        bc[k] = b + (size_t)(b_per_omega ? col : col % n_src) * 2 * c->n;
+        om[k] = omegas[col / n_src];
+      }
+      rc = block_stationary(c, bc, om, c->opts.tol, st, &max_res, bn);
+      if (rc == KRY_ENOCONV) status = rc;
+      else if (rc) return rc;
+      for (int k = 0; k < gg; ++k)
+        KRY_HIP(kry::launch_store_complex(c->st, zcol(c, 2 * k), zcol(c, 2 * k + 1),
+                                          z + (size_t)(c0 + k) * 2 * c->n, c->n, c->stream));
+    }
+    KRY_HIP(hipStreamSynchronize(c->stream));
+    if (st) {
+      st->max_residual = max_res;
+      st->ms_stationary = st->ms_total = now_ms() - t0;
+      st->converged = status == KRY_OK;
+      texport(c, st);
+    }
+    return status;
+  }
   rc = for_each_group(c, omegas, n_omega, n_src, b, b_per_omega, c->opts.tol, st, &max_res,
                       [&](int col, double, int zk, double) -> int {
                         KRY_HIP(kry::launch_store_complex(c->st, zcol(c, 2 * zk), zcol(c, 2 * zk + 1),
@@ -881,6 +1342,24 @@ int kry_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
   // error budget (relative to |y(T)|_M): shifted residual 0.05 tol,
   // transient steps 0.15 tol, dropped remainder 0.15 tol
   const double tol = c->opts.tol;
+  if (c->opts.block_width > 1) {
+    rc = ensure_basis(c, c->opts.krylov_dim);
+    if (rc) return rc;
+    rc = solve_blocked(c, omegas, n_omega, n_src, b, b_per_omega, T, yT, st, &max_res, &max_err,
+                       &t_trans);
+    if (rc && rc != KRY_ENOCONV) return rc;
+    KRY_HIP(hipStreamSynchronize(c->stream));
+    if (st) {
+      st->max_residual = max_res;
+      st->max_err_estimate = max_err;
+      st->ms_total = now_ms() - t0;
+      st->ms_transient = t_trans;
+      st->ms_stationary = st->ms_total - t_trans;
+      st->converged = rc == KRY_OK;
+      texport(c, st);
+    }
+    return rc;
+  }
   rc = for_each_group(
       c, omegas, n_omega, n_src, b, b_per_omega, 0.05 * tol, st, &max_res,
       [&](int col, double w, int zk, double bnorm) -> int {
@@ -1018,6 +1497,35 @@ int kry_grad(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
     texport(c, st);
   }
   return status;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int kry_block_arnoldi(kry_ctx* c, const double* V0, int32_t p, int32_t mb, void* V_out,
+                      double* H_out) {
+  if (!c || !V0 || !V_out || !H_out) return fail(c, KRY_EINVAL, "null argument");
+  if (p < 1 || p > 128 || mb < 1 || (mb + 1) * p > 4096) return fail(c, KRY_EINVAL, "invalid p or mb");
+  const int ws = (mb + 1) * p;
+  int rc = ensure_block(c, ws + 3 * p);
+  if (rc) return rc;
+  void* X = bslot(c, ws + 2 * p);
+  for (int k = 0; k < p; ++k)
+    KRY_HIP(kry::launch_load_real(c->st, V0 + (size_t)k * c->n, bslot(c, ws + 2 * p + k), c->n, c->stream));
+  std::vector<double> Rf, Hb;
+  int rank = 0;
+  rc = block_cholqr2(c, X, p, bslot(c, ws + p), bslot(c, 0), Rf, &rank);
+  if (rc) return rc;
+  int mbe = 0;
+  rc = block_arnoldi(c, p, mb, ws, Hb, &mbe, nullptr, false);
+  if (rc) return rc;
+  std::memcpy(H_out, Hb.data(), sizeof(double) * Hb.size());
+  for (int j = 0; j < (mb + 1) * p; ++j)
+    KRY_HIP(hipMemcpyAsync((char*)V_out + (size_t)j * c->n * c->esz, bslot(c, j), c->n * c->esz,
+                           hipMemcpyDeviceToDevice, c->stream));
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  return mbe;
 }
 
 }  // extern "C"

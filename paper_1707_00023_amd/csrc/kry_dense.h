@@ -41,4 +41,39 @@ void best_real_direction(int n, const cplx* q, double* w);
 double choose_step(int m, const double* H, int ldh, double hnext, double beta,
                    double tau_try, double rate, int K, double* u, double* err_out);
 
+// Rank-revealing Cholesky QR factor of a block W with Gram matrix
+// G = W^T M W (p x p, symmetric).  Columns are first scaled to unit
+// norm; diagonal pivoting; a direction whose remaining norm is below thr
+// relative to
+// its own column is dropped (rank r <= p).  The threshold is clamped below
+// at 1e-10.  Outputs (p x p, row-major):
+//   Cm: V = W Cm has M-orthonormal columns 0..r-1 and zero columns r..p-1,
+//   Rf: W ~= V Rf (rows r..p-1 zero), exact for the kept directions.
+// Returns r.
+int cholqr_factor(int p, const double* G, double thr, double* Cm, double* Rf);
+
+// Householder QR with column pivoting of a real m x q matrix S (column-
+// major): S ~= Q Rf with Q (m x q column-major; columns r.. zero) having
+// orthonormal columns and Rf (q x q row-major; rows r.. zero), rank r set
+// by |R_kk| > thr * (largest column norm).  Returns r.
+int qr_pivoted(int m, int q, const double* S, double thr, double* Q, double* Rf);
+
+// Least squares for one column of a block shifted system:
+// y = argmin | g - (Hbar + s Ibar) y |_2 with Hbar (K + q) x K real,
+// column-major with leading dimension ldh, zero below row k + bw of column
+// k; Ibar = [I_K; 0].  Banded complex Householder QR.  res receives
+// g - (Hbar + s Ibar) y (length K + q).  Directions with a vanishing
+// diagonal of R (zero basis columns) get y = 0.
+void block_shift_lsq(int K, int q, int bw, const double* H, int ldh, cplx s, const cplx* g, cplx* y,
+                     cplx* res);
+
+// Block step control for U(s) = e^{-s H} U0 (H K x K column-major, ldh;
+// U0 K x g column-major): the residual of column c is
+// |B U(s)[K-q:K, c]|_2 with B = Hbar[K:K+q, K-q:K] (Lemma 1 for a block).
+// Finds the largest of Ks equispaced candidates in (0, tau_try] with every
+// column's residual below rate[c] up to it; writes U(tau) into U (K x g)
+// and the per-column error bounds into err.  Returns tau or 0.
+double choose_step_block(int K, int q, int g, const double* H, int ldh, const double* U0,
+                         double tau_try, const double* rate, int Ks, double* U, double* err);
+
 }  // namespace kry

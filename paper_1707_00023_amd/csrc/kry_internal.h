@@ -101,6 +101,22 @@ hipError_t launch_store_complex(Storage st, const void* re, const void* im, doub
 hipError_t launch_assemble(Storage st, const void* re, const void* im, const void* yhat,
                            double sn, double cs, double* out, long long n, hipStream_t s);
 
+// w_c = A v_c for ncols columns at stride ld (columns of a block).
+hipError_t launch_stencil_cols(Storage st, const void* v, void* w, long long ld, int ncols,
+                               const DevGrid& g, const DevMats& m, hipStream_t s);
+
+// Block kernels on FP64 matrix cores (kry_block.hip).
+// partials[split][M x N] = X[:, :M]^T diag(w) Y[:, :N] over element splits.
+int gram_splits(long long n, int M, int N);
+hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, long long ld,
+                       const double* w, long long n, double* partials, int nsplit, hipStream_t s);
+// Out[:, :N] = (accumulate ? Out : 0) + alpha X[:, :M] C (C row-major M x N).
+hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int N, void* Out,
+                          long long ld, long long n, double alpha, int accumulate, hipStream_t s);
+// Energy weight of every entry (mu on H planes, eps on E planes).
+hipError_t launch_weights(const double* eps, const double* mu, double* w, long long N3,
+                          hipStream_t s);
+
 // Flux of z = zre + i zim through plane kf (per-block partials, *nblocks
 // of them) and, if rhs != nullptr, the adjoint right-hand side P M^-1 dP/dz
 // written into the complex interleaved rhs (zero elsewhere beforehand).

@@ -149,6 +149,10 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const T* __restrict__ v, T* 
                                                     DevGrid g, DevMats mt,
                                                     double* __restrict__ partials) {
   const long long N3 = g.N3;
+  if (!DOTS) {  // grid.y indexes columns at stride ldv
+    v += (long long)blockIdx.y * ldv;
+    w += (long long)blockIdx.y * ldv;
+  }
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   double wm[CPT][6];  // weight * output, for the dots
   long long cellq[CPT];
@@ -779,6 +783,31 @@ static hipError_t stencil_t(const void* v, void* w, const void* V, long long ldv
   }
 #undef KRY_STENCIL
   return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t stencil_cols_t(const void* v, void* w, long long ld, int ncols, const DevGrid& g,
+                                 const DevMats& m, hipStream_t s) {
+  const int cpt = cells_per_thread(g.N3);
+  const dim3 grid(cell_blocks(g.N3), ncols), blk(kBlock);
+  const T* vv = (const T*)v;
+  T* ww = (T*)w;
+  const bool mu = m.inv_mu != nullptr;
+  if (cpt == 4) {
+    if (mu) hipLaunchKernelGGL((k_stencil<T, true, 4, false>), grid, blk, 0, s, vv, ww, nullptr, ld, 0, g, m, nullptr);
+    else hipLaunchKernelGGL((k_stencil<T, false, 4, false>), grid, blk, 0, s, vv, ww, nullptr, ld, 0, g, m, nullptr);
+  } else {
+    if (mu) hipLaunchKernelGGL((k_stencil<T, true, 1, false>), grid, blk, 0, s, vv, ww, nullptr, ld, 0, g, m, nullptr);
+    else hipLaunchKernelGGL((k_stencil<T, false, 1, false>), grid, blk, 0, s, vv, ww, nullptr, ld, 0, g, m, nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stencil_cols(Storage st, const void* v, void* w, long long ld, int ncols,
+                               const DevGrid& g, const DevMats& m, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  return st == F64 ? stencil_cols_t<double>(v, w, ld, ncols, g, m, s)
+                   : stencil_cols_t<float>(v, w, ld, ncols, g, m, s);
 }
 
 hipError_t launch_stencil(Storage st, const void* v, void* w, const void* V, long long ldv, int cnt,

@@ -8,6 +8,7 @@ route (one exponential action of the augmented matrix), which needs no
 shifted solve and does not use Corollary 3.
 
     python tests/golden/make_golden.py c2        # ~1 h on one CPU core
+    python tests/golden/make_golden.py c3        # 4 of the 256 columns
 """
 from __future__ import annotations
 
@@ -28,6 +29,8 @@ from oracle import solve as osv  # noqa: E402
 N_SAMPLES = 4096
 N_PROJ = 4
 SAMPLE_SEED = 20170630
+# columns (omega index, theta index) evaluated for the batched workload
+SUBSETS = {"c3": [(0, 0), (15, 3), (31, 7), (16, 5)]}
 
 
 def sample_spec(n):
@@ -48,8 +51,11 @@ def main(cfg_name: str):
            "route": "augmented-matrix exponential action (expm_multiply)"}
     idx = sample_spec(wl.n)
     out["indices"] = idx.tolist()
-    for wi, omega in enumerate(wl.omegas):
-        for ti, theta in enumerate(inp.thetas):
+    cols = SUBSETS.get(cfg_name, [(wi, ti) for wi in range(len(wl.omegas))
+                                   for ti in range(len(inp.thetas))])
+    for wi, ti in cols:
+        omega, theta = wl.omegas[wi], float(inp.thetas[ti])
+        if True:
             b = wk.source_vector(wl, omega, float(theta))
             t0 = time.time()
             y = osv.augmented_solution(A, b, omega, wl.T)

@@ -3,29 +3,53 @@
 
 #include "../../paper_1707_00023_amd/csrc/kry_dense.h"
 
+using kry::cplx;
+
 extern "C" {
+
 void t_expm(int m, const double* A, double* E) { kry::expm(m, A, E); }
+
 int t_hess_solve(int N, const double* Mri, const double* rhs_ri, double* y_ri) {
-  return kry::hess_solve(N, reinterpret_cast<const kry::cplx*>(Mri),
-                         reinterpret_cast<const kry::cplx*>(rhs_ri),
-                         reinterpret_cast<kry::cplx*>(y_ri));
+  return kry::hess_solve(N, reinterpret_cast<const cplx*>(Mri), reinterpret_cast<const cplx*>(rhs_ri),
+                         reinterpret_cast<cplx*>(y_ri));
 }
+
 int t_dense_solve(int N, const double* Ari, const double* rhs_ri, double* y_ri) {
-  return kry::dense_solve(N, reinterpret_cast<const kry::cplx*>(Ari),
-                          reinterpret_cast<const kry::cplx*>(rhs_ri),
-                          reinterpret_cast<kry::cplx*>(y_ri));
+  return kry::dense_solve(N, reinterpret_cast<const cplx*>(Ari), reinterpret_cast<const cplx*>(rhs_ri),
+                          reinterpret_cast<cplx*>(y_ri));
 }
-int t_hess_shift_solve(int m, const double* H, int ldh, double sr, double si,
-                       const double* rhs_ri, double* y_ri) {
-  return kry::hess_shift_solve(m, H, ldh, kry::cplx(sr, si),
-                               reinterpret_cast<const kry::cplx*>(rhs_ri),
-                               reinterpret_cast<kry::cplx*>(y_ri));
+
+int t_hess_shift_solve(int m, const double* H, int ldh, double sr, double si, const double* rhs_ri,
+                       double* y_ri) {
+  return kry::hess_shift_solve(m, H, ldh, cplx(sr, si), reinterpret_cast<const cplx*>(rhs_ri),
+                               reinterpret_cast<cplx*>(y_ri));
 }
+
 void t_best_real_direction(int n, const double* q_ri, double* w) {
-  kry::best_real_direction(n, reinterpret_cast<const kry::cplx*>(q_ri), w);
+  kry::best_real_direction(n, reinterpret_cast<const cplx*>(q_ri), w);
 }
+
 double t_choose_step(int m, const double* H, int ldh, double hnext, double beta, double tau_try,
                      double rate, int K, double* u, double* err) {
   return kry::choose_step(m, H, ldh, hnext, beta, tau_try, rate, K, u, err);
+}
+
+int t_cholqr_factor(int p, const double* G, double thr, double* Cm, double* Rf) {
+  return kry::cholqr_factor(p, G, thr, Cm, Rf);
+}
+
+void t_block_shift_lsq(int K, int q, int bw, const double* H, int ldh, double sr, double si,
+                       const double* g_ri, double* y_ri, double* res_ri) {
+  kry::block_shift_lsq(K, q, bw, H, ldh, cplx(sr, si), reinterpret_cast<const cplx*>(g_ri),
+                       reinterpret_cast<cplx*>(y_ri), reinterpret_cast<cplx*>(res_ri));
+}
+
+int t_qr_pivoted(int m, int q, const double* S, double thr, double* Q, double* Rf) {
+  return kry::qr_pivoted(m, q, S, thr, Q, Rf);
+}
+
+double t_choose_step_block(int K, int q, int g, const double* H, int ldh, const double* U0,
+                           double tau_try, const double* rate, int Ks, double* U, double* err) {
+  return kry::choose_step_block(K, q, g, H, ldh, U0, tau_try, rate, Ks, U, err);
 }
 }

@@ -424,3 +424,83 @@ def test_grad_c4_full_size_against_frozen_path_differences():
         _announce(f"c4 fd h={h:g}: rel err {errs[h]:.3e}, worst cell {per_cell.max():.3e}")
     assert errs[1e-5] <= 1e-5
     assert errs[1e-6] <= 5e-5
+
+
+# -------------------------------------------------------------- block form --
+
+@pytest.mark.parametrize("shape,p,mb", [((12, 12, 12), 4, 6), ((11, 9, 13), 20, 3),
+                                        ((16, 16, 16), 32, 2)])
+def test_block_arnoldi_relation_and_orthogonality(shape, p, mb):
+    _announce(f"block arnoldi {shape} p={p} mb={mb}")
+    eps, mu, sig = _box(shape, 12)
+    s = _solver(eps, mu, sig, krylov_dim=30)
+    n = 6 * eps.size
+    V0 = np.random.default_rng(4).standard_normal((p, n))
+    V, H, steps = s.block_arnoldi(_t(V0), mb)
+    assert steps == mb
+    V = V.cpu().numpy().T                     # n x (mb+1) p
+    w = op.material_weights(eps, mu)
+    G = V.T @ (w[:, None] * V)
+    assert np.abs(G - np.eye((mb + 1) * p)).max() <= 1e-12
+    AV = np.stack([op.apply_A(eps, mu, sig, V[:, j]) for j in range(mb * p)], axis=1)
+    assert np.abs(AV - V @ H).max() <= 1e-12 * np.abs(AV).max()
+    for j in range(mb):                       # block upper Hessenberg
+        assert np.abs(H[(j + 2) * p:, j * p:(j + 1) * p]).max(initial=0.0) == 0.0
+    # the first block spans the start block
+    P0 = V[:, :p] @ (V[:, :p].T @ (w[:, None] * V0.T))
+    assert np.abs(P0 - V0.T).max() <= 1e-12 * np.abs(V0).max()
+
+
+def test_block_arnoldi_deficient_start_block():
+    _announce("block arnoldi deficient")
+    eps, mu, sig = _box((8, 8, 8), 13, with_mu=False)
+    s = _solver(eps, None, sig, krylov_dim=30)
+    n = 6 * eps.size
+    rng = np.random.default_rng(5)
+    V0 = rng.standard_normal((4, n))
+    V0[2] = 2.0 * V0[0] - V0[1]
+    V, H, steps = s.block_arnoldi(_t(V0), 4)
+    V = V.cpu().numpy().T
+    w = op.material_weights(eps, np.ones_like(eps))
+    G = V.T @ (w[:, None] * V)
+    d = np.diag(G)
+    zero = d < 0.5
+    # the dependence is either dropped (zero column) or kept as an extra
+    # orthonormal direction; the nonzero columns stay orthonormal either way
+    assert np.abs(G[~zero][:, ~zero] - np.eye((~zero).sum())).max() <= 1e-12
+    AV = np.stack([op.apply_A(eps, np.ones_like(eps), sig, V[:, j]) for j in range(4 * 4)], axis=1)
+    assert np.abs(AV - V @ H).max() <= 1e-12 * np.abs(AV).max()
+    P0 = V[:, :4] @ (V[:, :4].T @ (w[:, None] * V0.T))
+    assert np.abs(P0 - V0.T).max() <= 1e-10 * np.abs(V0).max()
+
+
+def test_block_stationary_per_column_shifts():
+    _announce("block stationary")
+    wl = wk.small(8, seed=14, n_spheres=4, layer=2)
+    inp = wk.generate(wl)
+    om = [2 * math.pi * 0.08, 2 * math.pi * 0.1, 2 * math.pi * 0.12]
+    th = [0.1, 0.3, 0.45]
+    B = np.stack([wk.source_vector(wl, w, t) for w, t in zip(om, th)])
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=48, tol=1e-11, block_width=6)
+    z = s.stationary(om, _t(B), b_per_omega=True).cpu().numpy()
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    for k, w in enumerate(om):
+        assert _rel(z[k], osv.stationary(A, B[k], w)) <= 1e-9
+
+
+@pytest.mark.parametrize("bw", [4, 8])
+def test_block_solve_matches_oracle(bw):
+    _announce(f"block solve bw={bw}")
+    wl = wk.small(9, seed=15, n_spheres=5, layer=2, T=50.0)
+    inp = wk.generate(wl)
+    om = [2 * math.pi * 0.09, 2 * math.pi * 0.11]
+    th = [0.2, 0.4]
+    cols = [(w, t) for w in om for t in th]
+    B = np.stack([wk.source_vector(wl, w, t) for (w, t) in cols])
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=48, tol=1e-9, block_width=bw)
+    y = s.solve_multifreq(om, _t(B), wl.T, b_per_omega=True).cpu().numpy()
+    assert s.last_stats["converged"] == 1
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    for c, (w, t) in enumerate(cols):
+        ref = osv.augmented_solution(A, B[c], w, wl.T)
+        assert _rel(y[c], ref) <= 1e-8

@@ -19,6 +19,7 @@ def lib(tmp_path_factory):
                    check=True)
     L = ctypes.CDLL(str(out))
     L.t_choose_step.restype = ctypes.c_double
+    L.t_choose_step_block.restype = ctypes.c_double
     return L
 
 
@@ -114,3 +115,95 @@ def test_choose_step_respects_residual_rate(lib):
     ts = np.linspace(0, tau, 200)
     rho = [abs(hnext * (beta * sla.expm(-t * H)[:, 0])[-1]) for t in ts]
     assert max(rho) <= 1.05 * rate
+
+
+def test_cholqr_factor_full_rank_and_deficient(lib):
+    rng = np.random.default_rng(8)
+    n, p = 200, 9
+    w = 1 + rng.random(n)
+    W = rng.standard_normal((n, p))
+    W[:, 4] = W[:, 1] - 2 * W[:, 7]          # exact dependence -> rank 8
+    W[:, 2] *= 1e-4                           # small but independent: kept
+    G = W.T @ (w[:, None] * W)
+    Cm = np.zeros((p, p))
+    Rf = np.zeros((p, p))
+    # a Gram-based factorisation resolves directions only to ~sqrt(eps): the
+    # exact dependence is detected with a 1e-6 threshold
+    r = lib.t_cholqr_factor(p, P(np.ascontiguousarray(G)), ctypes.c_double(1e-6), P(Cm), P(Rf))
+    assert r == 8
+    V = W @ Cm
+    Gv = V.T @ (w[:, None] * V)
+    expect = np.zeros((p, p))
+    expect[:r, :r] = np.eye(r)
+    assert np.abs(Gv - expect).max() < 1e-9
+    assert np.abs(V @ Rf - W).max() < 1e-6 * np.abs(W).max()
+    assert np.abs((V @ Rf - W)[:, 2]).max() < 1e-9 * np.abs(W[:, 2]).max()
+    assert np.all(Rf[r:] == 0)
+
+
+def test_block_shift_lsq_matches_numpy(lib):
+    rng = np.random.default_rng(9)
+    q, m = 4, 5
+    K = q * m
+    Hb = np.zeros((K + q, K))
+    for j in range(m):
+        Hb[: (j + 2) * q, j * q:(j + 1) * q] = rng.standard_normal(((j + 2) * q, q))
+    bw = 2 * q - 1
+    s = 0.37j
+    g = np.zeros(K + q, np.complex128)
+    g[:q] = rng.standard_normal(q) + 1j * rng.standard_normal(q)
+    y = np.zeros(K, np.complex128)
+    res = np.zeros(K + q, np.complex128)
+    lib.t_block_shift_lsq(K, q, bw, P(np.asfortranarray(Hb)), K + q, ctypes.c_double(s.real),
+                          ctypes.c_double(s.imag), P(g), P(y), P(res))
+    Ms = Hb.astype(np.complex128)
+    Ms[:K] += s * np.eye(K)
+    yref = np.linalg.lstsq(Ms, g, rcond=None)[0]
+    assert np.abs(y - yref).max() <= 1e-10 * np.abs(yref).max()
+    assert np.abs(res - (g - Ms @ y)).max() <= 1e-12 * np.abs(g).max()
+
+
+def test_choose_step_block_bounds_every_column(lib):
+    rng = np.random.default_rng(10)
+    q, m, g = 3, 4, 3
+    K = q * m
+    S = rng.standard_normal((K, K))
+    H = 0.5 * (S - S.T) + 0.05 * np.eye(K)
+    Hb = np.zeros((K + q, K))
+    Hb[:K] = H
+    Hb[K:, K - q:] = 0.4 * rng.standard_normal((q, q))
+    U0 = np.zeros((K, g))
+    U0[:q] = rng.standard_normal((q, g))
+    rate = np.array([1e-5, 2e-5, 5e-6])
+    U = np.zeros((K, g), order="F")
+    err = np.zeros(g)
+    tau, trial = 0.0, 3.0
+    for _ in range(20):
+        if tau > 0.0:
+            break
+        tau = lib.t_choose_step_block(K, q, g, P(np.asfortranarray(Hb)), K + q,
+                                      P(np.asfortranarray(U0)), ctypes.c_double(trial), P(rate),
+                                      16, P(U), P(err))
+        trial /= 16
+    assert tau < 3.0
+    assert 0 < tau <= 3.0
+    ref = sla.expm(-tau * H) @ U0
+    assert np.abs(U - ref).max() <= 1e-12 * np.abs(U0).max()
+    for t in np.linspace(0, tau, 100):
+        Ut = sla.expm(-t * H) @ U0
+        rho = np.linalg.norm(Hb[K:, K - q:] @ Ut[K - q:], axis=0)
+        assert np.all(rho <= 1.05 * rate)
+
+
+def test_qr_pivoted_resolves_to_rounding(lib):
+    rng = np.random.default_rng(11)
+    m, q = 60, 7
+    S = rng.standard_normal((m, q))
+    S[:, 3] = S[:, 0] + 1e-11 * rng.standard_normal(m)   # independent at 1e-11
+    S[:, 5] = 2 * S[:, 1] - S[:, 4]                       # exactly dependent
+    Q = np.zeros((m, q), order="F")
+    Rf = np.zeros((q, q))
+    r = lib.t_qr_pivoted(m, q, P(np.asfortranarray(S)), ctypes.c_double(1e-14), P(Q), P(Rf))
+    assert r == 6
+    assert np.abs(Q[:, :r].T @ Q[:, :r] - np.eye(r)).max() < 1e-14
+    assert np.abs(Q @ Rf - S).max() < 1e-13 * np.abs(S).max()
