@@ -57,6 +57,49 @@ def cpu_baseline(wl, inp):
                        f"extrapolated linearly to T={wl.T:g} and all {len(wl.omegas)} omega")}
 
 
+def compare_batched(args, wl, inp, dev):
+    """Batched (block) vs plain solves of the same columns, same tolerance."""
+    import numpy as np
+    import torch
+
+    import paper_1707_00023_amd as kry
+    import workloads as wk
+
+    eps = torch.as_tensor(inp.eps, device=dev)
+    sig = torch.as_tensor(inp.sigma, device=dev)
+    om = [wl.omegas[args.omega_index]]
+    th = inp.thetas[: args.columns]
+    B = torch.as_tensor(np.stack([wk.source_vector(wl, om[0], float(t)) for t in th]), device=dev)
+    out = {"metric": "batched vs plain time to solution (same columns, same tol)",
+           "workload": wl.name, "columns": len(th), "omega": om[0], "T": wl.T, "tol": wl.tol}
+    ys = {}
+    for name, bw in (("plain", 0), ("batched", args.block_width)):
+        s = kry.Solver(eps, None, sig, kry.Options(krylov_dim=wl.krylov_dim, tol=wl.tol,
+                                                   block_width=bw, block_steps=args.block_steps,
+                                                   timing=True))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y = s.solve_multifreq(om, B, wl.T)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = s.last_stats
+        ys[name] = y.cpu().numpy()
+        out[name] = {"s": dt, "s_per_column": dt / len(th),
+                     "stationary_s": st["ms_stationary"] / 1e3, "transient_s": st["ms_transient"] / 1e3,
+                     "matvecs_stationary": st["matvecs_stationary"],
+                     "matvecs_transient": st["matvecs_transient"],
+                     "kernels": {k: {"ms": st["kernel_ms"][i],
+                                     "gbs": (st["kernel_bytes"][i] / (st["kernel_ms"][i] * 1e6)
+                                             if st["kernel_ms"][i] > 0 else 0.0)}
+                                 for i, k in enumerate(kry.KERNEL_CLASSES)}}
+        print(f"[bench] {name}: {dt:.1f} s", file=sys.stderr, flush=True)
+        s.close()
+    d = np.linalg.norm(ys["batched"] - ys["plain"], axis=1) / np.linalg.norm(ys["plain"], axis=1)
+    out["max_rel_diff_batched_vs_plain"] = float(d.max())
+    out["speedup"] = out["plain"]["s"] / out["batched"]["s"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +107,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare-batched", action="store_true",
+                    help="batched workload only: time the block (batched) solve of a "
+                         "column subset against plain one-column-at-a-time solves")
+    ap.add_argument("--columns", type=int, default=8,
+                    help="with --compare-batched: columns (one omega, all angles)")
+    ap.add_argument("--omega-index", type=int, default=15)
+    ap.add_argument("--block-width", type=int, default=16)
+    ap.add_argument("--block-steps", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this solver has no multi-GPU path "
@@ -80,6 +131,9 @@ def main():
     wl = wk.CONFIGS[args.workload]
     inp = wk.generate(wl)
     dev = torch.device("cuda:0")
+    if args.compare_batched:
+        compare_batched(args, wl, inp, dev)
+        return
     eps = torch.as_tensor(inp.eps, device=dev)
     sig = torch.as_tensor(inp.sigma, device=dev)
     solver = kry.Solver(eps, None, sig, kry.Options(storage=wl.storage, krylov_dim=wl.krylov_dim,

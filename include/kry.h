@@ -75,6 +75,12 @@ typedef struct {
   int32_t timing;       /* 1: time every launch of the main kernel classes
                            with HIP events on the stream (adds a little
                            overhead); results in kry_stats.kernel_*        */
+  int32_t block_steps;  /* batched form: block Arnoldi steps per restart of
+                           the shifted solves (0: max(2, krylov_dim / p)) */
+  int32_t block_steps_transient; /* batched form: 0 = transients one
+                           column at a time (single-vector exponential);
+                           k > 0 = block exponential, k block steps per
+                           restart in time                                */
   int32_t orth;         /* Gram-Schmidt: 0 = classical twice with the second
                            projection delayed by one step (two basis sweeps
                            per step, default); 1 = classical twice, both

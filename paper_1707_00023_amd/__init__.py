@@ -39,7 +39,8 @@ class KryOpts(ctypes.Structure):
                 ("max_restarts", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("block_width", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("inner_product", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("timing", ctypes.c_int32), ("orth", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("block_steps", ctypes.c_int32),
+                ("block_steps_transient", ctypes.c_int32), ("orth", ctypes.c_int32)]
 
 
 class KryStats(ctypes.Structure):
@@ -125,6 +126,8 @@ class Options:
     timing: bool = False
     orth: str = "delayed"       # "delayed" (two basis sweeps per step) or "cgs2"
     block_width: int = 0        # > 1: batched form, groups of block_width/2 columns
+    block_steps: int = 0        # batched shifted solves: block steps per restart (0 auto)
+    block_steps_transient: int = 0  # batched exponential: block steps per restart (0 auto)
 
 
 class Solver:
@@ -154,7 +157,8 @@ class Solver:
         self.opts = KryOpts(1 if opts.storage == "f32" else 0, opts.krylov_dim,
                             opts.max_restarts, opts.tol, opts.block_width, 0, 0,
                             _stream_ptr().value,
-                            int(bool(opts.timing)), 1 if opts.orth == "cgs2" else 0)
+                            int(bool(opts.timing)), opts.block_steps,
+                            opts.block_steps_transient, 1 if opts.orth == "cgs2" else 0)
         self.storage = opts.storage
         ctx = ctypes.c_void_p()
         rc = lib.kry_create(ctypes.byref(self.grid), _ptr(e),

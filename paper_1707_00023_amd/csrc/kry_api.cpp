@@ -592,6 +592,9 @@ int kry_create(const kry_grid* grid, const double* eps, const double* mu, const 
   if (opts->orth != 0 && opts->orth != 1) return fail(nullptr, KRY_EINVAL, "invalid orth");
   if (opts->block_width < 0 || opts->block_width > 256)
     return fail(nullptr, KRY_EINVAL, "block_width out of range");
+  if (opts->block_steps < 0 || opts->block_steps > 512 || opts->block_steps_transient < 0 ||
+      opts->block_steps_transient > 512)
+    return fail(nullptr, KRY_EINVAL, "block steps out of range");
   std::vector<double> he(N3), hm, hs(N3, 0.0);
   if (hipMemcpy(he.data(), eps, sizeof(double) * N3, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(nullptr, KRY_EINVAL, "eps is not a readable device array");
@@ -1007,7 +1010,7 @@ int block_stationary(kry_ctx* c, const std::vector<const double*>& bcols, const 
                      double tol, kry_stats* st, double* max_res, std::vector<double>& bnorm) {
   const int g = (int)bcols.size();
   const int pmax = 2 * g;
-  const int mb = std::max(2, c->opts.krylov_dim / pmax);
+  const int mb = c->opts.block_steps > 0 ? c->opts.block_steps : std::max(2, c->opts.krylov_dim / pmax);
   const int ws = (mb + 1) * pmax;  // work slots: W, T2, start block
   int rc = ensure_block(c, ws + 3 * pmax);
   if (rc) return rc;
@@ -1114,6 +1117,12 @@ int block_stationary(kry_ctx* c, const std::vector<const double*>& bcols, const 
   return KRY_OK;
 }
 
+int transient_steps(kry_ctx* c) {
+  return c->opts.block_steps_transient > 0 ? c->opts.block_steps_transient : 32;
+}
+
+int expv_slot0(kry_ctx* c, double T, double abstol, double drop, kry_stats* st, double* err_est);
+
 // Transients for a group of g columns: X (slots at xs, g columns) holds
 // Im z_k; e^{-T A} X by restarts in time with block Arnoldi, left in X.
 // rate[k] is the residual rate of column k (its error budget / T).  The
@@ -1123,7 +1132,7 @@ int block_stationary(kry_ctx* c, const std::vector<const double*>& bcols, const 
 int block_transient(kry_ctx* c, int xs, int g, double T, const std::vector<double>& rate,
                     kry_stats* st, std::vector<double>& err) {
   const int p = g;
-  const int mb = std::max(2, c->opts.krylov_dim / p);
+  const int mb = transient_steps(c);
   const int ws = (mb + 1) * p;
   int rc = ensure_block(c, std::max(ws + 2 * p, xs + g));
   if (rc) return rc;
@@ -1239,27 +1248,47 @@ int solve_blocked(kry_ctx* c, const double* omegas, int n_omega, int n_src, cons
       ynorm[k] = std::sqrt(std::max(sn * sn * rr + cs * cs * ii + 2 * sn * cs * ri, 0.0));
       rate[k] = 0.15 * tol * std::max(ynorm[k], 1e-300) / std::max(T, 1e-300);
     }
-    // transient block: X = Im z_k, in slots after the transient workspace
-    const int mbt = std::max(2, c->opts.krylov_dim / gg);
-    const int xs = (mbt + 1) * gg + 2 * gg;
-    rc = ensure_block(c, xs + gg);
-    if (rc) return rc;
-    for (int k = 0; k < gg; ++k)
-      KRY_HIP(hipMemcpyAsync(bslot(c, xs + k), zcol(c, 2 * k + 1), c->ldv * c->esz,
-                             hipMemcpyDeviceToDevice, c->stream));
-    std::vector<double> err;
-    if (T > 0.0) {
-      rc = block_transient(c, xs, gg, T, rate, st, err);
-      if (rc == KRY_ENOCONV) status = rc;
-      else if (rc) return rc;
+    if (c->opts.block_steps_transient <= 0) {
+      // transients one column at a time with the single-vector exponential
+      // (a long basis lets it take far larger time steps than a short block)
+      for (int k = 0; k < gg; ++k) {
+        const double sn = std::sin(om[k] * T), cs = std::cos(om[k] * T);
+        KRY_HIP(hipMemcpyAsync(slot(c, 0), zcol(c, 2 * k + 1), c->ldv * c->esz,
+                               hipMemcpyDeviceToDevice, c->stream));
+        double err = 0.0;
+        if (T > 0.0) {
+          const double sc = std::max(ynorm[k], 1e-300);
+          rc = expv_slot0(c, T, 0.15 * tol * sc, 0.15 * tol * sc, st, &err);
+          if (rc == KRY_ENOCONV) status = rc;
+          else if (rc) return rc;
+        }
+        *max_err = std::max(*max_err, err / std::max(ynorm[k], 1e-300));
+        KRY_HIP(kry::launch_assemble(c->st, zcol(c, 2 * k), zcol(c, 2 * k + 1), slot(c, 0), sn, cs,
+                                     yT + (size_t)(c0 + k) * c->n, c->n, c->stream));
+      }
     } else {
-      err.assign(gg, 0.0);
-    }
-    for (int k = 0; k < gg; ++k) {
-      const double sn = std::sin(om[k] * T), cs = std::cos(om[k] * T);
-      *max_err = std::max(*max_err, err[k] / std::max(ynorm[k], 1e-300));
-      KRY_HIP(kry::launch_assemble(c->st, zcol(c, 2 * k), zcol(c, 2 * k + 1), bslot(c, xs + k), sn, cs,
-                                   yT + (size_t)(c0 + k) * c->n, c->n, c->stream));
+      // transient block: X = Im z_k, in slots after the transient workspace
+      const int mbt = transient_steps(c);
+      const int xs = (mbt + 1) * gg + 2 * gg;
+      rc = ensure_block(c, xs + gg);
+      if (rc) return rc;
+      for (int k = 0; k < gg; ++k)
+        KRY_HIP(hipMemcpyAsync(bslot(c, xs + k), zcol(c, 2 * k + 1), c->ldv * c->esz,
+                               hipMemcpyDeviceToDevice, c->stream));
+      std::vector<double> err;
+      if (T > 0.0) {
+        rc = block_transient(c, xs, gg, T, rate, st, err);
+        if (rc == KRY_ENOCONV) status = rc;
+        else if (rc) return rc;
+      } else {
+        err.assign(gg, 0.0);
+      }
+      for (int k = 0; k < gg; ++k) {
+        const double sn = std::sin(om[k] * T), cs = std::cos(om[k] * T);
+        *max_err = std::max(*max_err, err[k] / std::max(ynorm[k], 1e-300));
+        KRY_HIP(kry::launch_assemble(c->st, zcol(c, 2 * k), zcol(c, 2 * k + 1), bslot(c, xs + k), sn,
+                                     cs, yT + (size_t)(c0 + k) * c->n, c->n, c->stream));
+      }
     }
     KRY_HIP(hipStreamSynchronize(c->stream));
     *t_trans += now_ms() - t1;

@@ -19,74 +19,129 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// partials[split][M x N] = X[:, 0:M]^T diag(w) Y[:, 0:N] over the elements
-// [split * kchunk, (split + 1) * kchunk).  Workgroup = 4 waves = a 32 x 32
-// output tile (one 16 x 16 tile per wave); grid (nsplit, ceil(M/32),
-// ceil(N/32)).  Out-of-range rows, columns and elements contribute zeros.
+// Load four consecutive entries e..e+3 (e a multiple of 4, base 32-byte
+// aligned) as FP64, masking entries at or beyond `end`.
 template <typename T>
+__device__ __forceinline__ void load4(const T* __restrict__ p, long long e, long long end,
+                                      double (&v)[4]) {
+  if (e + 3 < end) {
+    if constexpr (sizeof(T) == 8) {
+      const double2 a = *reinterpret_cast<const double2*>(p + e);
+      const double2 b = *reinterpret_cast<const double2*>(p + e + 2);
+      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    } else {
+      const float4 a = *reinterpret_cast<const float4*>(p + e);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = (e + t < end) ? (double)p[e + t] : 0.0;
+  }
+}
+
+// partials[split][M x N] = X[:, 0:M]^T diag(w) Y[:, 0:N] over the elements
+// [split * kchunk, (split + 1) * kchunk) (kchunk a multiple of 16).  Each
+// wave owns 16 rows (columns of X) and NT 16-column tiles of Y; per
+// 16-element chunk lane (i, kk) reads entries e0 + 4 kk .. e0 + 4 kk + 3 of
+// its X column and of the NT Y columns with 32-byte loads and feeds them to
+// four MFMAs, the t-th taking entry e0 + 4 kk + t as its k = kk slot (a
+// permutation of the reduction order).  grid (nsplit, ceil(M / 64),
+// ceil(N / (16 NT))).  Out-of-range rows, columns and entries add zeros.
+template <typename T, int NT>
 __global__ __launch_bounds__(256) void k_gram_tn(const T* __restrict__ X, int M,
                                                  const T* __restrict__ Y, int N, long long ld,
                                                  const double* __restrict__ w, long long n,
                                                  long long kchunk, double* __restrict__ partials) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * 32 + (wave >> 1) * 16;
-  const int n0 = blockIdx.z * 32 + (wave & 1) * 16;
+  const int m0 = blockIdx.y * 64 + wave * 16;
+  const int nbase = blockIdx.z * 16 * NT;
   const int i = lane & 15, kk = lane >> 4;
   const long long e_begin = (long long)blockIdx.x * kchunk;
   const long long e_end = min(n, e_begin + kchunk);
-  const bool arow = m0 + i < M, bcol = n0 + i < N;
+  const bool arow = m0 + i < M;
   const T* xc = X + (long long)(arow ? m0 + i : 0) * ld;
-  const T* yc = Y + (long long)(bcol ? n0 + i : 0) * ld;
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
-  for (long long e0 = e_begin; e0 < e_end; e0 += 4) {
-    const long long e = e0 + kk;
-    const bool ok = e < e_end;
-    const double a = (arow && ok) ? (double)xc[e] : 0.0;
-    const double b = (bcol && ok) ? w[e] * (double)yc[e] : 0.0;
-    acc = mfma16(a, b, acc);
+  bool bcol[NT];
+  const T* yc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    bcol[t] = nbase + t * 16 + i < N;
+    yc[t] = Y + (long long)(bcol[t] ? nbase + t * 16 + i : 0) * ld;
+  }
+  v4d acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+  if (m0 < M) {
+    for (long long e0 = e_begin; e0 < e_end; e0 += 16) {
+      const long long eb = e0 + 4 * kk;
+      double xa[4], ww[4], yb[NT][4];
+      if (arow) load4(xc, eb, e_end, xa);
+      else xa[0] = xa[1] = xa[2] = xa[3] = 0.0;
+      load4(w, eb, e_end, ww);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (bcol[t]) load4(yc[t], eb, e_end, yb[t]);
+        else yb[t][0] = yb[t][1] = yb[t][2] = yb[t][3] = 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mfma16(xa[u], ww[u] * yb[t][u], acc[t]);
+    }
   }
   double* out = partials + (long long)blockIdx.x * M * N;
-  const int col = n0 + i;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = m0 + 4 * r + kk;
-    if (row < M && col < N) out[(long long)row * N + col] = acc[r];
+  for (int t = 0; t < NT; ++t) {
+    const int col = nbase + t * 16 + i;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = m0 + 4 * r + kk;
+      if (row < M && col < N) out[(long long)row * N + col] = acc[t][r];
+    }
   }
 }
 
 // Out[:, j] = (accumulate ? Out[:, j] : 0) + alpha sum_k X[:, k] C[k][j] for
-// j < N (C row-major M x N, FP64).  Each wave computes 16 elements x 64
-// columns (four 16 x 16 tiles of Out^T = C^T X^T): A = C^T (from C), B =
-// X^T (16 consecutive elements per k: coalesced).  grid (ceil(n / 64),
-// ceil(N / 64)).  Out may not overlap X.
-template <typename T>
+// j < N (C row-major M x N, FP64).  Each wave computes 16 entries x 16 NT
+// columns (NT tiles of Out^T = C^T X^T): A = C^T (from C), B = X^T (16
+// consecutive entries per k: coalesced).  Per iteration a lane loads four
+// basis entries (k = k0 + 4u + kk, u = 0..3) before the 4 NT MFMAs, so
+// four independent loads are in flight.  grid (ceil(n / 64),
+// ceil(N / (16 NT))).  Out may not overlap X.
+template <typename T, int NT>
 __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ X, int M,
                                                  const double* __restrict__ C, int N,
                                                  T* __restrict__ Out, long long ld, long long n,
                                                  double alpha, int accumulate) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long e0 = ((long long)blockIdx.x * 4 + wave) * 16;
-  const int jbase = blockIdx.y * 64;
+  const int jbase = blockIdx.y * 16 * NT;
   const int i = lane & 15, kk = lane >> 4;
   const long long e = e0 + i;
   const bool eok = e < n;
-  v4d acc[4];
+  v4d acc[NT];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < M; k0 += 4) {
-    const int k = k0 + kk;
-    const bool kok = k < M;
-    const double b = (kok && eok) ? (double)X[(long long)k * ld + e] : 0.0;
+  for (int t = 0; t < NT; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < M; k0 += 16) {
+    double b[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int j = jbase + t * 16 + i;
-      const double a = (kok && j < N) ? C[(long long)k * N + j] : 0.0;
-      acc[t] = mfma16(a, b, acc[t]);
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 4 * u + kk;
+      b[u] = (k < M && eok) ? (double)X[(long long)k * ld + e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 4 * u + kk;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int j = jbase + t * 16 + i;
+        const double a = (k < M && j < N) ? C[(long long)k * N + j] : 0.0;
+        acc[t] = mfma16(a, b[u], acc[t]);
+      }
     }
   }
   if (!eok) return;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < NT; ++t) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int j = jbase + t * 16 + 4 * r + kk;
@@ -112,7 +167,7 @@ __global__ void k_weights(const double* __restrict__ eps, const double* __restri
 }  // namespace
 
 int gram_splits(long long n, int M, int N) {
-  const int tiles = ((M + 31) / 32) * ((N + 31) / 32);
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
   long long s = 2048 / tiles;
   if (s < 1) s = 1;
   const long long maxs = (n + 255) / 256;
@@ -123,27 +178,45 @@ int gram_splits(long long n, int M, int N) {
 hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, long long ld,
                        const double* w, long long n, double* partials, int nsplit, hipStream_t s) {
   long long kchunk = (n + nsplit - 1) / nsplit;
-  kchunk = (kchunk + 3) / 4 * 4;
-  const dim3 grid(nsplit, (M + 31) / 32, (N + 31) / 32);
-  if (st == F64)
-    hipLaunchKernelGGL(k_gram_tn<double>, grid, dim3(256), 0, s, (const double*)X, M,
-                       (const double*)Y, N, ld, w, n, kchunk, partials);
-  else
-    hipLaunchKernelGGL(k_gram_tn<float>, grid, dim3(256), 0, s, (const float*)X, M,
+  kchunk = (kchunk + 15) / 16 * 16;
+  const int nt = N >= 64 ? 4 : (N + 15) / 16;
+  const dim3 grid(nsplit, (M + 63) / 64, (N + 16 * nt - 1) / (16 * nt));
+#define KRY_GRAM(NT)                                                                        \
+  if (st == F64)                                                                           \
+    hipLaunchKernelGGL((k_gram_tn<double, NT>), grid, dim3(256), 0, s, (const double*)X, M, \
+                       (const double*)Y, N, ld, w, n, kchunk, partials);                   \
+  else                                                                                     \
+    hipLaunchKernelGGL((k_gram_tn<float, NT>), grid, dim3(256), 0, s, (const float*)X, M,   \
                        (const float*)Y, N, ld, w, n, kchunk, partials);
+  switch (nt) {
+    case 1: KRY_GRAM(1) break;
+    case 2: KRY_GRAM(2) break;
+    case 3: KRY_GRAM(3) break;
+    default: KRY_GRAM(4) break;
+  }
+#undef KRY_GRAM
   return hipGetLastError();
 }
 
 hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int N, void* Out,
                           long long ld, long long n, double alpha, int accumulate, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((n + 63) / 64), (N + 63) / 64);
-  if (st == F64)
-    hipLaunchKernelGGL(k_gemm_nn<double>, grid, dim3(256), 0, s, (const double*)X, M, C, N,
-                       (double*)Out, ld, n, alpha, accumulate);
-  else
-    hipLaunchKernelGGL(k_gemm_nn<float>, grid, dim3(256), 0, s, (const float*)X, M, C, N,
-                       (float*)Out, ld, n, alpha, accumulate);
+  const int nt = N >= 64 ? 4 : (N + 15) / 16;
+  const dim3 grid((unsigned)((n + 63) / 64), (N + 16 * nt - 1) / (16 * nt));
+#define KRY_GEMM(NT)                                                                          \
+  if (st == F64)                                                                             \
+    hipLaunchKernelGGL((k_gemm_nn<double, NT>), grid, dim3(256), 0, s, (const double*)X, M, C, \
+                       N, (double*)Out, ld, n, alpha, accumulate);                          \
+  else                                                                                       \
+    hipLaunchKernelGGL((k_gemm_nn<float, NT>), grid, dim3(256), 0, s, (const float*)X, M, C,   \
+                       N, (float*)Out, ld, n, alpha, accumulate);
+  switch (nt) {
+    case 1: KRY_GEMM(1) break;
+    case 2: KRY_GEMM(2) break;
+    case 3: KRY_GEMM(3) break;
+    default: KRY_GEMM(4) break;
+  }
+#undef KRY_GEMM
   return hipGetLastError();
 }
 

@@ -55,19 +55,18 @@ def main(cfg_name: str):
                                    for ti in range(len(inp.thetas))])
     for wi, ti in cols:
         omega, theta = wl.omegas[wi], float(inp.thetas[ti])
-        if True:
-            b = wk.source_vector(wl, omega, float(theta))
-            t0 = time.time()
-            y = osv.augmented_solution(A, b, omega, wl.T)
-            dt = time.time() - t0
-            col = {"omega_index": wi, "theta_index": ti, "omega": omega,
-                   "theta": float(theta), "norm2": float(np.linalg.norm(y)),
-                   "values": y[idx].tolist(),
-                   "projections": [float(projection_vector(wl.n, k) @ y)
-                                   for k in range(N_PROJ)],
-                   "oracle_seconds": dt}
-            out["columns"].append(col)
-            print(f"{cfg_name} col ({wi},{ti}) |y|={col['norm2']:.6e} {dt:.1f}s", flush=True)
+        b = wk.source_vector(wl, omega, float(theta))
+        t0 = time.time()
+        y = osv.augmented_solution(A, b, omega, wl.T)
+        dt = time.time() - t0
+        col = {"omega_index": wi, "theta_index": ti, "omega": omega,
+               "theta": float(theta), "norm2": float(np.linalg.norm(y)),
+               "values": y[idx].tolist(),
+               "projections": [float(projection_vector(wl.n, k) @ y)
+                               for k in range(N_PROJ)],
+               "oracle_seconds": dt}
+        out["columns"].append(col)
+        print(f"{cfg_name} col ({wi},{ti}) |y|={col['norm2']:.6e} {dt:.1f}s", flush=True)
     with open(os.path.join(HERE, f"{cfg_name}_yT_samples.json"), "w") as f:
         json.dump(out, f)
 

@@ -488,16 +488,17 @@ def test_block_stationary_per_column_shifts():
         assert _rel(z[k], osv.stationary(A, B[k], w)) <= 1e-9
 
 
-@pytest.mark.parametrize("bw", [4, 8])
-def test_block_solve_matches_oracle(bw):
-    _announce(f"block solve bw={bw}")
+@pytest.mark.parametrize("bw,bst", [(4, 0), (8, 0), (4, 24), (8, 16)])
+def test_block_solve_matches_oracle(bw, bst):
+    _announce(f"block solve bw={bw} block transient steps={bst}")
     wl = wk.small(9, seed=15, n_spheres=5, layer=2, T=50.0)
     inp = wk.generate(wl)
     om = [2 * math.pi * 0.09, 2 * math.pi * 0.11]
     th = [0.2, 0.4]
     cols = [(w, t) for w in om for t in th]
     B = np.stack([wk.source_vector(wl, w, t) for (w, t) in cols])
-    s = _solver(inp.eps, None, inp.sigma, krylov_dim=48, tol=1e-9, block_width=bw)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=48, tol=1e-9, block_width=bw,
+                block_steps_transient=bst)
     y = s.solve_multifreq(om, _t(B), wl.T, b_per_omega=True).cpu().numpy()
     assert s.last_stats["converged"] == 1
     A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
