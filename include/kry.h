@@ -69,7 +69,10 @@ typedef struct {
                            = columns processed in groups of B/2 sharing one
                            block Krylov space (2 real columns per complex
                            source), block Gram-Schmidt on matrix cores     */
-  int32_t use_graph;    /* reserved: capture restart cycles in HIP graphs  */
+  int32_t use_graph;    /* 1: each single-vector Arnoldi cycle is captured
+                           once as a HIP graph and replayed (removes the
+                           launch cost of small grids); ignored when
+                           timing = 1                                     */
   int32_t inner_product;/* 0: energy inner product (the only mode)         */
   void* stream;         /* hipStream_t; NULL = the null stream             */
   int32_t timing;       /* 1: time every launch of the main kernel classes

@@ -126,6 +126,7 @@ class Options:
     timing: bool = False
     orth: str = "delayed"       # "delayed" (two basis sweeps per step) or "cgs2"
     block_width: int = 0        # > 1: batched form, groups of block_width/2 columns
+    use_graph: bool = False     # replay captured Arnoldi cycles (HIP graphs)
     block_steps: int = 0        # batched shifted solves: block steps per restart (0 auto)
     block_steps_transient: int = 0  # batched exponential: block steps per restart (0 auto)
 
@@ -155,7 +156,8 @@ class Solver:
         e, m, s = prep(eps), prep(mu), prep(sigma)
         self.grid = KryGrid(nx, ny, nz, 0)
         self.opts = KryOpts(1 if opts.storage == "f32" else 0, opts.krylov_dim,
-                            opts.max_restarts, opts.tol, opts.block_width, 0, 0,
+                            opts.max_restarts, opts.tol, opts.block_width,
+                            int(bool(opts.use_graph)), 0,
                             _stream_ptr().value,
                             int(bool(opts.timing)), opts.block_steps,
                             opts.block_steps_transient, 1 if opts.orth == "cgs2" else 0)

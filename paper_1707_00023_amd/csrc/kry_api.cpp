@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -59,6 +60,10 @@ struct kry_ctx {
   size_t gp_cap = 0;
   double* d_bc = nullptr;      // reduced Gram / coefficient matrices
   size_t bc_cap = 0;
+
+  // captured Arnoldi cycles (one per cycle length), replayed on `stream`
+  hipStream_t cstream = nullptr;  // private capture stream (default priority)
+  std::map<int, hipGraphExec_t> graphs;
 
   // optional per-kernel-class timing with HIP events
   struct Pending {
@@ -164,8 +169,14 @@ double mbytes(kry_ctx* c, bool stencil) {
 void* slot(kry_ctx* c, int i) { return (char*)c->V + (size_t)i * c->ldv * c->esz; }
 void* zcol(kry_ctx* c, int col) { return (char*)c->Z + (size_t)col * c->ldv * c->esz; }
 
+void drop_graphs(kry_ctx* c) {
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
 int ensure_basis(kry_ctx* c, int m) {
   if (m <= c->mcap && c->V) return KRY_OK;
+  drop_graphs(c);
   if (m + 2 > kry::kMaxCoef) return fail(c, KRY_ENOMEM, "krylov_dim too large");
   hipFree(c->V);
   hipFree(c->partials);
@@ -299,36 +310,81 @@ int arnoldi_cgs2(kry_ctx* c, int m, double* beta, int* m_eff) {
 // pass B sweeps the basis once to write v_j and the next candidate u_{j+1}.
 // After m steps the last candidate is reorthogonalised and normalised.
 // Same contract as arnoldi_cgs2 (start vector unnormalised in slot 0).
-int arnoldi_lag(kry_ctx* c, int m, double* beta, int* m_eff) {
+// Enqueue one delayed-reorthogonalisation Arnoldi cycle on stream s (no
+// host synchronisation inside, so the whole cycle can be captured).
+int enqueue_arnoldi_lag(kry_ctx* c, int m, hipStream_t s, bool timed) {
   const int nparts = kry::cell_blocks(c->g.N3);
-  hipStream_t s = c->stream;
   const long long ldv = c->ldv;
   const int ldh = m + 1;
-  KRY_HIP(hipMemsetAsync(c->d_H, 0, sizeof(double) * (size_t)(m + 1) * m, s));
+  KRY_HIP(kry::launch_fill(c->d_H, 0.0, (long long)(m + 1) * m, s));
   void* U = slot(c, c->mcap + 1);
   void* X = slot(c, c->mcap + 2);
   const double vb = vbytes(c);
   for (int j = 0; j < m; ++j) {
     const int cnt = j;
     void* uj = (j == 0) ? slot(c, 0) : U;
-    hipEvent_t e = tbeg(c);
+    hipEvent_t e = timed ? tbeg(c) : nullptr;
     KRY_HIP(kry::launch_stencil_lag(c->st, uj, X, c->V, ldv, cnt, c->g, c->mats, c->partials, s));
     tend(c, e, KRY_K_STENCIL, vb * (cnt + 2) + mbytes(c, true));
     KRY_HIP(kry::launch_reduce(c->partials, nparts, 2 * cnt + 2, 2 * cnt + 2, c->d_red1, s));
     KRY_HIP(kry::launch_lag_fin(c->d_red1, j, c->d_H, ldh, c->d_co, c->d_scal, s));
-    e = tbeg(c);
+    e = timed ? tbeg(c) : nullptr;
     KRY_HIP(kry::launch_lag_update(c->st, uj, X, c->V, ldv, cnt, c->d_co, slot(c, j), U, c->g, s));
     tend(c, e, KRY_K_UPDATE, vb * (cnt + 4));
   }
   // last candidate: second projection and normalisation -> v_m
-  hipEvent_t e = tbeg(c);
+  hipEvent_t e = timed ? tbeg(c) : nullptr;
   KRY_HIP(kry::launch_dots(c->st, U, c->V, ldv, m, c->g, c->mats, c->partials, s));
   tend(c, e, KRY_K_DOTS, vb * (m + 1) + mbytes(c, false));
   KRY_HIP(kry::launch_reduce(c->partials, nparts, m + 1, m + 1, c->d_red1, s));
   KRY_HIP(kry::launch_lag_final(c->d_red1, m, c->d_H, ldh, c->d_scal, s));
-  e = tbeg(c);
+  e = timed ? tbeg(c) : nullptr;
   KRY_HIP(kry::launch_update(c->st, U, c->V, ldv, m, c->d_red1, c->d_scal, slot(c, m), c->g, s));
   tend(c, e, KRY_K_UPDATE, vb * (m + 2));
+  return KRY_OK;
+}
+
+// The cycle as a HIP graph: captured once per cycle length on the private
+// stream, then replayed on the solver's stream.
+int launch_arnoldi_graph(kry_ctx* c, int m) {
+  auto it = c->graphs.find(m);
+  if (it == c->graphs.end()) {
+    if (!c->cstream) KRY_HIP(hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    KRY_HIP(hipStreamBeginCapture(c->cstream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_arnoldi_lag(c, m, c->cstream, false);
+    const hipError_t ec = hipStreamEndCapture(c->cstream, &graph);
+    if (rc) {
+      if (graph) hipGraphDestroy(graph);
+      return rc;
+    }
+    KRY_HIP(ec);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    KRY_HIP(ei);
+    it = c->graphs.emplace(m, exec).first;
+  }
+  KRY_HIP(hipGraphLaunch(it->second, c->stream));
+  return KRY_OK;
+}
+
+// Arnoldi with the second Gram-Schmidt projection delayed by one step (two
+// sweeps over the basis per step instead of four).  Step j applies A to
+// the candidate u_j (projected once, not yet reorthogonalised or
+// normalised): pass A computes x = A u_j with <x, v_i>, <u_j, v_i>, |u_j|^2
+// and <u_j, x>; the small step (k_lag_fin) completes column j-1 (second
+// projection of u_j and its norm), rebuilds A v_j from x through the
+// Arnoldi relation A V_{j-1} = V_j Hbar_{j-1}, and its first projection;
+// pass B sweeps the basis once to write v_j and the next candidate u_{j+1}.
+// After m steps the last candidate is reorthogonalised and normalised.
+// Same contract as arnoldi_cgs2 (start vector unnormalised in slot 0).
+int arnoldi_lag(kry_ctx* c, int m, double* beta, int* m_eff) {
+  hipStream_t s = c->stream;
+  const int ldh = m + 1;
+  int rc = (c->opts.use_graph && !c->opts.timing) ? launch_arnoldi_graph(c, m)
+                                                   : enqueue_arnoldi_lag(c, m, s, true);
+  if (rc) return rc;
   KRY_HIP(hipMemcpyAsync(c->h_H, c->d_H, sizeof(double) * (size_t)(m + 1) * m, hipMemcpyDeviceToHost, s));
   KRY_HIP(hipMemcpyAsync(c->h_scal, c->d_scal, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
   KRY_HIP(hipStreamSynchronize(s));
@@ -668,6 +724,8 @@ void kry_destroy(kry_ctx* c) {
   hipFree(c->d_Y);
   hipFree(c->d_colmap);
   hipFree(c->Z);
+  drop_graphs(c);
+  if (c->cstream) hipStreamDestroy(c->cstream);
   for (auto& p : c->pending) {
     hipEventDestroy(p.a);
     hipEventDestroy(p.b);

@@ -101,6 +101,9 @@ hipError_t launch_store_complex(Storage st, const void* re, const void* im, doub
 hipError_t launch_assemble(Storage st, const void* re, const void* im, const void* yhat,
                            double sn, double cs, double* out, long long n, hipStream_t s);
 
+// p[0:n] = v (a kernel, so that it can sit in a captured graph).
+hipError_t launch_fill(double* p, double v, long long n, hipStream_t s);
+
 // w_c = A v_c for ncols columns at stride ld (columns of a block).
 hipError_t launch_stencil_cols(Storage st, const void* v, void* w, long long ld, int ncols,
                                const DevGrid& g, const DevMats& m, hipStream_t s);

@@ -752,6 +752,11 @@ __global__ void k_grad_acc(const T* __restrict__ zre, const T* __restrict__ zim,
   g[c] -= acc;
 }
 
+__global__ void k_fill(double* __restrict__ p, double v, long long n) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -1017,6 +1022,12 @@ hipError_t launch_store_complex(Storage st, const void* re, const void* im, doub
   else
     hipLaunchKernelGGL(k_store_complex<float>, dim3(blocks_for(n)), dim3(kBlock), 0, s,
                        (const float*)re, (const float*)im, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, double v, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, v, n);
   return hipGetLastError();
 }
 

@@ -505,3 +505,32 @@ def test_block_solve_matches_oracle(bw, bst):
     for c, (w, t) in enumerate(cols):
         ref = osv.augmented_solution(A, B[c], w, wl.T)
         assert _rel(y[c], ref) <= 1e-8
+
+
+# ------------------------------------------------------------- HIP graphs --
+
+def test_graph_replay_matches_eager_bitwise():
+    # every restart cycle replays the captured graph; the eager run between
+    # the graph runs exercises interleaving with ordinary launches
+    _announce("graph replay vs eager")
+    wl = wk.C1
+    inp = wk.generate(wl)
+    b = _t(wk.source_vector(wl, wl.omegas[0], 0.0)[None, :])
+    eager = _solver(inp.eps, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=wl.tol)
+    graph = _solver(inp.eps, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=wl.tol, use_graph=True)
+    t0 = time.time()
+    y_e = eager.solve_multifreq(wl.omegas, b, wl.T).cpu().numpy()
+    t_e = time.time() - t0
+    outs = []
+    for rep in range(2):
+        t0 = time.time()
+        outs.append(graph.solve_multifreq(wl.omegas, b, wl.T).cpu().numpy())
+        t_g = time.time() - t0
+        eager.solve_multifreq(wl.omegas, b, wl.T)
+    _announce(f"c1 eager {t_e:.3f}s graph {t_g:.3f}s cycles {graph.last_stats['cycles_stationary']}")
+    for y in outs:
+        assert np.array_equal(y, y_e)
+    v = wk.random_state(wl.n, 3)
+    V1, H1, b1, s1 = eager.arnoldi(_t(v), 20)
+    V2, H2, b2, s2 = graph.arnoldi(_t(v), 20)
+    assert np.array_equal(H1, H2) and np.array_equal(V1.cpu().numpy(), V2.cpu().numpy())
