@@ -100,6 +100,45 @@ def compare_batched(args, wl, inp, dev):
     print(json.dumps(out), flush=True)
 
 
+COPY_BYTES = 1 << 30
+
+
+def traffic_probe(args, wl, inp, dev):
+    """Two Arnoldi cycles (m = the workload's Krylov dimension) on the
+    workload's grid, then one device copy of COPY_BYTES (the calibration
+    kernel: it moves exactly COPY_BYTES in and COPY_BYTES out)."""
+    import numpy as np
+    import torch
+
+    import paper_1707_00023_amd as kry
+    import workloads as wk
+
+    eps = torch.as_tensor(inp.eps, device=dev)
+    sig = torch.as_tensor(inp.sigma, device=dev)
+    s = kry.Solver(eps, None, sig, kry.Options(storage=wl.storage, krylov_dim=wl.krylov_dim,
+                                               tol=wl.tol))
+    tune = None if args.no_autotune else s.autotune()
+    v = torch.as_tensor(wk.random_state(wl.n, 1), device=dev)
+    m = wl.krylov_dim
+    for _ in range(2):
+        s.arnoldi(v, m)
+    src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    esz = 8 if wl.storage == "f64" else 4
+    vb = 6 * wl.N ** 3 * esz
+    mats = 24 * wl.N ** 3
+    out = {"probe": "two Arnoldi cycles + calibration copy", "workload": wl.name, "m": m,
+           "copy_bytes_each_way": COPY_BYTES, "launch_shapes": tune,
+           # algorithmic bytes per launch, averaged over the m steps of a cycle
+           "alg_bytes_per_launch": {
+               "k_stencil_lag": float(np.mean([vb * (j + 2) + mats for j in range(m)])),
+               "k_lag_update": float(np.mean([vb * (j + 4) for j in range(m)]))}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +154,10 @@ def main():
     ap.add_argument("--omega-index", type=int, default=15)
     ap.add_argument("--block-width", type=int, default=16)
     ap.add_argument("--block-steps", type=int, default=16)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run two Arnoldi cycles on the workload's grid and a calibration "
+                         "copy of known size (for hardware-counter runs), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this solver has no multi-GPU path "
@@ -134,10 +177,14 @@ def main():
     if args.compare_batched:
         compare_batched(args, wl, inp, dev)
         return
+    if args.traffic_probe:
+        traffic_probe(args, wl, inp, dev)
+        return
     eps = torch.as_tensor(inp.eps, device=dev)
     sig = torch.as_tensor(inp.sigma, device=dev)
     solver = kry.Solver(eps, None, sig, kry.Options(storage=wl.storage, krylov_dim=wl.krylov_dim,
                                                     tol=wl.tol, timing=True))
+    tune = None if args.no_autotune else solver.autotune()
     cols = [wk.source_vector(wl, w, float(th)) for w in wl.omegas for th in inp.thetas]
     b = torch.as_tensor(np.stack(cols), device=dev)
     per_omega = wl.n_theta > 1
@@ -197,6 +244,7 @@ def main():
                      "avg_launch_us": float(kms[dom] / max(kl[dom], 1) * 1e3),
                      "alg_bytes_per_launch": float(kb[dom] / max(kl[dom], 1)),
                      "traffic": None},
+        "launch_shapes": tune,
         "converged": bool(last["converged"]),
         "max_residual": last["max_residual"],
         "max_err_estimate": last["max_err_estimate"],

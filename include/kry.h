@@ -195,6 +195,25 @@ int kry_stationary(kry_ctx* ctx, const double* omegas, int32_t n_omega,
                    int32_t n_src, const double* b, int32_t b_per_omega,
                    double* z, kry_stats* stats);
 
+/* Launch shapes of the streaming kernels: cells per thread (1, 2 or 4) of
+ * the operator kernels (stencil), of the basis-update kernels and of the
+ * dot-product kernels, with the timings (microseconds, best of several
+ * launches, index 0/1/2 for 1/2/4 cells per thread) that chose them. */
+typedef struct {
+  int32_t cpt_stencil, cpt_update, cpt_dots;
+  double us_stencil[3], us_update[3], us_dots[3];
+} kry_tune;
+
+/* Time the operator+dots, update and dot kernels of one Arnoldi step with
+ * `cnt` basis vectors (0: krylov_dim / 2) for every launch shape on this
+ * context's grid and workspace, apply the fastest per kernel class, and
+ * report the choice and timings in *out (host).  Overwrites the context's
+ * Krylov workspace (no solve may be in progress on the stream). */
+int kry_autotune(kry_ctx* ctx, int32_t cnt, kry_tune* out);
+
+/* Apply a previously measured launch-shape choice (cpt_* fields of *t). */
+int kry_set_tune(kry_ctx* ctx, const kry_tune* t);
+
 /* Transmitted power and its gradient w.r.t. per-cell permittivity.
  * The loss is the period-averaged Poynting flux of the time-harmonic parts
  * Im(e^{i w t} z_w) of Corollary 3 through the plane z = plane_k, summed over

@@ -26,7 +26,8 @@ _CODES = {KRY_EINVAL: "KRY_EINVAL", KRY_ENOMEM: "KRY_ENOMEM", KRY_EHIP: "KRY_EHI
 
 EXPORTED = ("kry_create", "kry_destroy", "kry_last_error", "kry_size", "kry_apply",
             "kry_apply_f32", "kry_arnoldi", "kry_expv", "kry_solve_multifreq",
-            "kry_stationary", "kry_grad", "kry_block_arnoldi")
+            "kry_stationary", "kry_grad", "kry_block_arnoldi", "kry_autotune",
+            "kry_set_tune")
 
 
 class KryGrid(ctypes.Structure):
@@ -61,6 +62,12 @@ class KryStats(ctypes.Structure):
 
 
 KERNEL_CLASSES = ("stencil_dots", "gs_update", "gs_dots", "combine")
+
+
+class KryTune(ctypes.Structure):
+    _fields_ = [("cpt_stencil", ctypes.c_int32), ("cpt_update", ctypes.c_int32),
+                ("cpt_dots", ctypes.c_int32), ("us_stencil", ctypes.c_double * 3),
+                ("us_update", ctypes.c_double * 3), ("us_dots", ctypes.c_double * 3)]
 
 
 class KryError(RuntimeError):
@@ -101,6 +108,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                              ctypes.POINTER(KryStats)]
     lib.kry_block_arnoldi.argtypes = [P, P, I32, I32, P, P]
     lib.kry_block_arnoldi.restype = ctypes.c_int
+    lib.kry_autotune.argtypes = [P, I32, ctypes.POINTER(KryTune)]
+    lib.kry_autotune.restype = ctypes.c_int
+    lib.kry_set_tune.argtypes = [P, ctypes.POINTER(KryTune)]
+    lib.kry_set_tune.restype = ctypes.c_int
     for name in ("kry_apply", "kry_apply_f32", "kry_arnoldi", "kry_expv",
                  "kry_solve_multifreq", "kry_stationary", "kry_grad"):
         getattr(lib, name).restype = ctypes.c_int
@@ -230,6 +241,40 @@ class Solver:
         if rc < 0:
             self._check(rc)
         return V, H.T.copy(), beta.value, rc
+
+    def autotune(self, cache: Optional[str] = None, cnt: int = 0):
+        """Choose the kernels' launch shapes by timing them on this grid.
+
+        With `cache` (a JSON path) a measured choice is reused for the same
+        grid, storage, Krylov dimension and GPU architecture, and new
+        measurements are added to it.  Returns the choice as a dict.
+        """
+        import json
+        import torch
+        arch = getattr(torch.cuda.get_device_properties(self.device), "gcnArchName", "gpu")
+        key = (f"{self.grid.nx}x{self.grid.ny}x{self.grid.nz}-{self.storage}-"
+               f"m{self.opts.krylov_dim}-c{cnt}-{arch}")
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        t = KryTune()
+        if key in table:
+            e = table[key]
+            t.cpt_stencil, t.cpt_update, t.cpt_dots = e["cpt_stencil"], e["cpt_update"], e["cpt_dots"]
+            self._check(self._lib.kry_set_tune(self._ctx, ctypes.byref(t)))
+            return dict(e, cached=True)
+        self._check(self._lib.kry_autotune(self._ctx, int(cnt), ctypes.byref(t)))
+        e = {"cpt_stencil": t.cpt_stencil, "cpt_update": t.cpt_update, "cpt_dots": t.cpt_dots,
+             "us_stencil": list(t.us_stencil), "us_update": list(t.us_update),
+             "us_dots": list(t.us_dots)}
+        if cache:
+            table[key] = e
+            d = os.path.dirname(os.path.abspath(cache))
+            os.makedirs(d, exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        return dict(e, cached=False)
 
     def block_arnoldi(self, V0, mb: int):
         """(V ((mb+1) p, n), H ((mb+1) p, mb p) numpy, block steps) from the block V0 (p, n)."""

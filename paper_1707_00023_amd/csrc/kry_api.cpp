@@ -196,7 +196,7 @@ int ensure_basis(kry_ctx* c, int m) {
     (void)hipGetLastError();
     return fail(c, KRY_ENOMEM, "cannot allocate Krylov basis of " + std::to_string(vbytes) + " bytes");
   }
-  const size_t nparts = (size_t)kry::cell_blocks(c->g.N3);
+  const size_t nparts = (size_t)kry::cell_blocks(c->g.N3, 1);  // the most workgroups
   KRY_HIP(hipMalloc(&c->partials, sizeof(double) * nparts * (size_t)(2 * m + 4)));
   KRY_HIP(hipMalloc(&c->d_red1, sizeof(double) * (2 * m + 4)));
   KRY_HIP(hipMalloc(&c->d_red2, sizeof(double) * (2 * m + 4)));
@@ -239,7 +239,7 @@ int ensure_z(kry_ctx* c, int ncols) {
 // |x|_M^2 and <x, y_i>_M for i < cnt (y_i = slots of a contiguous array with
 // stride ldv), returned on the host (synchronises the stream).
 int host_dots(kry_ctx* c, const void* x, const void* Y, int cnt, std::vector<double>& out) {
-  const int nparts = kry::cell_blocks(c->g.N3);
+  const int nparts = kry::cell_blocks(c->g.N3, c->g.cpt_d);
   KRY_HIP(kry::launch_dots(c->st, x, Y, c->ldv, cnt, c->g, c->mats, c->partials, c->stream));
   KRY_HIP(kry::launch_reduce(c->partials, nparts, cnt + 1, cnt + 1, c->d_red1, c->stream));
   out.assign(cnt + 1, 0.0);
@@ -257,7 +257,8 @@ int host_dots(kry_ctx* c, const void* x, const void* Y, int cnt, std::vector<dou
 // w -= V h1, dots of pass 2 (classical Gram-Schmidt twice), then
 // v_{j+1} = (w - V h2) / nu.
 int arnoldi_cgs2(kry_ctx* c, int m, double* beta, int* m_eff) {
-  const int nparts = kry::cell_blocks(c->g.N3);
+  const int np_s = kry::cell_blocks(c->g.N3, c->g.cpt_s);
+  const int nparts = kry::cell_blocks(c->g.N3, c->g.cpt_d);
   hipStream_t s = c->stream;
   const long long ldv = c->ldv;
   KRY_HIP(hipMemsetAsync(c->d_H, 0, sizeof(double) * (size_t)(m + 1) * m, s));
@@ -273,7 +274,7 @@ int arnoldi_cgs2(kry_ctx* c, int m, double* beta, int* m_eff) {
     hipEvent_t e = tbeg(c);
     KRY_HIP(kry::launch_stencil(c->st, slot(c, j), W, c->V, ldv, cnt, c->g, c->mats, c->partials, s));
     tend(c, e, KRY_K_STENCIL, vb * (cnt + 2) + mbytes(c, true));
-    KRY_HIP(kry::launch_reduce(c->partials, nparts, cnt + 1, cnt + 1, c->d_red1, s));
+    KRY_HIP(kry::launch_reduce(c->partials, np_s, cnt + 1, cnt + 1, c->d_red1, s));
     e = tbeg(c);
     KRY_HIP(kry::launch_update(c->st, W, c->V, ldv, cnt, c->d_red1, nullptr, W, c->g, s));
     tend(c, e, KRY_K_UPDATE, vb * (cnt + 2));
@@ -313,7 +314,8 @@ int arnoldi_cgs2(kry_ctx* c, int m, double* beta, int* m_eff) {
 // Enqueue one delayed-reorthogonalisation Arnoldi cycle on stream s (no
 // host synchronisation inside, so the whole cycle can be captured).
 int enqueue_arnoldi_lag(kry_ctx* c, int m, hipStream_t s, bool timed) {
-  const int nparts = kry::cell_blocks(c->g.N3);
+  const int np_s = kry::cell_blocks(c->g.N3, c->g.cpt_s);
+  const int nparts = kry::cell_blocks(c->g.N3, c->g.cpt_d);
   const long long ldv = c->ldv;
   const int ldh = m + 1;
   KRY_HIP(kry::launch_fill(c->d_H, 0.0, (long long)(m + 1) * m, s));
@@ -326,7 +328,7 @@ int enqueue_arnoldi_lag(kry_ctx* c, int m, hipStream_t s, bool timed) {
     hipEvent_t e = timed ? tbeg(c) : nullptr;
     KRY_HIP(kry::launch_stencil_lag(c->st, uj, X, c->V, ldv, cnt, c->g, c->mats, c->partials, s));
     tend(c, e, KRY_K_STENCIL, vb * (cnt + 2) + mbytes(c, true));
-    KRY_HIP(kry::launch_reduce(c->partials, nparts, 2 * cnt + 2, 2 * cnt + 2, c->d_red1, s));
+    KRY_HIP(kry::launch_reduce(c->partials, np_s, 2 * cnt + 2, 2 * cnt + 2, c->d_red1, s));
     KRY_HIP(kry::launch_lag_fin(c->d_red1, j, c->d_H, ldh, c->d_co, c->d_scal, s));
     e = timed ? tbeg(c) : nullptr;
     KRY_HIP(kry::launch_lag_update(c->st, uj, X, c->V, ldv, cnt, c->d_co, slot(c, j), U, c->g, s));
@@ -674,6 +676,7 @@ int kry_create(const kry_grid* grid, const double* eps, const double* mu, const 
   c->g.ny = grid->ny;
   c->g.nz = grid->nz;
   c->g.N3 = N3;
+  c->g.cpt_s = c->g.cpt_u = c->g.cpt_d = kry::cells_per_thread(N3);
   c->n = 6 * N3;
   c->ldv = (c->n + 63) / 64 * 64;
   c->st = opts->storage == 1 ? kry::F32 : kry::F64;
@@ -1613,6 +1616,85 @@ int kry_block_arnoldi(kry_ctx* c, const double* V0, int32_t p, int32_t mb, void*
                            hipMemcpyDeviceToDevice, c->stream));
   KRY_HIP(hipStreamSynchronize(c->stream));
   return mbe;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int kry_set_tune(kry_ctx* c, const kry_tune* t) {
+  if (!c || !t) return fail(c, KRY_EINVAL, "null argument");
+  auto ok = [](int v) { return v == 1 || v == 2 || v == 4; };
+  if (!ok(t->cpt_stencil) || !ok(t->cpt_update) || !ok(t->cpt_dots))
+    return fail(c, KRY_EINVAL, "cells per thread must be 1, 2 or 4");
+  c->g.cpt_s = t->cpt_stencil;
+  c->g.cpt_u = t->cpt_update;
+  c->g.cpt_d = t->cpt_dots;
+  drop_graphs(c);  // captured launches carry the old shapes
+  return KRY_OK;
+}
+
+int kry_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {
+  if (!c || !out) return fail(c, KRY_EINVAL, "null argument");
+  const int m = c->opts.krylov_dim;
+  if (cnt <= 0) cnt = std::max(1, m / 2);
+  if (cnt > m) return fail(c, KRY_EINVAL, "cnt exceeds krylov_dim");
+  int rc = ensure_basis(c, m);
+  if (rc) return rc;
+  KRY_HIP(hipMemsetAsync(c->V, 0, (size_t)(c->mcap + 3) * c->ldv * c->esz, c->stream));
+  KRY_HIP(kry::launch_fill(c->d_co, 0.0, 2 * m + 4, c->stream));
+  hipEvent_t e0, e1;
+  KRY_HIP(hipEventCreate(&e0));
+  KRY_HIP(hipEventCreate(&e1));
+  Defer<std::function<void()>> free_ev{[&]() {
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  }};
+  const kry::DevGrid saved = c->g;
+  void* U = slot(c, c->mcap + 1);
+  void* X = slot(c, c->mcap + 2);
+  const int cpts[3] = {1, 2, 4};
+  auto time_us = [&](auto&& launch) -> double {
+    double best = 1e300;
+    for (int rep = 0; rep < 4; ++rep) {  // first launch warms up
+      hipEventRecord(e0, c->stream);
+      if (launch() != hipSuccess) return -1.0;
+      hipEventRecord(e1, c->stream);
+      hipEventSynchronize(e1);
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) best = std::min(best, (double)ms * 1e3);
+    }
+    return best;
+  };
+  for (int k = 0; k < 3; ++k) {
+    c->g.cpt_s = c->g.cpt_u = c->g.cpt_d = cpts[k];
+    out->us_stencil[k] = time_us([&]() {
+      return kry::launch_stencil_lag(c->st, U, X, c->V, c->ldv, cnt, c->g, c->mats, c->partials, c->stream);
+    });
+    out->us_update[k] = time_us([&]() {
+      return kry::launch_lag_update(c->st, U, X, c->V, c->ldv, cnt, c->d_co, slot(c, cnt), U, c->g, c->stream);
+    });
+    out->us_dots[k] = time_us([&]() {
+      return kry::launch_dots(c->st, U, c->V, c->ldv, cnt, c->g, c->mats, c->partials, c->stream);
+    });
+    if (out->us_stencil[k] < 0 || out->us_update[k] < 0 || out->us_dots[k] < 0) {
+      c->g = saved;
+      return fail(c, KRY_EHIP, "autotune launch failed");
+    }
+  }
+  auto pick = [&](const double* us) {
+    int b = 0;
+    for (int k = 1; k < 3; ++k)
+      if (us[k] < us[b]) b = k;
+    return cpts[b];
+  };
+  out->cpt_stencil = pick(out->us_stencil);
+  out->cpt_update = pick(out->us_update);
+  out->cpt_dots = pick(out->us_dots);
+  c->g = saved;
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  return kry_set_tune(c, out);
 }
 
 }  // extern "C"

@@ -11,6 +11,9 @@ enum Storage : int { F64 = 0, F32 = 1 };
 struct DevGrid {
   int nx, ny, nz;
   long long N3;  // cells
+  // cells per thread (1, 2 or 4) of the operator kernels, the basis-update
+  // kernels and the dot-product kernels (chosen by heuristic or autotuner)
+  int cpt_s = 1, cpt_u = 1, cpt_d = 1;
 };
 
 // Per-cell material data derived at context creation (all FP64, N3 each).
@@ -26,9 +29,10 @@ constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kChunk = 16;       // basis vectors per dot-product chunk
 constexpr int kMaxCoef = 1026;   // max coefficients staged by an update (m <= 1024)
 
-// Number of workgroups the cell-parallel kernels use, and cells per thread.
+// Default cells per thread for a grid, and the workgroups of a
+// cell-parallel launch with `cpt` cells per thread.
 int cells_per_thread(long long N3);
-int cell_blocks(long long N3);
+int cell_blocks(long long N3, int cpt);
 
 // w = A v (single column).  If V != nullptr also writes per-workgroup
 // partial sums of <w, V_i>_M for i < cnt and |w|_M^2 (slot cnt) into

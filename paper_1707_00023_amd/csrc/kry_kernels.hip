@@ -762,30 +762,38 @@ inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / k
 }  // namespace
 
 int cells_per_thread(long long N3) { return N3 >= (long long)kBlock * 4 * 1024 ? 4 : 1; }
-int cell_blocks(long long N3) {
-  const long long per = (long long)kBlock * cells_per_thread(N3);
+int cell_blocks(long long N3, int cpt) {
+  const long long per = (long long)kBlock * cpt;
   return (int)((N3 + per - 1) / per);
 }
+
+// dispatch a kernel template over cells per thread (1, 2, 4)
+#define KRY_CPT_SWITCH(cpt, X) \
+  switch (cpt) {               \
+    case 4: X(4) break;        \
+    case 2: X(2) break;        \
+    default: X(1) break;       \
+  }
 
 template <typename T>
 static hipError_t stencil_t(const void* v, void* w, const void* V, long long ldv, int cnt,
                             const DevGrid& g, const DevMats& m, double* partials, hipStream_t s) {
-  const int cpt = cells_per_thread(g.N3);
-  const dim3 grid(cell_blocks(g.N3)), blk(kBlock);
+  const int cpt = g.cpt_s;
+  const dim3 grid(cell_blocks(g.N3, cpt)), blk(kBlock);
   const T* vv = (const T*)v;
   T* ww = (T*)w;
   const T* VV = (const T*)V;
   const bool dots = V != nullptr;
   const bool mu = m.inv_mu != nullptr;
-#define KRY_STENCIL(C, M, D) \
-  hipLaunchKernelGGL((k_stencil<T, M, C, D>), grid, blk, 0, s, vv, ww, VV, ldv, cnt, g, m, partials)
-  if (cpt == 4) {
-    if (mu) { if (dots) KRY_STENCIL(4, true, true); else KRY_STENCIL(4, true, false); }
-    else { if (dots) KRY_STENCIL(4, false, true); else KRY_STENCIL(4, false, false); }
-  } else {
-    if (mu) { if (dots) KRY_STENCIL(1, true, true); else KRY_STENCIL(1, true, false); }
-    else { if (dots) KRY_STENCIL(1, false, true); else KRY_STENCIL(1, false, false); }
+#define KRY_STENCIL(C)                                                                           \
+  if (mu) {                                                                                      \
+    if (dots) hipLaunchKernelGGL((k_stencil<T, true, C, true>), grid, blk, 0, s, vv, ww, VV, ldv, cnt, g, m, partials); \
+    else hipLaunchKernelGGL((k_stencil<T, true, C, false>), grid, blk, 0, s, vv, ww, VV, ldv, cnt, g, m, partials);     \
+  } else {                                                                                       \
+    if (dots) hipLaunchKernelGGL((k_stencil<T, false, C, true>), grid, blk, 0, s, vv, ww, VV, ldv, cnt, g, m, partials); \
+    else hipLaunchKernelGGL((k_stencil<T, false, C, false>), grid, blk, 0, s, vv, ww, VV, ldv, cnt, g, m, partials);     \
   }
+  KRY_CPT_SWITCH(cpt, KRY_STENCIL)
 #undef KRY_STENCIL
   return hipGetLastError();
 }
@@ -793,18 +801,16 @@ static hipError_t stencil_t(const void* v, void* w, const void* V, long long ldv
 template <typename T>
 static hipError_t stencil_cols_t(const void* v, void* w, long long ld, int ncols, const DevGrid& g,
                                  const DevMats& m, hipStream_t s) {
-  const int cpt = cells_per_thread(g.N3);
-  const dim3 grid(cell_blocks(g.N3), ncols), blk(kBlock);
+  const int cpt = g.cpt_s;
+  const dim3 grid(cell_blocks(g.N3, cpt), ncols), blk(kBlock);
   const T* vv = (const T*)v;
   T* ww = (T*)w;
   const bool mu = m.inv_mu != nullptr;
-  if (cpt == 4) {
-    if (mu) hipLaunchKernelGGL((k_stencil<T, true, 4, false>), grid, blk, 0, s, vv, ww, nullptr, ld, 0, g, m, nullptr);
-    else hipLaunchKernelGGL((k_stencil<T, false, 4, false>), grid, blk, 0, s, vv, ww, nullptr, ld, 0, g, m, nullptr);
-  } else {
-    if (mu) hipLaunchKernelGGL((k_stencil<T, true, 1, false>), grid, blk, 0, s, vv, ww, nullptr, ld, 0, g, m, nullptr);
-    else hipLaunchKernelGGL((k_stencil<T, false, 1, false>), grid, blk, 0, s, vv, ww, nullptr, ld, 0, g, m, nullptr);
-  }
+#define KRY_SCOLS(C)                                                                                   \
+  if (mu) hipLaunchKernelGGL((k_stencil<T, true, C, false>), grid, blk, 0, s, vv, ww, nullptr, ld, 0, g, m, nullptr); \
+  else hipLaunchKernelGGL((k_stencil<T, false, C, false>), grid, blk, 0, s, vv, ww, nullptr, ld, 0, g, m, nullptr);
+  KRY_CPT_SWITCH(cpt, KRY_SCOLS)
+#undef KRY_SCOLS
   return hipGetLastError();
 }
 
@@ -824,20 +830,18 @@ hipError_t launch_stencil(Storage st, const void* v, void* w, const void* V, lon
 template <typename T>
 static hipError_t stencil_lag_t(const void* u, void* x, const void* V, long long ldv, int cnt,
                                 const DevGrid& g, const DevMats& m, double* partials, hipStream_t s) {
-  const int cpt = cells_per_thread(g.N3);
-  const dim3 grid(cell_blocks(g.N3)), blk(kBlock);
+  const int cpt = g.cpt_s;
+  const dim3 grid(cell_blocks(g.N3, cpt)), blk(kBlock);
   const T* uu = (const T*)u;
   T* xx = (T*)x;
   const T* VV = (const T*)V;
   const bool mu = m.inv_mu != nullptr;
   constexpr int CH = 8;
-  if (cpt == 4) {
-    if (mu) hipLaunchKernelGGL((k_stencil_lag<T, true, 4, CH>), grid, blk, 0, s, uu, xx, VV, ldv, cnt, g, m, partials);
-    else hipLaunchKernelGGL((k_stencil_lag<T, false, 4, CH>), grid, blk, 0, s, uu, xx, VV, ldv, cnt, g, m, partials);
-  } else {
-    if (mu) hipLaunchKernelGGL((k_stencil_lag<T, true, 1, CH>), grid, blk, 0, s, uu, xx, VV, ldv, cnt, g, m, partials);
-    else hipLaunchKernelGGL((k_stencil_lag<T, false, 1, CH>), grid, blk, 0, s, uu, xx, VV, ldv, cnt, g, m, partials);
-  }
+#define KRY_SLAG(C)                                                                                     \
+  if (mu) hipLaunchKernelGGL((k_stencil_lag<T, true, C, CH>), grid, blk, 0, s, uu, xx, VV, ldv, cnt, g, m, partials); \
+  else hipLaunchKernelGGL((k_stencil_lag<T, false, C, CH>), grid, blk, 0, s, uu, xx, VV, ldv, cnt, g, m, partials);
+  KRY_CPT_SWITCH(cpt, KRY_SLAG)
+#undef KRY_SLAG
   return hipGetLastError();
 }
 
@@ -852,14 +856,13 @@ static hipError_t lag_update_t(const void* u, const void* x, const void* V, long
                                const double* co, void* vnew, void* unext, const DevGrid& g,
                                hipStream_t s) {
   if (cnt > kMaxCoef) return hipErrorInvalidValue;
-  const int cpt = cells_per_thread(g.N3);
-  const dim3 grid(cell_blocks(g.N3)), blk(kBlock);
-  if (cpt == 4)
-    hipLaunchKernelGGL((k_lag_update<T, 4>), grid, blk, 0, s, (const T*)u, (const T*)x, (const T*)V,
-                       ldv, cnt, co, (T*)vnew, (T*)unext, g.N3);
-  else
-    hipLaunchKernelGGL((k_lag_update<T, 1>), grid, blk, 0, s, (const T*)u, (const T*)x, (const T*)V,
-                       ldv, cnt, co, (T*)vnew, (T*)unext, g.N3);
+  const int cpt = g.cpt_u;
+  const dim3 grid(cell_blocks(g.N3, cpt)), blk(kBlock);
+#define KRY_LUPD(C)                                                                                \
+  hipLaunchKernelGGL((k_lag_update<T, C>), grid, blk, 0, s, (const T*)u, (const T*)x, (const T*)V, \
+                     ldv, cnt, co, (T*)vnew, (T*)unext, g.N3);
+  KRY_CPT_SWITCH(cpt, KRY_LUPD)
+#undef KRY_LUPD
   return hipGetLastError();
 }
 
@@ -886,18 +889,16 @@ hipError_t launch_lag_final(const double* red, int m, double* H, int ldh, double
 template <typename T>
 static hipError_t dots_t(const void* x, const void* V, long long ldv, int cnt, const DevGrid& g,
                          const DevMats& m, double* partials, hipStream_t s) {
-  const int cpt = cells_per_thread(g.N3);
-  const dim3 grid(cell_blocks(g.N3)), blk(kBlock);
+  const int cpt = g.cpt_d;
+  const dim3 grid(cell_blocks(g.N3, cpt)), blk(kBlock);
   const bool mu = m.inv_mu != nullptr;
   const T* xx = (const T*)x;
   const T* VV = (const T*)V;
-  if (cpt == 4) {
-    if (mu) hipLaunchKernelGGL((k_dots<T, true, 4>), grid, blk, 0, s, xx, VV, ldv, cnt, g, m, partials);
-    else hipLaunchKernelGGL((k_dots<T, false, 4>), grid, blk, 0, s, xx, VV, ldv, cnt, g, m, partials);
-  } else {
-    if (mu) hipLaunchKernelGGL((k_dots<T, true, 1>), grid, blk, 0, s, xx, VV, ldv, cnt, g, m, partials);
-    else hipLaunchKernelGGL((k_dots<T, false, 1>), grid, blk, 0, s, xx, VV, ldv, cnt, g, m, partials);
-  }
+#define KRY_DOTS(C)                                                                                   \
+  if (mu) hipLaunchKernelGGL((k_dots<T, true, C>), grid, blk, 0, s, xx, VV, ldv, cnt, g, m, partials); \
+  else hipLaunchKernelGGL((k_dots<T, false, C>), grid, blk, 0, s, xx, VV, ldv, cnt, g, m, partials);
+  KRY_CPT_SWITCH(cpt, KRY_DOTS)
+#undef KRY_DOTS
   return hipGetLastError();
 }
 
@@ -911,14 +912,13 @@ template <typename T>
 static hipError_t update_t(const void* w, const void* V, long long ldv, int cnt, const double* coef,
                            const double* scale, void* out, const DevGrid& g, hipStream_t s) {
   if (cnt > kMaxCoef) return hipErrorInvalidValue;
-  const int cpt = cells_per_thread(g.N3);
-  const dim3 grid(cell_blocks(g.N3)), blk(kBlock);
-  if (cpt == 4)
-    hipLaunchKernelGGL((k_update<T, 4>), grid, blk, 0, s, (const T*)w, (const T*)V, ldv, cnt, coef,
-                       scale, (T*)out, g.N3);
-  else
-    hipLaunchKernelGGL((k_update<T, 1>), grid, blk, 0, s, (const T*)w, (const T*)V, ldv, cnt, coef,
-                       scale, (T*)out, g.N3);
+  const int cpt = g.cpt_u;
+  const dim3 grid(cell_blocks(g.N3, cpt)), blk(kBlock);
+#define KRY_UPD(C)                                                                                  \
+  hipLaunchKernelGGL((k_update<T, C>), grid, blk, 0, s, (const T*)w, (const T*)V, ldv, cnt, coef,   \
+                     scale, (T*)out, g.N3);
+  KRY_CPT_SWITCH(cpt, KRY_UPD)
+#undef KRY_UPD
   return hipGetLastError();
 }
 

@@ -534,3 +534,25 @@ def test_graph_replay_matches_eager_bitwise():
     V1, H1, b1, s1 = eager.arnoldi(_t(v), 20)
     V2, H2, b2, s2 = graph.arnoldi(_t(v), 20)
     assert np.array_equal(H1, H2) and np.array_equal(V1.cpu().numpy(), V2.cpu().numpy())
+
+
+# --------------------------------------------------------------- autotuner --
+
+def test_autotune_choice_and_results(tmp_path):
+    _announce("autotune")
+    wl = wk.small(40, seed=16, n_spheres=30, layer=4, T=40.0, krylov_dim=32, tol=1e-9)
+    inp = wk.generate(wl)
+    b = _t(wk.source_vector(wl, wl.omegas[0], 0.0)[None, :])
+    s0 = _solver(inp.eps, None, inp.sigma, krylov_dim=32, tol=1e-9)
+    y0 = s0.solve_multifreq(wl.omegas, b, wl.T).cpu().numpy()
+    s1 = _solver(inp.eps, None, inp.sigma, krylov_dim=32, tol=1e-9)
+    cache = str(tmp_path / "tune.json")
+    t = s1.autotune(cache=cache)
+    _announce(f"autotune {t}")
+    assert t["cpt_stencil"] in (1, 2, 4) and t["cpt_update"] in (1, 2, 4)
+    assert all(x > 0 for x in t["us_stencil"] + t["us_update"] + t["us_dots"])
+    y1 = s1.solve_multifreq(wl.omegas, b, wl.T).cpu().numpy()
+    assert _rel(y1, y0) <= 1e-10
+    s2 = _solver(inp.eps, None, inp.sigma, krylov_dim=32, tol=1e-9)
+    t2 = s2.autotune(cache=cache)
+    assert t2["cached"] and t2["cpt_update"] == t["cpt_update"]
