@@ -27,6 +27,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_128cube_traffic.md")
+CLASS_KERNEL = {"stencil_dots": "k_stencil_lag", "gs_update": "k_lag_update"}
+
+
+def measured_traffic(kernel_class, workload):
+    """HBM bytes per launch of the class's kernel from the committed counter
+    summary, or None if there is none or the kernel source changed since."""
+    import hashlib
+    import re
+    if workload != "c2" or kernel_class not in CLASS_KERNEL or not os.path.exists(TRAFFIC_FILE):
+        return None
+    src = os.path.join(ROOT, "paper_1707_00023_amd", "csrc", "kry_kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    pat = re.compile(r"traffic_bytes_per_launch (\S+) (\S+) source_sha256_16 (\S+)")
+    for line in open(TRAFFIC_FILE):
+        m = pat.search(line)
+        if m and m.group(1) == CLASS_KERNEL[kernel_class] and m.group(3) == h:
+            return float(m.group(2))
+    return None
 
 
 def cpu_baseline(wl, inp):
@@ -243,7 +262,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "avg_launch_us": float(kms[dom] / max(kl[dom], 1) * 1e3),
                      "alg_bytes_per_launch": float(kb[dom] / max(kl[dom], 1)),
-                     "traffic": None},
+                     "traffic": measured_traffic(kry.KERNEL_CLASSES[dom], args.workload)},
         "launch_shapes": tune,
         "converged": bool(last["converged"]),
         "max_residual": last["max_residual"],
