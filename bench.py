@@ -122,6 +122,43 @@ def compare_batched(args, wl, inp, dev):
 COPY_BYTES = 1 << 30
 
 
+def precision_compare(args, wl, inp, dev):
+    """FP32 storage (FP32 stencil, FP64 reductions and small dense) against
+    an FP64 run of the same frequencies; relative 2-norm error per omega."""
+    import numpy as np
+    import torch
+
+    import paper_1707_00023_amd as kry
+    import workloads as wk
+
+    eps = torch.as_tensor(inp.eps, device=dev)
+    sig = torch.as_tensor(inp.sigma, device=dev)
+    om = list(wl.omegas[: args.n_omega])
+    b = torch.as_tensor(wk.source_vector(wl, om[0], 0.0)[None, :], device=dev)
+    out = {"metric": "FP32-storage error vs FP64 GPU run, per omega", "workload": wl.name,
+           "n": wl.n, "omegas": om, "T": wl.T, "krylov_dim": wl.krylov_dim}
+    ys = {}
+    for name, storage, tol in (("f32", "f32", wl.tol), ("f64", "f64", 1e-8)):
+        s = kry.Solver(eps, None, sig, kry.Options(storage=storage, krylov_dim=wl.krylov_dim,
+                                                   tol=tol, verbose=True))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y = s.solve_multifreq(om, b, wl.T)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = s.last_stats
+        ys[name] = y
+        out[name] = {"tol": tol, "s": dt, "matvecs_stationary": st["matvecs_stationary"],
+                     "matvecs_transient": st["matvecs_transient"], "converged": bool(st["converged"]),
+                     "gcell_updates_per_s": wl.N ** 3 * (st["matvecs_stationary"] + st["matvecs_transient"]) / dt / 1e9}
+        print(f"[bench] {name}: {dt:.1f} s", file=sys.stderr, flush=True)
+        s.close()
+    err = (torch.linalg.norm(ys["f32"] - ys["f64"], dim=1) / torch.linalg.norm(ys["f64"], dim=1))
+    out["rel_err_per_omega"] = [float(e) for e in err.cpu()]
+    out["speedup_f32_over_f64"] = out["f64"]["s"] / out["f32"]["s"]
+    print(json.dumps(out), flush=True)
+
+
 def traffic_probe(args, wl, inp, dev):
     """Two Arnoldi cycles (m = the workload's Krylov dimension) on the
     workload's grid, then one device copy of COPY_BYTES (the calibration
@@ -174,6 +211,10 @@ def main():
     ap.add_argument("--block-width", type=int, default=16)
     ap.add_argument("--block-steps", type=int, default=16)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--precision-compare", action="store_true",
+                    help="FP32-storage solve of the first --n-omega frequencies against an "
+                         "FP64 solve of the same columns on the GPU")
+    ap.add_argument("--n-omega", type=int, default=2)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run two Arnoldi cycles on the workload's grid and a calibration "
                          "copy of known size (for hardware-counter runs), then exit")
@@ -198,6 +239,9 @@ def main():
         return
     if args.traffic_probe:
         traffic_probe(args, wl, inp, dev)
+        return
+    if args.precision_compare:
+        precision_compare(args, wl, inp, dev)
         return
     eps = torch.as_tensor(inp.eps, device=dev)
     sig = torch.as_tensor(inp.sigma, device=dev)

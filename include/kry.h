@@ -84,6 +84,8 @@ typedef struct {
                            column at a time (single-vector exponential);
                            k > 0 = block exponential, k block steps per
                            restart in time                                */
+  int32_t verbose;      /* 1: one progress line on stderr per 20 restart
+                           cycles / time steps (long solves)              */
   int32_t orth;         /* Gram-Schmidt: 0 = classical twice with the second
                            projection delayed by one step (two basis sweeps
                            per step, default); 1 = classical twice, both

@@ -41,7 +41,8 @@ class KryOpts(ctypes.Structure):
                 ("block_width", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("inner_product", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("timing", ctypes.c_int32), ("block_steps", ctypes.c_int32),
-                ("block_steps_transient", ctypes.c_int32), ("orth", ctypes.c_int32)]
+                ("block_steps_transient", ctypes.c_int32), ("verbose", ctypes.c_int32),
+                ("orth", ctypes.c_int32)]
 
 
 class KryStats(ctypes.Structure):
@@ -138,6 +139,7 @@ class Options:
     orth: str = "delayed"       # "delayed" (two basis sweeps per step) or "cgs2"
     block_width: int = 0        # > 1: batched form, groups of block_width/2 columns
     use_graph: bool = False     # replay captured Arnoldi cycles (HIP graphs)
+    verbose: bool = False       # progress lines on stderr during long solves
     block_steps: int = 0        # batched shifted solves: block steps per restart (0 auto)
     block_steps_transient: int = 0  # batched exponential: block steps per restart (0 auto)
 
@@ -171,7 +173,8 @@ class Solver:
                             int(bool(opts.use_graph)), 0,
                             _stream_ptr().value,
                             int(bool(opts.timing)), opts.block_steps,
-                            opts.block_steps_transient, 1 if opts.orth == "cgs2" else 0)
+                            opts.block_steps_transient, int(bool(opts.verbose)),
+                            1 if opts.orth == "cgs2" else 0)
         self.storage = opts.storage
         ctx = ctypes.c_void_p()
         rc = lib.kry_create(ctypes.byref(self.grid), _ptr(e),

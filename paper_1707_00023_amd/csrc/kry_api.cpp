@@ -528,6 +528,8 @@ int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> 
                                   c->d_colmap, 1, c->g, c->stream));
       tend(c, e, KRY_K_COMBINE, vbytes(c) * (me + 4.0 * ncol));
     }
+    if (c->opts.verbose && (cyc + 1) % 20 == 0)
+      std::fprintf(stderr, "[kry] shifted solve cycle %d: largest relative residual %.3e\n", cyc + 1, worst);
     bool any = false;
     for (int k = 0; k < nw; ++k) any |= active[k] != 0;
     if (!any || exact) {
@@ -611,6 +613,8 @@ int expv_slot0(kry_ctx* c, double T, double abstol, double drop, kry_stats* st, 
       if (t + tau > T * (1.0 - 1e-15)) tau = tmax;
     }
     err += step_err;
+    if (c->opts.verbose && steps % 20 == 0)
+      std::fprintf(stderr, "[kry] exponential step %d: t = %.4g of %.4g\n", steps, t + tau, T);
     KRY_HIP(hipMemcpyAsync(c->d_Y, u.data(), sizeof(double) * me, hipMemcpyHostToDevice, c->stream));
     hipEvent_t e = tbeg(c);
     KRY_HIP(kry::launch_combine(c->st, c->V, c->ldv, me, c->d_Y, 1, slot(c, 0), c->ldv, nullptr, 0,
@@ -1138,6 +1142,8 @@ int block_stationary(kry_ctx* c, const std::vector<const double*>& bcols, const 
     }
     rc = block_gemm(c, bslot(c, 0), K, Yz, 2 * g, zcol(c, 0), 1.0, 1);
     if (rc) return rc;
+    if (c->opts.verbose && (cyc + 1) % 20 == 0)
+      std::fprintf(stderr, "[kry] block shifted solve cycle %d: largest relative residual %.3e\n", cyc + 1, worst);
     nact = 0;
     for (int k = 0; k < g; ++k) nact += active[k];
     if (nact == 0) break;
