@@ -76,6 +76,22 @@ def cpu_baseline(wl, inp):
                        f"extrapolated linearly to T={wl.T:g} and all {len(wl.omegas)} omega")}
 
 
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def _kernel_entry(st, i):
+    """Per-class totals of one solve: time, launches, GB/s and (matrix-core
+    classes) TFLOP/s against the FP64 matrix peak."""
+    ms = st["kernel_ms"][i]
+    e = {"ms": ms, "launches": st["kernel_launches"][i],
+         "gbs": st["kernel_bytes"][i] / (ms * 1e6) if ms > 0 else 0.0}
+    if st["kernel_flops"][i] > 0 and ms > 0:
+        tf = st["kernel_flops"][i] / (ms * 1e9)
+        e["tflops"] = tf
+        e["mfma_frac"] = tf / FP64_MFMA_PEAK_TFLOPS
+    return e
+
+
 def compare_batched(args, wl, inp, dev):
     """Batched (block) vs plain solves of the same columns, same tolerance."""
     import numpy as np
@@ -107,10 +123,8 @@ def compare_batched(args, wl, inp, dev):
                      "stationary_s": st["ms_stationary"] / 1e3, "transient_s": st["ms_transient"] / 1e3,
                      "matvecs_stationary": st["matvecs_stationary"],
                      "matvecs_transient": st["matvecs_transient"],
-                     "kernels": {k: {"ms": st["kernel_ms"][i],
-                                     "gbs": (st["kernel_bytes"][i] / (st["kernel_ms"][i] * 1e6)
-                                             if st["kernel_ms"][i] > 0 else 0.0)}
-                                 for i, k in enumerate(kry.KERNEL_CLASSES)}}
+                     "kernels": {k: _kernel_entry(st, i) for i, k in enumerate(kry.KERNEL_CLASSES)
+                                 if st["kernel_launches"][i] > 0}}
         print(f"[bench] {name}: {dt:.1f} s", file=sys.stderr, flush=True)
         s.close()
     d = np.linalg.norm(ys["batched"] - ys["plain"], axis=1) / np.linalg.norm(ys["plain"], axis=1)

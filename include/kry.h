@@ -97,7 +97,9 @@ typedef struct {
 #define KRY_K_UPDATE 1  /* w -= V h (multi-vector update), two per step    */
 #define KRY_K_DOTS 2    /* second Gram-Schmidt dot pass                    */
 #define KRY_K_COMBINE 3 /* basis combinations V Y                          */
-#define KRY_K_CLASSES 4
+#define KRY_K_GRAM 4    /* block form: Gram products V^T M W (matrix cores) */
+#define KRY_K_GEMM 5    /* block form: updates W -= V C (matrix cores)      */
+#define KRY_K_CLASSES 6
 
 typedef struct {
   int64_t matvecs_stationary; /* operator applications, shifted solves     */
@@ -111,11 +113,14 @@ typedef struct {
   double ms_total;
   int32_t converged;          /* 1 if every column met its target          */
   /* filled when kry_opts.timing = 1 (else zero), per kernel class:
-     summed HIP-event durations, launches, and algorithmic bytes (each
-     vector read or written once, materials once per cell)              */
+     summed HIP-event durations, launches, algorithmic bytes (each
+     vector read or written once, materials once per cell) and
+     algorithmic FP64 flops of the matrix-core products (2 per
+     multiply-add; zero for the streaming classes)                     */
   double kernel_ms[KRY_K_CLASSES];
   int64_t kernel_launches[KRY_K_CLASSES];
   double kernel_bytes[KRY_K_CLASSES];
+  double kernel_flops[KRY_K_CLASSES];
 } kry_stats;
 
 /* Create a context for the grid and per-cell materials.

@@ -51,8 +51,8 @@ class KryStats(ctypes.Structure):
                 ("max_residual", ctypes.c_double), ("max_err_estimate", ctypes.c_double),
                 ("ms_stationary", ctypes.c_double), ("ms_transient", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("converged", ctypes.c_int32),
-                ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_int64 * 4),
-                ("kernel_bytes", ctypes.c_double * 4)]
+                ("kernel_ms", ctypes.c_double * 6), ("kernel_launches", ctypes.c_int64 * 6),
+                ("kernel_bytes", ctypes.c_double * 6), ("kernel_flops", ctypes.c_double * 6)]
 
     def as_dict(self):
         out = {}
@@ -62,7 +62,7 @@ class KryStats(ctypes.Structure):
         return out
 
 
-KERNEL_CLASSES = ("stencil_dots", "gs_update", "gs_dots", "combine")
+KERNEL_CLASSES = ("stencil_dots", "gs_update", "gs_dots", "combine", "block_gram", "block_gemm")
 
 
 class KryTune(ctypes.Structure):

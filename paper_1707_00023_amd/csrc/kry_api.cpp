@@ -69,13 +69,14 @@ struct kry_ctx {
   struct Pending {
     int cls;
     hipEvent_t a, b;
-    double bytes;
+    double bytes, flops;
   };
   std::vector<hipEvent_t> ev_pool;
   std::vector<Pending> pending;
   double k_ms[KRY_K_CLASSES] = {};
   long long k_launch[KRY_K_CLASSES] = {};
   double k_bytes[KRY_K_CLASSES] = {};
+  double k_flops[KRY_K_CLASSES] = {};
 
   std::string err;
 };
@@ -121,12 +122,12 @@ hipEvent_t tbeg(kry_ctx* c) {
   return a;
 }
 
-void tend(kry_ctx* c, hipEvent_t a, int cls, double bytes) {
+void tend(kry_ctx* c, hipEvent_t a, int cls, double bytes, double flops = 0.0) {
   if (!a) return;
   hipEvent_t b = take_event(c);
   if (!b) return;
   hipEventRecord(b, c->stream);
-  c->pending.push_back({cls, a, b, bytes});
+  c->pending.push_back({cls, a, b, bytes, flops});
 }
 
 // Fold completed event pairs into the per-class totals (after a stream sync).
@@ -137,6 +138,7 @@ void tresolve(kry_ctx* c) {
       c->k_ms[p.cls] += ms;
       c->k_launch[p.cls] += 1;
       c->k_bytes[p.cls] += p.bytes;
+      c->k_flops[p.cls] += p.flops;
     }
     c->ev_pool.push_back(p.a);
     c->ev_pool.push_back(p.b);
@@ -145,7 +147,8 @@ void tresolve(kry_ctx* c) {
 }
 
 void treset(kry_ctx* c) {
-  for (int k = 0; k < KRY_K_CLASSES; ++k) c->k_ms[k] = c->k_bytes[k] = 0.0, c->k_launch[k] = 0;
+  for (int k = 0; k < KRY_K_CLASSES; ++k)
+    c->k_ms[k] = c->k_bytes[k] = c->k_flops[k] = 0.0, c->k_launch[k] = 0;
 }
 
 void texport(kry_ctx* c, kry_stats* st) {
@@ -155,6 +158,7 @@ void texport(kry_ctx* c, kry_stats* st) {
     st->kernel_ms[k] = c->k_ms[k];
     st->kernel_launches[k] = c->k_launch[k];
     st->kernel_bytes[k] = c->k_bytes[k];
+    st->kernel_flops[k] = c->k_flops[k];
   }
 }
 
@@ -975,7 +979,7 @@ int block_gram_host(kry_ctx* c, const void* X, int M, const void* Y, int N, std:
   if (rc) return rc;
   hipEvent_t e = tbeg(c);
   KRY_HIP(kry::launch_gram(c->st, X, M, Y, N, c->ldv, c->d_w, c->n, c->d_gp, ns, c->stream));
-  tend(c, e, KRY_K_DOTS, vbytes(c) * (M + N) + 8.0 * c->n);
+  tend(c, e, KRY_K_GRAM, vbytes(c) * (M + N) + 8.0 * c->n, 2.0 * c->n * M * N);
   KRY_HIP(kry::launch_reduce(c->d_gp, ns, M * N, M * N, c->d_bc, c->stream));
   C.resize((size_t)M * N);
   KRY_HIP(hipMemcpyAsync(C.data(), c->d_bc, sizeof(double) * M * N, hipMemcpyDeviceToHost, c->stream));
@@ -991,7 +995,7 @@ int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, i
   KRY_HIP(hipMemcpyAsync(c->d_bc, C.data(), sizeof(double) * M * N, hipMemcpyHostToDevice, c->stream));
   hipEvent_t e = tbeg(c);
   KRY_HIP(kry::launch_gemm_nn(c->st, X, M, c->d_bc, N, Out, c->ldv, c->n, alpha, accumulate, c->stream));
-  tend(c, e, KRY_K_UPDATE, vbytes(c) * (M + (accumulate ? 2.0 : 1.0) * N));
+  tend(c, e, KRY_K_GEMM, vbytes(c) * (M + (accumulate ? 2.0 : 1.0) * N), 2.0 * c->n * M * N);
   // the host array may be reused by the caller right after
   KRY_HIP(hipStreamSynchronize(c->stream));
   return KRY_OK;

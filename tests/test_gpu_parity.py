@@ -339,6 +339,42 @@ def test_solve_c2_against_oracle_samples():
         assert abs(projection_vector(wl.n, k) @ y - p) <= 4e-8 * nrm
 
 
+GOLD_C3 = os.path.join(ROOT, "tests", "golden", "c3_yT_samples.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLD_C3), reason="c3 oracle samples not generated")
+def test_batched_c3_against_oracle_samples():
+    """Batched form at 96^3: four (omega, angle) columns of the 256-column
+    block, each with its own complex phase-ramp source, solved together in
+    one block Krylov space and compared with oracle samples."""
+    wl = wk.C3
+    _announce("batched solve c3 96^3, 4 golden columns, block width 8")
+    gold = json.load(open(GOLD_C3))
+    inp = wk.generate(wl)
+    cols = gold["columns"]
+    om = [wl.omegas[c["omega_index"]] for c in cols]
+    B = np.stack([wk.source_vector(wl, wl.omegas[c["omega_index"]],
+                                   float(inp.thetas[c["theta_index"]])) for c in cols])
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=wl.tol,
+                block_width=8, block_steps=16)
+    t0 = time.time()
+    y = s.solve_multifreq(om, _t(B), wl.T, b_per_omega=True).cpu().numpy()
+    _announce(f"c3 batched solve {time.time() - t0:.2f}s stats={s.last_stats}")
+    idx = np.asarray(gold["indices"])
+    import sys
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    from make_golden import projection_vector
+    P = [projection_vector(wl.n, k) for k in range(len(cols[0]["projections"]))]
+    for k, col in enumerate(cols):
+        assert abs(col["omega"] - om[k]) <= 1e-15 * om[k]
+        ref = np.asarray(col["values"])
+        nrm = col["norm2"]
+        assert np.linalg.norm(y[k, idx] - ref) <= 1e-8 * np.linalg.norm(ref)
+        assert abs(np.linalg.norm(y[k]) - nrm) <= 1e-8 * nrm
+        for p, pr in zip(P, col["projections"]):
+            assert abs(p @ y[k] - pr) <= 4e-8 * nrm
+
+
 # ---------------------------------------------------------- differentiation --
 
 def test_grad_matches_oracle_adjoint_and_fd():
