@@ -111,7 +111,7 @@ def compare_batched(args, wl, inp, dev):
     for name, bw in (("plain", 0), ("batched", args.block_width)):
         s = kry.Solver(eps, None, sig, kry.Options(krylov_dim=wl.krylov_dim, tol=wl.tol,
                                                    block_width=bw, block_steps=args.block_steps,
-                                                   timing=True))
+                                                   timing=True, s_step=args.s_step))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         y = s.solve_multifreq(om, B, wl.T)
@@ -154,7 +154,7 @@ def precision_compare(args, wl, inp, dev):
     ys = {}
     for name, storage, tol in (("f32", "f32", wl.tol), ("f64", "f64", 1e-8)):
         s = kry.Solver(eps, None, sig, kry.Options(storage=storage, krylov_dim=wl.krylov_dim,
-                                                   tol=tol, verbose=True))
+                                                   tol=tol, verbose=True, s_step=args.s_step))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         y = s.solve_multifreq(om, b, wl.T)
@@ -229,6 +229,8 @@ def main():
                     help="FP32-storage solve of the first --n-omega frequencies against an "
                          "FP64 solve of the same columns on the GPU")
     ap.add_argument("--n-omega", type=int, default=2)
+    ap.add_argument("--s-step", type=int, default=None,
+                    help="s-step Arnoldi block size (default: the library binding's default)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run two Arnoldi cycles on the workload's grid and a calibration "
                          "copy of known size (for hardware-counter runs), then exit")
@@ -248,6 +250,8 @@ def main():
     wl = wk.CONFIGS[args.workload]
     inp = wk.generate(wl)
     dev = torch.device("cuda:0")
+    if args.s_step is None:
+        args.s_step = kry.Options().s_step
     if args.compare_batched:
         compare_batched(args, wl, inp, dev)
         return
@@ -260,7 +264,7 @@ def main():
     eps = torch.as_tensor(inp.eps, device=dev)
     sig = torch.as_tensor(inp.sigma, device=dev)
     solver = kry.Solver(eps, None, sig, kry.Options(storage=wl.storage, krylov_dim=wl.krylov_dim,
-                                                    tol=wl.tol, timing=True))
+                                                    tol=wl.tol, timing=True, s_step=args.s_step))
     tune = None if args.no_autotune else solver.autotune()
     cols = [wk.source_vector(wl, w, float(th)) for w in wl.omegas for th in inp.thetas]
     b = torch.as_tensor(np.stack(cols), device=dev)
@@ -308,7 +312,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": f"{wl.N}^3", "unknowns": wl.n,
                    "n_omega": len(wl.omegas), "n_theta": wl.n_theta, "T": wl.T,
-                   "krylov_dim": wl.krylov_dim, "tol": wl.tol, "parallelism": "single-gpu"},
+                   "krylov_dim": wl.krylov_dim, "tol": wl.tol, "s_step": args.s_step,
+                   "parallelism": "single-gpu"},
         "gcell_updates_per_s": gcells,
         "matvecs": {"stationary": last["matvecs_stationary"], "transient": last["matvecs_transient"]},
         "phase_ms": {"stationary": last["ms_stationary"], "transient": last["ms_transient"]},

@@ -90,6 +90,12 @@ typedef struct {
                            projection delayed by one step (two basis sweeps
                            per step, default); 1 = classical twice, both
                            projections in the step (four sweeps)          */
+  int32_t s_step;       /* 0 or 1: one operator application per
+                           Gram-Schmidt step (as chosen by orth); s in
+                           2..16: s-step Arnoldi, s operator applications
+                           build a Chebyshev basis block that is
+                           orthogonalised as one tall-skinny block on the
+                           matrix cores (two basis sweeps per s steps)    */
 } kry_opts;
 
 /* Kernel classes reported by the per-kernel timing. */

@@ -42,7 +42,7 @@ class KryOpts(ctypes.Structure):
                 ("inner_product", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("timing", ctypes.c_int32), ("block_steps", ctypes.c_int32),
                 ("block_steps_transient", ctypes.c_int32), ("verbose", ctypes.c_int32),
-                ("orth", ctypes.c_int32)]
+                ("orth", ctypes.c_int32), ("s_step", ctypes.c_int32)]
 
 
 class KryStats(ctypes.Structure):
@@ -142,6 +142,7 @@ class Options:
     verbose: bool = False       # progress lines on stderr during long solves
     block_steps: int = 0        # batched shifted solves: block steps per restart (0 auto)
     block_steps_transient: int = 0  # batched exponential: block steps per restart (0 auto)
+    s_step: int = 0             # >= 2: s-step Arnoldi (Chebyshev block, matrix-core Gram-Schmidt)
 
 
 class Solver:
@@ -174,7 +175,7 @@ class Solver:
                             _stream_ptr().value,
                             int(bool(opts.timing)), opts.block_steps,
                             opts.block_steps_transient, int(bool(opts.verbose)),
-                            1 if opts.orth == "cgs2" else 0)
+                            1 if opts.orth == "cgs2" else 0, int(opts.s_step))
         self.storage = opts.storage
         ctx = ctypes.c_void_p()
         rc = lib.kry_create(ctypes.byref(self.grid), _ptr(e),

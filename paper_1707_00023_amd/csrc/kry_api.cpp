@@ -48,6 +48,9 @@ struct kry_ctx {
   int yrows = 0;  // rows of d_Y
   double* h_H = nullptr;     // pinned (mcap+1) x mcap
   double* h_scal = nullptr;  // pinned, 4 doubles
+  // half-width of the imaginary segment [-i rho, i rho] holding the
+  // spectrum of the curl part of A (bound 2 sqrt(3) / sqrt(min eps min mu))
+  double rho = 0.0;
 
   void* Z = nullptr;  // 2 * zcap columns (Re, Im per solution column)
   int zcap = 0;
@@ -194,7 +197,9 @@ int ensure_basis(kry_ctx* c, int m) {
   c->d_red1 = c->d_red2 = c->d_co = c->d_H = c->h_H = nullptr;
   c->mcap = 0;
   // slots 0..m: basis; m+1: candidate / work vector; m+2: operator output
-  const size_t vbytes = (size_t)(m + 3) * c->ldv * c->esz;
+  // (an s-step block uses slots m+1..m+s as its work block)
+  const int extra = std::max(2, c->opts.s_step);
+  const size_t vbytes = (size_t)(m + 1 + extra) * c->ldv * c->esz;
   if (hipMalloc(&c->V, vbytes) != hipSuccess) {
     c->V = nullptr;
     (void)hipGetLastError();
@@ -405,7 +410,10 @@ int arnoldi_lag(kry_ctx* c, int m, double* beta, int* m_eff) {
   return KRY_OK;
 }
 
+int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff);
+
 int arnoldi(kry_ctx* c, int m, double* beta, int* m_eff) {
+  if (c->opts.s_step > 1) return arnoldi_ca(c, m, beta, m_eff);
   return c->opts.orth == 1 ? arnoldi_cgs2(c, m, beta, m_eff) : arnoldi_lag(c, m, beta, m_eff);
 }
 
@@ -673,11 +681,15 @@ int kry_create(const kry_grid* grid, const double* eps, const double* mu, const 
     return fail(nullptr, KRY_EINVAL, "sigma is not a readable device array");
   if (!finite_all(he) || !finite_all(hm) || !finite_all(hs))
     return fail(nullptr, KRY_EINVAL, "non-finite material value");
+  double min_e = he[0], min_m = mu ? hm[0] : 1.0;
   for (long long i = 0; i < N3; ++i) {
     if (!(he[i] > 0.0)) return fail(nullptr, KRY_EINVAL, "eps must be > 0");
     if (mu && !(hm[i] > 0.0)) return fail(nullptr, KRY_EINVAL, "mu must be > 0");
     if (hs[i] < 0.0) return fail(nullptr, KRY_EINVAL, "sigma must be >= 0");
+    min_e = std::min(min_e, he[i]);
+    if (mu) min_m = std::min(min_m, hm[i]);
   }
+  if (opts->s_step < 0 || opts->s_step > 16) return fail(nullptr, KRY_EINVAL, "s_step out of range");
   c = new (std::nothrow) kry_ctx();
   if (!c) return fail(nullptr, KRY_ENOMEM, "host allocation failed");
   c->g.nx = grid->nx;
@@ -691,6 +703,9 @@ int kry_create(const kry_grid* grid, const double* eps, const double* mu, const 
   c->esz = opts->storage == 1 ? 4 : 8;
   c->opts = *opts;
   c->stream = (hipStream_t)opts->stream;
+  // |curl| <= 2 sqrt(3) on the unit grid (each component is a difference of
+  // two unit differences), scaled by the smallest eps and mu
+  c->rho = 2.0 * std::sqrt(3.0) / std::sqrt(min_e * min_m);
   // derived arrays: inv_eps, sigma (or sigma/mu), eps, [inv_mu, mu]
   const int narr = mu ? 5 : 3;
   std::vector<double> host((size_t)narr * N3);
@@ -935,11 +950,17 @@ namespace {
 
 void* bslot(kry_ctx* c, int i) { return (char*)c->BV + (size_t)i * c->ldv * c->esz; }
 
-int ensure_block(kry_ctx* c, int slots) {
+int ensure_weights(kry_ctx* c) {
   if (!c->d_w) {
     KRY_HIP(hipMalloc(&c->d_w, sizeof(double) * c->ldv));
     KRY_HIP(kry::launch_weights(c->mats.eps, c->mats.mu, c->d_w, c->g.N3, c->stream));
   }
+  return KRY_OK;
+}
+
+int ensure_block(kry_ctx* c, int slots) {
+  int rc = ensure_weights(c);
+  if (rc) return rc;
   if (slots > c->bslots || !c->BV) {
     hipFree(c->BV);
     c->BV = nullptr;
@@ -998,6 +1019,110 @@ int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, i
   tend(c, e, KRY_K_GEMM, vbytes(c) * (M + (accumulate ? 2.0 : 1.0) * N), 2.0 * c->n * M * N);
   // the host array may be reused by the caller right after
   KRY_HIP(hipStreamSynchronize(c->stream));
+  return KRY_OK;
+}
+
+// s-step Arnoldi (same contract as arnoldi_cgs2: start vector unnormalised
+// in slot 0; slots 0..m and h_H hold V_{m+1} and Hbar on return).  Each
+// block of s steps first applies the operator s times to build a Chebyshev
+// basis on the imaginary segment [-i rho, i rho] (where the spectrum of the
+// curl part lies): t_0 = v_j0, t_1 = A t_0 / rho, t_{k+1} = 2 A t_k / rho +
+// t_{k-1}, so that A [t_0..t_{s-1}] = rho [t_0..t_s] Tm with Tm[1][0] = 1,
+// Tm[k+1][k] = 1/2, Tm[k-1][k] = -1/2.  The block is then orthogonalised
+// against V_0..j0 by block classical Gram-Schmidt twice with a Cholesky QR
+// per pass, all as tall-skinny products on the matrix cores (V^T M T and
+// T - V C), two basis sweeps per s steps instead of two per step.  With
+// [t_0..t_s] = V_ext Rhat (Rhat from the projection coefficients and the
+// Cholesky factors), the new Hessenberg columns are exact algebra:
+//   Hbar[:, j0:j0+s] = (rho Rhat Tm - [Hbar_{j0} Rtop; 0]) Rs^{-1},
+// where Rtop and Rs are the rows of Rhat[:, :s] for V_0..j0-1 and for
+// v_j0..v_{j0+s-1}.  A block whose projected Gram matrix loses rank (an
+// invariant subspace, or too ill-conditioned a basis) sends the cycle to
+// the delayed Arnoldi from the same normalised start vector.
+int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
+  const int s = c->opts.s_step;
+  const int ldh = m + 1;
+  hipStream_t st = c->stream;
+  int rc = ensure_weights(c);
+  if (rc) return rc;
+  std::vector<double> d;
+  rc = host_dots(c, slot(c, 0), nullptr, 0, d);
+  if (rc) return rc;
+  double* H = c->h_H;
+  std::fill(H, H + (size_t)(m + 1) * m, 0.0);
+  const double b0 = std::sqrt(std::max(d[0], 0.0));
+  if (!(b0 > 0.0)) {
+    *beta = 0.0;
+    *m_eff = 0;
+    return KRY_OK;
+  }
+  // v_0 = start / b0 (d_red1[0] still holds |start|^2)
+  KRY_HIP(kry::launch_fin_start(c->d_red1, c->d_scal + 2, st));
+  KRY_HIP(kry::launch_scale(c->st, slot(c, 0), c->d_scal + 2, slot(c, 0), c->n, st));
+  const double rho = c->rho;
+  void* Tb = slot(c, c->mcap + 1);
+  const double mb_axpby = mbytes(c, true) - 8.0 * c->g.N3;
+  std::vector<double> C1, C2, G, R1, R2, Ri, ref;
+  for (int j0 = 0; j0 < m; j0 += s) {
+    const int ss = std::min(s, m - j0);
+    const int M = j0 + 1;
+    // Chebyshev block into slots j0+1..j0+ss
+    for (int k = 0; k < ss; ++k) {
+      hipEvent_t e = tbeg(c);
+      if (k == 0)
+        KRY_HIP(kry::launch_stencil_axpby(c->st, slot(c, j0), nullptr, slot(c, j0 + 1), 1.0 / rho, 0.0,
+                                          c->g, c->mats, st));
+      else
+        KRY_HIP(kry::launch_stencil_axpby(c->st, slot(c, j0 + k), slot(c, j0 + k - 1),
+                                          slot(c, j0 + k + 1), 2.0 / rho, 1.0, c->g, c->mats, st));
+      tend(c, e, KRY_K_STENCIL, vbytes(c) * (k == 0 ? 2.0 : 3.0) + mb_axpby);
+    }
+    void* S = slot(c, j0 + 1);
+    // pass 1: S -= V C1, R1 = chol(S^T M S), Tb = S R1^{-1}
+    rc = block_gram_host(c, slot(c, 0), M, S, ss, C1);
+    if (rc) return rc;
+    rc = block_gemm(c, slot(c, 0), M, C1, ss, S, -1.0, 1);
+    if (rc) return rc;
+    rc = block_gram_host(c, S, ss, S, ss, G);
+    if (rc) return rc;
+    ref.assign(ss, 0.0);
+    for (int k = 0; k < ss; ++k) {
+      double a = G[(size_t)k * ss + k];
+      for (int i = 0; i < M; ++i) a += C1[(size_t)i * ss + k] * C1[(size_t)i * ss + k];
+      ref[k] = a;
+    }
+    R1.resize((size_t)ss * ss);
+    R2.resize((size_t)ss * ss);
+    Ri.resize((size_t)ss * ss);
+    bool ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-10, R1.data());
+    if (ok) {
+      kry::inv_upper(ss, R1.data(), Ri.data());
+      rc = block_gemm(c, S, ss, Ri, ss, Tb, 1.0, 0);
+      if (rc) return rc;
+      // pass 2: Tb -= V C2, R2 = chol(Tb^T M Tb), S = Tb R2^{-1}
+      rc = block_gram_host(c, slot(c, 0), M, Tb, ss, C2);
+      if (rc) return rc;
+      rc = block_gemm(c, slot(c, 0), M, C2, ss, Tb, -1.0, 1);
+      if (rc) return rc;
+      rc = block_gram_host(c, Tb, ss, Tb, ss, G);
+      if (rc) return rc;
+      ref.assign(ss, 1.0);
+      ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-8, R2.data());
+    }
+    if (!ok) {  // dependent block: redo the cycle with one step per sweep
+      double b1 = 0.0;
+      rc = arnoldi_lag(c, m, &b1, m_eff);
+      *beta = b0 * b1;
+      return rc;
+    }
+    kry::inv_upper(ss, R2.data(), Ri.data());
+    rc = block_gemm(c, Tb, ss, Ri, ss, S, 1.0, 0);
+    if (rc) return rc;
+    kry::sstep_hessenberg(j0, ss, rho, C1.data(), C2.data(), R1.data(), R2.data(), H, ldh);
+  }
+  tresolve(c);
+  *beta = b0;
+  *m_eff = m;
   return KRY_OK;
 }
 

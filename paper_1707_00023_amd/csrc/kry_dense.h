@@ -76,4 +76,27 @@ void block_shift_lsq(int K, int q, int bw, const double* H, int ldh, cplx s, con
 double choose_step_block(int K, int q, int g, const double* H, int ldh, const double* U0,
                          double tau_try, const double* rate, int Ks, double* U, double* err);
 
+// Upper Cholesky factor R (p x p row-major, R^T R = G) of a symmetric
+// Gram matrix G (row-major).  Returns false when a pivot is not above
+// thr^2 ref[k] (ref[k]: squared norm of column k before any projection,
+// so a dependent direction is caught relative to its own size) or is not
+// finite.
+bool chol_upper(int p, const double* G, const double* ref, double thr, double* R);
+
+// X = R^{-1} for an upper-triangular p x p matrix R (both row-major).
+void inv_upper(int p, const double* R, double* X);
+
+// Hessenberg columns j0..j0+s-1 of an s-step Arnoldi block.  The block
+// [t_0..t_s] with t_0 = v_j0 obeys A [t_0..t_{s-1}] = rho [t_0..t_s] Tm
+// (Chebyshev basis on [-i rho, i rho]: Tm[1][0] = 1, Tm[k+1][k] = 1/2,
+// Tm[k-1][k] = -1/2).  Two projection passes gave t_k = V C1 + u_k,
+// u = q1 R1, q1 = V C2 + Q R2 (V = v_0..v_j0; C1, C2 (j0+1) x s row-major;
+// R1, R2 s x s upper row-major), so [t_1..t_s] = V (C1 + C2 R1) + Q R2 R1.
+// With [t_0..t_s] = V_ext Rhat this writes
+//   H[:, j0:j0+s] = (rho Rhat Tm - [H[:j0+1, :j0] Rtop; 0]) Rs^{-1}
+// into H (column-major, leading dimension ldh >= j0 + s + 1; columns < j0
+// already filled).  Entries below the first subdiagonal are left zero.
+void sstep_hessenberg(int j0, int s, double rho, const double* C1, const double* C2,
+                      const double* R1, const double* R2, double* H, int ldh);
+
 }  // namespace kry

@@ -48,6 +48,17 @@ int t_qr_pivoted(int m, int q, const double* S, double thr, double* Q, double* R
   return kry::qr_pivoted(m, q, S, thr, Q, Rf);
 }
 
+int t_chol_upper(int p, const double* G, const double* ref, double thr, double* R) {
+  return kry::chol_upper(p, G, ref, thr, R) ? 1 : 0;
+}
+
+void t_inv_upper(int p, const double* R, double* X) { kry::inv_upper(p, R, X); }
+
+void t_sstep_hessenberg(int j0, int s, double rho, const double* C1, const double* C2,
+                        const double* R1, const double* R2, double* H, int ldh) {
+  kry::sstep_hessenberg(j0, s, rho, C1, C2, R1, R2, H, ldh);
+}
+
 double t_choose_step_block(int K, int q, int g, const double* H, int ldh, const double* U0,
                            double tau_try, const double* rate, int Ks, double* U, double* err) {
   return kry::choose_step_block(K, q, g, H, ldh, U0, tau_try, rate, Ks, U, err);

@@ -105,11 +105,11 @@ def test_apply_at_c2_materials():
 
 # ---------------------------------------------------------------- Arnoldi --
 
-@pytest.mark.parametrize("orth", ["delayed", "cgs2"])
-def test_arnoldi_matches_definition_first_steps(orth):
-    _announce(f"arnoldi vs definition ({orth})")
+@pytest.mark.parametrize("orth,s_step", [("delayed", 0), ("cgs2", 0), ("delayed", 4)])
+def test_arnoldi_matches_definition_first_steps(orth, s_step):
+    _announce(f"arnoldi vs definition ({orth}, s_step {s_step})")
     eps, mu, sig = _box((6, 6, 6), 8)
-    s = _solver(eps, mu, sig, krylov_dim=8, orth=orth)
+    s = _solver(eps, mu, sig, krylov_dim=8, orth=orth, s_step=s_step)
     v = np.random.default_rng(3).standard_normal(6 * eps.size)
     m = 5
     V, H, beta, steps = s.arnoldi(_t(v), m)
@@ -120,12 +120,14 @@ def test_arnoldi_matches_definition_first_steps(orth):
     assert np.abs(V.cpu().numpy() - Vo.T).max() <= 1e-11 * np.abs(Vo).max()
 
 
-@pytest.mark.parametrize("m,orth", [(30, "delayed"), (64, "delayed"), (64, "cgs2")])
-def test_arnoldi_relation_and_orthogonality(m, orth):
-    _announce(f"arnoldi relation m={m} {orth}")
+@pytest.mark.parametrize("m,orth,s_step", [(30, "delayed", 0), (64, "delayed", 0), (64, "cgs2", 0),
+                                          (64, "delayed", 8), (30, "delayed", 7),
+                                          (32, "delayed", 16)])
+def test_arnoldi_relation_and_orthogonality(m, orth, s_step):
+    _announce(f"arnoldi relation m={m} {orth} s_step {s_step}")
     wl = wk.small(12, seed=4, n_spheres=5)
     inp = wk.generate(wl)
-    s = _solver(inp.eps, None, inp.sigma, krylov_dim=m, orth=orth)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=m, orth=orth, s_step=s_step)
     v = wk.random_state(wl.n, 9)
     V, H, beta, steps = s.arnoldi(_t(v), m)
     V = V.cpu().numpy().T
@@ -165,9 +167,9 @@ def test_delayed_equals_classical_twice():
     assert np.abs(Vd - Vc).max() <= 1e-10 * np.abs(Vc).max()
 
 
-@pytest.mark.parametrize("orth", ["delayed", "cgs2"])
-def test_arnoldi_happy_breakdown_on_separable_mode(orth):
-    _announce(f"arnoldi breakdown ({orth})")
+@pytest.mark.parametrize("orth,s_step", [("delayed", 0), ("cgs2", 0), ("delayed", 8)])
+def test_arnoldi_happy_breakdown_on_separable_mode(orth, s_step):
+    _announce(f"arnoldi breakdown ({orth}, s_step {s_step})")
     N = 6
     ones = np.ones((N, N, N))
     D = np.diag(-np.ones(N)) + np.diag(np.ones(N - 1), 1)
@@ -177,7 +179,7 @@ def test_arnoldi_happy_breakdown_on_separable_mode(orth):
     ex = np.einsum("k,j,i->kji", Vt[qz], Vt[qy], U[:, qx])
     v = np.zeros((6, N, N, N))
     v[3] = ex
-    s = _solver(2.0 * ones, None, 0.1 * ones, krylov_dim=20, orth=orth)
+    s = _solver(2.0 * ones, None, 0.1 * ones, krylov_dim=20, orth=orth, s_step=s_step)
     V, H, beta, steps = s.arnoldi(_t(v.reshape(-1)), 20)
     assert 1 <= steps <= 6
     Vn = V.cpu().numpy()
@@ -186,12 +188,12 @@ def test_arnoldi_happy_breakdown_on_separable_mode(orth):
 
 # ------------------------------------------------------------ exponential --
 
-@pytest.mark.parametrize("N,t", [(8, 13.0), (12, 40.0)])
-def test_expv_matches_oracle(N, t):
-    _announce(f"expv N={N} t={t}")
+@pytest.mark.parametrize("N,t,s_step", [(8, 13.0, 0), (12, 40.0, 0), (12, 40.0, 8)])
+def test_expv_matches_oracle(N, t, s_step):
+    _announce(f"expv N={N} t={t} s_step {s_step}")
     wl = wk.small(N, seed=N, n_spheres=4)
     inp = wk.generate(wl)
-    s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-10)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-10, s_step=s_step)
     rng = np.random.default_rng(5)
     v = rng.standard_normal((2, wl.n))
     y = s.expv(t, _t(v)).cpu().numpy()
@@ -202,13 +204,14 @@ def test_expv_matches_oracle(N, t):
 
 # ------------------------------------------------------- stationary part --
 
-def test_stationary_multishift_matches_oracle():
-    _announce("stationary multishift")
+@pytest.mark.parametrize("s_step", [0, 8])
+def test_stationary_multishift_matches_oracle(s_step):
+    _announce(f"stationary multishift s_step {s_step}")
     wl = wk.small(8, seed=2, n_spheres=4, layer=2)
     inp = wk.generate(wl)
     om = [2 * math.pi * 0.08, 2 * math.pi * 0.1, 2 * math.pi * 0.12]
     b = wk.source_vector(wl, om[0], 0.0)
-    s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-11)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-11, s_step=s_step)
     z = s.stationary(om, _t(b[None, :])).cpu().numpy()
     A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
     for k, w in enumerate(om):
@@ -231,12 +234,13 @@ def test_stationary_complex_source_per_omega():
 
 # ----------------------------------------------------------- full solves --
 
-def test_solve_c1_matches_oracle():
+@pytest.mark.parametrize("s_step", [0, 8])
+def test_solve_c1_matches_oracle(s_step):
     wl = wk.C1
-    _announce("solve c1 16^3")
+    _announce(f"solve c1 16^3 s_step {s_step}")
     inp = wk.generate(wl)
     b = wk.source_vector(wl, wl.omegas[0], 0.0)
-    s = _solver(inp.eps, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=wl.tol)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=wl.tol, s_step=s_step)
     y = s.solve_multifreq(wl.omegas, _t(b[None, :]), wl.T).cpu().numpy()[0]
     st = s.last_stats
     assert st["converged"] == 1
@@ -260,13 +264,14 @@ def test_solve_multi_source_multi_omega():
             assert _rel(y[k * 2 + si], ref) <= 1e-8
 
 
-def test_solve_fp32_storage():
-    _announce("solve fp32 storage")
+@pytest.mark.parametrize("s_step", [0, 8])
+def test_solve_fp32_storage(s_step):
+    _announce(f"solve fp32 storage s_step {s_step}")
     wl = wk.small(12, seed=7, n_spheres=6, layer=2, T=80.0)
     inp = wk.generate(wl)
     om = [2 * math.pi * 0.1]
     b = wk.source_vector(wl, om[0], 0.0)
-    s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-6, storage="f32")
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-6, storage="f32", s_step=s_step)
     y = s.solve_multifreq(om, _t(b[None, :]), wl.T).cpu().numpy()[0]
     A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
     y_or = osv.split_solution(A, b, om[0], wl.T)[0]

@@ -207,3 +207,105 @@ def test_qr_pivoted_resolves_to_rounding(lib):
     assert r == 6
     assert np.abs(Q[:, :r].T @ Q[:, :r] - np.eye(r)).max() < 1e-14
     assert np.abs(Q @ Rf - S).max() < 1e-13 * np.abs(S).max()
+
+
+# ------------------------------------------------------------ s-step Arnoldi --
+
+def _dissipative(rng, n):
+    """A = M^{-1}(S + K): K skew, S >= 0 diagonal, M > 0 diagonal."""
+    K = rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.08)
+    K = K - K.T
+    S = np.diag(0.3 * rng.random(n) * (rng.random(n) < 0.3))
+    w = 1.0 + 2.0 * rng.random(n)
+    return (S + K) / w[:, None], w
+
+
+def _arnoldi_mgs2(A, w, v0, m):
+    n = v0.size
+    V = np.zeros((n, m + 1))
+    H = np.zeros((m + 1, m))
+    V[:, 0] = v0 / np.sqrt(v0 @ (w * v0))
+    for j in range(m):
+        x = A @ V[:, j]
+        for _ in range(2):
+            for i in range(j + 1):
+                h = V[:, i] @ (w * x)
+                x = x - h * V[:, i]
+                H[i, j] += h
+        H[j + 1, j] = np.sqrt(x @ (w * x))
+        V[:, j + 1] = x / H[j + 1, j]
+    return V, H
+
+
+def _arnoldi_sstep(lib, A, w, v0, m, s, rho):
+    """The s-step cycle with the library's host algebra; the tall-skinny
+    products (done on the GPU by the library) are plain numpy here."""
+    n = v0.size
+    V = np.zeros((n, m + 1))
+    H = np.zeros((m + 1, m), order="F")
+    V[:, 0] = v0 / np.sqrt(v0 @ (w * v0))
+    j0 = 0
+    while j0 < m:
+        ss = min(s, m - j0)
+        M = j0 + 1
+        T = np.zeros((n, ss + 1))
+        T[:, 0] = V[:, j0]
+        T[:, 1] = A @ T[:, 0] / rho
+        for k in range(1, ss):
+            T[:, k + 1] = 2 * A @ T[:, k] / rho + T[:, k - 1]
+        Sb = T[:, 1:].copy()
+        Vb = V[:, :M]
+        C1 = np.ascontiguousarray(Vb.T @ (w[:, None] * Sb))
+        Sb -= Vb @ C1
+        G = np.ascontiguousarray(Sb.T @ (w[:, None] * Sb))
+        ref = np.diag(G) + (C1 ** 2).sum(axis=0)
+        R1 = np.zeros((ss, ss))
+        assert lib.t_chol_upper(ss, P(G), P(ref), ctypes.c_double(1e-10), P(R1)) == 1
+        Ri = np.zeros((ss, ss))
+        lib.t_inv_upper(ss, P(R1), P(Ri))
+        Tb = Sb @ Ri
+        C2 = np.ascontiguousarray(Vb.T @ (w[:, None] * Tb))
+        Tb -= Vb @ C2
+        G = np.ascontiguousarray(Tb.T @ (w[:, None] * Tb))
+        R2 = np.zeros((ss, ss))
+        assert lib.t_chol_upper(ss, P(G), P(np.ones(ss)), ctypes.c_double(1e-8), P(R2)) == 1
+        lib.t_inv_upper(ss, P(R2), P(Ri))
+        V[:, M:M + ss] = Tb @ Ri
+        lib.t_sstep_hessenberg(j0, ss, ctypes.c_double(rho), P(C1), P(C2), P(R1), P(R2), P(H), m + 1)
+        j0 += ss
+    return V, H
+
+
+@pytest.mark.parametrize("m,s", [(24, 8), (23, 5), (16, 16), (9, 2)])
+def test_sstep_arnoldi_host_algebra(lib, m, s):
+    rng = np.random.default_rng(40 + m + s)
+    n = 300
+    A, w = _dissipative(rng, n)
+    rho = float(np.abs(np.linalg.eigvals(A).imag).max())
+    v0 = rng.standard_normal(n)
+    V, H = _arnoldi_sstep(lib, A, w, v0, m, s, rho)
+    # Arnoldi relation, M-orthonormality, Hessenberg form with h_{j+1,j} > 0
+    assert np.abs(A @ V[:, :m] - V @ H).max() <= 1e-12 * np.abs(A).max()
+    assert np.abs(V.T @ (w[:, None] * V) - np.eye(m + 1)).max() <= 1e-12
+    assert np.all(np.tril(H, -2) == 0.0)
+    assert np.all(np.diag(H, -1) > 0.0)
+    # the Arnoldi factorisation is unique: same H as one-step Gram-Schmidt
+    Vr, Hr = _arnoldi_mgs2(A, w, v0, m)
+    assert np.abs(H - Hr).max() <= 1e-9 * np.abs(Hr).max()
+    assert np.abs(V - Vr).max() <= 1e-9 * np.abs(Vr).max()
+
+
+def test_chol_upper_flags_dependent_column(lib):
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((50, 4))
+    X[:, 2] = X[:, 0] - 0.5 * X[:, 1] + 1e-13 * rng.standard_normal(50)
+    G = np.ascontiguousarray(X.T @ X)
+    R = np.zeros((4, 4))
+    assert lib.t_chol_upper(4, P(G), P(np.diag(G).copy()), ctypes.c_double(1e-10), P(R)) == 0
+    Y = rng.standard_normal((50, 4))
+    G = np.ascontiguousarray(Y.T @ Y)
+    assert lib.t_chol_upper(4, P(G), P(np.diag(G).copy()), ctypes.c_double(1e-10), P(R)) == 1
+    assert np.abs(R.T @ R - G).max() <= 1e-12 * np.abs(G).max()
+    Ri = np.zeros((4, 4))
+    lib.t_inv_upper(4, P(R), P(Ri))
+    assert np.abs(Ri @ R - np.eye(4)).max() <= 1e-12
