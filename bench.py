@@ -154,7 +154,7 @@ def precision_compare(args, wl, inp, dev):
     ys = {}
     for name, storage, tol in (("f32", "f32", wl.tol), ("f64", "f64", 1e-8)):
         s = kry.Solver(eps, None, sig, kry.Options(storage=storage, krylov_dim=wl.krylov_dim,
-                                                   tol=tol, verbose=True, s_step=args.s_step))
+                                                   tol=tol, verbose=True, s_step=args.s_step_cli))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         y = s.solve_multifreq(om, b, wl.T)
@@ -250,8 +250,9 @@ def main():
     wl = wk.CONFIGS[args.workload]
     inp = wk.generate(wl)
     dev = torch.device("cuda:0")
+    args.s_step_cli = args.s_step
     if args.s_step is None:
-        args.s_step = kry.Options().s_step
+        args.s_step = 0 if wl.storage == "f32" else kry.DEFAULT_S_STEP
     if args.compare_batched:
         compare_batched(args, wl, inp, dev)
         return

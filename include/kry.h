@@ -92,10 +92,14 @@ typedef struct {
                            projections in the step (four sweeps)          */
   int32_t s_step;       /* 0 or 1: one operator application per
                            Gram-Schmidt step (as chosen by orth); s in
-                           2..16: s-step Arnoldi, s operator applications
+                           2..64: s-step Arnoldi, s operator applications
                            build a Chebyshev basis block that is
                            orthogonalised as one tall-skinny block on the
-                           matrix cores (two basis sweeps per s steps)    */
+                           matrix cores (two basis sweeps per s steps).  A
+                           block whose triangular factor has a condition
+                           estimate above 1e6 (FP64) or 1e2 (FP32 storage)
+                           is redone one step per sweep and halves s for
+                           the rest of the context's life                 */
 } kry_opts;
 
 /* Kernel classes reported by the per-kernel timing. */

@@ -62,6 +62,8 @@ class KryStats(ctypes.Structure):
         return out
 
 
+DEFAULT_S_STEP = 16
+
 KERNEL_CLASSES = ("stencil_dots", "gs_update", "gs_dots", "combine", "block_gram", "block_gemm")
 
 
@@ -142,7 +144,9 @@ class Options:
     verbose: bool = False       # progress lines on stderr during long solves
     block_steps: int = 0        # batched shifted solves: block steps per restart (0 auto)
     block_steps_transient: int = 0  # batched exponential: block steps per restart (0 auto)
-    s_step: int = 0             # >= 2: s-step Arnoldi (Chebyshev block, matrix-core Gram-Schmidt)
+    # s-step Arnoldi block size (Chebyshev block, matrix-core Gram-Schmidt);
+    # None: 16 with FP64 storage, 0 (one step per sweep) with FP32 storage
+    s_step: Optional[int] = None
 
 
 class Solver:
@@ -175,7 +179,9 @@ class Solver:
                             _stream_ptr().value,
                             int(bool(opts.timing)), opts.block_steps,
                             opts.block_steps_transient, int(bool(opts.verbose)),
-                            1 if opts.orth == "cgs2" else 0, int(opts.s_step))
+                            1 if opts.orth == "cgs2" else 0,
+                            int(opts.s_step if opts.s_step is not None
+                                else (0 if opts.storage == "f32" else DEFAULT_S_STEP)))
         self.storage = opts.storage
         ctx = ctypes.c_void_p()
         rc = lib.kry_create(ctypes.byref(self.grid), _ptr(e),

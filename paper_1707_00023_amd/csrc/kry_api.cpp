@@ -51,6 +51,9 @@ struct kry_ctx {
   // half-width of the imaginary segment [-i rho, i rho] holding the
   // spectrum of the curl part of A (bound 2 sqrt(3) / sqrt(min eps min mu))
   double rho = 0.0;
+  // s-step block size in use (opts.s_step, halved whenever a block's basis
+  // is too ill-conditioned for the Hessenberg algebra)
+  int s_eff = 0;
 
   void* Z = nullptr;  // 2 * zcap columns (Re, Im per solution column)
   int zcap = 0;
@@ -198,7 +201,7 @@ int ensure_basis(kry_ctx* c, int m) {
   c->mcap = 0;
   // slots 0..m: basis; m+1: candidate / work vector; m+2: operator output
   // (an s-step block uses slots m+1..m+s as its work block)
-  const int extra = std::max(2, c->opts.s_step);
+  const int extra = std::max(2, std::min(c->opts.s_step, m));
   const size_t vbytes = (size_t)(m + 1 + extra) * c->ldv * c->esz;
   if (hipMalloc(&c->V, vbytes) != hipSuccess) {
     c->V = nullptr;
@@ -413,7 +416,7 @@ int arnoldi_lag(kry_ctx* c, int m, double* beta, int* m_eff) {
 int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff);
 
 int arnoldi(kry_ctx* c, int m, double* beta, int* m_eff) {
-  if (c->opts.s_step > 1) return arnoldi_ca(c, m, beta, m_eff);
+  if (c->s_eff > 1) return arnoldi_ca(c, m, beta, m_eff);
   return c->opts.orth == 1 ? arnoldi_cgs2(c, m, beta, m_eff) : arnoldi_lag(c, m, beta, m_eff);
 }
 
@@ -689,7 +692,7 @@ int kry_create(const kry_grid* grid, const double* eps, const double* mu, const 
     min_e = std::min(min_e, he[i]);
     if (mu) min_m = std::min(min_m, hm[i]);
   }
-  if (opts->s_step < 0 || opts->s_step > 16) return fail(nullptr, KRY_EINVAL, "s_step out of range");
+  if (opts->s_step < 0 || opts->s_step > 64) return fail(nullptr, KRY_EINVAL, "s_step out of range");
   c = new (std::nothrow) kry_ctx();
   if (!c) return fail(nullptr, KRY_ENOMEM, "host allocation failed");
   c->g.nx = grid->nx;
@@ -706,6 +709,7 @@ int kry_create(const kry_grid* grid, const double* eps, const double* mu, const 
   // |curl| <= 2 sqrt(3) on the unit grid (each component is a difference of
   // two unit differences), scaled by the smallest eps and mu
   c->rho = 2.0 * std::sqrt(3.0) / std::sqrt(min_e * min_m);
+  c->s_eff = opts->s_step > 1 ? opts->s_step : 0;
   // derived arrays: inv_eps, sigma (or sigma/mu), eps, [inv_mu, mu]
   const int narr = mu ? 5 : 3;
   std::vector<double> host((size_t)narr * N3);
@@ -994,12 +998,14 @@ int ensure_gp(kry_ctx* c, size_t doubles, size_t bc) {
 
 // C (M x N, row-major, host) = X^T M Y for block columns X[:M], Y[:N]
 // (device pointers to the first column; stride ldv).  Synchronises.
-int block_gram_host(kry_ctx* c, const void* X, int M, const void* Y, int N, std::vector<double>& C) {
+// With X2 != nullptr, X is two segments (columns k >= M1 at X2).
+int block_gram_host(kry_ctx* c, const void* X, int M, const void* Y, int N, std::vector<double>& C,
+                    const void* X2 = nullptr, int M1 = 0) {
   const int ns = kry::gram_splits(c->n, M, N);
   int rc = ensure_gp(c, (size_t)ns * M * N, (size_t)M * N);
   if (rc) return rc;
   hipEvent_t e = tbeg(c);
-  KRY_HIP(kry::launch_gram(c->st, X, M, Y, N, c->ldv, c->d_w, c->n, c->d_gp, ns, c->stream));
+  KRY_HIP(kry::launch_gram(c->st, X, M, Y, N, c->ldv, c->d_w, c->n, c->d_gp, ns, c->stream, X2, M1));
   tend(c, e, KRY_K_GRAM, vbytes(c) * (M + N) + 8.0 * c->n, 2.0 * c->n * M * N);
   KRY_HIP(kry::launch_reduce(c->d_gp, ns, M * N, M * N, c->d_bc, c->stream));
   C.resize((size_t)M * N);
@@ -1009,13 +1015,15 @@ int block_gram_host(kry_ctx* c, const void* X, int M, const void* Y, int N, std:
 }
 
 // Out[:N] (=|+=) alpha X[:M] C with C (M x N row-major) from the host.
+// X in one or two segments as for block_gram_host.
 int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, int N, void* Out,
-               double alpha, int accumulate) {
+               double alpha, int accumulate, const void* X2 = nullptr, int M1 = 0) {
   int rc = ensure_gp(c, 0, (size_t)M * N);
   if (rc) return rc;
   KRY_HIP(hipMemcpyAsync(c->d_bc, C.data(), sizeof(double) * M * N, hipMemcpyHostToDevice, c->stream));
   hipEvent_t e = tbeg(c);
-  KRY_HIP(kry::launch_gemm_nn(c->st, X, M, c->d_bc, N, Out, c->ldv, c->n, alpha, accumulate, c->stream));
+  KRY_HIP(kry::launch_gemm_nn(c->st, X, M, c->d_bc, N, Out, c->ldv, c->n, alpha, accumulate, c->stream,
+                              X2, M1));
   tend(c, e, KRY_K_GEMM, vbytes(c) * (M + (accumulate ? 2.0 : 1.0) * N), 2.0 * c->n * M * N);
   // the host array may be reused by the caller right after
   KRY_HIP(hipStreamSynchronize(c->stream));
@@ -1030,8 +1038,10 @@ int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, i
 // t_{k-1}, so that A [t_0..t_{s-1}] = rho [t_0..t_s] Tm with Tm[1][0] = 1,
 // Tm[k+1][k] = 1/2, Tm[k-1][k] = -1/2.  The block is then orthogonalised
 // against V_0..j0 by block classical Gram-Schmidt twice with a Cholesky QR
-// per pass, all as tall-skinny products on the matrix cores (V^T M T and
-// T - V C), two basis sweeps per s steps instead of two per step.  With
+// per pass, all as tall-skinny products on the matrix cores: each pass is
+// one Gram product [V, S]^T M S (the projected Gram matrix follows by
+// Pythagoras) and one update (S - V C) R^{-1}, so a block of s steps costs
+// two sweeps over the basis instead of two per step.  With
 // [t_0..t_s] = V_ext Rhat (Rhat from the projection coefficients and the
 // Cholesky factors), the new Hessenberg columns are exact algebra:
 //   Hbar[:, j0:j0+s] = (rho Rhat Tm - [Hbar_{j0} Rtop; 0]) Rs^{-1},
@@ -1039,8 +1049,19 @@ int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, i
 // v_j0..v_{j0+s-1}.  A block whose projected Gram matrix loses rank (an
 // invariant subspace, or too ill-conditioned a basis) sends the cycle to
 // the delayed Arnoldi from the same normalised start vector.
+const std::vector<double>& stack_coef(int M, int s, const std::vector<double>& C,
+                                      const std::vector<double>& Rinv, std::vector<double>& K) {
+  K.resize((size_t)(M + s) * s);
+  kry::stack_coef(M, s, C.data(), Rinv.data(), K.data());
+  return K;
+}
+
 int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
-  const int s = c->opts.s_step;
+  const int s = c->s_eff;
+  // largest accepted condition estimate |R|_F |R^-1|_F of a block's
+  // triangular factor: errors of the stored basis reach Hbar amplified by
+  // it (FP64 storage: 1e-16 * 1e6; FP32 storage: 6e-8 * 1e2)
+  const double cond_max = c->st == kry::F64 ? 1e6 : 1e2;
   const int ldh = m + 1;
   hipStream_t st = c->stream;
   int rc = ensure_weights(c);
@@ -1062,7 +1083,7 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
   const double rho = c->rho;
   void* Tb = slot(c, c->mcap + 1);
   const double mb_axpby = mbytes(c, true) - 8.0 * c->g.N3;
-  std::vector<double> C1, C2, G, R1, R2, Ri, ref;
+  std::vector<double> C1, C2, G, P, R1, R2, Ri, ref, K;
   for (int j0 = 0; j0 < m; j0 += s) {
     const int ss = std::min(s, m - j0);
     const int M = j0 + 1;
@@ -1078,45 +1099,78 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
       tend(c, e, KRY_K_STENCIL, vbytes(c) * (k == 0 ? 2.0 : 3.0) + mb_axpby);
     }
     void* S = slot(c, j0 + 1);
-    // pass 1: S -= V C1, R1 = chol(S^T M S), Tb = S R1^{-1}
-    rc = block_gram_host(c, slot(c, 0), M, S, ss, C1);
-    if (rc) return rc;
-    rc = block_gemm(c, slot(c, 0), M, C1, ss, S, -1.0, 1);
-    if (rc) return rc;
-    rc = block_gram_host(c, S, ss, S, ss, G);
-    if (rc) return rc;
-    ref.assign(ss, 0.0);
-    for (int k = 0; k < ss; ++k) {
-      double a = G[(size_t)k * ss + k];
-      for (int i = 0; i < M; ++i) a += C1[(size_t)i * ss + k] * C1[(size_t)i * ss + k];
-      ref[k] = a;
-    }
     R1.resize((size_t)ss * ss);
     R2.resize((size_t)ss * ss);
     Ri.resize((size_t)ss * ss);
+    // pass 1: one Gram product [V, S]^T M S gives C1 = V^T M S and S^T M S,
+    // so the projected Gram matrix is S^T M S - C1^T C1 (Pythagoras; V is
+    // M-orthonormal); then Tb = (S - V C1) R1^{-1} in one product
+    rc = block_gram_host(c, slot(c, 0), M + ss, S, ss, P, S, M);
+    if (rc) return rc;
+    C1.assign(P.begin(), P.begin() + (size_t)M * ss);
+    G.resize((size_t)ss * ss);
+    ref.resize(ss);
+    kry::proj_gram(M, ss, P.data(), G.data(), ref.data());
     bool ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-10, R1.data());
     if (ok) {
       kry::inv_upper(ss, R1.data(), Ri.data());
-      rc = block_gemm(c, S, ss, Ri, ss, Tb, 1.0, 0);
+      rc = block_gemm(c, slot(c, 0), M + ss, stack_coef(M, ss, C1, Ri, K), ss, Tb, 1.0, 0, S, M);
       if (rc) return rc;
-      // pass 2: Tb -= V C2, R2 = chol(Tb^T M Tb), S = Tb R2^{-1}
-      rc = block_gram_host(c, slot(c, 0), M, Tb, ss, C2);
+    } else {
+      // cancellation in the projected Gram matrix: project explicitly
+      rc = block_gemm(c, slot(c, 0), M, C1, ss, S, -1.0, 1);
       if (rc) return rc;
-      rc = block_gemm(c, slot(c, 0), M, C2, ss, Tb, -1.0, 1);
+      rc = block_gram_host(c, S, ss, S, ss, G);
       if (rc) return rc;
-      rc = block_gram_host(c, Tb, ss, Tb, ss, G);
+      ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-10, R1.data());
+      if (ok) {
+        kry::inv_upper(ss, R1.data(), Ri.data());
+        rc = block_gemm(c, S, ss, Ri, ss, Tb, 1.0, 0);
+        if (rc) return rc;
+      }
+    }
+    if (ok) {
+      // pass 2, the same on Tb; the result Q lands in slots j0+1..j0+ss
+      rc = block_gram_host(c, slot(c, 0), M + ss, Tb, ss, P, Tb, M);
       if (rc) return rc;
-      ref.assign(ss, 1.0);
+      C2.assign(P.begin(), P.begin() + (size_t)M * ss);
+      G.resize((size_t)ss * ss);
+    ref.resize(ss);
+    kry::proj_gram(M, ss, P.data(), G.data(), ref.data());
+      std::fill(ref.begin(), ref.end(), 1.0);
       ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-8, R2.data());
     }
-    if (!ok) {  // dependent block: redo the cycle with one step per sweep
+    bool illc = false;
+    if (ok) {  // condition estimate of R = R2 R1
+      std::vector<double> R((size_t)ss * ss, 0.0), RI((size_t)ss * ss);
+      for (int a = 0; a < ss; ++a)
+        for (int k = a; k < ss; ++k) {
+          double v = 0.0;
+          for (int l = a; l <= k; ++l) v += R2[(size_t)a * ss + l] * R1[(size_t)l * ss + k];
+          R[(size_t)a * ss + k] = v;
+        }
+      kry::inv_upper(ss, R.data(), RI.data());
+      double f1 = 0.0, f2 = 0.0;
+      for (size_t i = 0; i < R.size(); ++i) f1 += R[i] * R[i], f2 += RI[i] * RI[i];
+      const double est = std::sqrt(f1 * f2);
+      illc = !(est <= cond_max);
+    }
+    if (!ok || illc) {
+      // dependent or ill-conditioned block: redo the cycle with one step per
+      // sweep; an ill-conditioned basis also halves s from here on
+      if (illc) {
+        c->s_eff = s / 2 >= 2 ? s / 2 : 0;
+        if (c->opts.verbose)
+          std::fprintf(stderr, "[kry] s-step basis ill-conditioned at s = %d: s = %d from now on\n", s,
+                       c->s_eff);
+      }
       double b1 = 0.0;
       rc = arnoldi_lag(c, m, &b1, m_eff);
       *beta = b0 * b1;
       return rc;
     }
     kry::inv_upper(ss, R2.data(), Ri.data());
-    rc = block_gemm(c, Tb, ss, Ri, ss, S, 1.0, 0);
+    rc = block_gemm(c, slot(c, 0), M + ss, stack_coef(M, ss, C2, Ri, K), ss, S, 1.0, 0, Tb, M);
     if (rc) return rc;
     kry::sstep_hessenberg(j0, ss, rho, C1.data(), C2.data(), R1.data(), R2.data(), H, ldh);
   }

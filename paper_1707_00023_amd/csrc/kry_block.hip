@@ -47,8 +47,11 @@ __device__ __forceinline__ void load4(const T* __restrict__ p, long long e, long
 // four MFMAs, the t-th taking entry e0 + 4 kk + t as its k = kk slot (a
 // permutation of the reduction order).  grid (nsplit, ceil(M / 64),
 // ceil(N / (16 NT))).  Out-of-range rows, columns and entries add zeros.
+// X is given in two segments: columns k < M1 at X + k ld, columns k >= M1
+// at X2 + (k - M1) ld (a basis and a block stored apart).
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void k_gram_tn(const T* __restrict__ X, int M,
+__global__ __launch_bounds__(256) void k_gram_tn(const T* __restrict__ X, int M1,
+                                                 const T* __restrict__ X2, int M,
                                                  const T* __restrict__ Y, int N, long long ld,
                                                  const double* __restrict__ w, long long n,
                                                  long long kchunk, double* __restrict__ partials) {
@@ -59,7 +62,8 @@ __global__ __launch_bounds__(256) void k_gram_tn(const T* __restrict__ X, int M,
   const long long e_begin = (long long)blockIdx.x * kchunk;
   const long long e_end = min(n, e_begin + kchunk);
   const bool arow = m0 + i < M;
-  const T* xc = X + (long long)(arow ? m0 + i : 0) * ld;
+  const int xr = arow ? m0 + i : 0;
+  const T* xc = xr < M1 ? X + (long long)xr * ld : X2 + (long long)(xr - M1) * ld;
   bool bcol[NT];
   const T* yc[NT];
 #pragma unroll
@@ -106,9 +110,11 @@ __global__ __launch_bounds__(256) void k_gram_tn(const T* __restrict__ X, int M,
 // consecutive entries per k: coalesced).  Per iteration a lane loads four
 // basis entries (k = k0 + 4u + kk, u = 0..3) before the 4 NT MFMAs, so
 // four independent loads are in flight.  grid (ceil(n / 64),
-// ceil(N / (16 NT))).  Out may not overlap X.
+// ceil(N / (16 NT))).  Out may not overlap X.  X in two segments as in
+// k_gram_tn (columns k >= M1 at X2 + (k - M1) ld).
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ X, int M,
+__global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ X, int M1,
+                                                 const T* __restrict__ X2, int M,
                                                  const double* __restrict__ C, int N,
                                                  T* __restrict__ Out, long long ld, long long n,
                                                  double alpha, int accumulate) {
@@ -126,7 +132,8 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ X, int M,
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = k0 + 4 * u + kk;
-      b[u] = (k < M && eok) ? (double)X[(long long)k * ld + e] : 0.0;
+      const T* xk = k < M1 ? X + (long long)k * ld : X2 + (long long)(k - M1) * ld;
+      b[u] = (k < M && eok) ? (double)xk[e] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -176,18 +183,23 @@ int gram_splits(long long n, int M, int N) {
 }
 
 hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, long long ld,
-                       const double* w, long long n, double* partials, int nsplit, hipStream_t s) {
+                       const double* w, long long n, double* partials, int nsplit, hipStream_t s,
+                       const void* X2, int M1) {
+  if (!X2) {  // one segment
+    M1 = M;
+    X2 = X;
+  }
   long long kchunk = (n + nsplit - 1) / nsplit;
   kchunk = (kchunk + 15) / 16 * 16;
   const int nt = N >= 64 ? 4 : (N + 15) / 16;
   const dim3 grid(nsplit, (M + 63) / 64, (N + 16 * nt - 1) / (16 * nt));
 #define KRY_GRAM(NT)                                                                        \
   if (st == F64)                                                                           \
-    hipLaunchKernelGGL((k_gram_tn<double, NT>), grid, dim3(256), 0, s, (const double*)X, M, \
-                       (const double*)Y, N, ld, w, n, kchunk, partials);                   \
+    hipLaunchKernelGGL((k_gram_tn<double, NT>), grid, dim3(256), 0, s, (const double*)X, M1, \
+                       (const double*)X2, M, (const double*)Y, N, ld, w, n, kchunk, partials); \
   else                                                                                     \
-    hipLaunchKernelGGL((k_gram_tn<float, NT>), grid, dim3(256), 0, s, (const float*)X, M,   \
-                       (const float*)Y, N, ld, w, n, kchunk, partials);
+    hipLaunchKernelGGL((k_gram_tn<float, NT>), grid, dim3(256), 0, s, (const float*)X, M1,   \
+                       (const float*)X2, M, (const float*)Y, N, ld, w, n, kchunk, partials);
   switch (nt) {
     case 1: KRY_GRAM(1) break;
     case 2: KRY_GRAM(2) break;
@@ -199,17 +211,22 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
 }
 
 hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int N, void* Out,
-                          long long ld, long long n, double alpha, int accumulate, hipStream_t s) {
+                          long long ld, long long n, double alpha, int accumulate, hipStream_t s,
+                          const void* X2, int M1) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (!X2) {
+    M1 = M;
+    X2 = X;
+  }
   const int nt = N >= 64 ? 4 : (N + 15) / 16;
   const dim3 grid((unsigned)((n + 63) / 64), (N + 16 * nt - 1) / (16 * nt));
 #define KRY_GEMM(NT)                                                                          \
   if (st == F64)                                                                             \
-    hipLaunchKernelGGL((k_gemm_nn<double, NT>), grid, dim3(256), 0, s, (const double*)X, M, C, \
-                       N, (double*)Out, ld, n, alpha, accumulate);                          \
+    hipLaunchKernelGGL((k_gemm_nn<double, NT>), grid, dim3(256), 0, s, (const double*)X, M1,  \
+                       (const double*)X2, M, C, N, (double*)Out, ld, n, alpha, accumulate);   \
   else                                                                                       \
-    hipLaunchKernelGGL((k_gemm_nn<float, NT>), grid, dim3(256), 0, s, (const float*)X, M, C,   \
-                       N, (float*)Out, ld, n, alpha, accumulate);
+    hipLaunchKernelGGL((k_gemm_nn<float, NT>), grid, dim3(256), 0, s, (const float*)X, M1,    \
+                       (const float*)X2, M, C, N, (float*)Out, ld, n, alpha, accumulate);
   switch (nt) {
     case 1: KRY_GEMM(1) break;
     case 2: KRY_GEMM(2) break;

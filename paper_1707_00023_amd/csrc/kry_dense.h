@@ -99,4 +99,15 @@ void inv_upper(int p, const double* R, double* X);
 void sstep_hessenberg(int j0, int s, double rho, const double* C1, const double* C2,
                       const double* R1, const double* R2, double* H, int ldh);
 
+// Projected Gram matrix of an s-column block S against an M-orthonormal
+// basis V from one product P = [V, S]^T M S ((M + s) x s, row-major):
+// G = S^T M S - C^T C with C = P[:M] (s x s, row-major) and ref[k] =
+// (S^T M S)_kk, the squared column norms before projection.
+void proj_gram(int M, int s, const double* P, double* G, double* ref);
+
+// Coefficients K ((M + s) x s, row-major) with [V, S] K = (S - V C) Rinv:
+// rows k < M are -(C Rinv)[k], rows M + a are Rinv[a] (C: M x s, Rinv:
+// s x s upper, both row-major).
+void stack_coef(int M, int s, const double* C, const double* Rinv, double* K);
+
 }  // namespace kry

@@ -118,12 +118,17 @@ hipError_t launch_stencil_cols(Storage st, const void* v, void* w, long long ld,
 
 // Block kernels on FP64 matrix cores (kry_block.hip).
 // partials[split][M x N] = X[:, :M]^T diag(w) Y[:, :N] over element splits.
+// With X2 != nullptr, X is two segments: columns k < M1 at X + k ld and
+// columns k >= M1 at X2 + (k - M1) ld.
 int gram_splits(long long n, int M, int N);
 hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, long long ld,
-                       const double* w, long long n, double* partials, int nsplit, hipStream_t s);
-// Out[:, :N] = (accumulate ? Out : 0) + alpha X[:, :M] C (C row-major M x N).
+                       const double* w, long long n, double* partials, int nsplit, hipStream_t s,
+                       const void* X2 = nullptr, int M1 = 0);
+// Out[:, :N] = (accumulate ? Out : 0) + alpha X[:, :M] C (C row-major M x N);
+// X in one or two segments as for launch_gram.  Out must not overlap X.
 hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int N, void* Out,
-                          long long ld, long long n, double alpha, int accumulate, hipStream_t s);
+                          long long ld, long long n, double alpha, int accumulate, hipStream_t s,
+                          const void* X2 = nullptr, int M1 = 0);
 // Energy weight of every entry (mu on H planes, eps on E planes).
 hipError_t launch_weights(const double* eps, const double* mu, double* w, long long N3,
                           hipStream_t s);

@@ -59,6 +59,12 @@ void t_sstep_hessenberg(int j0, int s, double rho, const double* C1, const doubl
   kry::sstep_hessenberg(j0, s, rho, C1, C2, R1, R2, H, ldh);
 }
 
+void t_proj_gram(int M, int s, const double* P, double* G, double* ref) { kry::proj_gram(M, s, P, G, ref); }
+
+void t_stack_coef(int M, int s, const double* C, const double* Rinv, double* K) {
+  kry::stack_coef(M, s, C, Rinv, K);
+}
+
 double t_choose_step_block(int K, int q, int g, const double* H, int ldh, const double* U0,
                            double tau_try, const double* rate, int Ks, double* U, double* err) {
   return kry::choose_step_block(K, q, g, H, ldh, U0, tau_try, rate, Ks, U, err);

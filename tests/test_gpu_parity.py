@@ -122,7 +122,8 @@ def test_arnoldi_matches_definition_first_steps(orth, s_step):
 
 @pytest.mark.parametrize("m,orth,s_step", [(30, "delayed", 0), (64, "delayed", 0), (64, "cgs2", 0),
                                           (64, "delayed", 8), (30, "delayed", 7),
-                                          (32, "delayed", 16)])
+                                          (32, "delayed", 16), (64, "delayed", 32),
+                                          (48, "delayed", 64)])
 def test_arnoldi_relation_and_orthogonality(m, orth, s_step):
     _announce(f"arnoldi relation m={m} {orth} s_step {s_step}")
     wl = wk.small(12, seed=4, n_spheres=5)

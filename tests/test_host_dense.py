@@ -237,7 +237,28 @@ def _arnoldi_mgs2(A, w, v0, m):
     return V, H
 
 
-def _arnoldi_sstep(lib, A, w, v0, m, s, rho):
+def _pass_pip(lib, Vb, w, S, thr, use_ref):
+    """One Gram-Schmidt pass as the library runs it: P = [V, S]^T M S in one
+    product, the projected Gram matrix by Pythagoras, Cholesky, and the
+    update [V, S] K = (S - V C) R^{-1} in one product."""
+    M, ss = Vb.shape[1], S.shape[1]
+    X = np.hstack([Vb, S])
+    Pm = np.ascontiguousarray(X.T @ (w[:, None] * S))
+    G = np.zeros((ss, ss))
+    ref = np.zeros(ss)
+    lib.t_proj_gram(M, ss, P(Pm), P(G), P(ref))
+    C = np.ascontiguousarray(Pm[:M])
+    R = np.zeros((ss, ss))
+    r = ref if use_ref else np.ones(ss)
+    assert lib.t_chol_upper(ss, P(G), P(r), ctypes.c_double(thr), P(R)) == 1
+    Ri = np.zeros((ss, ss))
+    lib.t_inv_upper(ss, P(R), P(Ri))
+    K = np.zeros((M + ss, ss))
+    lib.t_stack_coef(M, ss, P(C), P(Ri), P(K))
+    return X @ K, C, R
+
+
+def _arnoldi_sstep(lib, A, w, v0, m, s, rho, pip=False):
     """The s-step cycle with the library's host algebra; the tall-skinny
     products (done on the GPU by the library) are plain numpy here."""
     n = v0.size
@@ -255,6 +276,14 @@ def _arnoldi_sstep(lib, A, w, v0, m, s, rho):
             T[:, k + 1] = 2 * A @ T[:, k] / rho + T[:, k - 1]
         Sb = T[:, 1:].copy()
         Vb = V[:, :M]
+        if pip:
+            Tb, C1, R1 = _pass_pip(lib, Vb, w, Sb, 1e-10, True)
+            Q, C2, R2 = _pass_pip(lib, Vb, w, Tb, 1e-8, False)
+            V[:, M:M + ss] = Q
+            lib.t_sstep_hessenberg(j0, ss, ctypes.c_double(rho), P(C1), P(C2), P(R1), P(R2), P(H),
+                                   m + 1)
+            j0 += ss
+            continue
         C1 = np.ascontiguousarray(Vb.T @ (w[:, None] * Sb))
         Sb -= Vb @ C1
         G = np.ascontiguousarray(Sb.T @ (w[:, None] * Sb))
@@ -276,14 +305,15 @@ def _arnoldi_sstep(lib, A, w, v0, m, s, rho):
     return V, H
 
 
-@pytest.mark.parametrize("m,s", [(24, 8), (23, 5), (16, 16), (9, 2)])
-def test_sstep_arnoldi_host_algebra(lib, m, s):
+@pytest.mark.parametrize("m,s,pip", [(24, 8, False), (23, 5, False), (16, 16, False), (9, 2, False),
+                                     (24, 8, True), (23, 5, True), (16, 16, True)])
+def test_sstep_arnoldi_host_algebra(lib, m, s, pip):
     rng = np.random.default_rng(40 + m + s)
     n = 300
     A, w = _dissipative(rng, n)
     rho = float(np.abs(np.linalg.eigvals(A).imag).max())
     v0 = rng.standard_normal(n)
-    V, H = _arnoldi_sstep(lib, A, w, v0, m, s, rho)
+    V, H = _arnoldi_sstep(lib, A, w, v0, m, s, rho, pip)
     # Arnoldi relation, M-orthonormality, Hessenberg form with h_{j+1,j} > 0
     assert np.abs(A @ V[:, :m] - V @ H).max() <= 1e-12 * np.abs(A).max()
     assert np.abs(V.T @ (w[:, None] * V) - np.eye(m + 1)).max() <= 1e-12
