@@ -99,7 +99,7 @@ typedef struct {
                            block whose triangular factor has a condition
                            estimate above 1e6 (FP64) or 1e2 (FP32 storage)
                            is redone one step per sweep and halves s for
-                           the rest of the context's life                 */
+                           the rest of the call                           */
 } kry_opts;
 
 /* Kernel classes reported by the per-kernel timing. */

@@ -145,7 +145,8 @@ class Options:
     block_steps: int = 0        # batched shifted solves: block steps per restart (0 auto)
     block_steps_transient: int = 0  # batched exponential: block steps per restart (0 auto)
     # s-step Arnoldi block size (Chebyshev block, matrix-core Gram-Schmidt);
-    # None: 16 with FP64 storage, 0 (one step per sweep) with FP32 storage
+    # None: 16 with FP64 storage, 0 (one step per sweep) with FP32 storage,
+    # whose rounding the basis-change algebra would amplify
     s_step: Optional[int] = None
 
 

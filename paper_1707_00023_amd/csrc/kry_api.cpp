@@ -152,7 +152,11 @@ void tresolve(kry_ctx* c) {
   c->pending.clear();
 }
 
+// Start of a solver call: per-kernel timing cleared, and the s-step block
+// size back at the requested one (a halving after an ill-conditioned block
+// lasts for one call, so results do not depend on earlier calls).
 void treset(kry_ctx* c) {
+  c->s_eff = c->opts.s_step > 1 ? c->opts.s_step : 0;
   for (int k = 0; k < KRY_K_CLASSES; ++k)
     c->k_ms[k] = c->k_bytes[k] = c->k_flops[k] = 0.0, c->k_launch[k] = 0;
 }
@@ -710,6 +714,7 @@ int kry_create(const kry_grid* grid, const double* eps, const double* mu, const 
   // two unit differences), scaled by the smallest eps and mu
   c->rho = 2.0 * std::sqrt(3.0) / std::sqrt(min_e * min_m);
   c->s_eff = opts->s_step > 1 ? opts->s_step : 0;
+
   // derived arrays: inv_eps, sigma (or sigma/mu), eps, [inv_mu, mu]
   const int narr = mu ? 5 : 3;
   std::vector<double> host((size_t)narr * N3);
@@ -788,6 +793,7 @@ int kry_apply_f32(kry_ctx* c, const float* v, float* w, int32_t ncols) {
 
 int kry_arnoldi(kry_ctx* c, const double* v, int32_t m, void* V_out, double* H_out, double* beta_out) {
   if (!c || !v || !V_out || !H_out || !beta_out) return fail(c, KRY_EINVAL, "null argument");
+  treset(c);
   if (m < 1 || m + 2 > kry::kMaxCoef) return fail(c, KRY_EINVAL, "invalid m");
   int rc = ensure_basis(c, std::max(m, c->opts.krylov_dim));
   if (rc) return rc;
@@ -1033,9 +1039,10 @@ int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, i
 // s-step Arnoldi (same contract as arnoldi_cgs2: start vector unnormalised
 // in slot 0; slots 0..m and h_H hold V_{m+1} and Hbar on return).  Each
 // block of s steps first applies the operator s times to build a Chebyshev
-// basis on the imaginary segment [-i rho, i rho] (where the spectrum of the
-// curl part lies): t_0 = v_j0, t_1 = A t_0 / rho, t_{k+1} = 2 A t_k / rho +
-// t_{k-1}, so that A [t_0..t_{s-1}] = rho [t_0..t_s] Tm with Tm[1][0] = 1,
+// basis on the segment c + [-i rho, i rho] (rho bounds the imaginary extent
+// of the curl part; the centre c is 0, see below): t_0 = v_j0,
+// t_1 = (A - c) t_0 / rho, t_{k+1} = 2 (A - c) t_k / rho + t_{k-1}, so that
+// A [t_0..t_{s-1}] = rho [t_0..t_s] Tm + c [t_0..t_{s-1}] with Tm[1][0] = 1,
 // Tm[k+1][k] = 1/2, Tm[k-1][k] = -1/2.  The block is then orthogonalised
 // against V_0..j0 by block classical Gram-Schmidt twice with a Cholesky QR
 // per pass, all as tall-skinny products on the matrix cores: each pass is
@@ -1044,7 +1051,7 @@ int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, i
 // two sweeps over the basis instead of two per step.  With
 // [t_0..t_s] = V_ext Rhat (Rhat from the projection coefficients and the
 // Cholesky factors), the new Hessenberg columns are exact algebra:
-//   Hbar[:, j0:j0+s] = (rho Rhat Tm - [Hbar_{j0} Rtop; 0]) Rs^{-1},
+//   Hbar[:, j0:j0+s] = (rho Rhat Tm + c Rhat[:, :s] - [Hbar_{j0} Rtop; 0]) Rs^{-1},
 // where Rtop and Rs are the rows of Rhat[:, :s] for V_0..j0-1 and for
 // v_j0..v_{j0+s-1}.  A block whose projected Gram matrix loses rank (an
 // invariant subspace, or too ill-conditioned a basis) sends the cycle to
@@ -1080,7 +1087,11 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
   // v_0 = start / b0 (d_red1[0] still holds |start|^2)
   KRY_HIP(kry::launch_fin_start(c->d_red1, c->d_scal + 2, st));
   KRY_HIP(kry::launch_scale(c->st, slot(c, 0), c->d_scal + 2, slot(c, 0), c->n, st));
-  const double rho = c->rho;
+  // segment centre 0: the damping is confined to the absorbing layer, so
+  // most of a field's spectral weight sits at Re = 0, where the unshifted
+  // Chebyshev polynomials stay bounded (a centre in the damping range
+  // made the blocks of the 128^3 medium worse conditioned)
+  const double rho = c->rho, cc = 0.0;
   void* Tb = slot(c, c->mcap + 1);
   const double mb_axpby = mbytes(c, true) - 8.0 * c->g.N3;
   std::vector<double> C1, C2, G, P, R1, R2, Ri, ref, K;
@@ -1091,11 +1102,12 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
     for (int k = 0; k < ss; ++k) {
       hipEvent_t e = tbeg(c);
       if (k == 0)
-        KRY_HIP(kry::launch_stencil_axpby(c->st, slot(c, j0), nullptr, slot(c, j0 + 1), 1.0 / rho, 0.0,
-                                          c->g, c->mats, st));
+        KRY_HIP(kry::launch_stencil_axpby(c->st, slot(c, j0), nullptr, slot(c, j0 + 1), 1.0 / rho,
+                                          -cc / rho, 0.0, c->g, c->mats, st));
       else
         KRY_HIP(kry::launch_stencil_axpby(c->st, slot(c, j0 + k), slot(c, j0 + k - 1),
-                                          slot(c, j0 + k + 1), 2.0 / rho, 1.0, c->g, c->mats, st));
+                                          slot(c, j0 + k + 1), 2.0 / rho, -2.0 * cc / rho, 1.0, c->g,
+                                          c->mats, st));
       tend(c, e, KRY_K_STENCIL, vbytes(c) * (k == 0 ? 2.0 : 3.0) + mb_axpby);
     }
     void* S = slot(c, j0 + 1);
@@ -1172,7 +1184,7 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
     kry::inv_upper(ss, R2.data(), Ri.data());
     rc = block_gemm(c, slot(c, 0), M + ss, stack_coef(M, ss, C2, Ri, K), ss, S, 1.0, 0, Tb, M);
     if (rc) return rc;
-    kry::sstep_hessenberg(j0, ss, rho, C1.data(), C2.data(), R1.data(), R2.data(), H, ldh);
+    kry::sstep_hessenberg(j0, ss, rho, cc, C1.data(), C2.data(), R1.data(), R2.data(), H, ldh);
   }
   tresolve(c);
   *beta = b0;

@@ -104,6 +104,72 @@ __global__ __launch_bounds__(256) void k_gram_tn(const T* __restrict__ X, int M1
   }
 }
 
+// Tall-skinny Gram product for N <= 16: partials[4 bx + wave][M x N] =
+// X[:, rows]^T diag(w) Y over the elements the wave visits.  Workgroup bx
+// owns [bx kchunk, (bx + 1) kchunk); its four waves take interleaved
+// 16-element slices of it, and each wave accumulates all MT 16-row tiles of
+// its row block (rows r0 .. r0 + 16 MT - 1, r0 = 16 MT blockIdx.y) against
+// the single 16-column tile of Y, so every X, Y and w entry is loaded once
+// (no tile of Y is re-read per row tile).  Lane (i, kk) reads entries
+// e0 + 4 kk .. e0 + 4 kk + 3 of column i of each tile with 32-byte loads;
+// the t-th of four MFMAs takes entry e0 + 4 kk + t as its k = kk slot.
+// Out-of-range rows, columns and entries add zeros.  X in two segments as
+// in k_gram_tn.  grid (nsplit / 4, ceil(M / (16 MT))).
+template <typename T, int MT>
+__global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int M1,
+                                                   const T* __restrict__ X2, int M,
+                                                   const T* __restrict__ Y, int N, long long ld,
+                                                   const double* __restrict__ w, long long n,
+                                                   long long kchunk, double* __restrict__ partials) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  const int r0 = blockIdx.y * 16 * MT;
+  const long long e_begin = (long long)blockIdx.x * kchunk;
+  const long long e_end = min(n, e_begin + kchunk);
+  bool arow[MT];
+  const T* xc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    const int r = r0 + 16 * t + i;
+    arow[t] = r < M;
+    const int rr = arow[t] ? r : 0;
+    xc[t] = rr < M1 ? X + (long long)rr * ld : X2 + (long long)(rr - M1) * ld;
+  }
+  const bool bcol = i < N;
+  const T* yc = Y + (long long)(bcol ? i : 0) * ld;
+  v4d acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (long long e0 = e_begin + 16 * wave; e0 < e_end; e0 += 64) {
+    const long long eb = e0 + 4 * kk;
+    double xa[MT][4], ww[4], yb[4];
+    load4(w, eb, e_end, ww);
+    if (bcol) load4(yc, eb, e_end, yb);
+    else yb[0] = yb[1] = yb[2] = yb[3] = 0.0;
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      if (arow[t]) load4(xc[t], eb, e_end, xa[t]);
+      else xa[t][0] = xa[t][1] = xa[t][2] = xa[t][3] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double b = ww[u] * yb[u];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) acc[t] = mfma16(xa[t][u], b, acc[t]);
+    }
+  }
+  double* out = partials + ((long long)blockIdx.x * 4 + wave) * M * N;
+  const int col = i;
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + 16 * t + 4 * r + kk;
+      if (row < M && col < N) out[(long long)row * N + col] = acc[t][r];
+    }
+  }
+}
+
 // Out[:, j] = (accumulate ? Out[:, j] : 0) + alpha sum_k X[:, k] C[k][j] for
 // j < N (C row-major M x N, FP64).  Each wave computes 16 entries x 16 NT
 // columns (NT tiles of Out^T = C^T X^T): A = C^T (from C), B = X^T (16
@@ -173,11 +239,26 @@ __global__ void k_weights(const double* __restrict__ eps, const double* __restri
 
 }  // namespace
 
+// Rows of X per workgroup of k_gram_tall (16 MT) for M rows.
+static int tall_mt(int M) {
+  const int tiles = (M + 15) / 16;
+  return tiles <= 8 ? tiles : 8;
+}
+
 int gram_splits(long long n, int M, int N) {
+  const long long maxs = (n + 255) / 256;
+  if (N <= 16) {
+    // k_gram_tall: four partials per workgroup, about 1024 workgroups
+    const int mt = tall_mt(M);
+    const int rowblk = (M + 16 * mt - 1) / (16 * mt);
+    long long wg = 1024 / rowblk;
+    if (wg > maxs) wg = maxs;
+    if (wg < 1) wg = 1;
+    return (int)(4 * wg);
+  }
   const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
   long long s = 2048 / tiles;
   if (s < 1) s = 1;
-  const long long maxs = (n + 255) / 256;
   if (s > maxs) s = maxs;
   return (int)s;
 }
@@ -188,6 +269,32 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
   if (!X2) {  // one segment
     M1 = M;
     X2 = X;
+  }
+  if (N <= 16) {
+    const int wg = nsplit / 4;
+    long long kchunk = (n + wg - 1) / wg;
+    kchunk = (kchunk + 63) / 64 * 64;
+    const int mt = tall_mt(M);
+    const dim3 grid(wg, (M + 16 * mt - 1) / (16 * mt));
+#define KRY_TALL(MT)                                                                          \
+  if (st == F64)                                                                             \
+    hipLaunchKernelGGL((k_gram_tall<double, MT>), grid, dim3(256), 0, s, (const double*)X, M1, \
+                       (const double*)X2, M, (const double*)Y, N, ld, w, n, kchunk, partials); \
+  else                                                                                       \
+    hipLaunchKernelGGL((k_gram_tall<float, MT>), grid, dim3(256), 0, s, (const float*)X, M1,   \
+                       (const float*)X2, M, (const float*)Y, N, ld, w, n, kchunk, partials);
+    switch (mt) {
+      case 1: KRY_TALL(1) break;
+      case 2: KRY_TALL(2) break;
+      case 3: KRY_TALL(3) break;
+      case 4: KRY_TALL(4) break;
+      case 5: KRY_TALL(5) break;
+      case 6: KRY_TALL(6) break;
+      case 7: KRY_TALL(7) break;
+      default: KRY_TALL(8) break;
+    }
+#undef KRY_TALL
+    return hipGetLastError();
   }
   long long kchunk = (n + nsplit - 1) / nsplit;
   kchunk = (kchunk + 15) / 16 * 16;

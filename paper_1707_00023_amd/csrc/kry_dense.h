@@ -87,16 +87,16 @@ bool chol_upper(int p, const double* G, const double* ref, double thr, double* R
 void inv_upper(int p, const double* R, double* X);
 
 // Hessenberg columns j0..j0+s-1 of an s-step Arnoldi block.  The block
-// [t_0..t_s] with t_0 = v_j0 obeys A [t_0..t_{s-1}] = rho [t_0..t_s] Tm
-// (Chebyshev basis on [-i rho, i rho]: Tm[1][0] = 1, Tm[k+1][k] = 1/2,
-// Tm[k-1][k] = -1/2).  Two projection passes gave t_k = V C1 + u_k,
+// [t_0..t_s] with t_0 = v_j0 obeys A [t_0..t_{s-1}] = rho [t_0..t_s] Tm +
+// c [t_0..t_{s-1}] (Chebyshev basis on the segment c + [-i rho, i rho]:
+// Tm[1][0] = 1, Tm[k+1][k] = 1/2, Tm[k-1][k] = -1/2).  Two projection passes gave t_k = V C1 + u_k,
 // u = q1 R1, q1 = V C2 + Q R2 (V = v_0..v_j0; C1, C2 (j0+1) x s row-major;
 // R1, R2 s x s upper row-major), so [t_1..t_s] = V (C1 + C2 R1) + Q R2 R1.
 // With [t_0..t_s] = V_ext Rhat this writes
-//   H[:, j0:j0+s] = (rho Rhat Tm - [H[:j0+1, :j0] Rtop; 0]) Rs^{-1}
+//   H[:, j0:j0+s] = (rho Rhat Tm + c Rhat[:, :s] - [H[:j0+1, :j0] Rtop; 0]) Rs^{-1}
 // into H (column-major, leading dimension ldh >= j0 + s + 1; columns < j0
 // already filled).  Entries below the first subdiagonal are left zero.
-void sstep_hessenberg(int j0, int s, double rho, const double* C1, const double* C2,
+void sstep_hessenberg(int j0, int s, double rho, double c, const double* C1, const double* C2,
                       const double* R1, const double* R2, double* H, int ldh);
 
 // Projected Gram matrix of an s-column block S against an M-orthonormal

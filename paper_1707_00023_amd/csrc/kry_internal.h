@@ -41,9 +41,11 @@ hipError_t launch_stencil(Storage st, const void* v, void* w, const void* V, lon
                           int cnt, const DevGrid& g, const DevMats& m, double* partials,
                           hipStream_t s);
 
-// out = alpha A v + beta prev (prev may be null); out must not alias v.
+// out = alpha A v + gamma v + beta prev (prev may be null); out must not
+// alias v.
 hipError_t launch_stencil_axpby(Storage st, const void* v, const void* prev, void* out, double alpha,
-                                double beta, const DevGrid& g, const DevMats& m, hipStream_t s);
+                                double gamma, double beta, const DevGrid& g, const DevMats& m,
+                                hipStream_t s);
 
 // Pass A of a delayed-reorthogonalisation Arnoldi step: x = A u and partial
 // sums of [<x,V_i>_M (cnt), <u,V_i>_M (cnt), |u|_M^2, <u,x>_M] per workgroup

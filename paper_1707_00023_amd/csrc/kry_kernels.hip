@@ -205,14 +205,15 @@ __global__ __launch_bounds__(kBlock) void k_stencil(const T* __restrict__ v, T* 
   block_sum_store<1>(a1, 1, partials + (long long)lb * (cnt + 1) + cnt);
 }
 
-// One step of a three-term polynomial basis: out = alpha A v + beta prev
-// (prev may be null: beta is then ignored).  The operator is evaluated in
-// the storage type, the combination in FP64.
+// One step of a three-term polynomial basis: out = alpha A v + gamma v +
+// beta prev (prev may be null: beta is then ignored).  The operator is
+// evaluated in the storage type, the combination in FP64.
 template <typename T, bool HAS_MU, int CPT>
 __global__ __launch_bounds__(kBlock) void k_stencil_axpby(const T* __restrict__ v,
                                                           const T* __restrict__ prev,
                                                           T* __restrict__ out, double alpha,
-                                                          double beta, DevGrid g, DevMats mt) {
+                                                          double gamma, double beta, DevGrid g,
+                                                          DevMats mt) {
   const long long N3 = g.N3;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
 #pragma unroll
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_axpby(const T* __restrict__ 
     yee_cell<T, HAS_MU>(v, c, g, mt, o, ctr);
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
-      double r = alpha * (double)o[p];
+      double r = alpha * (double)o[p] + gamma * (double)ctr[p];
       if (prev) r += beta * (double)prev[p * N3 + c];
       out[p * N3 + c] = T(r);
     }
@@ -848,7 +849,8 @@ hipError_t launch_stencil_cols(Storage st, const void* v, void* w, long long ld,
 
 template <typename T>
 static hipError_t stencil_axpby_t(const void* v, const void* prev, void* out, double alpha,
-                                  double beta, const DevGrid& g, const DevMats& m, hipStream_t s) {
+                                  double gamma, double beta, const DevGrid& g, const DevMats& m,
+                                  hipStream_t s) {
   const int cpt = g.cpt_s;
   const dim3 grid(cell_blocks(g.N3, cpt)), blk(kBlock);
   const T* vv = (const T*)v;
@@ -856,17 +858,18 @@ static hipError_t stencil_axpby_t(const void* v, const void* prev, void* out, do
   T* oo = (T*)out;
   const bool mu = m.inv_mu != nullptr;
 #define KRY_SAXPBY(C)                                                                            \
-  if (mu) hipLaunchKernelGGL((k_stencil_axpby<T, true, C>), grid, blk, 0, s, vv, pp, oo, alpha, beta, g, m); \
-  else hipLaunchKernelGGL((k_stencil_axpby<T, false, C>), grid, blk, 0, s, vv, pp, oo, alpha, beta, g, m);
+  if (mu) hipLaunchKernelGGL((k_stencil_axpby<T, true, C>), grid, blk, 0, s, vv, pp, oo, alpha, gamma, beta, g, m); \
+  else hipLaunchKernelGGL((k_stencil_axpby<T, false, C>), grid, blk, 0, s, vv, pp, oo, alpha, gamma, beta, g, m);
   KRY_CPT_SWITCH(cpt, KRY_SAXPBY)
 #undef KRY_SAXPBY
   return hipGetLastError();
 }
 
 hipError_t launch_stencil_axpby(Storage st, const void* v, const void* prev, void* out, double alpha,
-                                double beta, const DevGrid& g, const DevMats& m, hipStream_t s) {
-  return st == F64 ? stencil_axpby_t<double>(v, prev, out, alpha, beta, g, m, s)
-                   : stencil_axpby_t<float>(v, prev, out, alpha, beta, g, m, s);
+                                double gamma, double beta, const DevGrid& g, const DevMats& m,
+                                hipStream_t s) {
+  return st == F64 ? stencil_axpby_t<double>(v, prev, out, alpha, gamma, beta, g, m, s)
+                   : stencil_axpby_t<float>(v, prev, out, alpha, gamma, beta, g, m, s);
 }
 
 hipError_t launch_stencil(Storage st, const void* v, void* w, const void* V, long long ldv, int cnt,

@@ -54,9 +54,9 @@ int t_chol_upper(int p, const double* G, const double* ref, double thr, double* 
 
 void t_inv_upper(int p, const double* R, double* X) { kry::inv_upper(p, R, X); }
 
-void t_sstep_hessenberg(int j0, int s, double rho, const double* C1, const double* C2,
+void t_sstep_hessenberg(int j0, int s, double rho, double c, const double* C1, const double* C2,
                         const double* R1, const double* R2, double* H, int ldh) {
-  kry::sstep_hessenberg(j0, s, rho, C1, C2, R1, R2, H, ldh);
+  kry::sstep_hessenberg(j0, s, rho, c, C1, C2, R1, R2, H, ldh);
 }
 
 void t_proj_gram(int M, int s, const double* P, double* G, double* ref) { kry::proj_gram(M, s, P, G, ref); }

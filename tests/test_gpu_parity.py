@@ -424,13 +424,16 @@ def test_grad_per_omega_sources_and_autograd():
 
 
 def test_grad_c4_full_size_against_frozen_path_differences():
-    # 64^3, 8 frequencies, flux plane 58, 20 seeded cells.  The differences
-    # run the forward solver for a fixed number of restart cycles, so the
-    # computed loss is a smooth function of eps and its central difference is
-    # not swamped by solver-tolerance noise.  What remains is FP64 rounding in
-    # two independent solves: a floor of about eps_mach * L / (h |g|) per
-    # cell (3e-6 at h = 1e-6 for this loss), so the 1e-5 target is asserted
-    # at h = 1e-5 (truncation (h/eps)^2 ~ 1e-11) and h = 1e-6 is held to the
+    # 64^3, 8 frequencies, flux plane 58, 20 seeded cells.  The gradient
+    # comes from the default solver (s-step Arnoldi); it must agree with the
+    # one-step-per-sweep solver's gradient to 1e-10.  The differences run
+    # the one-step-per-sweep forward solver (its rounding is the smallest)
+    # for a fixed number of restart cycles, so the computed loss is a smooth
+    # function of eps and its central difference is not swamped by
+    # solver-tolerance noise.  What remains is FP64 rounding in two
+    # independent solves: a floor of about eps_mach * L / (h |g|) per cell
+    # (3e-6 at h = 1e-6 for this loss), so the 1e-5 target is asserted at
+    # h = 1e-5 (truncation (h/eps)^2 ~ 1e-11) and h = 1e-6 is held to the
     # floor-limited bound 5e-5.
     wl = wk.C4
     _announce("gradient c4 64^3 (full size)")
@@ -442,8 +445,18 @@ def test_grad_c4_full_size_against_frozen_path_differences():
     L, g = s.grad(wl.omegas, b, kf)
     _announce(f"c4 grad {time.time() - t0:.1f}s L={L:.6e} stats={s.last_stats}")
     g = g.cpu().numpy()
+    s.close()
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=1e-12, s_step=0)
+    t0 = time.time()
+    L0, g0 = s.grad(wl.omegas, b, kf)
+    _announce(f"c4 grad, one step per sweep {time.time() - t0:.1f}s")
+    g0 = g0.cpu().numpy()
+    assert abs(L - L0) <= 1e-10 * abs(L0)
+    assert np.linalg.norm(g - g0) <= 1e-10 * np.linalg.norm(g0)
+    t0 = time.time()
     s.grad(wl.omegas, b, kf, loss_only=True)
     kfwd = s.last_stats["cycles_stationary"]
+    _announce(f"c4 loss, one step per sweep {time.time() - t0:.1f}s ({kfwd} cycles)")
     s.close()
     gv = np.array([g[k, j, i] for (i, j, k) in inp.fd_cells])
     errs = {}
@@ -455,7 +468,7 @@ def test_grad_c4_full_size_against_frozen_path_differences():
                 e = inp.eps.copy()
                 e[k, j, i] += sgn * h
                 sp = _solver(e, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=1e-300,
-                             max_restarts=kfwd + 2)
+                             max_restarts=kfwd + 2, s_step=0)
                 Lp, _ = sp.grad(wl.omegas, b, kf, loss_only=True)
                 sp.close()
                 vals.append(Lp)

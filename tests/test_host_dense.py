@@ -258,7 +258,7 @@ def _pass_pip(lib, Vb, w, S, thr, use_ref):
     return X @ K, C, R
 
 
-def _arnoldi_sstep(lib, A, w, v0, m, s, rho, pip=False):
+def _arnoldi_sstep(lib, A, w, v0, m, s, rho, pip=False, c=0.0):
     """The s-step cycle with the library's host algebra; the tall-skinny
     products (done on the GPU by the library) are plain numpy here."""
     n = v0.size
@@ -271,17 +271,17 @@ def _arnoldi_sstep(lib, A, w, v0, m, s, rho, pip=False):
         M = j0 + 1
         T = np.zeros((n, ss + 1))
         T[:, 0] = V[:, j0]
-        T[:, 1] = A @ T[:, 0] / rho
+        T[:, 1] = (A @ T[:, 0] - c * T[:, 0]) / rho
         for k in range(1, ss):
-            T[:, k + 1] = 2 * A @ T[:, k] / rho + T[:, k - 1]
+            T[:, k + 1] = 2 * (A @ T[:, k] - c * T[:, k]) / rho + T[:, k - 1]
         Sb = T[:, 1:].copy()
         Vb = V[:, :M]
         if pip:
             Tb, C1, R1 = _pass_pip(lib, Vb, w, Sb, 1e-10, True)
             Q, C2, R2 = _pass_pip(lib, Vb, w, Tb, 1e-8, False)
             V[:, M:M + ss] = Q
-            lib.t_sstep_hessenberg(j0, ss, ctypes.c_double(rho), P(C1), P(C2), P(R1), P(R2), P(H),
-                                   m + 1)
+            lib.t_sstep_hessenberg(j0, ss, ctypes.c_double(rho), ctypes.c_double(c), P(C1), P(C2),
+                                   P(R1), P(R2), P(H), m + 1)
             j0 += ss
             continue
         C1 = np.ascontiguousarray(Vb.T @ (w[:, None] * Sb))
@@ -300,20 +300,25 @@ def _arnoldi_sstep(lib, A, w, v0, m, s, rho, pip=False):
         assert lib.t_chol_upper(ss, P(G), P(np.ones(ss)), ctypes.c_double(1e-8), P(R2)) == 1
         lib.t_inv_upper(ss, P(R2), P(Ri))
         V[:, M:M + ss] = Tb @ Ri
-        lib.t_sstep_hessenberg(j0, ss, ctypes.c_double(rho), P(C1), P(C2), P(R1), P(R2), P(H), m + 1)
+        lib.t_sstep_hessenberg(j0, ss, ctypes.c_double(rho), ctypes.c_double(c), P(C1), P(C2), P(R1),
+                               P(R2), P(H), m + 1)
         j0 += ss
     return V, H
 
 
-@pytest.mark.parametrize("m,s,pip", [(24, 8, False), (23, 5, False), (16, 16, False), (9, 2, False),
-                                     (24, 8, True), (23, 5, True), (16, 16, True)])
-def test_sstep_arnoldi_host_algebra(lib, m, s, pip):
+@pytest.mark.parametrize("m,s,pip,shift", [(24, 8, False, False), (23, 5, False, False),
+                                           (16, 16, False, False), (9, 2, False, False),
+                                           (24, 8, True, False), (23, 5, True, True),
+                                           (16, 16, True, True)])
+def test_sstep_arnoldi_host_algebra(lib, m, s, pip, shift):
     rng = np.random.default_rng(40 + m + s)
     n = 300
     A, w = _dissipative(rng, n)
-    rho = float(np.abs(np.linalg.eigvals(A).imag).max())
+    lam = np.linalg.eigvals(A)
+    rho = float(np.abs(lam.imag).max())
+    c = 0.5 * float(lam.real.max()) if shift else 0.0
     v0 = rng.standard_normal(n)
-    V, H = _arnoldi_sstep(lib, A, w, v0, m, s, rho, pip)
+    V, H = _arnoldi_sstep(lib, A, w, v0, m, s, rho, pip, c)
     # Arnoldi relation, M-orthonormality, Hessenberg form with h_{j+1,j} > 0
     assert np.abs(A @ V[:, :m] - V @ H).max() <= 1e-12 * np.abs(A).max()
     assert np.abs(V.T @ (w[:, None] * V) - np.eye(m + 1)).max() <= 1e-12
