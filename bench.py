@@ -28,7 +28,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_128cube_traffic.md")
-CLASS_KERNEL = {"stencil_dots": "k_stencil_lag", "gs_update": "k_lag_update"}
+# kernel class -> (kernel in the counter summary, source file it is built from)
+CLASS_KERNEL = {"block_gram": ("k_gram_tall", "kry_block.hip"),
+                "block_gemm": ("k_gemm_cols", "kry_block.hip"),
+                "operator": ("k_stencil_axpby", "kry_kernels.hip")}
 
 
 def measured_traffic(kernel_class, workload):
@@ -38,12 +41,13 @@ def measured_traffic(kernel_class, workload):
     import re
     if workload != "c2" or kernel_class not in CLASS_KERNEL or not os.path.exists(TRAFFIC_FILE):
         return None
-    src = os.path.join(ROOT, "paper_1707_00023_amd", "csrc", "kry_kernels.hip")
+    kernel, source = CLASS_KERNEL[kernel_class]
+    src = os.path.join(ROOT, "paper_1707_00023_amd", "csrc", source)
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     pat = re.compile(r"traffic_bytes_per_launch (\S+) (\S+) source_sha256_16 (\S+)")
     for line in open(TRAFFIC_FILE):
         m = pat.search(line)
-        if m and m.group(1) == CLASS_KERNEL[kernel_class] and m.group(3) == h:
+        if m and m.group(1) == kernel and m.group(3) == h:
             return float(m.group(2))
     return None
 
@@ -174,9 +178,11 @@ def precision_compare(args, wl, inp, dev):
 
 
 def traffic_probe(args, wl, inp, dev):
-    """Two Arnoldi cycles (m = the workload's Krylov dimension) on the
-    workload's grid, then one device copy of COPY_BYTES (the calibration
-    kernel: it moves exactly COPY_BYTES in and COPY_BYTES out)."""
+    """Two Arnoldi cycles (the workload's Krylov dimension, the default
+    s-step block size) on the workload's grid, then one device copy of
+    COPY_BYTES (the calibration kernel: it moves exactly COPY_BYTES in and
+    COPY_BYTES out), timed with events.  Prints the algorithmic bytes of
+    every kernel launch of a cycle, in launch order."""
     import numpy as np
     import torch
 
@@ -186,7 +192,7 @@ def traffic_probe(args, wl, inp, dev):
     eps = torch.as_tensor(inp.eps, device=dev)
     sig = torch.as_tensor(inp.sigma, device=dev)
     s = kry.Solver(eps, None, sig, kry.Options(storage=wl.storage, krylov_dim=wl.krylov_dim,
-                                               tol=wl.tol))
+                                               tol=wl.tol, s_step=args.s_step))
     tune = None if args.no_autotune else s.autotune()
     v = torch.as_tensor(wk.random_state(wl.n, 1), device=dev)
     m = wl.krylov_dim
@@ -195,17 +201,30 @@ def traffic_probe(args, wl, inp, dev):
     src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     dst.copy_(src)
+    e1.record()
     torch.cuda.synchronize()
+    copy_ms = e0.elapsed_time(e1)
     esz = 8 if wl.storage == "f64" else 4
-    vb = 6 * wl.N ** 3 * esz
-    mats = 24 * wl.N ** 3
-    out = {"probe": "two Arnoldi cycles + calibration copy", "workload": wl.name, "m": m,
-           "copy_bytes_each_way": COPY_BYTES, "launch_shapes": tune,
-           # algorithmic bytes per launch, averaged over the m steps of a cycle
-           "alg_bytes_per_launch": {
-               "k_stencil_lag": float(np.mean([vb * (j + 2) + mats for j in range(m)])),
-               "k_lag_update": float(np.mean([vb * (j + 4) for j in range(m)]))}}
+    n = wl.n
+    vb = n * esz
+    N3 = wl.N ** 3
+    sst = args.s_step
+    launches = []  # (kernel, algorithmic bytes) in launch order of one cycle
+    for j0 in range(0, m, sst):
+        ss = min(sst, m - j0)
+        M = j0 + 1
+        for k in range(ss):
+            launches.append(("k_stencil_axpby", (2 if k == 0 else 3) * vb + 16 * N3))
+        for _ in range(2):  # two passes: Gram [V, S]^T M S, update [V, S] K
+            launches.append(("k_gram_tall", (M + ss) * vb + 8 * n))  # S is part of [V, S]
+            launches.append(("k_gemm_cols", (M + 2 * ss) * vb))
+    out = {"probe": "two s-step Arnoldi cycles + calibration copy", "workload": wl.name, "m": m,
+           "s_step": sst, "copy_bytes_each_way": COPY_BYTES, "copy_ms": copy_ms,
+           "copy_gbs": 2 * COPY_BYTES / (copy_ms * 1e6), "launch_shapes": tune,
+           "cycle_launches": launches}
     print(json.dumps(out), flush=True)
 
 

@@ -103,9 +103,11 @@ typedef struct {
 } kry_opts;
 
 /* Kernel classes reported by the per-kernel timing. */
-#define KRY_K_STENCIL 0 /* operator fused with the first Gram-Schmidt dots */
-#define KRY_K_UPDATE 1  /* w -= V h (multi-vector update), two per step    */
-#define KRY_K_DOTS 2    /* second Gram-Schmidt dot pass                    */
+#define KRY_K_STENCIL 0 /* operator applications (fused with the first
+                           Gram-Schmidt dots in the one-step Arnoldi; the
+                           polynomial-basis stencil in the s-step one)    */
+#define KRY_K_UPDATE 1  /* one-step Arnoldi: w -= V h (multi-vector update) */
+#define KRY_K_DOTS 2    /* one-step Arnoldi: second Gram-Schmidt dot pass  */
 #define KRY_K_COMBINE 3 /* basis combinations V Y                          */
 #define KRY_K_GRAM 4    /* block form: Gram products V^T M W (matrix cores) */
 #define KRY_K_GEMM 5    /* block form: updates W -= V C (matrix cores)      */

@@ -64,7 +64,9 @@ class KryStats(ctypes.Structure):
 
 DEFAULT_S_STEP = 16
 
-KERNEL_CLASSES = ("stencil_dots", "gs_update", "gs_dots", "combine", "block_gram", "block_gemm")
+# operator: the Yee stencil (fused with the first Gram-Schmidt dots in the
+# one-step Arnoldi, the polynomial-basis stencil in the s-step Arnoldi)
+KERNEL_CLASSES = ("operator", "gs_update", "gs_dots", "combine", "block_gram", "block_gemm")
 
 
 class KryTune(ctypes.Structure):

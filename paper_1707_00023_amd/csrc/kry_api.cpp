@@ -1012,7 +1012,9 @@ int block_gram_host(kry_ctx* c, const void* X, int M, const void* Y, int N, std:
   if (rc) return rc;
   hipEvent_t e = tbeg(c);
   KRY_HIP(kry::launch_gram(c->st, X, M, Y, N, c->ldv, c->d_w, c->n, c->d_gp, ns, c->stream, X2, M1));
-  tend(c, e, KRY_K_GRAM, vbytes(c) * (M + N) + 8.0 * c->n, 2.0 * c->n * M * N);
+  // algorithmic bytes: every distinct column once (Y may be part of X)
+  const bool y_in_x = (X2 && Y == X2 && N == M - M1) || (!X2 && Y == X && N <= M);
+  tend(c, e, KRY_K_GRAM, vbytes(c) * (y_in_x ? M : M + N) + 8.0 * c->n, 2.0 * c->n * M * N);
   KRY_HIP(kry::launch_reduce(c->d_gp, ns, M * N, M * N, c->d_bc, c->stream));
   C.resize((size_t)M * N);
   KRY_HIP(hipMemcpyAsync(C.data(), c->d_bc, sizeof(double) * M * N, hipMemcpyDeviceToHost, c->stream));
@@ -1218,7 +1220,9 @@ int block_cholqr2(kry_ctx* c, void* W, int p, void* T2, void* Out, std::vector<d
   return KRY_OK;
 }
 
-// Block Arnoldi (classical Gram-Schmidt twice, block CholQR2): start block
+// Block Arnoldi (block classical Gram-Schmidt twice, each pass one Gram
+// product [V, W]^T M W with the projected Gram matrix by Pythagoras, a
+// rank-revealing Cholesky QR, and one update (W - V C) Cm): start block
 // V_0 already orthonormal in slots [0, p); fills slots up to (mb+1) p and
 // Hb ((mb+1) p x mb p, column-major).  Stops early (*mb_eff) when a new
 // block is entirely dependent (an invariant block Krylov space).  Work
@@ -1229,7 +1233,8 @@ int block_arnoldi(kry_ctx* c, int p, int mb, int ws, std::vector<double>& Hb, in
   Hb.assign((size_t)ldh * mb * p, 0.0);
   void* W = bslot(c, ws);
   void* T2 = bslot(c, ws + p);
-  std::vector<double> Cc, Rf;
+  std::vector<double> P1, P2, C1, C2, G((size_t)p * p), ref(p), Cm1((size_t)p * p), Rf1((size_t)p * p),
+      Cm2((size_t)p * p), Rf2((size_t)p * p), K;
   *mb_eff = mb;
   for (int j = 0; j < mb; ++j) {
     hipEvent_t e = tbeg(c);
@@ -1237,20 +1242,55 @@ int block_arnoldi(kry_ctx* c, int p, int mb, int ws, std::vector<double>& Hb, in
     tend(c, e, KRY_K_STENCIL, vbytes(c) * 2.0 * p + mbytes(c, true) - 8.0 * c->g.N3);
     if (st) (transient ? st->matvecs_transient : st->matvecs_stationary) += p;
     const int M = (j + 1) * p;
-    for (int pass = 0; pass < 2; ++pass) {
-      int rc = block_gram_host(c, bslot(c, 0), M, W, p, Cc);
-      if (rc) return rc;
-      rc = block_gemm(c, bslot(c, 0), M, Cc, p, W, -1.0, 1);
-      if (rc) return rc;
-      for (int a = 0; a < M; ++a)
-        for (int b = 0; b < p; ++b) Hb[a + (size_t)(j * p + b) * ldh] += Cc[(size_t)a * p + b];
-    }
-    int rank = 0;
-    int rc = block_cholqr2(c, W, p, T2, bslot(c, (j + 1) * p), Rf, &rank);
+    // pass 1: [V, W]^T M W in one product, projected Gram by Pythagoras,
+    // rank-revealing Cholesky QR, T2 = (W - V C1) Cm1 in one product
+    int rc = block_gram_host(c, bslot(c, 0), M + p, W, p, P1, W, M);
     if (rc) return rc;
+    C1.assign(P1.begin(), P1.begin() + (size_t)M * p);
+    kry::proj_gram(M, p, P1.data(), G.data(), ref.data());
+    bool cancel = false;  // projected norms lost to rounding: project explicitly
+    for (int k = 0; k < p; ++k) cancel |= !(G[(size_t)k * p + k] > 1e-12 * ref[k]) && ref[k] > 0.0;
+    int r1;
+    if (!cancel) {
+      r1 = kry::cholqr_factor(p, G.data(), 1e-10, Cm1.data(), Rf1.data());
+      K.resize((size_t)(M + p) * p);
+      kry::stack_coef_full(M, p, C1.data(), Cm1.data(), K.data());
+      rc = block_gemm(c, bslot(c, 0), M + p, K, p, T2, 1.0, 0, W, M);
+      if (rc) return rc;
+    } else {
+      rc = block_gemm(c, bslot(c, 0), M, C1, p, W, -1.0, 1);
+      if (rc) return rc;
+      rc = block_gram_host(c, W, p, W, p, G);
+      if (rc) return rc;
+      r1 = kry::cholqr_factor(p, G.data(), 1e-10, Cm1.data(), Rf1.data());
+      rc = block_gemm(c, W, p, Cm1, p, T2, 1.0, 0);
+      if (rc) return rc;
+    }
+    // pass 2 on T2 (nearly orthogonal to V: no cancellation), result Q in
+    // the next basis block
+    rc = block_gram_host(c, bslot(c, 0), M + p, T2, p, P2, T2, M);
+    if (rc) return rc;
+    C2.assign(P2.begin(), P2.begin() + (size_t)M * p);
+    kry::proj_gram(M, p, P2.data(), G.data(), ref.data());
+    const int r2 = kry::cholqr_factor(p, G.data(), 1e-10, Cm2.data(), Rf2.data());
+    K.resize((size_t)(M + p) * p);
+    kry::stack_coef_full(M, p, C2.data(), Cm2.data(), K.data());
+    rc = block_gemm(c, bslot(c, 0), M + p, K, p, bslot(c, (j + 1) * p), 1.0, 0, T2, M);
+    if (rc) return rc;
+    // W = V (C1 + C2 Rf1) + Q (Rf2 Rf1)
+    for (int a = 0; a < M; ++a)
+      for (int b = 0; b < p; ++b) {
+        double v = C1[(size_t)a * p + b];
+        for (int l = 0; l < p; ++l) v += C2[(size_t)a * p + l] * Rf1[(size_t)l * p + b];
+        Hb[a + (size_t)(j * p + b) * ldh] = v;
+      }
     for (int a = 0; a < p; ++a)
-      for (int b = 0; b < p; ++b) Hb[(j + 1) * p + a + (size_t)(j * p + b) * ldh] = Rf[(size_t)a * p + b];
-    if (rank == 0) {  // the block space is invariant: stop here
+      for (int b = 0; b < p; ++b) {
+        double v = 0.0;
+        for (int l = 0; l < p; ++l) v += Rf2[(size_t)a * p + l] * Rf1[(size_t)l * p + b];
+        Hb[(j + 1) * p + a + (size_t)(j * p + b) * ldh] = v;
+      }
+    if (std::min(r1, r2) == 0) {  // the block space is invariant: stop here
       *mb_eff = j + 1;
       break;
     }

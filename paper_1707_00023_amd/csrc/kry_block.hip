@@ -115,7 +115,11 @@ __global__ __launch_bounds__(256) void k_gram_tn(const T* __restrict__ X, int M1
 // the t-th of four MFMAs takes entry e0 + 4 kk + t as its k = kk slot.
 // Out-of-range rows, columns and entries add zeros.  X in two segments as
 // in k_gram_tn.  grid (nsplit / 4, ceil(M / (16 MT))).
-template <typename T, int MT>
+// YSEG: Y is the second segment of X itself (Y = X2, N = M - M1 <= 16, one
+// row block).  Row tile 0 then holds Y and tiles 1.. the first segment, so
+// the Y operand is the tile-0 data already in registers (Y is read once,
+// not twice); output rows are mapped back to the [X; X2] order.
+template <typename T, int MT, bool YSEG>
 __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int M1,
                                                    const T* __restrict__ X2, int M,
                                                    const T* __restrict__ Y, int N, long long ld,
@@ -131,9 +135,19 @@ __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int 
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
     const int r = r0 + 16 * t + i;
-    arow[t] = r < M;
-    const int rr = arow[t] ? r : 0;
-    xc[t] = rr < M1 ? X + (long long)rr * ld : X2 + (long long)(rr - M1) * ld;
+    if (YSEG) {  // virtual rows: [0, 16) second segment, [16, 16 + M1) first
+      if (t == 0) {
+        arow[t] = i < N;
+        xc[t] = X2 + (long long)(arow[t] ? i : 0) * ld;
+      } else {
+        arow[t] = r - 16 < M1;
+        xc[t] = X + (long long)(arow[t] ? r - 16 : 0) * ld;
+      }
+    } else {
+      arow[t] = r < M;
+      const int rr = arow[t] ? r : 0;
+      xc[t] = rr < M1 ? X + (long long)rr * ld : X2 + (long long)(rr - M1) * ld;
+    }
   }
   const bool bcol = i < N;
   const T* yc = Y + (long long)(bcol ? i : 0) * ld;
@@ -144,12 +158,18 @@ __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int 
     const long long eb = e0 + 4 * kk;
     double xa[MT][4], ww[4], yb[4];
     load4(w, eb, e_end, ww);
-    if (bcol) load4(yc, eb, e_end, yb);
-    else yb[0] = yb[1] = yb[2] = yb[3] = 0.0;
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
       if (arow[t]) load4(xc[t], eb, e_end, xa[t]);
       else xa[t][0] = xa[t][1] = xa[t][2] = xa[t][3] = 0.0;
+    }
+    if (YSEG) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) yb[u] = xa[0][u];
+    } else if (bcol) {
+      load4(yc, eb, e_end, yb);
+    } else {
+      yb[0] = yb[1] = yb[2] = yb[3] = 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -164,7 +184,9 @@ __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int 
   for (int t = 0; t < MT; ++t) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = r0 + 16 * t + 4 * r + kk;
+      const int vr = r0 + 16 * t + 4 * r + kk;
+      int row = vr;
+      if (YSEG) row = vr < 16 ? (vr < N ? M1 + vr : M) : (vr - 16 < M1 ? vr - 16 : M);
       if (row < M && col < N) out[(long long)row * N + col] = acc[t][r];
     }
   }
@@ -227,6 +249,67 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ X, int M1
   }
 }
 
+// Update for N <= 16 output columns on the vector ALUs: Out[:, j] =
+// (accumulate ? Out[:, j] : 0) + alpha sum_k X[:, k] C[k][j].  A thread owns
+// EPT entries (stride 256, consecutive threads consecutive entries, so
+// every column access is coalesced) and all N outputs of each; the
+// coefficients sit in LDS and are read as broadcasts.  The dense part is
+// 2 N M flops per entry, far below the FP64 vector rate at the bandwidth
+// this kernel moves, so the matrix cores gain nothing here.  X in two
+// segments as in k_gram_tn.  Out may not overlap X.
+template <typename T, int EPT>
+__global__ __launch_bounds__(256) void k_gemm_cols(const T* __restrict__ X, int M1,
+                                                   const T* __restrict__ X2, int M,
+                                                   const double* __restrict__ C, int N,
+                                                   T* __restrict__ Out, long long ld, long long n,
+                                                   double alpha, int accumulate) {
+  extern __shared__ double sC[];  // M x 16
+  for (int t = threadIdx.x; t < M * 16; t += 256) {
+    const int k = t >> 4, j = t & 15;
+    sC[t] = j < N ? C[(long long)k * N + j] : 0.0;
+  }
+  __syncthreads();
+  const long long base = (long long)blockIdx.x * 256 * EPT + threadIdx.x;
+  double acc[EPT][16];
+  bool ok[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    ok[q] = base + 256LL * q < n;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[q][j] = 0.0;
+  }
+#pragma unroll 2
+  for (int k = 0; k < M; ++k) {
+    const T* xk = k < M1 ? X + (long long)k * ld : X2 + (long long)(k - M1) * ld;
+    double x[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) x[q] = ok[q] ? (double)xk[base + 256LL * q] : 0.0;
+    const double2* row = reinterpret_cast<const double2*>(sC + 16 * k);
+#pragma unroll
+    for (int j2 = 0; j2 < 8; ++j2) {
+      const double2 cc = row[j2];
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        acc[q][2 * j2] += x[q] * cc.x;
+        acc[q][2 * j2 + 1] += x[q] * cc.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    if (!ok[q]) continue;
+    const long long e = base + 256LL * q;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (j < N) {
+        T* o = Out + (long long)j * ld + e;
+        const double prev = accumulate ? (double)*o : 0.0;
+        *o = T(prev + alpha * acc[q][j]);
+      }
+    }
+  }
+}
+
 // Energy weights per entry: mu on the three H planes, eps on the E planes.
 __global__ void k_weights(const double* __restrict__ eps, const double* __restrict__ mu,
                           double* __restrict__ w, long long N3) {
@@ -274,15 +357,23 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
     const int wg = nsplit / 4;
     long long kchunk = (n + wg - 1) / wg;
     kchunk = (kchunk + 63) / 64 * 64;
-    const int mt = tall_mt(M);
-    const dim3 grid(wg, (M + 16 * mt - 1) / (16 * mt));
-#define KRY_TALL(MT)                                                                          \
-  if (st == F64)                                                                             \
-    hipLaunchKernelGGL((k_gram_tall<double, MT>), grid, dim3(256), 0, s, (const double*)X, M1, \
-                       (const double*)X2, M, (const double*)Y, N, ld, w, n, kchunk, partials); \
-  else                                                                                       \
-    hipLaunchKernelGGL((k_gram_tall<float, MT>), grid, dim3(256), 0, s, (const float*)X, M1,   \
+    // Y is the second segment of X: one row block with Y as tile 0
+    const bool yseg = Y == X2 && N == M - M1 && M1 + 16 <= 128;
+    const int mt = yseg ? 1 + (M1 + 15) / 16 : tall_mt(M);
+    const dim3 grid(wg, yseg ? 1 : (M + 16 * mt - 1) / (16 * mt));
+#define KRY_TALL_(MT, YS)                                                                          \
+  if (st == F64)                                                                                  \
+    hipLaunchKernelGGL((k_gram_tall<double, MT, YS>), grid, dim3(256), 0, s, (const double*)X, M1,  \
+                       (const double*)X2, M, (const double*)Y, N, ld, w, n, kchunk, partials);      \
+  else                                                                                            \
+    hipLaunchKernelGGL((k_gram_tall<float, MT, YS>), grid, dim3(256), 0, s, (const float*)X, M1,    \
                        (const float*)X2, M, (const float*)Y, N, ld, w, n, kchunk, partials);
+#define KRY_TALL(MT)          \
+  if (yseg) {                 \
+    KRY_TALL_(MT, true)       \
+  } else {                    \
+    KRY_TALL_(MT, false)      \
+  }
     switch (mt) {
       case 1: KRY_TALL(1) break;
       case 2: KRY_TALL(2) break;
@@ -294,6 +385,7 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
       default: KRY_TALL(8) break;
     }
 #undef KRY_TALL
+#undef KRY_TALL_
     return hipGetLastError();
   }
   long long kchunk = (n + nsplit - 1) / nsplit;
@@ -324,6 +416,18 @@ hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int
   if (!X2) {
     M1 = M;
     X2 = X;
+  }
+  if (N <= 16 && M <= 256) {
+    constexpr int EPT = 2;
+    const dim3 grid((unsigned)((n + 256 * EPT - 1) / (256 * EPT)));
+    const size_t lds = sizeof(double) * 16 * (size_t)M;
+    if (st == F64)
+      hipLaunchKernelGGL((k_gemm_cols<double, EPT>), grid, dim3(256), lds, s, (const double*)X, M1,
+                         (const double*)X2, M, C, N, (double*)Out, ld, n, alpha, accumulate);
+    else
+      hipLaunchKernelGGL((k_gemm_cols<float, EPT>), grid, dim3(256), lds, s, (const float*)X, M1,
+                         (const float*)X2, M, C, N, (float*)Out, ld, n, alpha, accumulate);
+    return hipGetLastError();
   }
   const int nt = N >= 64 ? 4 : (N + 15) / 16;
   const dim3 grid((unsigned)((n + 63) / 64), (N + 16 * nt - 1) / (16 * nt));

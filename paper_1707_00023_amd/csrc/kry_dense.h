@@ -110,4 +110,8 @@ void proj_gram(int M, int s, const double* P, double* G, double* ref);
 // s x s upper, both row-major).
 void stack_coef(int M, int s, const double* C, const double* Rinv, double* K);
 
+// As stack_coef for a general (not triangular) s x s factor F:
+// [V, S] K = (S - V C) F.
+void stack_coef_full(int M, int s, const double* C, const double* F, double* K);
+
 }  // namespace kry

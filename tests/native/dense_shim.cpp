@@ -65,6 +65,10 @@ void t_stack_coef(int M, int s, const double* C, const double* Rinv, double* K) 
   kry::stack_coef(M, s, C, Rinv, K);
 }
 
+void t_stack_coef_full(int M, int s, const double* C, const double* F, double* K) {
+  kry::stack_coef_full(M, s, C, F, K);
+}
+
 double t_choose_step_block(int K, int q, int g, const double* H, int ldh, const double* U0,
                            double tau_try, const double* rate, int Ks, double* U, double* err) {
   return kry::choose_step_block(K, q, g, H, ldh, U0, tau_try, rate, Ks, U, err);

@@ -344,3 +344,18 @@ def test_chol_upper_flags_dependent_column(lib):
     Ri = np.zeros((4, 4))
     lib.t_inv_upper(4, P(R), P(Ri))
     assert np.abs(Ri @ R - np.eye(4)).max() <= 1e-12
+
+
+def test_stack_coef_products(lib):
+    # [V, S] K == (S - V C) F, for triangular (stack_coef) and general F
+    rng = np.random.default_rng(11)
+    n, M, s = 40, 7, 5
+    V, S = rng.standard_normal((n, M)), rng.standard_normal((n, s))
+    C = np.ascontiguousarray(rng.standard_normal((M, s)))
+    Fu = np.ascontiguousarray(np.triu(rng.standard_normal((s, s))))
+    Fg = np.ascontiguousarray(rng.standard_normal((s, s)))
+    K = np.zeros((M + s, s))
+    lib.t_stack_coef(M, s, P(C), P(Fu), P(K))
+    assert np.abs(np.hstack([V, S]) @ K - (S - V @ C) @ Fu).max() <= 1e-12
+    lib.t_stack_coef_full(M, s, P(C), P(Fg), P(K))
+    assert np.abs(np.hstack([V, S]) @ K - (S - V @ C) @ Fg).max() <= 1e-12
