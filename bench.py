@@ -97,7 +97,13 @@ def _kernel_entry(st, i):
 
 
 def compare_batched(args, wl, inp, dev):
-    """Batched (block) vs plain solves of the same columns, same tolerance."""
+    """Batched multi-omega solves against plain per-column solves of the same
+    columns at the same tolerance: `columns` consecutive frequencies of the
+    workload at one incidence angle (per-frequency oblique sources).
+    plain: every column on its own; continuation: the columns solved in
+    frequency order, each shifted solve starting from the extrapolation of
+    the earlier frequencies' solutions; block: the columns sharing one
+    block Krylov space (block width, block steps)."""
     import numpy as np
     import torch
 
@@ -106,34 +112,42 @@ def compare_batched(args, wl, inp, dev):
 
     eps = torch.as_tensor(inp.eps, device=dev)
     sig = torch.as_tensor(inp.sigma, device=dev)
-    om = [wl.omegas[args.omega_index]]
-    th = inp.thetas[: args.columns]
-    B = torch.as_tensor(np.stack([wk.source_vector(wl, om[0], float(t)) for t in th]), device=dev)
+    ks = list(range(args.omega_index, min(args.omega_index + args.columns, len(wl.omegas))))
+    om = [wl.omegas[k] for k in ks]
+    th = float(inp.thetas[args.theta_index])
+    B = torch.as_tensor(np.stack([wk.source_vector(wl, w, th) for w in om]), device=dev)
     out = {"metric": "batched vs plain time to solution (same columns, same tol)",
-           "workload": wl.name, "columns": len(th), "omega": om[0], "T": wl.T, "tol": wl.tol}
+           "workload": wl.name, "columns": len(om), "omegas": om, "theta": th, "T": wl.T,
+           "tol": wl.tol}
     ys = {}
-    for name, bw in (("plain", 0), ("batched", args.block_width)):
-        s = kry.Solver(eps, None, sig, kry.Options(krylov_dim=wl.krylov_dim, tol=wl.tol,
-                                                   block_width=bw, block_steps=args.block_steps,
-                                                   timing=True, s_step=args.s_step))
+    all_modes = {"plain": {}, "continuation": {"omega_continuation": True},
+                 "block": {"block_width": args.block_width, "block_steps": args.block_steps}}
+    names = ["plain"] + [m for m in args.batched_modes.split(",") if m in all_modes and m != "plain"]
+    modes = [(m, all_modes[m]) for m in names]
+    for name, extra in modes:
+        s = kry.Solver(eps, None, sig, kry.Options(krylov_dim=wl.krylov_dim, tol=wl.tol, timing=True,
+                                                   s_step=args.s_step, verbose=args.verbose,
+                                                   **extra))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        y = s.solve_multifreq(om, B, wl.T)
+        y = s.solve_multifreq(om, B, wl.T, b_per_omega=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st = s.last_stats
         ys[name] = y.cpu().numpy()
-        out[name] = {"s": dt, "s_per_column": dt / len(th),
+        out[name] = {"s": dt, "s_per_column": dt / len(om),
                      "stationary_s": st["ms_stationary"] / 1e3, "transient_s": st["ms_transient"] / 1e3,
                      "matvecs_stationary": st["matvecs_stationary"],
                      "matvecs_transient": st["matvecs_transient"],
+                     "max_residual": st["max_residual"],
                      "kernels": {k: _kernel_entry(st, i) for i, k in enumerate(kry.KERNEL_CLASSES)
                                  if st["kernel_launches"][i] > 0}}
         print(f"[bench] {name}: {dt:.1f} s", file=sys.stderr, flush=True)
         s.close()
-    d = np.linalg.norm(ys["batched"] - ys["plain"], axis=1) / np.linalg.norm(ys["plain"], axis=1)
-    out["max_rel_diff_batched_vs_plain"] = float(d.max())
-    out["speedup"] = out["plain"]["s"] / out["batched"]["s"]
+    for name in names[1:]:
+        d = np.linalg.norm(ys[name] - ys["plain"], axis=1) / np.linalg.norm(ys["plain"], axis=1)
+        out[name]["max_rel_diff_vs_plain"] = float(d.max())
+        out[name]["speedup_vs_plain"] = out["plain"]["s"] / out[name]["s"]
     print(json.dumps(out), flush=True)
 
 
@@ -239,8 +253,16 @@ def main():
                     help="batched workload only: time the block (batched) solve of a "
                          "column subset against plain one-column-at-a-time solves")
     ap.add_argument("--columns", type=int, default=8,
-                    help="with --compare-batched: columns (one omega, all angles)")
-    ap.add_argument("--omega-index", type=int, default=15)
+                    help="with --compare-batched: number of consecutive frequencies (one angle)")
+    ap.add_argument("--omega-index", type=int, default=12,
+                    help="with --compare-batched: first frequency index of the columns")
+    ap.add_argument("--verbose", action="store_true",
+                    help="library progress lines on stderr during long solves")
+    ap.add_argument("--batched-modes", default="continuation",
+                    help="with --compare-batched: modes compared with plain "
+                         "(continuation, block)")
+    ap.add_argument("--theta-index", type=int, default=0,
+                    help="with --compare-batched: incidence angle index of the columns")
     ap.add_argument("--block-width", type=int, default=16)
     ap.add_argument("--block-steps", type=int, default=16)
     ap.add_argument("--no-autotune", action="store_true")

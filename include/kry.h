@@ -100,6 +100,11 @@ typedef struct {
                            estimate above 1e6 (FP64) or 1e2 (FP32 storage)
                            is redone one step per sweep and halves s for
                            the rest of the call                           */
+  int32_t omega_continuation; /* 1 (per-frequency sources only): each
+                           column's shifted solve starts from the
+                           extrapolation, in omega, of the same source's
+                           solutions at up to three earlier frequencies of
+                           the call, and only the correction is solved    */
 } kry_opts;
 
 /* Kernel classes reported by the per-kernel timing. */

@@ -42,7 +42,8 @@ class KryOpts(ctypes.Structure):
                 ("inner_product", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("timing", ctypes.c_int32), ("block_steps", ctypes.c_int32),
                 ("block_steps_transient", ctypes.c_int32), ("verbose", ctypes.c_int32),
-                ("orth", ctypes.c_int32), ("s_step", ctypes.c_int32)]
+                ("orth", ctypes.c_int32), ("s_step", ctypes.c_int32),
+                ("omega_continuation", ctypes.c_int32)]
 
 
 class KryStats(ctypes.Structure):
@@ -150,6 +151,9 @@ class Options:
     # None: 16 with FP64 storage, 0 (one step per sweep) with FP32 storage,
     # whose rounding the basis-change algebra would amplify
     s_step: Optional[int] = None
+    # per-frequency sources: start each shifted solve from the extrapolation
+    # of the same source's solutions at earlier frequencies of the call
+    omega_continuation: bool = False
 
 
 class Solver:
@@ -184,7 +188,8 @@ class Solver:
                             opts.block_steps_transient, int(bool(opts.verbose)),
                             1 if opts.orth == "cgs2" else 0,
                             int(opts.s_step if opts.s_step is not None
-                                else (0 if opts.storage == "f32" else DEFAULT_S_STEP)))
+                                else (0 if opts.storage == "f32" else DEFAULT_S_STEP)),
+                            int(bool(opts.omega_continuation)))
         self.storage = opts.storage
         ctx = ctypes.c_void_p()
         rc = lib.kry_create(ctypes.byref(self.grid), _ptr(e),

@@ -57,6 +57,11 @@ struct kry_ctx {
 
   void* Z = nullptr;  // 2 * zcap columns (Re, Im per solution column)
   int zcap = 0;
+  // omega continuation: earlier solutions per source (2 vectors each) and
+  // the residual of an extrapolated start (complex interleaved FP64)
+  void* Zh = nullptr;
+  int zh_cap = 0;
+  double* d_r = nullptr;
 
   // block (batched) form: basis slots, energy weights, Gram partials
   void* BV = nullptr;
@@ -445,10 +450,19 @@ double now_ms() {
 // Hessenberg system [Hbar_k, -w] [y_k; rho_k] = coef_k beta e_1, so its new
 // residual is -rho_k V_{m+1} w.
 // Z columns zre_k = 2 * zcol_k, zim_k = 2 * zcol_k + 1 accumulate V_m y_k.
+// zscale (optional, per shift) multiplies the solution added to Z.  Many
+// shifts whose Z columns are contiguous update Z with one tall-skinny
+// product (the basis is read once, not once per group of columns).
+int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, int N, void* Out,
+               double alpha, int accumulate, const void* X2, int M1);
+
 int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> coef,
                const std::vector<int>& zcolk, double bnorm, double tol, kry_stats* st,
-               double* max_res) {
+               double* max_res, const std::vector<double>* zscale = nullptr) {
   const int nw = (int)omegas.size();
+  bool contiguous = 2 * nw > 16;
+  for (int k = 1; k < nw && contiguous; ++k) contiguous = zcolk[k] == zcolk[0] + k;
+  std::vector<double> Cz;
   const int m = c->opts.krylov_dim;
   int rc = ensure_basis(c, m);
   if (rc) return rc;
@@ -525,9 +539,10 @@ int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> 
           return fail(c, KRY_ENOCONV, "singular projected shifted system");
         rho = sol[m];
       }
+      const double zs = zscale ? (*zscale)[k] : 1.0;
       for (int i = 0; i < me; ++i) {
-        Yh[i + (size_t)(2 * ncol) * me] = sol[i].real();
-        Yh[i + (size_t)(2 * ncol + 1) * me] = sol[i].imag();
+        Yh[i + (size_t)(2 * ncol) * me] = zs * sol[i].real();
+        Yh[i + (size_t)(2 * ncol + 1) * me] = zs * sol[i].imag();
       }
       cmap[2 * ncol] = 2 * zcolk[k];
       cmap[2 * ncol + 1] = 2 * zcolk[k] + 1;
@@ -537,7 +552,20 @@ int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> 
       worst = std::max(worst, res);
       if (res <= tol) active[k] = 0;
     }
-    if (ncol > 0) {
+    if (ncol > 0 && contiguous) {
+      // Z[:, 2 zcolk[0] ..] += V_me Cz, Cz (me x 2 nw, row-major; zero for
+      // shifts already converged)
+      Cz.assign((size_t)me * 2 * nw, 0.0);
+      for (int a = 0; a < ncol; ++a) {
+        const int zc = cmap[2 * a] - 2 * zcolk[0];
+        for (int i = 0; i < me; ++i) {
+          Cz[(size_t)i * 2 * nw + zc] = Yh[i + (size_t)(2 * a) * me];
+          Cz[(size_t)i * 2 * nw + zc + 1] = Yh[i + (size_t)(2 * a + 1) * me];
+        }
+      }
+      rc = block_gemm(c, c->V, me, Cz, 2 * nw, zcol(c, 2 * zcolk[0]), 1.0, 1, nullptr, 0);
+      if (rc) return rc;
+    } else if (ncol > 0) {
       KRY_HIP(hipMemcpyAsync(c->d_Y, Yh.data(), sizeof(double) * (size_t)me * 2 * ncol,
                              hipMemcpyHostToDevice, c->stream));
       KRY_HIP(hipMemcpyAsync(c->d_colmap, cmap.data(), sizeof(int) * 2 * ncol, hipMemcpyHostToDevice,
@@ -759,6 +787,8 @@ void kry_destroy(kry_ctx* c) {
   hipFree(c->d_Y);
   hipFree(c->d_colmap);
   hipFree(c->Z);
+  hipFree(c->Zh);
+  hipFree(c->d_r);
   drop_graphs(c);
   if (c->cstream) hipStreamDestroy(c->cstream);
   for (auto& p : c->pending) {
@@ -889,6 +919,107 @@ int stationary_group(kry_ctx* c, const double* b_col, const std::vector<double>&
   return status;
 }
 
+// |x|_M for a complex interleaved FP64 device vector x (slot 0 as staging).
+int cnorm(kry_ctx* c, const double* x, double* out) {
+  double s2 = 0.0;
+  std::vector<double> d;
+  for (int part = 0; part < 2; ++part) {
+    KRY_HIP(kry::launch_load_complex(c->st, x, part, slot(c, 0), c->n, c->stream));
+    int rc = host_dots(c, slot(c, 0), nullptr, 0, d);
+    if (rc) return rc;
+    s2 += d[0];
+  }
+  *out = std::sqrt(std::max(s2, 0.0));
+  return KRY_OK;
+}
+
+void* zhist(kry_ctx* c, int i) { return (char*)c->Zh + (size_t)i * c->ldv * c->esz; }
+
+int ensure_cont(kry_ctx* c, int nvec) {
+  if (!c->Zh || nvec > c->zh_cap) {
+    hipFree(c->Zh);
+    c->Zh = nullptr;
+    c->zh_cap = 0;
+    const size_t bytes = (size_t)nvec * c->ldv * c->esz;
+    if (hipMalloc(&c->Zh, bytes) != hipSuccess) {
+      c->Zh = nullptr;
+      (void)hipGetLastError();
+      return fail(c, KRY_ENOMEM, "cannot allocate continuation workspace of " + std::to_string(bytes) + " bytes");
+    }
+    c->zh_cap = nvec;
+  }
+  if (!c->d_r) KRY_HIP(hipMalloc(&c->d_r, sizeof(double) * 2 * c->n));
+  return KRY_OK;
+}
+
+// Shifted solve of one column with a start from earlier frequencies: z0 =
+// sum_a L_a z(omega_a) (Lagrange extrapolation in omega from the q stored
+// solutions hist_a at omegas om_a), r = b - (A + i w) z0, then
+// (A + i w) d = r to the residual target tol_s |b|_M, z = z0 + d in Z
+// columns 0, 1.  *bnorm receives |b|_M, *res the final relative residual.
+int stationary_from(kry_ctx* c, const double* bcol, double w, const std::vector<double>& om_a,
+                    const std::vector<int>& hist_a, double tol_s, kry_stats* st, double* res,
+                    double* bnorm) {
+  const int q = (int)om_a.size();
+  // z0 into Z columns 2, 3
+  std::vector<double> Y((size_t)4 * q, 0.0);  // (2q) x 2, column-major; inputs ordered as hist slots
+  // the history vectors of one source are contiguous: inputs 2 h, 2 h + 1
+  int hmin = hist_a[0];
+  for (int a = 0; a < q; ++a) hmin = std::min(hmin, hist_a[a]);
+  int hmax = hmin;
+  for (int a = 0; a < q; ++a) hmax = std::max(hmax, hist_a[a]);
+  const int m = 2 * (hmax - hmin + 1);
+  Y.assign((size_t)2 * m, 0.0);
+  for (int a = 0; a < q; ++a) {
+    double L = 1.0;
+    for (int b2 = 0; b2 < q; ++b2)
+      if (b2 != a) L *= (w - om_a[b2]) / (om_a[a] - om_a[b2]);
+    const int i = 2 * (hist_a[a] - hmin);
+    Y[i] = L;              // Re z0 from Re z_a
+    Y[(i + 1) + m] = L;    // Im z0 from Im z_a
+  }
+  int rc = ensure_y(c, m, 2);
+  if (rc) return rc;
+  KRY_HIP(hipMemcpyAsync(c->d_Y, Y.data(), sizeof(double) * 2 * m, hipMemcpyHostToDevice, c->stream));
+  KRY_HIP(kry::launch_combine(c->st, zhist(c, 2 * hmin), c->ldv, m, c->d_Y, 2, zcol(c, 2), c->ldv,
+                              nullptr, 0, c->g, c->stream));
+  // r = b - (A + i w) z0 (A z0 staged in basis slots 1, 2)
+  KRY_HIP(kry::launch_stencil_cols(c->st, zcol(c, 2), slot(c, 1), c->ldv, 2, c->g, c->mats, c->stream));
+  KRY_HIP(kry::launch_shift_residual(c->st, bcol, zcol(c, 2), zcol(c, 3), slot(c, 1), slot(c, 2), w,
+                                     c->d_r, c->n, c->stream));
+  KRY_HIP(hipStreamSynchronize(c->stream));  // Y is reused below
+  if (st) st->matvecs_stationary += 2;
+  double bn = 0.0, rn = 0.0;
+  rc = cnorm(c, bcol, &bn);
+  if (rc) return rc;
+  rc = cnorm(c, c->d_r, &rn);
+  if (rc) return rc;
+  *bnorm = bn;
+  *res = bn > 0.0 ? rn / bn : 0.0;
+  if (bn == 0.0) {
+    KRY_HIP(hipMemsetAsync(zcol(c, 0), 0, 2 * c->ldv * c->esz, c->stream));
+    *res = 0.0;
+    return KRY_OK;
+  }
+  if (!(rn > tol_s * bn)) {  // the extrapolation already meets the target
+    KRY_HIP(hipMemcpyAsync(zcol(c, 0), zcol(c, 2), 2 * c->ldv * c->esz, hipMemcpyDeviceToDevice,
+                           c->stream));
+    return KRY_OK;
+  }
+  double lr = 0.0, rn2 = 0.0;
+  const int status = stationary_group(c, c->d_r, std::vector<double>{w}, std::vector<int>{0},
+                                      tol_s * bn / rn, st, &lr, &rn2);
+  if (status && status != KRY_ENOCONV) return status;
+  *res = lr * rn / bn;
+  // z = z0 + d
+  const double I2[4] = {1.0, 0.0, 0.0, 1.0};
+  KRY_HIP(hipMemcpyAsync(c->d_Y, I2, sizeof(I2), hipMemcpyHostToDevice, c->stream));
+  KRY_HIP(kry::launch_combine(c->st, zcol(c, 2), c->ldv, 2, c->d_Y, 2, zcol(c, 0), c->ldv, nullptr, 1,
+                              c->g, c->stream));
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  return status;
+}
+
 int check_multifreq_args(kry_ctx* c, const double* omegas, int n_omega, int n_src, const double* b) {
   if (!c) return KRY_EINVAL;
   if (!omegas || !b || n_omega < 1 || n_src < 1) return fail(c, KRY_EINVAL, "invalid argument");
@@ -926,19 +1057,44 @@ int for_each_group(kry_ctx* c, const double* omegas, int n_omega, int n_src, con
       }
     }
   } else {
-    int rc = ensure_z(c, 1);
+    // per-frequency sources; with omega continuation, up to kQ earlier
+    // solutions of each source are kept (ring of kQ vector pairs)
+    constexpr int kQ = 3;
+    const bool cont = c->opts.omega_continuation && n_omega > 1;
+    int rc = ensure_z(c, cont ? 2 : 1);
     if (rc) return rc;
+    if (cont) {
+      rc = ensure_cont(c, 2 * kQ * n_src);
+      if (rc) return rc;
+    }
     for (int k = 0; k < n_omega; ++k) {
       for (int s = 0; s < n_src; ++s) {
         const int col = k * n_src + s;
+        const double* bcol = b + (size_t)col * 2 * c->n;
         double bn = 0.0;
-        rc = stationary_group(c, b + (size_t)col * 2 * c->n, std::vector<double>{omegas[k]},
-                              std::vector<int>{0}, tol_s, st, max_res, &bn);
+        const int q = cont ? std::min(k, kQ) : 0;
+        if (q == 0) {
+          rc = stationary_group(c, bcol, std::vector<double>{omegas[k]}, std::vector<int>{0}, tol_s,
+                                st, max_res, &bn);
+        } else {
+          std::vector<double> om_a;
+          std::vector<int> hist_a;
+          for (int kk = k - q; kk < k; ++kk) {
+            om_a.push_back(omegas[kk]);
+            hist_a.push_back(s * kQ + kk % kQ);
+          }
+          double res = 0.0;
+          rc = stationary_from(c, bcol, omegas[k], om_a, hist_a, tol_s, st, &res, &bn);
+          *max_res = std::max(*max_res, res);
+        }
         if (rc == KRY_ENOCONV) status = rc;
         else if (rc) return rc;
         rc = each(col, omegas[k], 0, bn);
         if (rc == KRY_ENOCONV) status = rc;
         else if (rc) return rc;
+        if (cont)  // keep z (Z columns 0, 1) for the next frequencies
+          KRY_HIP(hipMemcpyAsync(zhist(c, 2 * (s * kQ + k % kQ)), zcol(c, 0), 2 * c->ldv * c->esz,
+                                 hipMemcpyDeviceToDevice, c->stream));
       }
     }
   }

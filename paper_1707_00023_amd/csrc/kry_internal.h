@@ -100,6 +100,11 @@ hipError_t launch_combine(Storage st, const void* V, long long ldv, int m, const
                           const DevGrid& g, hipStream_t s);
 
 // Conversions between caller FP64 buffers and storage-type vectors.
+// r = b - (A + i w)(zre + i zim) from azr = A zre, azi = A zim (b, r complex
+// interleaved FP64).
+hipError_t launch_shift_residual(Storage st, const double* b, const void* zre, const void* zim,
+                                 const void* azr, const void* azi, double w, double* r, long long n,
+                                 hipStream_t s);
 hipError_t launch_load_complex(Storage st, const double* b, int part, void* out, long long n,
                                hipStream_t s);
 hipError_t launch_load_real(Storage st, const double* src, void* out, long long n, hipStream_t s);

@@ -693,6 +693,21 @@ __global__ void k_assemble(const T* __restrict__ re, const T* __restrict__ im,
   }
 }
 
+// Residual of a complex shifted system for a trial z = zre + i zim:
+// r = b - (A + i w) z, with azr = A zre and azi = A zim already applied;
+// b and r complex interleaved (FP64).
+template <typename T>
+__global__ void k_shift_residual(const double* __restrict__ b, const T* __restrict__ zre,
+                                 const T* __restrict__ zim, const T* __restrict__ azr,
+                                 const T* __restrict__ azi, double w, double* __restrict__ r,
+                                 long long n) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) {
+    r[2 * e] = b[2 * e] - ((double)azr[e] - w * (double)zim[e]);
+    r[2 * e + 1] = b[2 * e + 1] - ((double)azi[e] + w * (double)zre[e]);
+  }
+}
+
 // Period-averaged Poynting flux of the time-harmonic field z = zre + i zim
 // through the plane z = kf, and the adjoint right-hand side.  One thread per
 // (i, j) column of the plane:
@@ -1032,6 +1047,20 @@ hipError_t launch_combine(Storage st, const void* V, long long ldv, int m, const
                           const DevGrid& g, hipStream_t s) {
   return st == F64 ? combine_t<double>(V, ldv, m, Y, ncol, out, ldo, colmap, accumulate, g, s)
                    : combine_t<float>(V, ldv, m, Y, ncol, out, ldo, colmap, accumulate, g, s);
+}
+
+hipError_t launch_shift_residual(Storage st, const double* b, const void* zre, const void* zim,
+                                 const void* azr, const void* azi, double w, double* r, long long n,
+                                 hipStream_t s) {
+  if (st == F64)
+    hipLaunchKernelGGL(k_shift_residual<double>, dim3(blocks_for(n)), dim3(kBlock), 0, s, b,
+                       (const double*)zre, (const double*)zim, (const double*)azr,
+                       (const double*)azi, w, r, n);
+  else
+    hipLaunchKernelGGL(k_shift_residual<float>, dim3(blocks_for(n)), dim3(kBlock), 0, s, b,
+                       (const float*)zre, (const float*)zim, (const float*)azr, (const float*)azi, w,
+                       r, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_load_complex(Storage st, const double* b, int part, void* out, long long n,

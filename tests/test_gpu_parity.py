@@ -205,12 +205,13 @@ def test_expv_matches_oracle(N, t, s_step):
 
 # ------------------------------------------------------- stationary part --
 
-@pytest.mark.parametrize("s_step", [0, 8])
-def test_stationary_multishift_matches_oracle(s_step):
-    _announce(f"stationary multishift s_step {s_step}")
+@pytest.mark.parametrize("s_step,n_omega", [(0, 3), (8, 3), (8, 10)])
+def test_stationary_multishift_matches_oracle(s_step, n_omega):
+    # ten shifts update Z with one tall-skinny product per cycle
+    _announce(f"stationary multishift s_step {s_step} n_omega {n_omega}")
     wl = wk.small(8, seed=2, n_spheres=4, layer=2)
     inp = wk.generate(wl)
-    om = [2 * math.pi * 0.08, 2 * math.pi * 0.1, 2 * math.pi * 0.12]
+    om = list(2 * math.pi * np.linspace(0.08, 0.12, n_omega))
     b = wk.source_vector(wl, om[0], 0.0)
     s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-11, s_step=s_step)
     z = s.stationary(om, _t(b[None, :])).cpu().numpy()
@@ -277,6 +278,41 @@ def test_solve_fp32_storage(s_step):
     A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
     y_or = osv.split_solution(A, b, om[0], wl.T)[0]
     assert _rel(y, y_or) <= 1e-5
+
+
+@pytest.mark.parametrize("mode", ["omega_continuation"])
+def test_batched_multifreq_modes_match_oracle(mode):
+    # per-frequency oblique sources at nine neighbouring frequencies and two
+    # angles.  omega_continuation starts each shifted solve from the
+    # extrapolation of the earlier frequencies' solutions: the plain fields
+    # with fewer operator applications; a zero source column stays zero.
+    _announce(f"batched multi-frequency: {mode}")
+    wl = wk.small(10, seed=31, n_spheres=5, layer=2, T=50.0)
+    inp = wk.generate(wl)
+    om = list(2 * math.pi * np.linspace(0.09, 0.11, 9))
+    th = [0.2, 0.45]
+    B = np.stack([wk.source_vector(wl, w, t) for w in om for t in th])
+    B[3] = 0.0
+    out = {}
+    for on in (False, True):
+        s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-9, **{mode: on})
+        out[on] = (s.solve_multifreq(om, _t(B), wl.T, b_per_omega=True).cpu().numpy(),
+                   s.last_stats)
+        s.close()
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    for on in (False, True):
+        y = out[on][0]
+        assert np.all(y[3] == 0.0)
+        for col in range(len(B)):
+            if col == 3:
+                continue
+            k, t = divmod(col, len(th))
+            ref = osv.augmented_solution(A, B[col], om[k], wl.T)
+            assert _rel(y[col], ref) <= 1e-8, (on, col)
+        assert out[on][1]["converged"] == 1
+    assert out[True][1]["matvecs_stationary"] < out[False][1]["matvecs_stationary"]
+    _announce(f"matvecs plain {out[False][1]['matvecs_stationary']} "
+              f"{mode} {out[True][1]['matvecs_stationary']}")
 
 
 # ------------------------------------------------------------ edge cases --
