@@ -228,9 +228,11 @@ typedef struct {
   double us_stencil[3], us_update[3], us_dots[3];
 } kry_tune;
 
-/* Time the operator+dots, update and dot kernels of one Arnoldi step with
- * `cnt` basis vectors (0: krylov_dim / 2) for every launch shape on this
- * context's grid and workspace, apply the fastest per kernel class, and
+/* Time the operator kernel the solver runs (the s-step basis stencil when
+ * opts.s_step > 1, else the stencil fused with the first Gram-Schmidt
+ * dots), and the update and dot kernels of one one-step Arnoldi step with
+ * `cnt` basis vectors (0: krylov_dim / 2), for every launch shape on this
+ * context's grid and workspace; apply the fastest per kernel class, and
  * report the choice and timings in *out (host).  Overwrites the context's
  * Krylov workspace (no solve may be in progress on the stream). */
 int kry_autotune(kry_ctx* ctx, int32_t cnt, kry_tune* out);

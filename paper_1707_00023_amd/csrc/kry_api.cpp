@@ -552,7 +552,28 @@ int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> 
       worst = std::max(worst, res);
       if (res <= tol) active[k] = 0;
     }
-    if (ncol > 0 && contiguous) {
+    bool any_active = false;
+    for (int k = 0; k < nw; ++k) any_active |= active[k] != 0;
+    const bool restart = !exact && any_active && cyc + 1 < maxcyc;
+    // the Z update and the next start vector s = V_{m+1} w in one sweep of
+    // the basis (s overwrites slot 0: each cell is read before it is written)
+    const bool fused = restart && !contiguous && 2 * ncol + 1 <= 8;
+    if (fused) {
+      std::vector<double> Yf((size_t)M1 * (2 * ncol + 1), 0.0);
+      for (int col = 0; col < 2 * ncol; ++col)
+        for (int i = 0; i < me; ++i) Yf[i + (size_t)col * M1] = Yh[i + (size_t)col * me];
+      for (int i = 0; i < M1; ++i) Yf[i + (size_t)(2 * ncol) * M1] = wt[i];
+      KRY_HIP(hipMemcpyAsync(c->d_Y, Yf.data(), sizeof(double) * Yf.size(), hipMemcpyHostToDevice,
+                             c->stream));
+      if (ncol > 0)
+        KRY_HIP(hipMemcpyAsync(c->d_colmap, cmap.data(), sizeof(int) * 2 * ncol, hipMemcpyHostToDevice,
+                               c->stream));
+      hipEvent_t e = tbeg(c);
+      KRY_HIP(kry::launch_combine(c->st, c->V, c->ldv, M1, c->d_Y, 2 * ncol + 1, c->Z, c->ldv,
+                                  c->d_colmap, 1, c->g, c->stream, slot(c, 0)));
+      tend(c, e, KRY_K_COMBINE, vbytes(c) * (M1 + 4.0 * ncol + 1.0));
+      KRY_HIP(hipStreamSynchronize(c->stream));  // Yf is a local array
+    } else if (ncol > 0 && contiguous) {
       // Z[:, 2 zcolk[0] ..] += V_me Cz, Cz (me x 2 nw, row-major; zero for
       // shifts already converged)
       Cz.assign((size_t)me * 2 * nw, 0.0);
@@ -577,6 +598,7 @@ int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> 
     }
     if (c->opts.verbose && (cyc + 1) % 20 == 0)
       std::fprintf(stderr, "[kry] shifted solve cycle %d: largest relative residual %.3e\n", cyc + 1, worst);
+    if (fused) continue;  // slot 0 already holds the next start vector
     bool any = false;
     for (int k = 0; k < nw; ++k) any |= active[k] != 0;
     if (!any || exact) {
@@ -956,10 +978,11 @@ int ensure_cont(kry_ctx* c, int nvec) {
 // sum_a L_a z(omega_a) (Lagrange extrapolation in omega from the q stored
 // solutions hist_a at omegas om_a), r = b - (A + i w) z0, then
 // (A + i w) d = r to the residual target tol_s |b|_M, z = z0 + d in Z
-// columns 0, 1.  *bnorm receives |b|_M, *res the final relative residual.
+// pair zk (columns 2 zk, 2 zk + 1); Z pair zs is scratch.  *bnorm receives
+// |b|_M, *res the final relative residual.
 int stationary_from(kry_ctx* c, const double* bcol, double w, const std::vector<double>& om_a,
                     const std::vector<int>& hist_a, double tol_s, kry_stats* st, double* res,
-                    double* bnorm) {
+                    double* bnorm, int zk = 0, int zs = 1) {
   const int q = (int)om_a.size();
   // z0 into Z columns 2, 3
   std::vector<double> Y((size_t)4 * q, 0.0);  // (2q) x 2, column-major; inputs ordered as hist slots
@@ -981,11 +1004,11 @@ int stationary_from(kry_ctx* c, const double* bcol, double w, const std::vector<
   int rc = ensure_y(c, m, 2);
   if (rc) return rc;
   KRY_HIP(hipMemcpyAsync(c->d_Y, Y.data(), sizeof(double) * 2 * m, hipMemcpyHostToDevice, c->stream));
-  KRY_HIP(kry::launch_combine(c->st, zhist(c, 2 * hmin), c->ldv, m, c->d_Y, 2, zcol(c, 2), c->ldv,
+  KRY_HIP(kry::launch_combine(c->st, zhist(c, 2 * hmin), c->ldv, m, c->d_Y, 2, zcol(c, 2 * zs), c->ldv,
                               nullptr, 0, c->g, c->stream));
   // r = b - (A + i w) z0 (A z0 staged in basis slots 1, 2)
-  KRY_HIP(kry::launch_stencil_cols(c->st, zcol(c, 2), slot(c, 1), c->ldv, 2, c->g, c->mats, c->stream));
-  KRY_HIP(kry::launch_shift_residual(c->st, bcol, zcol(c, 2), zcol(c, 3), slot(c, 1), slot(c, 2), w,
+  KRY_HIP(kry::launch_stencil_cols(c->st, zcol(c, 2 * zs), slot(c, 1), c->ldv, 2, c->g, c->mats, c->stream));
+  KRY_HIP(kry::launch_shift_residual(c->st, bcol, zcol(c, 2 * zs), zcol(c, 2 * zs + 1), slot(c, 1), slot(c, 2), w,
                                      c->d_r, c->n, c->stream));
   KRY_HIP(hipStreamSynchronize(c->stream));  // Y is reused below
   if (st) st->matvecs_stationary += 2;
@@ -997,24 +1020,24 @@ int stationary_from(kry_ctx* c, const double* bcol, double w, const std::vector<
   *bnorm = bn;
   *res = bn > 0.0 ? rn / bn : 0.0;
   if (bn == 0.0) {
-    KRY_HIP(hipMemsetAsync(zcol(c, 0), 0, 2 * c->ldv * c->esz, c->stream));
+    KRY_HIP(hipMemsetAsync(zcol(c, 2 * zk), 0, 2 * c->ldv * c->esz, c->stream));
     *res = 0.0;
     return KRY_OK;
   }
   if (!(rn > tol_s * bn)) {  // the extrapolation already meets the target
-    KRY_HIP(hipMemcpyAsync(zcol(c, 0), zcol(c, 2), 2 * c->ldv * c->esz, hipMemcpyDeviceToDevice,
+    KRY_HIP(hipMemcpyAsync(zcol(c, 2 * zk), zcol(c, 2 * zs), 2 * c->ldv * c->esz, hipMemcpyDeviceToDevice,
                            c->stream));
     return KRY_OK;
   }
   double lr = 0.0, rn2 = 0.0;
-  const int status = stationary_group(c, c->d_r, std::vector<double>{w}, std::vector<int>{0},
+  const int status = stationary_group(c, c->d_r, std::vector<double>{w}, std::vector<int>{zk},
                                       tol_s * bn / rn, st, &lr, &rn2);
   if (status && status != KRY_ENOCONV) return status;
   *res = lr * rn / bn;
   // z = z0 + d
   const double I2[4] = {1.0, 0.0, 0.0, 1.0};
   KRY_HIP(hipMemcpyAsync(c->d_Y, I2, sizeof(I2), hipMemcpyHostToDevice, c->stream));
-  KRY_HIP(kry::launch_combine(c->st, zcol(c, 2), c->ldv, 2, c->d_Y, 2, zcol(c, 0), c->ldv, nullptr, 1,
+  KRY_HIP(kry::launch_combine(c->st, zcol(c, 2 * zs), c->ldv, 2, c->d_Y, 2, zcol(c, 2 * zk), c->ldv, nullptr, 1,
                               c->g, c->stream));
   KRY_HIP(hipStreamSynchronize(c->stream));
   return status;
@@ -1914,8 +1937,17 @@ int kry_grad(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
   const double t0 = now_ms();
   rc = ensure_basis(c, c->opts.krylov_dim);
   if (rc) return rc;
-  rc = ensure_z(c, n_omega + 1);
+  // Z pairs: forward solutions 0..n_omega-1, the adjoint solution n_omega,
+  // and with omega continuation a scratch pair n_omega + 1 (allocated now:
+  // growing Z later would drop the forward solutions)
+  constexpr int kQ = 3;
+  const bool cont = c->opts.omega_continuation && n_omega > 1 && dL_deps;
+  rc = ensure_z(c, n_omega + (cont ? 2 : 1));
   if (rc) return rc;
+  if (cont) {
+    rc = ensure_cont(c, 2 * kQ);
+    if (rc) return rc;
+  }
   const long long n = c->n, N3 = c->g.N3;
   double* rhs = nullptr;
   double* fpart = nullptr;
@@ -1967,10 +1999,26 @@ int kry_grad(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
     if (!dL_deps) continue;  // loss only
     // adjoint: (A + i w) x = P M^-1 a, x in Z column n_omega
     double bn = 0.0;
-    rc = stationary_group(c, rhs, std::vector<double>{om[k]}, std::vector<int>{n_omega}, tol, st,
-                          &max_res, &bn);
+    const int q = cont ? std::min(k, kQ) : 0;
+    if (q == 0) {
+      rc = stationary_group(c, rhs, std::vector<double>{om[k]}, std::vector<int>{n_omega}, tol, st,
+                            &max_res, &bn);
+    } else {
+      std::vector<double> om_a;
+      std::vector<int> hist_a;
+      for (int kk = k - q; kk < k; ++kk) {
+        om_a.push_back(om[kk]);
+        hist_a.push_back(kk % kQ);
+      }
+      double res = 0.0;
+      rc = stationary_from(c, rhs, om[k], om_a, hist_a, tol, st, &res, &bn, n_omega, n_omega + 1);
+      max_res = std::max(max_res, res);
+    }
     if (rc == KRY_ENOCONV) status = rc;
     else if (rc) return rc;
+    if (cont)
+      KRY_HIP(hipMemcpyAsync(zhist(c, 2 * (k % kQ)), zcol(c, 2 * n_omega), 2 * c->ldv * c->esz,
+                             hipMemcpyDeviceToDevice, c->stream));
     const double* bk = b_per_omega ? b + (size_t)k * 2 * n : b;
     KRY_HIP(kry::launch_grad_acc(c->st, zre, zim, zcol(c, 2 * n_omega), zcol(c, 2 * n_omega + 1), bk,
                                  om[k], dL_deps, N3, c->stream));
@@ -2066,7 +2114,12 @@ int kry_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {
   };
   for (int k = 0; k < 3; ++k) {
     c->g.cpt_s = c->g.cpt_u = c->g.cpt_d = cpts[k];
+    // the operator kernel the solver runs: the s-step basis stencil, or the
+    // stencil fused with the Gram-Schmidt dots of the one-step Arnoldi
     out->us_stencil[k] = time_us([&]() {
+      if (c->opts.s_step > 1)
+        return kry::launch_stencil_axpby(c->st, U, slot(c, cnt), X, 2.0 / c->rho, 0.0, 1.0, c->g,
+                                         c->mats, c->stream);
       return kry::launch_stencil_lag(c->st, U, X, c->V, c->ldv, cnt, c->g, c->mats, c->partials, c->stream);
     });
     out->us_update[k] = time_us([&]() {

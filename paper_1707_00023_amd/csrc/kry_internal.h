@@ -94,10 +94,12 @@ hipError_t launch_scale(Storage st, const void* x, const double* scale, void* ou
                         hipStream_t s);
 
 // out_c (= or +=) sum_{i<m} V_i Y[i + c*m] for c < ncol; column c goes to
-// out + colmap[c] * ldo (colmap may be nullptr: identity).
+// out + colmap[c] * ldo (colmap may be nullptr: identity).  With out_last,
+// the last column goes there instead, assigned (never accumulated); it may
+// be one of the V_i, and then ncol must be at most 8.
 hipError_t launch_combine(Storage st, const void* V, long long ldv, int m, const double* Y,
                           int ncol, void* out, long long ldo, const int* colmap, int accumulate,
-                          const DevGrid& g, hipStream_t s);
+                          const DevGrid& g, hipStream_t s, void* out_last = nullptr);
 
 // Conversions between caller FP64 buffers and storage-type vectors.
 // r = b - (A + i w)(zre + i zim) from azr = A zre, azi = A zim (b, r complex

@@ -605,12 +605,16 @@ __global__ void k_scale(const T* __restrict__ x, const double* __restrict__ s, T
 }
 
 // out_c (=|+=) sum_{i<m} V_i Y[i + c*m]; columns processed CC at a time.
+// With out_last != null the last column (c = ncol - 1) is written to
+// out_last instead, never accumulated; out_last may be one of the V_i (a
+// thread reads every V_i at its cells before writing them), so then all
+// columns must be in one workgroup row (ncol <= CC).
 template <typename T, int CC>
 __global__ __launch_bounds__(kBlock) void k_combine(const T* V, long long ldv, int m,
                                                     const double* __restrict__ Y, int ncol,
                                                     T* out, long long ldo,
                                                     const int* __restrict__ colmap, int accumulate,
-                                                    long long N3) {
+                                                    T* out_last, long long N3) {
   extern __shared__ double sY[];  // m * CC
   const int c0 = blockIdx.y * CC;
   const int nc = min(CC, ncol - c0);
@@ -641,12 +645,14 @@ __global__ __launch_bounds__(kBlock) void k_combine(const T* V, long long ldv, i
 #pragma unroll
   for (int cc = 0; cc < CC; ++cc) {
     if (cc >= nc) break;
-    const int col = colmap ? colmap[c0 + cc] : (c0 + cc);
-    T* o = out + (long long)col * ldo;
+    const bool last = out_last && c0 + cc == ncol - 1;
+    const int col = last ? 0 : (colmap ? colmap[c0 + cc] : (c0 + cc));
+    T* o = last ? out_last : out + (long long)col * ldo;
+    const int acc_on = last ? 0 : accumulate;
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
       const long long e = p * N3 + c;
-      const double prev = accumulate ? (double)o[e] : 0.0;
+      const double prev = acc_on ? (double)o[e] : 0.0;
       o[e] = T(prev + acc[cc][p]);
     }
   }
@@ -1025,28 +1031,30 @@ hipError_t launch_scale(Storage st, const void* x, const double* scale, void* ou
 
 template <typename T>
 static hipError_t combine_t(const void* V, long long ldv, int m, const double* Y, int ncol, void* out,
-                            long long ldo, const int* colmap, int accumulate, const DevGrid& g,
-                            hipStream_t s) {
+                            long long ldo, const int* colmap, int accumulate, void* out_last,
+                            const DevGrid& g, hipStream_t s) {
   if (m <= 0 || ncol <= 0) return hipSuccess;
+  constexpr int CC = 8;
+  if (out_last && ncol > CC) return hipErrorInvalidValue;
   const unsigned gx = blocks_for(g.N3);
   if (ncol == 1) {
     const size_t shm = sizeof(double) * (size_t)m;
     hipLaunchKernelGGL((k_combine<T, 1>), dim3(gx, 1), dim3(kBlock), shm, s, (const T*)V, ldv, m, Y,
-                       ncol, (T*)out, ldo, colmap, accumulate, g.N3);
+                       ncol, (T*)out, ldo, colmap, accumulate, (T*)out_last, g.N3);
   } else {
-    constexpr int CC = 8;
     const size_t shm = sizeof(double) * (size_t)m * CC;
     hipLaunchKernelGGL((k_combine<T, CC>), dim3(gx, (ncol + CC - 1) / CC), dim3(kBlock), shm, s,
-                       (const T*)V, ldv, m, Y, ncol, (T*)out, ldo, colmap, accumulate, g.N3);
+                       (const T*)V, ldv, m, Y, ncol, (T*)out, ldo, colmap, accumulate, (T*)out_last,
+                       g.N3);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_combine(Storage st, const void* V, long long ldv, int m, const double* Y, int ncol,
                           void* out, long long ldo, const int* colmap, int accumulate,
-                          const DevGrid& g, hipStream_t s) {
-  return st == F64 ? combine_t<double>(V, ldv, m, Y, ncol, out, ldo, colmap, accumulate, g, s)
-                   : combine_t<float>(V, ldv, m, Y, ncol, out, ldo, colmap, accumulate, g, s);
+                          const DevGrid& g, hipStream_t s, void* out_last) {
+  return st == F64 ? combine_t<double>(V, ldv, m, Y, ncol, out, ldo, colmap, accumulate, out_last, g, s)
+                   : combine_t<float>(V, ldv, m, Y, ncol, out, ldo, colmap, accumulate, out_last, g, s);
 }
 
 hipError_t launch_shift_residual(Storage st, const double* b, const void* zre, const void* zim,

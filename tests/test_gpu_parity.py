@@ -419,18 +419,21 @@ def test_batched_c3_against_oracle_samples():
 
 # ---------------------------------------------------------- differentiation --
 
-def test_grad_matches_oracle_adjoint_and_fd():
-    _announce("gradient vs oracle")
+@pytest.mark.parametrize("cont", [False, True])
+def test_grad_matches_oracle_adjoint_and_fd(cont):
+    # cont: the adjoint solves start from the extrapolation of the earlier
+    # frequencies' adjoint solutions
+    _announce(f"gradient vs oracle (omega continuation {cont})")
     from oracle import grad as og
     N, kf = 7, 5
     wl = wk.small(N, seed=22, n_spheres=3, layer=1, radius=(0.8, 1.6),
-                  omegas=(2 * math.pi * 0.09, 2 * math.pi * 0.11), src_k=1)
+                  omegas=(2 * math.pi * 0.09, 2 * math.pi * 0.1, 2 * math.pi * 0.11), src_k=1)
     inp = wk.generate(wl)
     b = wk.source_vector(wl, wl.omegas[0], 0.0)
-    s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-12)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-12, omega_continuation=cont)
     L, g = s.grad(wl.omegas, _t(b[None, :]), kf)
     g = g.cpu().numpy()
-    b_cols = np.stack([b, b], axis=1)
+    b_cols = np.stack([b] * len(wl.omegas), axis=1)
     Lo, go = og.loss_and_grad(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, kf)
     assert abs(L - Lo) <= 1e-10 * abs(Lo)
     assert np.linalg.norm(g - go) <= 1e-8 * np.linalg.norm(go)
