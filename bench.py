@@ -293,7 +293,7 @@ def main():
     dev = torch.device("cuda:0")
     args.s_step_cli = args.s_step
     if args.s_step is None:
-        args.s_step = 0 if wl.storage == "f32" else kry.DEFAULT_S_STEP
+        args.s_step = kry.DEFAULT_S_STEP
     if args.compare_batched:
         compare_batched(args, wl, inp, dev)
         return

@@ -94,12 +94,14 @@ typedef struct {
                            Gram-Schmidt step (as chosen by orth); s in
                            2..64: s-step Arnoldi, s operator applications
                            build a Chebyshev basis block that is
-                           orthogonalised as one tall-skinny block on the
-                           matrix cores (two basis sweeps per s steps).  A
+                           orthogonalised as one tall-skinny block (two
+                           basis sweeps per s steps).  The block is FP64
+                           also with FP32 storage (only the orthonormal
+                           result is rounded to FP32; FP32 storage with
+                           krylov_dim > 112 runs one step per sweep).  A
                            block whose triangular factor has a condition
-                           estimate above 1e6 (FP64) or 1e2 (FP32 storage)
-                           is redone one step per sweep and halves s for
-                           the rest of the call                           */
+                           estimate above 1e6 is redone one step per sweep
+                           and halves s for the rest of the call          */
   int32_t omega_continuation; /* 1 (per-frequency sources only): each
                            column's shifted solve starts from the
                            extrapolation, in omega, of the same source's

@@ -147,9 +147,8 @@ class Options:
     verbose: bool = False       # progress lines on stderr during long solves
     block_steps: int = 0        # batched shifted solves: block steps per restart (0 auto)
     block_steps_transient: int = 0  # batched exponential: block steps per restart (0 auto)
-    # s-step Arnoldi block size (Chebyshev block, matrix-core Gram-Schmidt);
-    # None: 16 with FP64 storage, 0 (one step per sweep) with FP32 storage,
-    # whose rounding the basis-change algebra would amplify
+    # s-step Arnoldi block size (Chebyshev block orthogonalised as one
+    # tall-skinny block; the block is FP64 with either storage); None: 16
     s_step: Optional[int] = None
     # per-frequency sources: start each shifted solve from the extrapolation
     # of the same source's solutions at earlier frequencies of the call
@@ -187,8 +186,7 @@ class Solver:
                             int(bool(opts.timing)), opts.block_steps,
                             opts.block_steps_transient, int(bool(opts.verbose)),
                             1 if opts.orth == "cgs2" else 0,
-                            int(opts.s_step if opts.s_step is not None
-                                else (0 if opts.storage == "f32" else DEFAULT_S_STEP)),
+                            int(opts.s_step if opts.s_step is not None else DEFAULT_S_STEP),
                             int(bool(opts.omega_continuation)))
         self.storage = opts.storage
         ctx = ctypes.c_void_p()

@@ -61,6 +61,9 @@ struct kry_ctx {
   // the residual of an extrapolated start (complex interleaved FP64)
   void* Zh = nullptr;
   int zh_cap = 0;
+  // FP64 work block of the s-step Arnoldi under FP32 storage
+  double* SB = nullptr;
+  int sb_cap = 0;
   double* d_r = nullptr;
 
   // block (batched) form: basis slots, energy weights, Gram partials
@@ -210,7 +213,7 @@ int ensure_basis(kry_ctx* c, int m) {
   c->mcap = 0;
   // slots 0..m: basis; m+1: candidate / work vector; m+2: operator output
   // (an s-step block uses slots m+1..m+s as its work block)
-  const int extra = std::max(2, std::min(c->opts.s_step, m));
+  const int extra = c->st == kry::F64 ? std::max(2, std::min(c->opts.s_step, m)) : 2;
   const size_t vbytes = (size_t)(m + 1 + extra) * c->ldv * c->esz;
   if (hipMalloc(&c->V, vbytes) != hipSuccess) {
     c->V = nullptr;
@@ -454,7 +457,7 @@ double now_ms() {
 // shifts whose Z columns are contiguous update Z with one tall-skinny
 // product (the basis is read once, not once per group of columns).
 int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, int N, void* Out,
-               double alpha, int accumulate, const void* X2, int M1);
+               double alpha, int accumulate, const void* X2, int M1, int st1, int st2, int sto);
 
 int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> coef,
                const std::vector<int>& zcolk, double bnorm, double tol, kry_stats* st,
@@ -584,7 +587,7 @@ int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> 
           Cz[(size_t)i * 2 * nw + zc + 1] = Yh[i + (size_t)(2 * a + 1) * me];
         }
       }
-      rc = block_gemm(c, c->V, me, Cz, 2 * nw, zcol(c, 2 * zcolk[0]), 1.0, 1, nullptr, 0);
+      rc = block_gemm(c, c->V, me, Cz, 2 * nw, zcol(c, 2 * zcolk[0]), 1.0, 1, nullptr, 0, -1, -1, -1);
       if (rc) return rc;
     } else if (ncol > 0) {
       KRY_HIP(hipMemcpyAsync(c->d_Y, Yh.data(), sizeof(double) * (size_t)me * 2 * ncol,
@@ -811,6 +814,7 @@ void kry_destroy(kry_ctx* c) {
   hipFree(c->Z);
   hipFree(c->Zh);
   hipFree(c->d_r);
+  hipFree(c->SB);
   drop_graphs(c);
   if (c->cstream) hipStreamDestroy(c->cstream);
   for (auto& p : c->pending) {
@@ -1139,6 +1143,21 @@ namespace {
 
 void* bslot(kry_ctx* c, int i) { return (char*)c->BV + (size_t)i * c->ldv * c->esz; }
 
+int ensure_sblock(kry_ctx* c, int nvec) {
+  if (c->SB && nvec <= c->sb_cap) return KRY_OK;
+  hipFree(c->SB);
+  c->SB = nullptr;
+  c->sb_cap = 0;
+  const size_t bytes = (size_t)nvec * c->ldv * sizeof(double);
+  if (hipMalloc(&c->SB, bytes) != hipSuccess) {
+    c->SB = nullptr;
+    (void)hipGetLastError();
+    return fail(c, KRY_ENOMEM, "cannot allocate s-step block of " + std::to_string(bytes) + " bytes");
+  }
+  c->sb_cap = nvec;
+  return KRY_OK;
+}
+
 int ensure_weights(kry_ctx* c) {
   if (!c->d_w) {
     KRY_HIP(hipMalloc(&c->d_w, sizeof(double) * c->ldv));
@@ -1184,16 +1203,28 @@ int ensure_gp(kry_ctx* c, size_t doubles, size_t bc) {
 // C (M x N, row-major, host) = X^T M Y for block columns X[:M], Y[:N]
 // (device pointers to the first column; stride ldv).  Synchronises.
 // With X2 != nullptr, X is two segments (columns k >= M1 at X2).
+// Bytes of one vector of storage type st (-1: the context's).
+double vbytes_of(kry_ctx* c, int st) {
+  const int t = st < 0 ? (int)c->st : st;
+  return 6.0 * c->g.N3 * (t == kry::F64 ? 8.0 : 4.0);
+}
+
+// st1: element type of X's first segment, st2 of X2 and Y (-1: the
+// context's storage type).
 int block_gram_host(kry_ctx* c, const void* X, int M, const void* Y, int N, std::vector<double>& C,
-                    const void* X2 = nullptr, int M1 = 0) {
+                    const void* X2 = nullptr, int M1 = 0, int st1 = -1, int st2 = -1) {
   const int ns = kry::gram_splits(c->n, M, N);
   int rc = ensure_gp(c, (size_t)ns * M * N, (size_t)M * N);
   if (rc) return rc;
+  const kry::Storage s1 = st1 < 0 ? c->st : (kry::Storage)st1;
   hipEvent_t e = tbeg(c);
-  KRY_HIP(kry::launch_gram(c->st, X, M, Y, N, c->ldv, c->d_w, c->n, c->d_gp, ns, c->stream, X2, M1));
+  KRY_HIP(kry::launch_gram(s1, X, M, Y, N, c->ldv, c->d_w, c->n, c->d_gp, ns, c->stream, X2, M1, st2));
   // algorithmic bytes: every distinct column once (Y may be part of X)
   const bool y_in_x = (X2 && Y == X2 && N == M - M1) || (!X2 && Y == X && N <= M);
-  tend(c, e, KRY_K_GRAM, vbytes(c) * (y_in_x ? M : M + N) + 8.0 * c->n, 2.0 * c->n * M * N);
+  const int seg1 = X2 ? M1 : M;
+  const double xb = vbytes_of(c, s1) * seg1 + vbytes_of(c, st2 < 0 ? s1 : st2) * (M - seg1);
+  tend(c, e, KRY_K_GRAM, xb + (y_in_x ? 0.0 : vbytes_of(c, st2 < 0 ? s1 : st2) * N) + 8.0 * c->n,
+       2.0 * c->n * M * N);
   KRY_HIP(kry::launch_reduce(c->d_gp, ns, M * N, M * N, c->d_bc, c->stream));
   C.resize((size_t)M * N);
   KRY_HIP(hipMemcpyAsync(C.data(), c->d_bc, sizeof(double) * M * N, hipMemcpyDeviceToHost, c->stream));
@@ -1203,15 +1234,22 @@ int block_gram_host(kry_ctx* c, const void* X, int M, const void* Y, int N, std:
 
 // Out[:N] (=|+=) alpha X[:M] C with C (M x N row-major) from the host.
 // X in one or two segments as for block_gram_host.
+// st1, st2, sto: element types of X's first segment, of X2 and of Out (-1:
+// the context's storage type).
 int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, int N, void* Out,
-               double alpha, int accumulate, const void* X2 = nullptr, int M1 = 0) {
+               double alpha, int accumulate, const void* X2 = nullptr, int M1 = 0, int st1 = -1,
+               int st2 = -1, int sto = -1) {
   int rc = ensure_gp(c, 0, (size_t)M * N);
   if (rc) return rc;
+  const kry::Storage s1 = st1 < 0 ? c->st : (kry::Storage)st1;
   KRY_HIP(hipMemcpyAsync(c->d_bc, C.data(), sizeof(double) * M * N, hipMemcpyHostToDevice, c->stream));
   hipEvent_t e = tbeg(c);
-  KRY_HIP(kry::launch_gemm_nn(c->st, X, M, c->d_bc, N, Out, c->ldv, c->n, alpha, accumulate, c->stream,
-                              X2, M1));
-  tend(c, e, KRY_K_GEMM, vbytes(c) * (M + (accumulate ? 2.0 : 1.0) * N), 2.0 * c->n * M * N);
+  KRY_HIP(kry::launch_gemm_nn(s1, X, M, c->d_bc, N, Out, c->ldv, c->n, alpha, accumulate, c->stream,
+                              X2, M1, st2, sto));
+  const int seg1 = X2 ? M1 : M;
+  const double xb = vbytes_of(c, s1) * seg1 + vbytes_of(c, st2 < 0 ? s1 : st2) * (M - seg1);
+  tend(c, e, KRY_K_GEMM, xb + vbytes_of(c, sto < 0 ? s1 : sto) * (accumulate ? 2.0 : 1.0) * N,
+       2.0 * c->n * M * N);
   // the host array may be reused by the caller right after
   KRY_HIP(hipStreamSynchronize(c->stream));
   return KRY_OK;
@@ -1247,13 +1285,28 @@ const std::vector<double>& stack_coef(int M, int s, const std::vector<double>& C
 int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
   const int s = c->s_eff;
   // largest accepted condition estimate |R|_F |R^-1|_F of a block's
-  // triangular factor: errors of the stored basis reach Hbar amplified by
-  // it (FP64 storage: 1e-16 * 1e6; FP32 storage: 6e-8 * 1e2)
-  const double cond_max = c->st == kry::F64 ? 1e6 : 1e2;
+  // triangular factor: rounding of the stored block reaches Hbar amplified
+  // by it, and the block is always FP64 (1e-16 * 1e6)
+  const double cond_max = 1e6;
   const int ldh = m + 1;
   hipStream_t st = c->stream;
   int rc = ensure_weights(c);
   if (rc) return rc;
+  // the work block: FP64 storage keeps it in the basis slots (S right after
+  // v_j0, Tb after the basis); FP32 storage keeps an FP64 copy of v_j0, S
+  // and Tb apart, and only the final orthonormal block is rounded to FP32
+  const bool wide = c->st == kry::F32;
+  if (wide && m > 112) {  // the mixed-type Gram product keeps [V, S] in one row block
+    double b1 = 0.0;
+    const int r = arnoldi_lag(c, m, &b1, m_eff);
+    *beta = b1;
+    return r;
+  }
+  if (wide) {
+    rc = ensure_sblock(c, 2 * s + 1);
+    if (rc) return rc;
+  }
+  const int f64 = (int)kry::F64;
   std::vector<double> d;
   rc = host_dots(c, slot(c, 0), nullptr, 0, d);
   if (rc) return rc;
@@ -1273,32 +1326,40 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
   // Chebyshev polynomials stay bounded (a centre in the damping range
   // made the blocks of the 128^3 medium worse conditioned)
   const double rho = c->rho, cc = 0.0;
-  void* Tb = slot(c, c->mcap + 1);
+  auto sb = [&](int i) { return (void*)((char*)c->SB + (size_t)i * c->ldv * sizeof(double)); };
+  void* Tb = wide ? sb(s + 1) : slot(c, c->mcap + 1);
   const double mb_axpby = mbytes(c, true) - 8.0 * c->g.N3;
+  const double vb64 = vbytes_of(c, f64);
   std::vector<double> C1, C2, G, P, R1, R2, Ri, ref, K;
   for (int j0 = 0; j0 < m; j0 += s) {
     const int ss = std::min(s, m - j0);
     const int M = j0 + 1;
-    // Chebyshev block into slots j0+1..j0+ss
+    // t_0 (FP64), then the Chebyshev block t_1..t_ss into S
+    void* t0 = slot(c, j0);
+    void* S = slot(c, j0 + 1);
+    if (wide) {
+      KRY_HIP(kry::launch_store_real(c->st, slot(c, j0), (double*)sb(0), c->n, st));
+      t0 = sb(0);
+      S = sb(1);
+    }
+    auto tk = [&](int k) { return k == 0 ? t0 : (void*)((char*)S + (size_t)(k - 1) * c->ldv * 8); };
     for (int k = 0; k < ss; ++k) {
       hipEvent_t e = tbeg(c);
       if (k == 0)
-        KRY_HIP(kry::launch_stencil_axpby(c->st, slot(c, j0), nullptr, slot(c, j0 + 1), 1.0 / rho,
-                                          -cc / rho, 0.0, c->g, c->mats, st));
+        KRY_HIP(kry::launch_stencil_axpby(kry::F64, tk(0), nullptr, tk(1), 1.0 / rho, -cc / rho, 0.0,
+                                          c->g, c->mats, st));
       else
-        KRY_HIP(kry::launch_stencil_axpby(c->st, slot(c, j0 + k), slot(c, j0 + k - 1),
-                                          slot(c, j0 + k + 1), 2.0 / rho, -2.0 * cc / rho, 1.0, c->g,
-                                          c->mats, st));
-      tend(c, e, KRY_K_STENCIL, vbytes(c) * (k == 0 ? 2.0 : 3.0) + mb_axpby);
+        KRY_HIP(kry::launch_stencil_axpby(kry::F64, tk(k), tk(k - 1), tk(k + 1), 2.0 / rho,
+                                          -2.0 * cc / rho, 1.0, c->g, c->mats, st));
+      tend(c, e, KRY_K_STENCIL, vb64 * (k == 0 ? 2.0 : 3.0) + mb_axpby);
     }
-    void* S = slot(c, j0 + 1);
     R1.resize((size_t)ss * ss);
     R2.resize((size_t)ss * ss);
     Ri.resize((size_t)ss * ss);
     // pass 1: one Gram product [V, S]^T M S gives C1 = V^T M S and S^T M S,
     // so the projected Gram matrix is S^T M S - C1^T C1 (Pythagoras; V is
     // M-orthonormal); then Tb = (S - V C1) R1^{-1} in one product
-    rc = block_gram_host(c, slot(c, 0), M + ss, S, ss, P, S, M);
+    rc = block_gram_host(c, slot(c, 0), M + ss, S, ss, P, S, M, -1, f64);
     if (rc) return rc;
     C1.assign(P.begin(), P.begin() + (size_t)M * ss);
     G.resize((size_t)ss * ss);
@@ -1307,29 +1368,30 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
     bool ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-10, R1.data());
     if (ok) {
       kry::inv_upper(ss, R1.data(), Ri.data());
-      rc = block_gemm(c, slot(c, 0), M + ss, stack_coef(M, ss, C1, Ri, K), ss, Tb, 1.0, 0, S, M);
+      rc = block_gemm(c, slot(c, 0), M + ss, stack_coef(M, ss, C1, Ri, K), ss, Tb, 1.0, 0, S, M, -1,
+                      f64, f64);
       if (rc) return rc;
     } else {
       // cancellation in the projected Gram matrix: project explicitly
-      rc = block_gemm(c, slot(c, 0), M, C1, ss, S, -1.0, 1);
+      rc = block_gemm(c, slot(c, 0), M, C1, ss, S, -1.0, 1, nullptr, 0, -1, -1, f64);
       if (rc) return rc;
-      rc = block_gram_host(c, S, ss, S, ss, G);
+      rc = block_gram_host(c, S, ss, S, ss, G, nullptr, 0, f64, f64);
       if (rc) return rc;
       ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-10, R1.data());
       if (ok) {
         kry::inv_upper(ss, R1.data(), Ri.data());
-        rc = block_gemm(c, S, ss, Ri, ss, Tb, 1.0, 0);
+        rc = block_gemm(c, S, ss, Ri, ss, Tb, 1.0, 0, nullptr, 0, f64, f64, f64);
         if (rc) return rc;
       }
     }
     if (ok) {
-      // pass 2, the same on Tb; the result Q lands in slots j0+1..j0+ss
-      rc = block_gram_host(c, slot(c, 0), M + ss, Tb, ss, P, Tb, M);
+      // pass 2, the same on Tb
+      rc = block_gram_host(c, slot(c, 0), M + ss, Tb, ss, P, Tb, M, -1, f64);
       if (rc) return rc;
       C2.assign(P.begin(), P.begin() + (size_t)M * ss);
       G.resize((size_t)ss * ss);
-    ref.resize(ss);
-    kry::proj_gram(M, ss, P.data(), G.data(), ref.data());
+      ref.resize(ss);
+      kry::proj_gram(M, ss, P.data(), G.data(), ref.data());
       std::fill(ref.begin(), ref.end(), 1.0);
       ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-8, R2.data());
     }
@@ -1362,8 +1424,10 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
       *beta = b0 * b1;
       return rc;
     }
+    // Q = (Tb - V C2) R2^{-1} into the basis slots j0+1..j0+ss (storage type)
     kry::inv_upper(ss, R2.data(), Ri.data());
-    rc = block_gemm(c, slot(c, 0), M + ss, stack_coef(M, ss, C2, Ri, K), ss, S, 1.0, 0, Tb, M);
+    rc = block_gemm(c, slot(c, 0), M + ss, stack_coef(M, ss, C2, Ri, K), ss, slot(c, j0 + 1), 1.0, 0, Tb,
+                    M, -1, f64, -1);
     if (rc) return rc;
     kry::sstep_hessenberg(j0, ss, rho, cc, C1.data(), C2.data(), R1.data(), R2.data(), H, ldh);
   }

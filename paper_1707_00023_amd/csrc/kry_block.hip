@@ -119,10 +119,12 @@ __global__ __launch_bounds__(256) void k_gram_tn(const T* __restrict__ X, int M1
 // row block).  Row tile 0 then holds Y and tiles 1.. the first segment, so
 // the Y operand is the tile-0 data already in registers (Y is read once,
 // not twice); output rows are mapped back to the [X; X2] order.
-template <typename T, int MT, bool YSEG>
+// T2: element type of the second segment (and of Y); a second segment of
+// another type than the first is supported in the YSEG layout only.
+template <typename T, typename T2, int MT, bool YSEG>
 __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int M1,
-                                                   const T* __restrict__ X2, int M,
-                                                   const T* __restrict__ Y, int N, long long ld,
+                                                   const T2* __restrict__ X2, int M,
+                                                   const T2* __restrict__ Y, int N, long long ld,
                                                    const double* __restrict__ w, long long n,
                                                    long long kchunk, double* __restrict__ partials) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -130,15 +132,18 @@ __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int 
   const int r0 = blockIdx.y * 16 * MT;
   const long long e_begin = (long long)blockIdx.x * kchunk;
   const long long e_end = min(n, e_begin + kchunk);
+  static_assert(YSEG || sizeof(T) == sizeof(T2), "mixed element types need the YSEG layout");
   bool arow[MT];
   const T* xc[MT];
+  const T2* x2c = X2;  // YSEG: tile 0 (the second segment)
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
     const int r = r0 + 16 * t + i;
     if (YSEG) {  // virtual rows: [0, 16) second segment, [16, 16 + M1) first
       if (t == 0) {
         arow[t] = i < N;
-        xc[t] = X2 + (long long)(arow[t] ? i : 0) * ld;
+        x2c = X2 + (long long)(arow[t] ? i : 0) * ld;
+        xc[t] = X;
       } else {
         arow[t] = r - 16 < M1;
         xc[t] = X + (long long)(arow[t] ? r - 16 : 0) * ld;
@@ -146,11 +151,12 @@ __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int 
     } else {
       arow[t] = r < M;
       const int rr = arow[t] ? r : 0;
-      xc[t] = rr < M1 ? X + (long long)rr * ld : X2 + (long long)(rr - M1) * ld;
+      xc[t] = rr < M1 ? X + (long long)rr * ld
+                      : reinterpret_cast<const T*>(X2) + (long long)(rr - M1) * ld;
     }
   }
   const bool bcol = i < N;
-  const T* yc = Y + (long long)(bcol ? i : 0) * ld;
+  const T2* yc = Y + (long long)(bcol ? i : 0) * ld;
   v4d acc[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
@@ -160,8 +166,9 @@ __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int 
     load4(w, eb, e_end, ww);
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      if (arow[t]) load4(xc[t], eb, e_end, xa[t]);
-      else xa[t][0] = xa[t][1] = xa[t][2] = xa[t][3] = 0.0;
+      if (!arow[t]) xa[t][0] = xa[t][1] = xa[t][2] = xa[t][3] = 0.0;
+      else if (YSEG && t == 0) load4(x2c, eb, e_end, xa[t]);
+      else load4(xc[t], eb, e_end, xa[t]);
     }
     if (YSEG) {
 #pragma unroll
@@ -257,11 +264,12 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ X, int M1
 // 2 N M flops per entry, far below the FP64 vector rate at the bandwidth
 // this kernel moves, so the matrix cores gain nothing here.  X in two
 // segments as in k_gram_tn.  Out may not overlap X.
-template <typename T, int EPT>
+// T2: element type of the second segment; TO: of Out.
+template <typename T, typename T2, typename TO, int EPT>
 __global__ __launch_bounds__(256) void k_gemm_cols(const T* __restrict__ X, int M1,
-                                                   const T* __restrict__ X2, int M,
+                                                   const T2* __restrict__ X2, int M,
                                                    const double* __restrict__ C, int N,
-                                                   T* __restrict__ Out, long long ld, long long n,
+                                                   TO* __restrict__ Out, long long ld, long long n,
                                                    double alpha, int accumulate) {
   extern __shared__ double sC[];  // M x 16
   for (int t = threadIdx.x; t < M * 16; t += 256) {
@@ -280,10 +288,16 @@ __global__ __launch_bounds__(256) void k_gemm_cols(const T* __restrict__ X, int 
   }
 #pragma unroll 2
   for (int k = 0; k < M; ++k) {
-    const T* xk = k < M1 ? X + (long long)k * ld : X2 + (long long)(k - M1) * ld;
     double x[EPT];
+    if (k < M1) {
+      const T* xk = X + (long long)k * ld;
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) x[q] = ok[q] ? (double)xk[base + 256LL * q] : 0.0;
+      for (int q = 0; q < EPT; ++q) x[q] = ok[q] ? (double)xk[base + 256LL * q] : 0.0;
+    } else {
+      const T2* xk = X2 + (long long)(k - M1) * ld;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) x[q] = ok[q] ? (double)xk[base + 256LL * q] : 0.0;
+    }
     const double2* row = reinterpret_cast<const double2*>(sC + 16 * k);
 #pragma unroll
     for (int j2 = 0; j2 < 8; ++j2) {
@@ -302,9 +316,9 @@ __global__ __launch_bounds__(256) void k_gemm_cols(const T* __restrict__ X, int 
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       if (j < N) {
-        T* o = Out + (long long)j * ld + e;
+        TO* o = Out + (long long)j * ld + e;
         const double prev = accumulate ? (double)*o : 0.0;
-        *o = T(prev + alpha * acc[q][j]);
+        *o = TO(prev + alpha * acc[q][j]);
       }
     }
   }
@@ -348,10 +362,12 @@ int gram_splits(long long n, int M, int N) {
 
 hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, long long ld,
                        const double* w, long long n, double* partials, int nsplit, hipStream_t s,
-                       const void* X2, int M1) {
+                       const void* X2, int M1, int st2_) {
+  const Storage st2 = st2_ < 0 ? st : (Storage)st2_;
   if (!X2) {  // one segment
     M1 = M;
     X2 = X;
+    if (st2 != st) return hipErrorInvalidValue;
   }
   if (N <= 16) {
     const int wg = nsplit / 4;
@@ -359,20 +375,25 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
     kchunk = (kchunk + 63) / 64 * 64;
     // Y is the second segment of X: one row block with Y as tile 0
     const bool yseg = Y == X2 && N == M - M1 && M1 + 16 <= 128;
+    if (st2 != st && !(yseg && st == F32 && st2 == F64)) return hipErrorInvalidValue;
     const int mt = yseg ? 1 + (M1 + 15) / 16 : tall_mt(M);
     const dim3 grid(wg, yseg ? 1 : (M + 16 * mt - 1) / (16 * mt));
-#define KRY_TALL_(MT, YS)                                                                          \
-  if (st == F64)                                                                                  \
-    hipLaunchKernelGGL((k_gram_tall<double, MT, YS>), grid, dim3(256), 0, s, (const double*)X, M1,  \
-                       (const double*)X2, M, (const double*)Y, N, ld, w, n, kchunk, partials);      \
-  else                                                                                            \
-    hipLaunchKernelGGL((k_gram_tall<float, MT, YS>), grid, dim3(256), 0, s, (const float*)X, M1,    \
-                       (const float*)X2, M, (const float*)Y, N, ld, w, n, kchunk, partials);
-#define KRY_TALL(MT)          \
-  if (yseg) {                 \
-    KRY_TALL_(MT, true)       \
-  } else {                    \
-    KRY_TALL_(MT, false)      \
+#define KRY_TALL_(T, T2, MT, YS)                                                                  \
+  hipLaunchKernelGGL((k_gram_tall<T, T2, MT, YS>), grid, dim3(256), 0, s, (const T*)X, M1,         \
+                     (const T2*)X2, M, (const T2*)Y, N, ld, w, n, kchunk, partials);
+#define KRY_TALL(MT)                                   \
+  if (yseg) {                                          \
+    if (st == F64) {                                   \
+      KRY_TALL_(double, double, MT, true)              \
+    } else if (st2 == F64) {                           \
+      KRY_TALL_(float, double, MT, true)               \
+    } else {                                           \
+      KRY_TALL_(float, float, MT, true)                \
+    }                                                  \
+  } else if (st == F64) {                              \
+    KRY_TALL_(double, double, MT, false)               \
+  } else {                                             \
+    KRY_TALL_(float, float, MT, false)                 \
   }
     switch (mt) {
       case 1: KRY_TALL(1) break;
@@ -388,6 +409,7 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
 #undef KRY_TALL_
     return hipGetLastError();
   }
+  if (st2 != st) return hipErrorInvalidValue;
   long long kchunk = (n + nsplit - 1) / nsplit;
   kchunk = (kchunk + 15) / 16 * 16;
   const int nt = N >= 64 ? 4 : (N + 15) / 16;
@@ -411,24 +433,40 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
 
 hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int N, void* Out,
                           long long ld, long long n, double alpha, int accumulate, hipStream_t s,
-                          const void* X2, int M1) {
+                          const void* X2, int M1, int st2_, int sto_) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  const Storage st2 = st2_ < 0 ? st : (Storage)st2_;
+  const Storage sto = sto_ < 0 ? st : (Storage)sto_;
   if (!X2) {
     M1 = M;
     X2 = X;
+    if (st2 != st) return hipErrorInvalidValue;
   }
+  const bool mixed = st2 != st || sto != st;
   if (N <= 16 && M <= 256) {
     constexpr int EPT = 2;
     const dim3 grid((unsigned)((n + 256 * EPT - 1) / (256 * EPT)));
     const size_t lds = sizeof(double) * 16 * (size_t)M;
-    if (st == F64)
-      hipLaunchKernelGGL((k_gemm_cols<double, EPT>), grid, dim3(256), lds, s, (const double*)X, M1,
-                         (const double*)X2, M, C, N, (double*)Out, ld, n, alpha, accumulate);
-    else
-      hipLaunchKernelGGL((k_gemm_cols<float, EPT>), grid, dim3(256), lds, s, (const float*)X, M1,
-                         (const float*)X2, M, C, N, (float*)Out, ld, n, alpha, accumulate);
+#define KRY_GCOLS(T, T2, TO)                                                                       \
+  hipLaunchKernelGGL((k_gemm_cols<T, T2, TO, EPT>), grid, dim3(256), lds, s, (const T*)X, M1,       \
+                     (const T2*)X2, M, C, N, (TO*)Out, ld, n, alpha, accumulate);
+    if (st == F64 && st2 == F64 && sto == F64) {
+      KRY_GCOLS(double, double, double)
+    } else if (st == F32 && st2 == F32 && sto == F32) {
+      KRY_GCOLS(float, float, float)
+    } else if (st == F32 && st2 == F64 && sto == F64) {
+      KRY_GCOLS(float, double, double)
+    } else if (st == F32 && st2 == F64 && sto == F32) {
+      KRY_GCOLS(float, double, float)
+    } else if (st == F32 && st2 == F32 && sto == F64) {
+      KRY_GCOLS(float, float, double)
+    } else {
+      return hipErrorInvalidValue;
+    }
+#undef KRY_GCOLS
     return hipGetLastError();
   }
+  if (mixed) return hipErrorInvalidValue;
   const int nt = N >= 64 ? 4 : (N + 15) / 16;
   const dim3 grid((unsigned)((n + 63) / 64), (N + 16 * nt - 1) / (16 * nt));
 #define KRY_GEMM(NT)                                                                          \

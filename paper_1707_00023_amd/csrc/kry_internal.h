@@ -130,14 +130,18 @@ hipError_t launch_stencil_cols(Storage st, const void* v, void* w, long long ld,
 // With X2 != nullptr, X is two segments: columns k < M1 at X + k ld and
 // columns k >= M1 at X2 + (k - M1) ld.
 int gram_splits(long long n, int M, int N);
+// st2 (-1: st) is the element type of X2 and Y; a type other than st is
+// supported for st = F32, st2 = F64 with Y = X2 and N = M - M1 <= 16.
 hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, long long ld,
                        const double* w, long long n, double* partials, int nsplit, hipStream_t s,
-                       const void* X2 = nullptr, int M1 = 0);
+                       const void* X2 = nullptr, int M1 = 0, int st2 = -1);
 // Out[:, :N] = (accumulate ? Out : 0) + alpha X[:, :M] C (C row-major M x N);
 // X in one or two segments as for launch_gram.  Out must not overlap X.
+// st2, sto (-1: st): element types of X2 and Out; mixed types (st = F32
+// with F64 in X2 and/or Out) for N <= 16, M <= 256 only.
 hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int N, void* Out,
                           long long ld, long long n, double alpha, int accumulate, hipStream_t s,
-                          const void* X2 = nullptr, int M1 = 0);
+                          const void* X2 = nullptr, int M1 = 0, int st2 = -1, int sto = -1);
 // Energy weight of every entry (mu on H planes, eps on E planes).
 hipError_t launch_weights(const double* eps, const double* mu, double* w, long long N3,
                           hipStream_t s);

@@ -150,6 +150,28 @@ def test_arnoldi_relation_and_orthogonality(m, orth, s_step):
     assert abs(math.sqrt(r @ (w * r)) - est) <= 1e-10 * max(est, 1e-300) + 1e-13 * beta
 
 
+@pytest.mark.parametrize("m,s_step", [(32, 16), (30, 8)])
+def test_sstep_arnoldi_fp32_storage(m, s_step):
+    # FP32 storage: the Chebyshev block and both Gram-Schmidt passes are
+    # FP64, only the orthonormal result is rounded to FP32, so the relation
+    # and the orthogonality hold to FP32 rounding
+    _announce(f"s-step arnoldi fp32 storage m={m} s={s_step}")
+    wl = wk.small(12, seed=4, n_spheres=5)
+    inp = wk.generate(wl)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=m, storage="f32", s_step=s_step)
+    v = wk.random_state(wl.n, 9)
+    V, H, beta, steps = s.arnoldi(_t(v), m)
+    assert steps == m
+    V = V.cpu().numpy().astype(np.float64).T
+    w = op.material_weights(inp.eps, inp.mu)
+    G = V.T @ (w[:, None] * V)
+    assert np.abs(G - np.eye(m + 1)).max() <= 2e-6
+    AV = np.stack([op.apply_A(inp.eps, inp.mu, inp.sigma, V[:, j]) for j in range(m)], axis=1)
+    assert np.abs(AV - V @ H).max() <= 2e-6 * np.abs(AV).max()
+    Vo, Ho, bo = okr.krylov_basis(inp.eps, inp.mu, inp.sigma, v, 5)
+    assert np.abs(H[:6, :5] - Ho).max() <= 1e-5 * np.abs(Ho).max()
+
+
 def test_delayed_equals_classical_twice():
     _announce("arnoldi delayed vs cgs2")
     wl = wk.C1
