@@ -29,11 +29,13 @@ def hipcc():
 def _flags(src):
     f = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          "-I", os.path.join(ROOT, "include")]
+    # hipcc compiles .cpp sources as HIP too: give every source the target
+    # (host-only sources then carry an empty gfx950 device part); no
+    # packed-FP32 instructions in device code
+    f += ["-x", "hip", f"--offload-arch={ARCH}",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
     if src.endswith(".hip"):
-        # no packed-FP32 instructions in device code
-        f += ["-x", "hip", f"--offload-arch={ARCH}",
-              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-munsafe-fp-atomics"]
+        f += ["-munsafe-fp-atomics"]
     return f
 
 

@@ -54,6 +54,10 @@ struct kry_ctx {
   // s-step block size in use (opts.s_step, halved whenever a block's basis
   // is too ill-conditioned for the Hessenberg algebra)
   int s_eff = 0;
+  // Newton-basis shifts for the next s-step cycle: Ritz values of the last
+  // cycle's H in Leja order (alpha, q per step; none before the first cycle
+  // of a call, which uses the Chebyshev basis)
+  std::vector<double> sh_alpha, sh_q;
 
   void* Z = nullptr;  // 2 * zcap columns (Re, Im per solution column)
   int zcap = 0;
@@ -165,6 +169,8 @@ void tresolve(kry_ctx* c) {
 // lasts for one call, so results do not depend on earlier calls).
 void treset(kry_ctx* c) {
   c->s_eff = c->opts.s_step > 1 ? c->opts.s_step : 0;
+  c->sh_alpha.clear();
+  c->sh_q.clear();
   for (int k = 0; k < KRY_K_CLASSES; ++k)
     c->k_ms[k] = c->k_bytes[k] = c->k_flops[k] = 0.0, c->k_launch[k] = 0;
 }
@@ -459,10 +465,16 @@ double now_ms() {
 int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, int N, void* Out,
                double alpha, int accumulate, const void* X2, int M1, int st1, int st2, int sto);
 
+// A shift whose residual grows 1e4-fold above its best (the collinear
+// restart can do that to shifts far from the seed) is dropped and listed in
+// *diverged (its Z columns then hold garbage); the caller solves it again.
 int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> coef,
                const std::vector<int>& zcolk, double bnorm, double tol, kry_stats* st,
-               double* max_res, const std::vector<double>* zscale = nullptr) {
+               double* max_res, const std::vector<double>* zscale = nullptr,
+               std::vector<int>* diverged = nullptr) {
   const int nw = (int)omegas.size();
+  std::vector<double> best(nw);
+  for (int k = 0; k < nw; ++k) best[k] = std::abs(coef[k]) / bnorm;
   bool contiguous = 2 * nw > 16;
   for (int k = 1; k < nw && contiguous; ++k) contiguous = zcolk[k] == zcolk[0] + k;
   std::vector<double> Cz;
@@ -552,6 +564,13 @@ int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> 
       ++ncol;
       coef[k] = exact ? cplx(0.0) : -rho;  // new residual: coef_k * (V_{m+1} w), |V w|_M = 1
       const double res = std::abs(coef[k]) / bnorm;
+      if (diverged && nw > 1 && (!std::isfinite(res) || res > 1e4 * best[k])) {
+        active[k] = 0;
+        coef[k] = 0.0;
+        diverged->push_back(k);
+        continue;
+      }
+      best[k] = std::min(best[k], res);
       worst = std::max(worst, res);
       if (res <= tol) active[k] = 0;
     }
@@ -931,16 +950,57 @@ int stationary_group(kry_ctx* c, const double* b_col, const std::vector<double>&
   if (bnorm == 0.0) return KRY_OK;
   int status = KRY_OK;
   const double tol_part = tol_rel / ((nre2 > 0 && nim2 > 0) ? std::sqrt(2.0) : 1.0);
-  if (nre2 > 0.0) {  // slot 0 holds Re b
-    rc = multishift(c, omegas, std::vector<cplx>(nw, cplx(1.0, 0.0)), zcolk, bnorm, tol_part, st, max_res);
-    if (rc == KRY_ENOCONV) status = rc;
-    else if (rc) return rc;
+  // shifts in groups of neighbours: at most 16, spanning at most a tenth of
+  // their mean frequency (one restart direction has to serve every shift
+  // of a group, which a wide band of shifts defeats)
+  std::vector<int> order(nw);
+  for (int k = 0; k < nw; ++k) order[k] = k;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return omegas[a] < omegas[b]; });
+  std::vector<std::vector<int>> groups;
+  for (int k : order) {
+    if (!groups.empty()) {
+      auto& g = groups.back();
+      const double lo = omegas[g.front()], hi = omegas[k];
+      if ((int)g.size() < 16 && hi - lo <= 0.1 * std::max(0.5 * (lo + hi), 1e-300)) {
+        g.push_back(k);
+        continue;
+      }
+    }
+    groups.push_back({k});
   }
-  if (nim2 > 0.0) {
-    KRY_HIP(kry::launch_load_complex(c->st, b_col, 1, slot(c, 0), c->n, c->stream));
-    rc = multishift(c, omegas, std::vector<cplx>(nw, cplx(0.0, 1.0)), zcolk, bnorm, tol_part, st, max_res);
-    if (rc == KRY_ENOCONV) status = rc;
-    else if (rc) return rc;
+  std::vector<int> redo;
+  auto solve = [&](const std::vector<int>& idx, bool single) -> int {
+    std::vector<double> om;
+    std::vector<int> zc;
+    for (int k : idx) {
+      om.push_back(omegas[k]);
+      zc.push_back(zcolk[k]);
+    }
+    std::vector<int> div;
+    for (int part = 0; part < 2; ++part) {
+      if ((part == 0 ? nre2 : nim2) <= 0.0) continue;
+      KRY_HIP(kry::launch_load_complex(c->st, b_col, part, slot(c, 0), c->n, c->stream));
+      const cplx cf = part == 0 ? cplx(1.0, 0.0) : cplx(0.0, 1.0);
+      const int r = multishift(c, om, std::vector<cplx>(om.size(), cf), zc, bnorm, tol_part, st,
+                               max_res, nullptr, single ? nullptr : &div);
+      if (r == KRY_ENOCONV) status = r;
+      else if (r) return r;
+    }
+    for (int i : div)
+      if (std::find(redo.begin(), redo.end(), idx[i]) == redo.end()) redo.push_back(idx[i]);
+    return KRY_OK;
+  };
+  for (const auto& g : groups) {
+    rc = solve(g, false);
+    if (rc) return rc;
+  }
+  // shifts dropped by a group: again on their own, from zero
+  for (int k : redo) {
+    if (c->opts.verbose)
+      std::fprintf(stderr, "[kry] shift omega = %.6f solved again on its own\n", omegas[k]);
+    KRY_HIP(hipMemsetAsync(zcol(c, 2 * zcolk[k]), 0, 2 * c->ldv * c->esz, c->stream));
+    rc = solve(std::vector<int>{k}, true);
+    if (rc) return rc;
   }
   return status;
 }
@@ -1321,18 +1381,34 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
   // v_0 = start / b0 (d_red1[0] still holds |start|^2)
   KRY_HIP(kry::launch_fin_start(c->d_red1, c->d_scal + 2, st));
   KRY_HIP(kry::launch_scale(c->st, slot(c, 0), c->d_scal + 2, slot(c, 0), c->n, st));
-  // segment centre 0: the damping is confined to the absorbing layer, so
-  // most of a field's spectral weight sits at Re = 0, where the unshifted
-  // Chebyshev polynomials stay bounded (a centre in the damping range
-  // made the blocks of the 128^3 medium worse conditioned)
-  const double rho = c->rho, cc = 0.0;
+  // basis recurrence t_{k+1} = (A t_k - alpha_k t_k + q_k t_{k-1}) / sig_k:
+  // Newton steps on the Leja-ordered Ritz values of the previous cycle when
+  // there are s of them, else the Chebyshev basis on [-i rho, i rho]
+  // (centre 0: the damping is confined to the absorbing layer, so most of
+  // a field's spectral weight sits at Re = 0)
+  const double rho = c->rho;
+  const bool newton = (int)c->sh_alpha.size() >= s;
+  // block size of this cycle: the Chebyshev basis (before any Ritz values)
+  // is kept to blocks of at most 16, the Newton basis takes s
+  const int bs = newton ? s : std::min(s, 16);
+  std::vector<double> al(bs, 0.0), qq(bs, 0.0), sg(bs, 0.0);
+  for (int k = 0; k < bs; ++k) {
+    if (newton) {
+      al[k] = c->sh_alpha[k];
+      qq[k] = c->sh_q[k];
+      sg[k] = rho;
+    } else {  // t_1 = A t_0 / rho, t_{k+1} = 2 A t_k / rho + t_{k-1}
+      sg[k] = k == 0 ? rho : 0.5 * rho;
+      qq[k] = k == 0 ? 0.0 : 0.5 * rho;
+    }
+  }
   auto sb = [&](int i) { return (void*)((char*)c->SB + (size_t)i * c->ldv * sizeof(double)); };
   void* Tb = wide ? sb(s + 1) : slot(c, c->mcap + 1);
   const double mb_axpby = mbytes(c, true) - 8.0 * c->g.N3;
   const double vb64 = vbytes_of(c, f64);
   std::vector<double> C1, C2, G, P, R1, R2, Ri, ref, K;
-  for (int j0 = 0; j0 < m; j0 += s) {
-    const int ss = std::min(s, m - j0);
+  for (int j0 = 0; j0 < m; j0 += bs) {
+    const int ss = std::min(bs, m - j0);
     const int M = j0 + 1;
     // t_0 (FP64), then the Chebyshev block t_1..t_ss into S
     void* t0 = slot(c, j0);
@@ -1343,15 +1419,17 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
       S = sb(1);
     }
     auto tk = [&](int k) { return k == 0 ? t0 : (void*)((char*)S + (size_t)(k - 1) * c->ldv * 8); };
+    std::vector<double> Tm((size_t)(ss + 1) * ss, 0.0);  // A t_k = [t_0..t_ss] Tm[:, k]
     for (int k = 0; k < ss; ++k) {
+      const bool prev = k > 0 && qq[k] != 0.0;
       hipEvent_t e = tbeg(c);
-      if (k == 0)
-        KRY_HIP(kry::launch_stencil_axpby(kry::F64, tk(0), nullptr, tk(1), 1.0 / rho, -cc / rho, 0.0,
-                                          c->g, c->mats, st));
-      else
-        KRY_HIP(kry::launch_stencil_axpby(kry::F64, tk(k), tk(k - 1), tk(k + 1), 2.0 / rho,
-                                          -2.0 * cc / rho, 1.0, c->g, c->mats, st));
-      tend(c, e, KRY_K_STENCIL, vb64 * (k == 0 ? 2.0 : 3.0) + mb_axpby);
+      KRY_HIP(kry::launch_stencil_axpby(kry::F64, tk(k), prev ? tk(k - 1) : nullptr, tk(k + 1),
+                                        1.0 / sg[k], -al[k] / sg[k], prev ? qq[k] / sg[k] : 0.0,
+                                        c->g, c->mats, st));
+      tend(c, e, KRY_K_STENCIL, vb64 * (prev ? 3.0 : 2.0) + mb_axpby);
+      Tm[(size_t)(k + 1) * ss + k] = sg[k];
+      Tm[(size_t)k * ss + k] = al[k];
+      if (prev) Tm[(size_t)(k - 1) * ss + k] = -qq[k];
     }
     R1.resize((size_t)ss * ss);
     R2.resize((size_t)ss * ss);
@@ -1365,6 +1443,7 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
     G.resize((size_t)ss * ss);
     ref.resize(ss);
     kry::proj_gram(M, ss, P.data(), G.data(), ref.data());
+    const std::vector<double> nrm2 = ref;  // squared column norms of S
     bool ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-10, R1.data());
     if (ok) {
       kry::inv_upper(ss, R1.data(), Ri.data());
@@ -1396,13 +1475,13 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
       ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-8, R2.data());
     }
     bool illc = false;
-    if (ok) {  // condition estimate of R = R2 R1
+    if (ok) {  // condition estimate of R = R2 R1 with unit columns of S
       std::vector<double> R((size_t)ss * ss, 0.0), RI((size_t)ss * ss);
       for (int a = 0; a < ss; ++a)
         for (int k = a; k < ss; ++k) {
           double v = 0.0;
           for (int l = a; l <= k; ++l) v += R2[(size_t)a * ss + l] * R1[(size_t)l * ss + k];
-          R[(size_t)a * ss + k] = v;
+          R[(size_t)a * ss + k] = v / std::sqrt(std::max(nrm2[k], 1e-300));
         }
       kry::inv_upper(ss, R.data(), RI.data());
       double f1 = 0.0, f2 = 0.0;
@@ -1414,9 +1493,9 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
       // dependent or ill-conditioned block: redo the cycle with one step per
       // sweep; an ill-conditioned basis also halves s from here on
       if (illc) {
-        c->s_eff = s / 2 >= 2 ? s / 2 : 0;
+        c->s_eff = bs / 2 >= 2 ? bs / 2 : 0;
         if (c->opts.verbose)
-          std::fprintf(stderr, "[kry] s-step basis ill-conditioned at s = %d: s = %d from now on\n", s,
+          std::fprintf(stderr, "[kry] s-step basis ill-conditioned at s = %d: s = %d from now on\n", bs,
                        c->s_eff);
       }
       double b1 = 0.0;
@@ -1429,11 +1508,24 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
     rc = block_gemm(c, slot(c, 0), M + ss, stack_coef(M, ss, C2, Ri, K), ss, slot(c, j0 + 1), 1.0, 0, Tb,
                     M, -1, f64, -1);
     if (rc) return rc;
-    kry::sstep_hessenberg(j0, ss, rho, cc, C1.data(), C2.data(), R1.data(), R2.data(), H, ldh);
+    kry::sstep_hessenberg_tm(j0, ss, Tm.data(), C1.data(), C2.data(), R1.data(), R2.data(), H, ldh);
   }
   tresolve(c);
   *beta = b0;
   *m_eff = m;
+  // shifts for the later cycles of this call: Ritz values of the first
+  // cycle's H in Leja order (they only steer the basis' conditioning, so
+  // one estimate of the spectrum serves the whole call)
+  if (!newton) {
+    std::vector<double> re(m), im(m);
+    c->sh_alpha.assign(s, 0.0);
+    c->sh_q.assign(s, 0.0);
+    if (!kry::hess_eigvals(m, H, ldh, re.data(), im.data()) ||
+        kry::leja_steps(m, re.data(), im.data(), s, rho, c->sh_alpha.data(), c->sh_q.data()) < s) {
+      c->sh_alpha.clear();
+      c->sh_q.clear();
+    }
+  }
   return KRY_OK;
 }
 

@@ -104,49 +104,51 @@ __global__ __launch_bounds__(256) void k_gram_tn(const T* __restrict__ X, int M1
   }
 }
 
-// Tall-skinny Gram product for N <= 16: partials[4 bx + wave][M x N] =
-// X[:, rows]^T diag(w) Y over the elements the wave visits.  Workgroup bx
-// owns [bx kchunk, (bx + 1) kchunk); its four waves take interleaved
-// 16-element slices of it, and each wave accumulates all MT 16-row tiles of
-// its row block (rows r0 .. r0 + 16 MT - 1, r0 = 16 MT blockIdx.y) against
-// the single 16-column tile of Y, so every X, Y and w entry is loaded once
-// (no tile of Y is re-read per row tile).  Lane (i, kk) reads entries
-// e0 + 4 kk .. e0 + 4 kk + 3 of column i of each tile with 32-byte loads;
-// the t-th of four MFMAs takes entry e0 + 4 kk + t as its k = kk slot.
-// Out-of-range rows, columns and entries add zeros.  X in two segments as
-// in k_gram_tn.  grid (nsplit / 4, ceil(M / (16 MT))).
-// YSEG: Y is the second segment of X itself (Y = X2, N = M - M1 <= 16, one
-// row block).  Row tile 0 then holds Y and tiles 1.. the first segment, so
-// the Y operand is the tile-0 data already in registers (Y is read once,
+// Tall-skinny Gram product for N <= 16 NT (NT = 1, 2): partials[4 bx +
+// wave][M x N] = X[:, rows]^T diag(w) Y over the elements the wave visits.
+// Workgroup bx owns [bx kchunk, (bx + 1) kchunk); its four waves take
+// interleaved 16-element slices of it, and each wave accumulates all MT
+// 16-row tiles of its row block (r0 = 16 MT blockIdx.y) against the NT
+// 16-column tiles of Y, so every X, Y and w entry is loaded once.  Lane
+// (i, kk) reads entries e0 + 4 kk .. e0 + 4 kk + 3 of column i of each tile
+// with 32-byte loads; the u-th of four MFMAs per tile pair takes entry
+// e0 + 4 kk + u as its k = kk slot.  Out-of-range rows, columns and entries
+// add zeros.  X in two segments as in k_gram_tn.  grid (nsplit / 4,
+// ceil(M / (16 MT))).
+// YSEG: Y is the second segment of X itself (Y = X2, N = M - M1, one row
+// block).  Row tiles 0..NT-1 then hold Y and the later tiles the first
+// segment, so the Y operand is data already in registers (Y is read once,
 // not twice); output rows are mapped back to the [X; X2] order.
 // T2: element type of the second segment (and of Y); a second segment of
 // another type than the first is supported in the YSEG layout only.
-template <typename T, typename T2, int MT, bool YSEG>
+template <typename T, typename T2, int MT, int NT, bool YSEG>
 __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int M1,
                                                    const T2* __restrict__ X2, int M,
                                                    const T2* __restrict__ Y, int N, long long ld,
                                                    const double* __restrict__ w, long long n,
                                                    long long kchunk, double* __restrict__ partials) {
+  static_assert(!YSEG || MT > NT, "YSEG keeps Y in the first NT row tiles");
+  static_assert(YSEG || sizeof(T) == sizeof(T2), "mixed element types need the YSEG layout");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, kk = lane >> 4;
   const int r0 = blockIdx.y * 16 * MT;
   const long long e_begin = (long long)blockIdx.x * kchunk;
   const long long e_end = min(n, e_begin + kchunk);
-  static_assert(YSEG || sizeof(T) == sizeof(T2), "mixed element types need the YSEG layout");
+  constexpr int YT = YSEG ? NT : 0;  // row tiles holding the second segment
   bool arow[MT];
   const T* xc[MT];
-  const T2* x2c = X2;  // YSEG: tile 0 (the second segment)
+  const T2* x2c[NT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
     const int r = r0 + 16 * t + i;
-    if (YSEG) {  // virtual rows: [0, 16) second segment, [16, 16 + M1) first
-      if (t == 0) {
-        arow[t] = i < N;
-        x2c = X2 + (long long)(arow[t] ? i : 0) * ld;
-        xc[t] = X;
+    xc[t] = X;
+    if (YSEG) {  // virtual rows: [0, 16 NT) second segment, then the first
+      if (t < YT) {
+        arow[t] = r < N;
+        x2c[t] = X2 + (long long)(arow[t] ? r : 0) * ld;
       } else {
-        arow[t] = r - 16 < M1;
-        xc[t] = X + (long long)(arow[t] ? r - 16 : 0) * ld;
+        arow[t] = r - 16 * YT < M1;
+        xc[t] = X + (long long)(arow[t] ? r - 16 * YT : 0) * ld;
       }
     } else {
       arow[t] = r < M;
@@ -155,46 +157,63 @@ __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int 
                       : reinterpret_cast<const T*>(X2) + (long long)(rr - M1) * ld;
     }
   }
-  const bool bcol = i < N;
-  const T2* yc = Y + (long long)(bcol ? i : 0) * ld;
-  v4d acc[MT];
+  bool bcol[NT];
+  const T2* yc[NT];
 #pragma unroll
-  for (int t = 0; t < MT; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < NT; ++q) {
+    bcol[q] = 16 * q + i < N;
+    yc[q] = Y + (long long)(bcol[q] ? 16 * q + i : 0) * ld;
+  }
+  v4d acc[MT][NT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int q = 0; q < NT; ++q) acc[t][q] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
   for (long long e0 = e_begin + 16 * wave; e0 < e_end; e0 += 64) {
     const long long eb = e0 + 4 * kk;
-    double xa[MT][4], ww[4], yb[4];
+    double xa[MT][4], ww[4], yb[NT][4];
     load4(w, eb, e_end, ww);
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
       if (!arow[t]) xa[t][0] = xa[t][1] = xa[t][2] = xa[t][3] = 0.0;
-      else if (YSEG && t == 0) load4(x2c, eb, e_end, xa[t]);
+      else if (YSEG && t < YT) load4(x2c[t < YT ? t : 0], eb, e_end, xa[t]);
       else load4(xc[t], eb, e_end, xa[t]);
     }
-    if (YSEG) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) yb[u] = xa[0][u];
-    } else if (bcol) {
-      load4(yc, eb, e_end, yb);
-    } else {
-      yb[0] = yb[1] = yb[2] = yb[3] = 0.0;
+    for (int q = 0; q < NT; ++q) {
+      if (YSEG) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) yb[q][u] = xa[q][u];
+      } else if (bcol[q]) {
+        load4(yc[q], eb, e_end, yb[q]);
+      } else {
+        yb[q][0] = yb[q][1] = yb[q][2] = yb[q][3] = 0.0;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double b = ww[u] * yb[u];
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int t = 0; t < MT; ++t) acc[t] = mfma16(xa[t][u], b, acc[t]);
-    }
+      for (int q = 0; q < NT; ++q) {
+        const double b = ww[u] * yb[q][u];
+#pragma unroll
+        for (int t = 0; t < MT; ++t) acc[t][q] = mfma16(xa[t][u], b, acc[t][q]);
+      }
   }
   double* out = partials + ((long long)blockIdx.x * 4 + wave) * M * N;
-  const int col = i;
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int vr = r0 + 16 * t + 4 * r + kk;
-      int row = vr;
-      if (YSEG) row = vr < 16 ? (vr < N ? M1 + vr : M) : (vr - 16 < M1 ? vr - 16 : M);
-      if (row < M && col < N) out[(long long)row * N + col] = acc[t][r];
+    for (int q = 0; q < NT; ++q) {
+      const int col = 16 * q + i;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int vr = r0 + 16 * t + 4 * r + kk;
+        int row = vr;
+        if (YSEG)
+          row = vr < 16 * YT ? (vr < N ? M1 + vr : M) : (vr - 16 * YT < M1 ? vr - 16 * YT : M);
+        if (row < M && col < N) out[(long long)row * N + col] = acc[t][q][r];
+      }
     }
   }
 }
@@ -264,27 +283,29 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ X, int M1
 // 2 N M flops per entry, far below the FP64 vector rate at the bandwidth
 // this kernel moves, so the matrix cores gain nothing here.  X in two
 // segments as in k_gram_tn.  Out may not overlap X.
-// T2: element type of the second segment; TO: of Out.
-template <typename T, typename T2, typename TO, int EPT>
+// T2: element type of the second segment; TO: of Out.  NO (16 or 32): the
+// largest N, the width of the coefficient rows in LDS and of a thread's
+// accumulators.
+template <typename T, typename T2, typename TO, int EPT, int NO>
 __global__ __launch_bounds__(256) void k_gemm_cols(const T* __restrict__ X, int M1,
                                                    const T2* __restrict__ X2, int M,
                                                    const double* __restrict__ C, int N,
                                                    TO* __restrict__ Out, long long ld, long long n,
                                                    double alpha, int accumulate) {
-  extern __shared__ double sC[];  // M x 16
-  for (int t = threadIdx.x; t < M * 16; t += 256) {
-    const int k = t >> 4, j = t & 15;
+  extern __shared__ double sC[];  // M x NO
+  for (int t = threadIdx.x; t < M * NO; t += 256) {
+    const int k = t / NO, j = t % NO;
     sC[t] = j < N ? C[(long long)k * N + j] : 0.0;
   }
   __syncthreads();
   const long long base = (long long)blockIdx.x * 256 * EPT + threadIdx.x;
-  double acc[EPT][16];
+  double acc[EPT][NO];
   bool ok[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     ok[q] = base + 256LL * q < n;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[q][j] = 0.0;
+    for (int j = 0; j < NO; ++j) acc[q][j] = 0.0;
   }
 #pragma unroll 2
   for (int k = 0; k < M; ++k) {
@@ -298,9 +319,9 @@ __global__ __launch_bounds__(256) void k_gemm_cols(const T* __restrict__ X, int 
 #pragma unroll
       for (int q = 0; q < EPT; ++q) x[q] = ok[q] ? (double)xk[base + 256LL * q] : 0.0;
     }
-    const double2* row = reinterpret_cast<const double2*>(sC + 16 * k);
+    const double2* row = reinterpret_cast<const double2*>(sC + NO * k);
 #pragma unroll
-    for (int j2 = 0; j2 < 8; ++j2) {
+    for (int j2 = 0; j2 < NO / 2; ++j2) {
       const double2 cc = row[j2];
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
@@ -314,7 +335,7 @@ __global__ __launch_bounds__(256) void k_gemm_cols(const T* __restrict__ X, int 
     if (!ok[q]) continue;
     const long long e = base + 256LL * q;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < NO; ++j) {
       if (j < N) {
         TO* o = Out + (long long)j * ld + e;
         const double prev = accumulate ? (double)*o : 0.0;
@@ -344,7 +365,7 @@ static int tall_mt(int M) {
 
 int gram_splits(long long n, int M, int N) {
   const long long maxs = (n + 255) / 256;
-  if (N <= 16) {
+  if (N <= 32) {
     // k_gram_tall: four partials per workgroup, about 1024 workgroups
     const int mt = tall_mt(M);
     const int rowblk = (M + 16 * mt - 1) / (16 * mt);
@@ -369,31 +390,42 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
     X2 = X;
     if (st2 != st) return hipErrorInvalidValue;
   }
-  if (N <= 16) {
+  if (N <= 32) {
     const int wg = nsplit / 4;
     long long kchunk = (n + wg - 1) / wg;
     kchunk = (kchunk + 63) / 64 * 64;
-    // Y is the second segment of X: one row block with Y as tile 0
-    const bool yseg = Y == X2 && N == M - M1 && M1 + 16 <= 128;
+    const int nt = (N + 15) / 16;
+    // Y is the second segment of X: one row block with Y in the first nt
+    // row tiles
+    const bool yseg = Y == X2 && N == M - M1 && M1 + 16 * nt <= 128;
     if (st2 != st && !(yseg && st == F32 && st2 == F64)) return hipErrorInvalidValue;
-    const int mt = yseg ? 1 + (M1 + 15) / 16 : tall_mt(M);
+    const int mt = yseg ? nt + (M1 + 15) / 16 : tall_mt(M);
+    if (yseg && mt > 8) return hipErrorInvalidValue;
     const dim3 grid(wg, yseg ? 1 : (M + 16 * mt - 1) / (16 * mt));
-#define KRY_TALL_(T, T2, MT, YS)                                                                  \
-  hipLaunchKernelGGL((k_gram_tall<T, T2, MT, YS>), grid, dim3(256), 0, s, (const T*)X, M1,         \
+#define KRY_TALL_(T, T2, MT, NT, YS)                                                              \
+  hipLaunchKernelGGL((k_gram_tall<T, T2, MT, NT, YS>), grid, dim3(256), 0, s, (const T*)X, M1,     \
                      (const T2*)X2, M, (const T2*)Y, N, ld, w, n, kchunk, partials);
-#define KRY_TALL(MT)                                   \
-  if (yseg) {                                          \
-    if (st == F64) {                                   \
-      KRY_TALL_(double, double, MT, true)              \
-    } else if (st2 == F64) {                           \
-      KRY_TALL_(float, double, MT, true)               \
-    } else {                                           \
-      KRY_TALL_(float, float, MT, true)                \
-    }                                                  \
-  } else if (st == F64) {                              \
-    KRY_TALL_(double, double, MT, false)               \
-  } else {                                             \
-    KRY_TALL_(float, float, MT, false)                 \
+#define KRY_TALL_NT(MT, NT)                             \
+  if (yseg) {                                           \
+    if constexpr (MT > NT) {                            \
+      if (st == F64) {                                  \
+        KRY_TALL_(double, double, MT, NT, true)         \
+      } else if (st2 == F64) {                          \
+        KRY_TALL_(float, double, MT, NT, true)          \
+      } else {                                          \
+        KRY_TALL_(float, float, MT, NT, true)           \
+      }                                                 \
+    }                                                   \
+  } else if (st == F64) {                               \
+    KRY_TALL_(double, double, MT, NT, false)            \
+  } else {                                              \
+    KRY_TALL_(float, float, MT, NT, false)              \
+  }
+#define KRY_TALL(MT)                \
+  if (nt == 1) {                    \
+    KRY_TALL_NT(MT, 1)              \
+  } else {                          \
+    KRY_TALL_NT(MT, 2)              \
   }
     switch (mt) {
       case 1: KRY_TALL(1) break;
@@ -406,6 +438,7 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
       default: KRY_TALL(8) break;
     }
 #undef KRY_TALL
+#undef KRY_TALL_NT
 #undef KRY_TALL_
     return hipGetLastError();
   }
@@ -443,13 +476,22 @@ hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int
     if (st2 != st) return hipErrorInvalidValue;
   }
   const bool mixed = st2 != st || sto != st;
-  if (N <= 16 && M <= 256) {
-    constexpr int EPT = 2;
-    const dim3 grid((unsigned)((n + 256 * EPT - 1) / (256 * EPT)));
-    const size_t lds = sizeof(double) * 16 * (size_t)M;
-#define KRY_GCOLS(T, T2, TO)                                                                       \
-  hipLaunchKernelGGL((k_gemm_cols<T, T2, TO, EPT>), grid, dim3(256), lds, s, (const T*)X, M1,       \
+  if ((N <= 16 && M <= 256) || (N <= 32 && M <= 128)) {
+    // N <= 16: two entries per thread, 16 accumulators each; N <= 32: one
+    // entry per thread, 32 accumulators
+    const bool wide = N > 16;
+    const int ept = wide ? 1 : 2;
+    const dim3 grid((unsigned)((n + 256 * ept - 1) / (256 * ept)));
+    const size_t lds = sizeof(double) * (wide ? 32 : 16) * (size_t)M;
+#define KRY_GCOLS_(T, T2, TO, EPT, NO)                                                             \
+  hipLaunchKernelGGL((k_gemm_cols<T, T2, TO, EPT, NO>), grid, dim3(256), lds, s, (const T*)X, M1,   \
                      (const T2*)X2, M, C, N, (TO*)Out, ld, n, alpha, accumulate);
+#define KRY_GCOLS(T, T2, TO)         \
+  if (wide) {                        \
+    KRY_GCOLS_(T, T2, TO, 1, 32)     \
+  } else {                           \
+    KRY_GCOLS_(T, T2, TO, 2, 16)     \
+  }
     if (st == F64 && st2 == F64 && sto == F64) {
       KRY_GCOLS(double, double, double)
     } else if (st == F32 && st2 == F32 && sto == F32) {
@@ -464,6 +506,7 @@ hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int
       return hipErrorInvalidValue;
     }
 #undef KRY_GCOLS
+#undef KRY_GCOLS_
     return hipGetLastError();
   }
   if (mixed) return hipErrorInvalidValue;

@@ -99,6 +99,29 @@ void inv_upper(int p, const double* R, double* X);
 void sstep_hessenberg(int j0, int s, double rho, double c, const double* C1, const double* C2,
                       const double* R1, const double* R2, double* H, int ldh);
 
+// The same for a general basis-change matrix: A [t_0..t_{s-1}] =
+// [t_0..t_s] Tm with Tm ((s+1) x s, row-major) upper Hessenberg with a
+// nonzero subdiagonal (Chebyshev, Newton, ... recurrences).
+void sstep_hessenberg_tm(int j0, int s, const double* Tm, const double* C1, const double* C2,
+                         const double* R1, const double* R2, double* H, int ldh);
+
+// Eigenvalues (re[k], im[k], k < m) of an m x m upper-Hessenberg matrix H
+// (column-major, leading dimension ldh; entries below the subdiagonal are
+// ignored) by the implicitly shifted double-shift QR iteration (Francis).
+// Returns false if an eigenvalue does not converge in 60 m sweeps.
+bool hess_eigvals(int m, const double* H, int ldh, double* re, double* im);
+
+// Newton-basis steps from shifts theta_k (Ritz values): picks at most s
+// shifts in Leja order (each new shift maximises the product of its
+// distances to the ones already taken; a complex shift is taken with its
+// conjugate right after it) and writes, per step k < s, the recurrence
+// t_{k+1} = (A t_k - alpha_k t_k + q_k t_{k-1}) / scale as alpha[k] and
+// q[k] (q_k = beta^2 / scale on the second step of a conjugate pair
+// alpha +- i beta, else 0).  A pair that would be cut by the block end is
+// replaced by its real part.  Returns the number of shifts used (s).
+int leja_steps(int nr, const double* re, const double* im, int s, double scale, double* alpha,
+               double* q);
+
 // Projected Gram matrix of an s-column block S against an M-orthonormal
 // basis V from one product P = [V, S]^T M S ((M + s) x s, row-major):
 // G = S^T M S - C^T C with C = P[:M] (s x s, row-major) and ref[k] =

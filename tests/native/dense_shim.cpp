@@ -69,6 +69,20 @@ void t_stack_coef_full(int M, int s, const double* C, const double* F, double* K
   kry::stack_coef_full(M, s, C, F, K);
 }
 
+void t_sstep_hessenberg_tm(int j0, int s, const double* Tm, const double* C1, const double* C2,
+                           const double* R1, const double* R2, double* H, int ldh) {
+  kry::sstep_hessenberg_tm(j0, s, Tm, C1, C2, R1, R2, H, ldh);
+}
+
+int t_hess_eigvals(int m, const double* H, int ldh, double* re, double* im) {
+  return kry::hess_eigvals(m, H, ldh, re, im) ? 1 : 0;
+}
+
+int t_leja_steps(int nr, const double* re, const double* im, int s, double scale, double* alpha,
+                 double* q) {
+  return kry::leja_steps(nr, re, im, s, scale, alpha, q);
+}
+
 double t_choose_step_block(int K, int q, int g, const double* H, int ldh, const double* U0,
                            double tau_try, const double* rate, int Ks, double* U, double* err) {
   return kry::choose_step_block(K, q, g, H, ldh, U0, tau_try, rate, Ks, U, err);

@@ -359,3 +359,104 @@ def test_stack_coef_products(lib):
     assert np.abs(np.hstack([V, S]) @ K - (S - V @ C) @ Fu).max() <= 1e-12
     lib.t_stack_coef_full(M, s, P(C), P(Fg), P(K))
     assert np.abs(np.hstack([V, S]) @ K - (S - V @ C) @ Fg).max() <= 1e-12
+
+
+@pytest.mark.parametrize("m,seed", [(1, 0), (2, 1), (5, 2), (30, 3), (64, 4)])
+def test_hess_eigvals_matches_numpy(lib, m, seed):
+    rng = np.random.default_rng(seed)
+    H = np.triu(rng.standard_normal((m, m)), -1)
+    Hf = np.asfortranarray(H)
+    re, im = np.zeros(m), np.zeros(m)
+    assert lib.t_hess_eigvals(m, P(Hf), m, P(re), P(im)) == 1
+    got = np.sort_complex(re + 1j * im)
+    ref = np.sort_complex(np.linalg.eigvals(H))
+    assert np.abs(got - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
+
+
+def test_hess_eigvals_of_arnoldi_matrix(lib):
+    # Ritz values of a dissipative operator's Arnoldi matrix: conjugate pairs
+    # and Re >= 0 (the energy-product field of values)
+    rng = np.random.default_rng(9)
+    A, w = _dissipative(rng, 300)
+    V, H = _arnoldi_mgs2(A, w, rng.standard_normal(300), 40)
+    Hm = np.asfortranarray(H[:40])
+    re, im = np.zeros(40), np.zeros(40)
+    assert lib.t_hess_eigvals(40, P(Hm), 40, P(re), P(im)) == 1
+    got = np.sort_complex(re + 1j * im)
+    ref = np.sort_complex(np.linalg.eigvals(H[:40]))
+    assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
+    assert re.min() >= -1e-10
+
+
+def test_leja_steps_pairs_and_cut(lib):
+    re = np.array([0.1, 0.1, 0.3, 0.05, 0.05, 0.2])
+    im = np.array([2.0, -2.0, 0.0, -1.0, 1.0, 0.0])
+    for s in (1, 2, 3, 4, 6):
+        al, q = np.zeros(s), np.zeros(s)
+        k = lib.t_leja_steps(6, P(re), P(im), s, ctypes.c_double(3.0), P(al), P(q))
+        assert k == s
+        # second step of a pair carries beta^2 / scale, first steps none
+        for i in range(k):
+            if q[i] != 0.0:
+                assert i > 0 and q[i - 1] == 0.0 and al[i] == al[i - 1]
+                assert q[i] in (4.0 / 3.0, 1.0 / 3.0)
+    # the first shift is the largest in modulus (the pair at +-2i)
+    al, q = np.zeros(2), np.zeros(2)
+    lib.t_leja_steps(6, P(re), P(im), 2, ctypes.c_double(3.0), P(al), P(q))
+    assert al[0] == 0.1 and q[1] == pytest.approx(4.0 / 3.0)
+    # a pair cut by the block end is replaced by its real part
+    al, q = np.zeros(1), np.zeros(1)
+    lib.t_leja_steps(6, P(re), P(im), 1, ctypes.c_double(3.0), P(al), P(q))
+    assert al[0] == 0.1 and q[0] == 0.0
+
+
+def _arnoldi_sstep_newton(lib, A, w, v0, m, s, alpha, q, scale):
+    """s-step cycle with a Newton basis t_{k+1} = (A t_k - alpha_k t_k +
+    q_k t_{k-1}) / scale and the library's host algebra (Pythagorean
+    passes, general basis-change matrix)."""
+    n = v0.size
+    V = np.zeros((n, m + 1))
+    H = np.zeros((m + 1, m), order="F")
+    V[:, 0] = v0 / np.sqrt(v0 @ (w * v0))
+    j0 = 0
+    while j0 < m:
+        ss = min(s, m - j0)
+        M = j0 + 1
+        T = np.zeros((n, ss + 1))
+        T[:, 0] = V[:, j0]
+        Tm = np.zeros((ss + 1, ss))
+        for k in range(ss):
+            prev = T[:, k - 1] if k > 0 else 0.0
+            qk = q[k] if k > 0 else 0.0
+            T[:, k + 1] = (A @ T[:, k] - alpha[k] * T[:, k] + qk * prev) / scale
+            Tm[k + 1, k] = scale
+            Tm[k, k] = alpha[k]
+            if k > 0:
+                Tm[k - 1, k] = -qk
+        Tb, C1, R1 = _pass_pip(lib, V[:, :M], w, T[:, 1:].copy(), 1e-10, True)
+        Q, C2, R2 = _pass_pip(lib, V[:, :M], w, Tb, 1e-8, False)
+        V[:, M:M + ss] = Q
+        lib.t_sstep_hessenberg_tm(j0, ss, P(np.ascontiguousarray(Tm)), P(C1), P(C2), P(R1), P(R2),
+                                  P(H), m + 1)
+        j0 += ss
+    return V, H
+
+
+@pytest.mark.parametrize("m,s", [(24, 8), (30, 16), (24, 24)])
+def test_sstep_newton_basis_host_algebra(lib, m, s):
+    rng = np.random.default_rng(70 + m + s)
+    n = 300
+    A, w = _dissipative(rng, n)
+    v0 = rng.standard_normal(n)
+    # shifts: Ritz values of a first cycle, in Leja order
+    _, H1 = _arnoldi_mgs2(A, w, rng.standard_normal(n), s)
+    re, im = np.zeros(s), np.zeros(s)
+    assert lib.t_hess_eigvals(s, P(np.asfortranarray(H1[:s])), s, P(re), P(im)) == 1
+    scale = float(np.abs(np.linalg.eigvals(A)).max())
+    al, q = np.zeros(s), np.zeros(s)
+    assert lib.t_leja_steps(s, P(re), P(im), s, ctypes.c_double(scale), P(al), P(q)) == s
+    V, H = _arnoldi_sstep_newton(lib, A, w, v0, m, s, al, q, scale)
+    assert np.abs(A @ V[:, :m] - V @ H).max() <= 1e-12 * np.abs(A).max()
+    assert np.abs(V.T @ (w[:, None] * V) - np.eye(m + 1)).max() <= 1e-12
+    Vr, Hr = _arnoldi_mgs2(A, w, v0, m)
+    assert np.abs(H - Hr).max() <= 1e-9 * np.abs(Hr).max()
