@@ -1348,6 +1348,11 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
   // triangular factor: rounding of the stored block reaches Hbar amplified
   // by it, and the block is always FP64 (1e-16 * 1e6)
   const double cond_max = 1e6;
+  // one pass (the Gram matrix of the projected block by Pythagoras) leaves
+  // a loss of orthogonality of order u * cond(R1)^2; the second pass is
+  // skipped when the column-scaled estimate of cond(R1) puts that below
+  // 1e-11 (u = 1.1e-16)
+  const double one_pass_max = 300.0;
   const int ldh = m + 1;
   hipStream_t st = c->stream;
   int rc = ensure_weights(c);
@@ -1403,13 +1408,16 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
     }
   }
   auto sb = [&](int i) { return (void*)((char*)c->SB + (size_t)i * c->ldv * sizeof(double)); };
-  void* Tb = wide ? sb(s + 1) : slot(c, c->mcap + 1);
+  void* Tb0 = wide ? sb(s + 1) : slot(c, c->mcap + 1);
   const double mb_axpby = mbytes(c, true) - 8.0 * c->g.N3;
   const double vb64 = vbytes_of(c, f64);
   std::vector<double> C1, C2, G, P, R1, R2, Ri, ref, K;
   for (int j0 = 0; j0 < m; j0 += bs) {
     const int ss = std::min(bs, m - j0);
     const int M = j0 + 1;
+    // the update kernel for these shapes reads all its entries of every
+    // input row before writing them, so FP64 storage can update S in place
+    const bool inplace = !wide && ((ss <= 16 && M + ss <= 256) || (ss <= 32 && M + ss <= 128));
     // t_0 (FP64), then the Chebyshev block t_1..t_ss into S
     void* t0 = slot(c, j0);
     void* S = slot(c, j0 + 1);
@@ -1444,11 +1452,26 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
     ref.resize(ss);
     kry::proj_gram(M, ss, P.data(), G.data(), ref.data());
     const std::vector<double> nrm2 = ref;  // squared column norms of S
+    // column-scaled condition estimate |R|_F |R^-1|_F of an upper factor
+    auto cond_est = [&](const std::vector<double>& R) {
+      std::vector<double> Rs((size_t)ss * ss, 0.0), RI((size_t)ss * ss);
+      for (int a = 0; a < ss; ++a)
+        for (int k = a; k < ss; ++k)
+          Rs[(size_t)a * ss + k] = R[(size_t)a * ss + k] / std::sqrt(std::max(nrm2[k], 1e-300));
+      kry::inv_upper(ss, Rs.data(), RI.data());
+      double f1 = 0.0, f2 = 0.0;
+      for (size_t i = 0; i < Rs.size(); ++i) f1 += Rs[i] * Rs[i], f2 += RI[i] * RI[i];
+      return std::sqrt(f1 * f2);
+    };
     bool ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-10, R1.data());
+    // a well-conditioned block is final after one pass: written straight
+    // into the basis slots in the storage type
+    const bool one = ok && (inplace || wide) && cond_est(R1) <= one_pass_max;
+    void* Tb = inplace ? S : Tb0;
     if (ok) {
       kry::inv_upper(ss, R1.data(), Ri.data());
-      rc = block_gemm(c, slot(c, 0), M + ss, stack_coef(M, ss, C1, Ri, K), ss, Tb, 1.0, 0, S, M, -1,
-                      f64, f64);
+      rc = block_gemm(c, slot(c, 0), M + ss, stack_coef(M, ss, C1, Ri, K), ss,
+                      one ? slot(c, j0 + 1) : Tb, 1.0, 0, S, M, -1, f64, one ? -1 : f64);
       if (rc) return rc;
     } else {
       // cancellation in the projected Gram matrix: project explicitly
@@ -1463,7 +1486,11 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
         if (rc) return rc;
       }
     }
-    if (ok) {
+    if (ok && one) {
+      C2.assign((size_t)M * ss, 0.0);
+      std::fill(R2.begin(), R2.end(), 0.0);
+      for (int a = 0; a < ss; ++a) R2[(size_t)a * ss + a] = 1.0;
+    } else if (ok) {
       // pass 2, the same on Tb
       rc = block_gram_host(c, slot(c, 0), M + ss, Tb, ss, P, Tb, M, -1, f64);
       if (rc) return rc;
@@ -1475,19 +1502,15 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
       ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-8, R2.data());
     }
     bool illc = false;
-    if (ok) {  // condition estimate of R = R2 R1 with unit columns of S
-      std::vector<double> R((size_t)ss * ss, 0.0), RI((size_t)ss * ss);
+    if (ok && !one) {  // condition estimate of R = R2 R1 with unit columns of S
+      std::vector<double> R((size_t)ss * ss, 0.0);
       for (int a = 0; a < ss; ++a)
         for (int k = a; k < ss; ++k) {
           double v = 0.0;
           for (int l = a; l <= k; ++l) v += R2[(size_t)a * ss + l] * R1[(size_t)l * ss + k];
-          R[(size_t)a * ss + k] = v / std::sqrt(std::max(nrm2[k], 1e-300));
+          R[(size_t)a * ss + k] = v;
         }
-      kry::inv_upper(ss, R.data(), RI.data());
-      double f1 = 0.0, f2 = 0.0;
-      for (size_t i = 0; i < R.size(); ++i) f1 += R[i] * R[i], f2 += RI[i] * RI[i];
-      const double est = std::sqrt(f1 * f2);
-      illc = !(est <= cond_max);
+      illc = !(cond_est(R) <= cond_max);
     }
     if (!ok || illc) {
       // dependent or ill-conditioned block: redo the cycle with one step per
@@ -1504,10 +1527,12 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
       return rc;
     }
     // Q = (Tb - V C2) R2^{-1} into the basis slots j0+1..j0+ss (storage type)
-    kry::inv_upper(ss, R2.data(), Ri.data());
-    rc = block_gemm(c, slot(c, 0), M + ss, stack_coef(M, ss, C2, Ri, K), ss, slot(c, j0 + 1), 1.0, 0, Tb,
-                    M, -1, f64, -1);
-    if (rc) return rc;
+    if (!one) {
+      kry::inv_upper(ss, R2.data(), Ri.data());
+      rc = block_gemm(c, slot(c, 0), M + ss, stack_coef(M, ss, C2, Ri, K), ss, slot(c, j0 + 1), 1.0, 0,
+                      Tb, M, -1, f64, -1);
+      if (rc) return rc;
+    }
     kry::sstep_hessenberg_tm(j0, ss, Tm.data(), C1.data(), C2.data(), R1.data(), R2.data(), H, ldh);
   }
   tresolve(c);

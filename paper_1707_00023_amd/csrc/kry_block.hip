@@ -282,15 +282,17 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T* __restrict__ X, int M1
 // coefficients sit in LDS and are read as broadcasts.  The dense part is
 // 2 N M flops per entry, far below the FP64 vector rate at the bandwidth
 // this kernel moves, so the matrix cores gain nothing here.  X in two
-// segments as in k_gram_tn.  Out may not overlap X.
+// segments as in k_gram_tn.  A thread reads its entries of every input row
+// before it writes any output, and no other thread touches those entries,
+// so Out may be rows of X or X2 themselves (an in-place update; no
+// __restrict__ on them for that reason).
 // T2: element type of the second segment; TO: of Out.  NO (16 or 32): the
 // largest N, the width of the coefficient rows in LDS and of a thread's
 // accumulators.
 template <typename T, typename T2, typename TO, int EPT, int NO>
-__global__ __launch_bounds__(256) void k_gemm_cols(const T* __restrict__ X, int M1,
-                                                   const T2* __restrict__ X2, int M,
+__global__ __launch_bounds__(256) void k_gemm_cols(const T* X, int M1, const T2* X2, int M,
                                                    const double* __restrict__ C, int N,
-                                                   TO* __restrict__ Out, long long ld, long long n,
+                                                   TO* Out, long long ld, long long n,
                                                    double alpha, int accumulate) {
   extern __shared__ double sC[];  // M x NO
   for (int t = threadIdx.x; t < M * NO; t += 256) {
@@ -307,18 +309,11 @@ __global__ __launch_bounds__(256) void k_gemm_cols(const T* __restrict__ X, int 
 #pragma unroll
     for (int j = 0; j < NO; ++j) acc[q][j] = 0.0;
   }
-#pragma unroll 2
-  for (int k = 0; k < M; ++k) {
+  // one row k of a segment: acc += x_k C[k][:]
+  auto row_update = [&](const auto* xk, int k) {
     double x[EPT];
-    if (k < M1) {
-      const T* xk = X + (long long)k * ld;
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) x[q] = ok[q] ? (double)xk[base + 256LL * q] : 0.0;
-    } else {
-      const T2* xk = X2 + (long long)(k - M1) * ld;
-#pragma unroll
-      for (int q = 0; q < EPT; ++q) x[q] = ok[q] ? (double)xk[base + 256LL * q] : 0.0;
-    }
+    for (int q = 0; q < EPT; ++q) x[q] = ok[q] ? (double)xk[base + 256LL * q] : 0.0;
     const double2* row = reinterpret_cast<const double2*>(sC + NO * k);
 #pragma unroll
     for (int j2 = 0; j2 < NO / 2; ++j2) {
@@ -329,7 +324,12 @@ __global__ __launch_bounds__(256) void k_gemm_cols(const T* __restrict__ X, int 
         acc[q][2 * j2 + 1] += x[q] * cc.y;
       }
     }
-  }
+  };
+  // the two segments in loops of their own (no branch in the loop body)
+#pragma unroll 2
+  for (int k = 0; k < M1; ++k) row_update(X + (long long)k * ld, k);
+#pragma unroll 2
+  for (int k = M1; k < M; ++k) row_update(X2 + (long long)(k - M1) * ld, k);
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     if (!ok[q]) continue;

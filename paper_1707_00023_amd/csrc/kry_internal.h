@@ -136,7 +136,10 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
                        const double* w, long long n, double* partials, int nsplit, hipStream_t s,
                        const void* X2 = nullptr, int M1 = 0, int st2 = -1);
 // Out[:, :N] = (accumulate ? Out : 0) + alpha X[:, :M] C (C row-major M x N);
-// X in one or two segments as for launch_gram.  Out must not overlap X.
+// X in one or two segments as for launch_gram.  Out must not overlap X,
+// except for N <= 16 with M <= 256 and N <= 32 with M <= 128 (the
+// column-owning kernel), where Out may be rows of X or X2 of the same
+// element type (in place).
 // st2, sto (-1: st): element types of X2 and Out; mixed types (st = F32
 // with F64 in X2 and/or Out) for N <= 16, M <= 256 only.
 hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int N, void* Out,
