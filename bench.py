@@ -34,9 +34,12 @@ CLASS_KERNEL = {"block_gram": ("k_gram_tall", "kry_block.hip"),
                 "operator": ("k_stencil_axpby", "kry_kernels.hip")}
 
 
-def measured_traffic(kernel_class, workload):
-    """HBM bytes per launch of the class's kernel from the committed counter
-    summary, or None if there is none or the kernel source changed since."""
+def measured_traffic(kernel_class, workload, alg_bytes_per_launch):
+    """HBM bytes per launch of the class's kernel: the ratio of counted to
+    algorithmic bytes from the committed counter summary (two rocprofv3
+    --pmc runs of this script with --calibration-copy) times this run's
+    algorithmic bytes per launch; None if there is no summary or the kernel
+    source changed since."""
     import hashlib
     import re
     if workload != "c2" or kernel_class not in CLASS_KERNEL or not os.path.exists(TRAFFIC_FILE):
@@ -44,11 +47,11 @@ def measured_traffic(kernel_class, workload):
     kernel, source = CLASS_KERNEL[kernel_class]
     src = os.path.join(ROOT, "paper_1707_00023_amd", "csrc", source)
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    pat = re.compile(r"traffic_bytes_per_launch (\S+) (\S+) source_sha256_16 (\S+)")
+    pat = re.compile(r"traffic_ratio (\S+) (\S+) source_sha256_16 (\S+)")
     for line in open(TRAFFIC_FILE):
         m = pat.search(line)
         if m and m.group(1) == kernel and m.group(3) == h:
-            return float(m.group(2))
+            return float(m.group(2)) * alg_bytes_per_launch
     return None
 
 
@@ -165,7 +168,7 @@ def precision_compare(args, wl, inp, dev):
 
     eps = torch.as_tensor(inp.eps, device=dev)
     sig = torch.as_tensor(inp.sigma, device=dev)
-    om = list(wl.omegas[: args.n_omega])
+    om = list(wl.omegas[args.omega_offset: args.omega_offset + args.n_omega])
     b = torch.as_tensor(wk.source_vector(wl, om[0], 0.0)[None, :], device=dev)
     out = {"metric": "FP32-storage error vs FP64 GPU run, per omega", "workload": wl.name,
            "n": wl.n, "omegas": om, "T": wl.T, "krylov_dim": wl.krylov_dim}
@@ -188,57 +191,6 @@ def precision_compare(args, wl, inp, dev):
     err = (torch.linalg.norm(ys["f32"] - ys["f64"], dim=1) / torch.linalg.norm(ys["f64"], dim=1))
     out["rel_err_per_omega"] = [float(e) for e in err.cpu()]
     out["speedup_f32_over_f64"] = out["f64"]["s"] / out["f32"]["s"]
-    print(json.dumps(out), flush=True)
-
-
-def traffic_probe(args, wl, inp, dev):
-    """Two Arnoldi cycles (the workload's Krylov dimension, the default
-    s-step block size) on the workload's grid, then one device copy of
-    COPY_BYTES (the calibration kernel: it moves exactly COPY_BYTES in and
-    COPY_BYTES out), timed with events.  Prints the algorithmic bytes of
-    every kernel launch of a cycle, in launch order."""
-    import numpy as np
-    import torch
-
-    import paper_1707_00023_amd as kry
-    import workloads as wk
-
-    eps = torch.as_tensor(inp.eps, device=dev)
-    sig = torch.as_tensor(inp.sigma, device=dev)
-    s = kry.Solver(eps, None, sig, kry.Options(storage=wl.storage, krylov_dim=wl.krylov_dim,
-                                               tol=wl.tol, s_step=args.s_step))
-    tune = None if args.no_autotune else s.autotune()
-    v = torch.as_tensor(wk.random_state(wl.n, 1), device=dev)
-    m = wl.krylov_dim
-    for _ in range(2):
-        s.arnoldi(v, m)
-    src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
-    dst = torch.empty_like(src)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_ms = e0.elapsed_time(e1)
-    esz = 8 if wl.storage == "f64" else 4
-    n = wl.n
-    vb = n * esz
-    N3 = wl.N ** 3
-    sst = args.s_step
-    launches = []  # (kernel, algorithmic bytes) in launch order of one cycle
-    for j0 in range(0, m, sst):
-        ss = min(sst, m - j0)
-        M = j0 + 1
-        for k in range(ss):
-            launches.append(("k_stencil_axpby", (2 if k == 0 else 3) * vb + 16 * N3))
-        for _ in range(2):  # two passes: Gram [V, S]^T M S, update [V, S] K
-            launches.append(("k_gram_tall", (M + ss) * vb + 8 * n))  # S is part of [V, S]
-            launches.append(("k_gemm_cols", (M + 2 * ss) * vb))
-    out = {"probe": "two s-step Arnoldi cycles + calibration copy", "workload": wl.name, "m": m,
-           "s_step": sst, "copy_bytes_each_way": COPY_BYTES, "copy_ms": copy_ms,
-           "copy_gbs": 2 * COPY_BYTES / (copy_ms * 1e6), "launch_shapes": tune,
-           "cycle_launches": launches}
     print(json.dumps(out), flush=True)
 
 
@@ -270,11 +222,13 @@ def main():
                     help="FP32-storage solve of the first --n-omega frequencies against an "
                          "FP64 solve of the same columns on the GPU")
     ap.add_argument("--n-omega", type=int, default=2)
+    ap.add_argument("--omega-offset", type=int, default=0,
+                    help="precision compare: index of the first frequency")
     ap.add_argument("--s-step", type=int, default=None,
                     help="s-step Arnoldi block size (default: the library binding's default)")
-    ap.add_argument("--traffic-probe", action="store_true",
-                    help="run two Arnoldi cycles on the workload's grid and a calibration "
-                         "copy of known size (for hardware-counter runs), then exit")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="after the timed steps, one device copy of 1 GiB each way (the "
+                         "reference dispatch that scales HBM counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this solver has no multi-GPU path "
@@ -296,9 +250,6 @@ def main():
         args.s_step = kry.DEFAULT_S_STEP
     if args.compare_batched:
         compare_batched(args, wl, inp, dev)
-        return
-    if args.traffic_probe:
-        traffic_probe(args, wl, inp, dev)
         return
     if args.precision_compare:
         precision_compare(args, wl, inp, dev)
@@ -330,6 +281,21 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt * 1000.0 / args.steps
+    calib = None
+    if args.calibration_copy:
+        # a device copy that moves exactly COPY_BYTES in and COPY_BYTES out:
+        # the reference dispatch for scaling HBM counters to bytes
+        src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        cms = e0.elapsed_time(e1)
+        calib = {"bytes_each_way": COPY_BYTES, "ms": cms, "gbs": 2 * COPY_BYTES / (cms * 1e6)}
+        del src, dst
 
     kms = np.sum([s["kernel_ms"] for s in stats], axis=0)
     kl = np.sum([s["kernel_launches"] for s in stats], axis=0)
@@ -360,6 +326,7 @@ def main():
         "matvecs": {"stationary": last["matvecs_stationary"], "transient": last["matvecs_transient"]},
         "phase_ms": {"stationary": last["ms_stationary"], "transient": last["ms_transient"]},
         "kernels": {name: {"ms": float(kms[i]) / args.steps, "launches": int(kl[i]) // args.steps,
+                           "bytes": float(kb[i]) / args.steps,
                            "gbs": float(kb[i] / (kms[i] * 1e-3) / 1e9) if kms[i] > 0 else 0.0}
                     for i, name in enumerate(kry.KERNEL_CLASSES)},
         "roofline": {"bound": "hbm", "kernel": kry.KERNEL_CLASSES[dom],
@@ -367,12 +334,15 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "avg_launch_us": float(kms[dom] / max(kl[dom], 1) * 1e3),
                      "alg_bytes_per_launch": float(kb[dom] / max(kl[dom], 1)),
-                     "traffic": measured_traffic(kry.KERNEL_CLASSES[dom], args.workload)},
+                     "traffic": measured_traffic(kry.KERNEL_CLASSES[dom], args.workload,
+                                                 float(kb[dom] / max(kl[dom], 1)))},
         "launch_shapes": tune,
         "converged": bool(last["converged"]),
         "max_residual": last["max_residual"],
         "max_err_estimate": last["max_err_estimate"],
     }
+    if calib is not None:
+        out["calibration_copy"] = calib
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, inp)

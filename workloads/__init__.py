@@ -76,7 +76,7 @@ C4 = Workload("c4_64cube_grad", 64, 4, 1.0, 250, (1.5, 3.0), (2.0, 3.0), 6,
               _lin(0.09, 0.11, 8), 1, None, 64, 1e-13, "f64", 4,
               flux_plane=58, n_fd_cells=20)
 C5 = Workload("c5_256cube_fp32", 256, 8, 1.0, 6000, (1.5, 3.0), (2.0, 3.0), 10,
-              _lin(0.08, 0.12, 16), 1, 600.0, 48, 1e-5, "f32", 5)
+              _lin(0.08, 0.12, 16), 1, 600.0, 48, 2e-6, "f32", 5)
 
 CONFIGS = {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c5": C5}
 
