@@ -190,6 +190,19 @@ def precision_compare(args, wl, inp, dev):
         s.close()
     err = (torch.linalg.norm(ys["f32"] - ys["f64"], dim=1) / torch.linalg.norm(ys["f64"], dim=1))
     out["rel_err_per_omega"] = [float(e) for e in err.cpu()]
+    if args.single_ref > 0:
+        # the first frequencies solved again one at a time in FP64: a check
+        # of the many-shift solves of both runs
+        s = kry.Solver(eps, None, sig, kry.Options(storage="f64", krylov_dim=wl.krylov_dim, tol=1e-8,
+                                                   s_step=args.s_step_cli))
+        ref = []
+        for k in range(min(args.single_ref, len(om))):
+            y1 = s.solve_multifreq([om[k]], b, wl.T)[0]
+            ref.append({name: float(torch.linalg.norm(ys[name][k] - y1) / torch.linalg.norm(y1))
+                        for name in ("f32", "f64")})
+            print(f"[bench] single omega {k} done", file=sys.stderr, flush=True)
+        s.close()
+        out["rel_err_vs_single_f64"] = ref
     out["speedup_f32_over_f64"] = out["f64"]["s"] / out["f32"]["s"]
     print(json.dumps(out), flush=True)
 
@@ -222,6 +235,9 @@ def main():
                     help="FP32-storage solve of the first --n-omega frequencies against an "
                          "FP64 solve of the same columns on the GPU")
     ap.add_argument("--n-omega", type=int, default=2)
+    ap.add_argument("--single-ref", type=int, default=0,
+                    help="precision compare: also solve the first K frequencies one at a time "
+                         "in FP64 and report both runs' errors against them")
     ap.add_argument("--omega-offset", type=int, default=0,
                     help="precision compare: index of the first frequency")
     ap.add_argument("--s-step", type=int, default=None,

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <limits>
 #include <map>
 #include <new>
 #include <string>
@@ -465,7 +466,7 @@ double now_ms() {
 int block_gemm(kry_ctx* c, const void* X, int M, const std::vector<double>& C, int N, void* Out,
                double alpha, int accumulate, const void* X2, int M1, int st1, int st2, int sto);
 
-// A shift whose residual grows 1e4-fold above its best (the collinear
+// A shift whose residual grows 100-fold above its best (the collinear
 // restart can do that to shifts far from the seed) is dropped and listed in
 // *diverged (its Z columns then hold garbage); the caller solves it again.
 int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> coef,
@@ -473,8 +474,7 @@ int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> 
                double* max_res, const std::vector<double>* zscale = nullptr,
                std::vector<int>* diverged = nullptr) {
   const int nw = (int)omegas.size();
-  std::vector<double> best(nw);
-  for (int k = 0; k < nw; ++k) best[k] = std::abs(coef[k]) / bnorm;
+  std::vector<double> best(nw, std::numeric_limits<double>::infinity());  // smallest residual so far
   bool contiguous = 2 * nw > 16;
   for (int k = 1; k < nw && contiguous; ++k) contiguous = zcolk[k] == zcolk[0] + k;
   std::vector<double> Cz;
@@ -564,7 +564,7 @@ int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> 
       ++ncol;
       coef[k] = exact ? cplx(0.0) : -rho;  // new residual: coef_k * (V_{m+1} w), |V w|_M = 1
       const double res = std::abs(coef[k]) / bnorm;
-      if (diverged && nw > 1 && (!std::isfinite(res) || res > 1e4 * best[k])) {
+      if (diverged && nw > 1 && (!std::isfinite(res) || res > 1e2 * best[k])) {
         active[k] = 0;
         coef[k] = 0.0;
         diverged->push_back(k);
@@ -928,9 +928,18 @@ namespace {
 // Shifted solves for a group of columns sharing one complex source (slot
 // data from b_col): z_k = (A + i w_k)^{-1} b for the listed shifts, stored
 // in Z columns 2*zcolk[k] (Re) and 2*zcolk[k]+1 (Im).
+int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, double tol_rel,
+                 double bn, kry_stats* st);
+int cnorm(kry_ctx* c, const double* x, double* out);
+
+// spare >= 0: a free Z pair; once every shift reports convergence, its
+// true residual b - (A + i w) z is checked, and corrected once where it
+// misses the target (the residual of a shift that is not the restart seed
+// is carried as a coefficient of the shared start vector, and rounding can
+// open a gap between the two).  b_col must not be c->d_r when spare >= 0.
 int stationary_group(kry_ctx* c, const double* b_col, const std::vector<double>& omegas,
                      const std::vector<int>& zcolk, double tol_rel, kry_stats* st, double* max_res,
-                     double* bnorm_out) {
+                     double* bnorm_out, int spare = -1) {
   const int nw = (int)omegas.size();
   for (int k = 0; k < nw; ++k) {
     KRY_HIP(hipMemsetAsync(zcol(c, 2 * zcolk[k]), 0, 2 * c->ldv * c->esz, c->stream));
@@ -1002,6 +1011,46 @@ int stationary_group(kry_ctx* c, const double* b_col, const std::vector<double>&
     rc = solve(std::vector<int>{k}, true);
     if (rc) return rc;
   }
+  if (spare >= 0 && status == KRY_OK) {  // shifts reported converged
+    for (int k = 0; k < nw; ++k) {
+      rc = refine_shift(c, b_col, omegas[k], zcolk[k], spare, tol_rel, bnorm, st);
+      if (rc == KRY_ENOCONV) status = rc;
+      else if (rc) return rc;
+    }
+  }
+  return status;
+}
+
+// r = b - (A + i w) z_k; where |r|_M > 2 tol_rel |b|_M, solve (A + i w) d = r
+// into the spare pair and add d to z_k.
+int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, double tol_rel,
+                 double bn, kry_stats* st) {
+  if (!c->d_r) {  // the residual vector (complex, n entries)
+    if (hipMalloc(&c->d_r, sizeof(double) * 2 * c->n) != hipSuccess) {
+      c->d_r = nullptr;
+      (void)hipGetLastError();
+      return fail(c, KRY_ENOMEM, "cannot allocate the residual vector");
+    }
+  }
+  KRY_HIP(kry::launch_stencil_cols(c->st, zcol(c, 2 * zk), slot(c, 1), c->ldv, 2, c->g, c->mats, c->stream));
+  KRY_HIP(kry::launch_shift_residual(c->st, bcol, zcol(c, 2 * zk), zcol(c, 2 * zk + 1), slot(c, 1), slot(c, 2),
+                                     w, c->d_r, c->n, c->stream));
+  if (st) st->matvecs_stationary += 2;
+  double rn = 0.0;
+  int rc = cnorm(c, c->d_r, &rn);
+  if (rc) return rc;
+  if (!(rn > 2.0 * tol_rel * bn)) return KRY_OK;
+  if (c->opts.verbose)
+    std::fprintf(stderr, "[kry] shift omega = %.6f: true relative residual %.3e, corrected\n", w, rn / bn);
+  double lr = 0.0, rn2 = 0.0;
+  const int status = stationary_group(c, c->d_r, std::vector<double>{w}, std::vector<int>{spare},
+                                      tol_rel * bn / rn, st, &lr, &rn2, -1);
+  if (status && status != KRY_ENOCONV) return status;
+  const double I2[4] = {1.0, 0.0, 0.0, 1.0};
+  KRY_HIP(hipMemcpyAsync(c->d_Y, I2, sizeof(I2), hipMemcpyHostToDevice, c->stream));
+  KRY_HIP(kry::launch_combine(c->st, zcol(c, 2 * spare), c->ldv, 2, c->d_Y, 2, zcol(c, 2 * zk), c->ldv, nullptr,
+                              1, c->g, c->stream));
+  KRY_HIP(hipStreamSynchronize(c->stream));
   return status;
 }
 
@@ -1095,7 +1144,7 @@ int stationary_from(kry_ctx* c, const double* bcol, double w, const std::vector<
   }
   double lr = 0.0, rn2 = 0.0;
   const int status = stationary_group(c, c->d_r, std::vector<double>{w}, std::vector<int>{zk},
-                                      tol_s * bn / rn, st, &lr, &rn2);
+                                      tol_s * bn / rn, st, &lr, &rn2, -1);
   if (status && status != KRY_ENOCONV) return status;
   *res = lr * rn / bn;
   // z = z0 + d
@@ -1127,14 +1176,14 @@ int for_each_group(kry_ctx* c, const double* omegas, int n_omega, int n_src, con
     if (rc0) return rc0;
   }
   if (!b_per_omega) {
-    int rc = ensure_z(c, n_omega);
+    int rc = ensure_z(c, n_omega + 1);  // pair n_omega: refinement scratch
     if (rc) return rc;
     std::vector<double> om(omegas, omegas + n_omega);
     std::vector<int> zc(n_omega);
     for (int k = 0; k < n_omega; ++k) zc[k] = k;
     for (int s = 0; s < n_src; ++s) {
       double bn = 0.0;
-      rc = stationary_group(c, b + (size_t)s * 2 * c->n, om, zc, tol_s, st, max_res, &bn);
+      rc = stationary_group(c, b + (size_t)s * 2 * c->n, om, zc, tol_s, st, max_res, &bn, n_omega);
       if (rc == KRY_ENOCONV) status = rc;
       else if (rc) return rc;
       for (int k = 0; k < n_omega; ++k) {
@@ -1148,7 +1197,7 @@ int for_each_group(kry_ctx* c, const double* omegas, int n_omega, int n_src, con
     // solutions of each source are kept (ring of kQ vector pairs)
     constexpr int kQ = 3;
     const bool cont = c->opts.omega_continuation && n_omega > 1;
-    int rc = ensure_z(c, cont ? 2 : 1);
+    int rc = ensure_z(c, 2);  // pair 0: z; pair 1: continuation start, refinement scratch
     if (rc) return rc;
     if (cont) {
       rc = ensure_cont(c, 2 * kQ * n_src);
@@ -1162,7 +1211,7 @@ int for_each_group(kry_ctx* c, const double* omegas, int n_omega, int n_src, con
         const int q = cont ? std::min(k, kQ) : 0;
         if (q == 0) {
           rc = stationary_group(c, bcol, std::vector<double>{omegas[k]}, std::vector<int>{0}, tol_s,
-                                st, max_res, &bn);
+                                st, max_res, &bn, 1);
         } else {
           std::vector<double> om_a;
           std::vector<int> hist_a;
@@ -1173,6 +1222,7 @@ int for_each_group(kry_ctx* c, const double* omegas, int n_omega, int n_src, con
           double res = 0.0;
           rc = stationary_from(c, bcol, omegas[k], om_a, hist_a, tol_s, st, &res, &bn);
           *max_res = std::max(*max_res, res);
+          if (rc == KRY_OK) rc = refine_shift(c, bcol, omegas[k], 0, 1, tol_s, bn, st);
         }
         if (rc == KRY_ENOCONV) status = rc;
         else if (rc) return rc;
@@ -2153,7 +2203,7 @@ int kry_grad(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
     std::vector<int> zc(n_omega);
     for (int k = 0; k < n_omega; ++k) zc[k] = k;
     double bn = 0.0;
-    rc = stationary_group(c, b, om, zc, tol, st, &max_res, &bn);
+    rc = stationary_group(c, b, om, zc, tol, st, &max_res, &bn, n_omega);  // pair n_omega: scratch
     if (rc == KRY_ENOCONV) status = rc;
     else if (rc) return rc;
   } else {

@@ -487,6 +487,7 @@ def test_grad_per_omega_sources_and_autograd():
     assert np.linalg.norm(g - go) <= 1e-8 * np.linalg.norm(go)
 
 
+@pytest.mark.timeout(900)  # 80 frozen-path loss evaluations at 64^3
 def test_grad_c4_full_size_against_frozen_path_differences():
     # 64^3, 8 frequencies, flux plane 58, 20 seeded cells.  The gradient
     # comes from the default solver (s-step Arnoldi); it must agree with the
@@ -526,7 +527,9 @@ def test_grad_c4_full_size_against_frozen_path_differences():
     errs = {}
     for h in (1e-5, 1e-6):
         fd = []
-        for (i, j, k) in inp.fd_cells:
+        for n_done, (i, j, k) in enumerate(inp.fd_cells):
+            if n_done % 5 == 0:
+                _announce(f"c4 fd h={h:g}: cell {n_done} of {len(inp.fd_cells)}")
             vals = []
             for sgn in (1.0, -1.0):
                 e = inp.eps.copy()
