@@ -93,9 +93,13 @@ typedef struct {
   int32_t s_step;       /* 0 or 1: one operator application per
                            Gram-Schmidt step (as chosen by orth); s in
                            2..64: s-step Arnoldi, s operator applications
-                           build a Chebyshev basis block that is
+                           build a basis block (Chebyshev in a call's first
+                           restart cycle, then Newton steps on that cycle's
+                           Ritz values in Leja order) that is
                            orthogonalised as one tall-skinny block (two
-                           basis sweeps per s steps).  The block is FP64
+                           basis sweeps per pass; a second pass only where
+                           the first leaves a loss of orthogonality of
+                           order u cond^2 above 1e-11).  The block is FP64
                            also with FP32 storage (only the orthonormal
                            result is rounded to FP32; FP32 storage with
                            krylov_dim > 112 runs one step per sweep).  A
@@ -205,10 +209,14 @@ int kry_expv(kry_ctx* ctx, double t, const double* v, double* y,
  *    0, b holds n_src columns shared by every w; otherwise n_omega*n_src
  *    columns, column (w, s) at index w*n_src + s.
  * yT: device FP64, n x (n_omega*n_src), column (w, s) at w*n_src + s.
- * The shifted systems of all w that share a source are solved in one real
- * Krylov sequence (restarted multi-shift FOM, residuals collinear across
- * shifts, cf. Corollaries 1 and 2); the transients are then integrated per
- * column.  stats: host, may be NULL. */
+ * The shifted systems of the w that share a source are solved in real
+ * Krylov sequences shared by groups of neighbouring w (at most 16, spanning
+ * at most a tenth of their mean; restarted multi-shift method with the
+ * residuals kept collinear across a group, cf. Corollaries 1 and 2); a
+ * shift that diverges in its group is solved again alone, and every shift's
+ * true residual is checked and corrected once where it misses the target.
+ * The transients are then integrated per column.  stats: host, may be
+ * NULL. */
 int kry_solve_multifreq(kry_ctx* ctx, const double* omegas, int32_t n_omega,
                         int32_t n_src, const double* b, int32_t b_per_omega,
                         double T, double* yT, kry_stats* stats);
