@@ -962,21 +962,10 @@ int stationary_group(kry_ctx* c, const double* b_col, const std::vector<double>&
   // shifts in groups of neighbours: at most 16, spanning at most a tenth of
   // their mean frequency (one restart direction has to serve every shift
   // of a group, which a wide band of shifts defeats)
-  std::vector<int> order(nw);
-  for (int k = 0; k < nw; ++k) order[k] = k;
-  std::sort(order.begin(), order.end(), [&](int a, int b) { return omegas[a] < omegas[b]; });
-  std::vector<std::vector<int>> groups;
-  for (int k : order) {
-    if (!groups.empty()) {
-      auto& g = groups.back();
-      const double lo = omegas[g.front()], hi = omegas[k];
-      if ((int)g.size() < 16 && hi - lo <= 0.1 * std::max(0.5 * (lo + hi), 1e-300)) {
-        g.push_back(k);
-        continue;
-      }
-    }
-    groups.push_back({k});
-  }
+  std::vector<int> gid(nw);
+  const int ng = kry::group_shifts(nw, omegas.data(), 16, 0.1, gid.data());
+  std::vector<std::vector<int>> groups(ng);
+  for (int k = 0; k < nw; ++k) groups[gid[k]].push_back(k);
   std::vector<int> redo;
   auto solve = [&](const std::vector<int>& idx, bool single) -> int {
     std::vector<double> om;

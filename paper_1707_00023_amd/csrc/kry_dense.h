@@ -122,6 +122,14 @@ bool hess_eigvals(int m, const double* H, int ldh, double* re, double* im);
 int leja_steps(int nr, const double* re, const double* im, int s, double scale, double* alpha,
                double* q);
 
+// Groups of neighbouring shifts, one shared Krylov sequence each: the n
+// shifts w are taken in increasing order, and a group is closed when the
+// next shift would make it larger than max_size or its spread (highest
+// minus lowest) larger than rel_band times the mean of those two.  Writes
+// group[k], the 0-based group of shift k (groups numbered in increasing
+// order of their shifts); returns the number of groups.
+int group_shifts(int n, const double* w, int max_size, double rel_band, int* group);
+
 // Projected Gram matrix of an s-column block S against an M-orthonormal
 // basis V from one product P = [V, S]^T M S ((M + s) x s, row-major):
 // G = S^T M S - C^T C with C = P[:M] (s x s, row-major) and ref[k] =

@@ -78,6 +78,10 @@ int t_hess_eigvals(int m, const double* H, int ldh, double* re, double* im) {
   return kry::hess_eigvals(m, H, ldh, re, im) ? 1 : 0;
 }
 
+int t_group_shifts(int n, const double* w, int max_size, double rel_band, int* group) {
+  return kry::group_shifts(n, w, max_size, rel_band, group);
+}
+
 int t_leja_steps(int nr, const double* re, const double* im, int s, double scale, double* alpha,
                  double* q) {
   return kry::leja_steps(nr, re, im, s, scale, alpha, q);

@@ -460,3 +460,45 @@ def test_sstep_newton_basis_host_algebra(lib, m, s):
     assert np.abs(V.T @ (w[:, None] * V) - np.eye(m + 1)).max() <= 1e-12
     Vr, Hr = _arnoldi_mgs2(A, w, v0, m)
     assert np.abs(H - Hr).max() <= 1e-9 * np.abs(Hr).max()
+
+
+def _groups_valid(w, gid, ng, max_size, band):
+    """Each group is a run of consecutive values, within its size and band
+    limits, and no group could have taken the next value (greedy)."""
+    order = np.argsort(w, kind="stable")
+    ids = gid[order]
+    assert ids[0] == 0 and np.all(np.diff(ids) >= 0) and np.all(np.diff(ids) <= 1)
+    assert ids[-1] == ng - 1
+    for g in range(ng):
+        mem = np.sort(w[gid == g])
+        assert 1 <= mem.size <= max_size
+        assert mem[-1] - mem[0] <= band * 0.5 * (mem[0] + mem[-1]) + 1e-15
+        nxt = np.sort(w)[np.searchsorted(np.sort(w), mem[-1], side="right"):]
+        if nxt.size:  # the next value would break a limit
+            lo, hi = mem[0], nxt[0]
+            assert mem.size == max_size or hi - lo > band * 0.5 * (lo + hi)
+
+
+def test_group_shifts(lib):
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    lib.t_group_shifts.restype = ctypes.c_int
+    # 16 frequencies over 2 pi [0.08, 0.12]: four groups of neighbours
+    w = 2 * np.pi * np.linspace(0.08, 0.12, 16)
+    gid = np.zeros(16, dtype=np.int32)
+    ng = lib.t_group_shifts(16, P(w), 16, ctypes.c_double(0.1), P(gid))
+    assert ng == 4
+    _groups_valid(w, gid, ng, 16, 0.1)
+    assert list(gid[:4]) == [0] * 4 and list(gid[4:8]) == [1] * 4
+    # a narrow band in one group; the size limit splits it
+    w = 2 * np.pi * np.linspace(0.1, 0.101, 40)
+    gid = np.zeros(40, dtype=np.int32)
+    ng = lib.t_group_shifts(40, P(w), 16, ctypes.c_double(0.1), P(gid))
+    assert ng == 3 and list(np.bincount(gid)) == [16, 16, 8]
+    # unsorted input, a zero shift and a single shift
+    rng = np.random.default_rng(5)
+    for n in (1, 7, 33):
+        w = np.concatenate([[0.0], rng.uniform(0.0, 2.0, n - 1)]) if n > 1 else np.array([0.7])
+        rng.shuffle(w)
+        gid = np.zeros(n, dtype=np.int32)
+        ng = lib.t_group_shifts(n, P(w), 5, ctypes.c_double(0.1), P(gid))
+        _groups_valid(w, gid, ng, 5, 0.1)
