@@ -1457,7 +1457,7 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
     // the update kernel for these shapes reads all its entries of every
     // input row before writing them, so FP64 storage can update S in place
     const bool inplace = !wide && ((ss <= 16 && M + ss <= 256) || (ss <= 32 && M + ss <= 128));
-    // t_0 (FP64), then the Chebyshev block t_1..t_ss into S
+    // t_0 (FP64), then the basis block t_1..t_ss into S
     void* t0 = slot(c, j0);
     void* S = slot(c, j0 + 1);
     if (wide) {
