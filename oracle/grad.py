@@ -28,7 +28,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .operator import assemble_A
-from .solve import DENSE_MAX, SPLU_MAX, stationary
+from .solve import _route, shifted_solve, stationary
 
 
 def flux(z, N, kf):
@@ -54,31 +54,23 @@ def flux_seed(z, N, kf):
     return a.reshape(-1)
 
 
-def _adjoint_solve(A, a, omega):
+def _adjoint_solve(A, a, omega, method=None):
+    """lam = (A + i w I)^-T a on the explicit transpose (no structural
+    shortcut), by the same checked library routes as the forward solve."""
     n = A.shape[0]
-    At = A.T.tocsr().astype(np.complex128)
-    if n <= DENSE_MAX:
-        Ad = At.toarray()
-        Ad[np.diag_indices(n)] += 1j * omega
-        return np.linalg.solve(Ad, a)
-    As = (At + 1j * omega * sp.identity(n, format="csr")).tocsc()
-    if n <= SPLU_MAX:
-        lu = spla.splu(As)
-        lam = lu.solve(a)
-        return lam + lu.solve(a - As @ lam)
-    lam, _ = spla.gmres(As, a, rtol=1e-13, restart=200, maxiter=200)
-    return lam
+    At = (A.T.astype(np.complex128) + 1j * omega * sp.identity(n, format="csr")).tocsr()
+    return shifted_solve(At, a, _route(n, method))[0]
 
 
-def loss(eps, mu, sigma, b_cols, omegas, kf):
+def loss(eps, mu, sigma, b_cols, omegas, kf, method=None):
     """L = sum_w P_w; returns (L, list of z)."""
     A = assemble_A(eps, mu, sigma)
     N = eps.shape[0]
-    zs = [stationary(A, b_cols[:, c], omegas[c]) for c in range(len(omegas))]
+    zs = [stationary(A, b_cols[:, c], omegas[c], method=method) for c in range(len(omegas))]
     return sum(flux(z, N, kf) for z in zs), zs
 
 
-def loss_and_grad(eps, mu, sigma, b_cols, omegas, kf):
+def loss_and_grad(eps, mu, sigma, b_cols, omegas, kf, method=None):
     """(L, dL/d eps) with the adjoint formula above; dL/d eps has shape N^3."""
     A = assemble_A(eps, mu, sigma)
     N = eps.shape[0]
@@ -86,10 +78,10 @@ def loss_and_grad(eps, mu, sigma, b_cols, omegas, kf):
     L = 0.0
     g = np.zeros(n3)
     for c, w in enumerate(omegas):
-        z = stationary(A, b_cols[:, c], w)
+        z = stationary(A, b_cols[:, c], w, method=method)
         L += flux(z, N, kf)
         a = flux_seed(z, N, kf)
-        lam = _adjoint_solve(A, a, w)
+        lam = _adjoint_solve(A, a, w, method)
         Az = A @ z
         contrib = np.real(lam[3 * n3:] * Az[3 * n3:]).reshape(3, n3).sum(axis=0)
         g += contrib / eps.reshape(-1)

@@ -34,24 +34,60 @@ DENSE_MAX = 3072       # n up to which dense matrices are used
 SPLU_MAX = 6 * 16 ** 3  # n up to which the sparse LU is used for z
 
 
-def stationary(A, b, omega, rtol=1e-13):
-    """z = (A + i w I)^-1 b (the vector z_stat of Corollary 3, angular w)."""
-    n = A.shape[0]
+def _route(n, method):
+    if method is None:
+        return "dense" if n <= DENSE_MAX else ("splu" if n <= SPLU_MAX else "gmres")
+    if method not in ("dense", "splu", "gmres"):
+        raise ValueError(f"unknown route {method!r}")
+    return method
+
+
+def shifted_solve(As, b, route, rtol=1e-13):
+    """x = As^-1 b for a complex sparse As by one library route; returns
+    (x, true relative residual |b - As x| / |b|).
+
+    dense: LU of the full matrix; splu: SuperLU plus one step of iterative
+    refinement; gmres: restarted GMRES(200) to rtol, then GMRES on the true
+    residual once more (iterative refinement).  A GMRES route whose true
+    residual misses 100 rtol raises: the oracle never hands back an answer it
+    has not checked.
+    """
+    n = As.shape[0]
     b = np.asarray(b, dtype=np.complex128)
-    if n <= DENSE_MAX:
-        Ad = A.toarray().astype(np.complex128)
-        Ad[np.diag_indices(n)] += 1j * omega
-        return np.linalg.solve(Ad, b)
-    As = (A.astype(np.complex128) + 1j * omega * sp.identity(n, format="csr")).tocsc()
-    if n <= SPLU_MAX:
-        lu = spla.splu(As)
-        z = lu.solve(b)
-        # one step of iterative refinement
-        return z + lu.solve(b - As @ z)
-    z, info = spla.gmres(As, b, rtol=rtol, restart=200, maxiter=200)
-    r = b - As @ z
-    dz, _ = spla.gmres(As, r, rtol=rtol, restart=200, maxiter=50)
-    return z + dz
+    bn = np.linalg.norm(b)
+    if bn == 0.0:
+        return np.zeros(n, dtype=np.complex128), 0.0
+    if route == "dense":
+        x = np.linalg.solve(As.toarray(), b)
+    elif route == "splu":
+        lu = spla.splu(As.tocsc())
+        x = lu.solve(b)
+        x = x + lu.solve(b - As @ x)
+    else:
+        x, info = spla.gmres(As, b, rtol=rtol, restart=200, maxiter=200)
+        dx, info2 = spla.gmres(As, b - As @ x, rtol=rtol, restart=200, maxiter=50)
+        x = x + dx
+        res = np.linalg.norm(b - As @ x) / bn
+        if res > 100 * rtol:
+            raise RuntimeError(f"oracle GMRES did not converge: true relative residual "
+                               f"{res:.2e} (info {info}, {info2}), target {rtol:.1e}")
+        return x, res
+    return x, float(np.linalg.norm(b - As @ x) / bn)
+
+
+def stationary_with_residual(A, b, omega, rtol=1e-13, method=None):
+    """(z, true relative residual) with z = (A + i w I)^-1 b, the vector z_stat
+    of Corollary 3 (angular w).  ``method`` forces a route (dense, splu,
+    gmres); by default dense LU up to n = DENSE_MAX, SuperLU up to SPLU_MAX,
+    GMRES above."""
+    n = A.shape[0]
+    As = (A.astype(np.complex128) + 1j * omega * sp.identity(n, format="csr")).tocsr()
+    return shifted_solve(As, b, _route(n, method), rtol)
+
+
+def stationary(A, b, omega, rtol=1e-13, method=None):
+    """z = (A + i w I)^-1 b (the vector z_stat of Corollary 3, angular w)."""
+    return stationary_with_residual(A, b, omega, rtol, method)[0]
 
 
 def expv(A, t, v):
@@ -88,14 +124,21 @@ def augmented_matrix(A, b, omega):
     return sp.bmat([[-A, B], [None, Om]], format="csr")
 
 
-def augmented_solution(A, b, omega, T):
-    """y(T) from the variation-of-constants integral, without Corollary 3."""
+def augmented_solution(A, b, omega, T, method=None):
+    """y(T) from the variation-of-constants integral, without Corollary 3.
+
+    ``method``: "dense" (expm of the full augmented matrix) or "sparse"
+    (expm_multiply); by default dense up to n = DENSE_MAX."""
     n = A.shape[0]
     G = augmented_matrix(A, b, omega)
     e = np.zeros(n + 2)
     e[n + 1] = 1.0
-    if n <= DENSE_MAX:
+    if method is None:
+        method = "dense" if n <= DENSE_MAX else "sparse"
+    if method == "dense":
         return (sla.expm(T * G.toarray()) @ e)[:n]
+    if method != "sparse":
+        raise ValueError(f"unknown route {method!r}")
     return spla.expm_multiply(T * G, e)[:n]
 
 

@@ -313,3 +313,130 @@ def test_krylov_basis_definition_properties():
     # energy dissipativity carries to the projection: the symmetric part of
     # H (an orthogonal projection in the energy product) is positive semidefinite
     assert np.linalg.eigvalsh(0.5 * (H[:m] + H[:m].T)).min() > -1e-12
+
+
+# --- the flux: hand cases and the discrete Poynting balance ----------------
+
+def test_flux_hand_cases_fix_planes_and_signs():
+    # 3^3 grid, plane kf = 1: E sits on the plane, H half a cell below (k = 0)
+    # and above (k = 1); the flux is the z-component of E x H,
+    # 1/2 Re(Ex conj(Hy) - Ey conj(Hx)), with H averaged over the two planes.
+    N, kf = 3, 1
+
+    def state(**entries):
+        z = np.zeros((6, N, N, N), dtype=np.complex128)
+        for name, (k, val) in entries.items():
+            z[wk.COMPONENTS.index(name), k, 1, 2] = val
+        return z.reshape(-1)
+
+    assert og.flux(state(Ex=(1, 1.0), Hy=(0, 2.0)), N, kf) == pytest.approx(0.5, abs=1e-15)
+    assert og.flux(state(Ex=(1, 1.0), Hy=(1, 2.0)), N, kf) == pytest.approx(0.5, abs=1e-15)
+    assert og.flux(state(Ey=(1, 1.0), Hx=(1, 2.0)), N, kf) == pytest.approx(-0.5, abs=1e-15)
+    assert og.flux(state(Ey=(1, 1.0), Hx=(0, 2.0)), N, kf) == pytest.approx(-0.5, abs=1e-15)
+    # the phase enters through Re(E conj(H)): in phase 1/4, in quadrature 0
+    assert og.flux(state(Ex=(1, 1j), Hy=(0, 1j)), N, kf) == pytest.approx(0.25, abs=1e-15)
+    assert og.flux(state(Ex=(1, 1j), Hy=(0, 1.0)), N, kf) == pytest.approx(0.0, abs=1e-15)
+    # fields off the plane, or H two half-cells away, carry no flux here
+    assert og.flux(state(Ex=(1, 1.0), Hy=(2, 5.0)), N, kf) == 0.0
+    assert og.flux(state(Ex=(0, 1.0), Hy=(0, 5.0)), N, kf) == 0.0
+    assert og.flux(state(Ez=(1, 1.0), Hx=(1, 5.0), Hy=(0, 3.0)), N, kf) == 0.0
+
+
+def _dissipation_above(z, sigma, N, kf):
+    """Power absorbed above the two staggered cuts that straddle plane kf.
+
+    Cut a (between H at kf - 1/2 and E at kf) leaves every component of the
+    cells k >= kf above it; cut b (between E, Hz at kf and Ez, Hx, Hy at
+    kf + 1/2) leaves the cells k > kf and the Ez, Hx, Hy of layer kf above it.
+    With S = diag(sigma) on all six components, the real part of
+    z^H (S + K + i w M) z restricted to a region with no source is
+    sum sigma |z|^2 plus the K-coupling across the cut, i.e. the inflow."""
+    Z = z.reshape(6, N, N, N)
+    mag = np.abs(Z) ** 2
+    above_a = np.sum(sigma[kf:] * mag[:, kf:].sum(axis=0))
+    above_b = np.sum(sigma[kf + 1:] * mag[:, kf + 1:].sum(axis=0))
+    above_b += np.sum(sigma[kf] * (mag[0, kf] + mag[1, kf] + mag[5, kf]))
+    return above_a, above_b
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.4])
+def test_flux_equals_dissipated_power_above_plane(theta):
+    # Discrete Poynting theorem: for (A + i w) z = b with b zero above a cut,
+    # Re of z^H M (A + i w) z over the components above the cut is zero
+    # (K restricted to them is real skew, i w M is imaginary), so the flux
+    # through the cut equals the absorbed power sum sigma |z|^2 above it.
+    # The flux through plane kf with H averaged over kf - 1/2 and kf + 1/2 is
+    # the mean of the inflows through cuts a and b, each twice its power.
+    N, kf = 6, 3
+    wl = wk.small(N, seed=5, n_spheres=3, layer=2, radius=(0.8, 1.5), src_k=1)
+    inp = wk.generate(wl)
+    mu = 1.0 + np.random.default_rng(4).uniform(0.0, 1.0, size=inp.eps.shape)
+    A = op.assemble_A(inp.eps, mu, inp.sigma)
+    omega = 2 * math.pi * 0.1
+    b = wk.source_vector(wl, omega, theta)
+    z = osv.stationary(A, b, omega)
+    pa, pb = _dissipation_above(z, inp.sigma, N, kf)
+    P = og.flux(z, N, kf)
+    assert pa > 0 and pb > 0
+    assert abs(P - 0.25 * (pa + pb)) <= 1e-12 * P
+
+    # plausible mistakes in the flux fail the balance: H averaged over the
+    # planes kf, kf + 1, or the Ey Hx term with the wrong sign
+    Z = z.reshape(6, N, N, N)
+
+    def flux_variant(h_lo, h_hi, sign):
+        hx = 0.5 * (Z[0, h_lo] + Z[0, h_hi])
+        hy = 0.5 * (Z[1, h_lo] + Z[1, h_hi])
+        return 0.5 * float(np.real(np.sum(Z[3, kf] * np.conj(hy) + sign * Z[4, kf] * np.conj(hx))))
+
+    assert flux_variant(kf - 1, kf, -1) == pytest.approx(P, rel=1e-14)
+    for wrong in (flux_variant(kf, kf + 1, -1), flux_variant(kf - 1, kf, +1)):
+        assert abs(wrong - 0.25 * (pa + pb)) > 1e-3 * P
+
+
+# --- the sparse and iterative oracle routes against independent ones ------
+
+@pytest.mark.parametrize("theta", [0.0, 0.4])
+def test_augmented_sparse_route_matches_split(theta):
+    # n = 4374 > DENSE_MAX: the augmented matrix goes through expm_multiply
+    # (the route of the stored full-size expected values), the split through
+    # SuperLU and expm_multiply of A alone (both pinned to dense routines)
+    wl, inp = _medium(9, seed=2, n_spheres=4)
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    omega, T = 2 * math.pi * 0.1, 9.0
+    b = wk.source_vector(wl, omega, theta)
+    assert A.shape[0] > osv.DENSE_MAX
+    y_aug = osv.augmented_solution(A, b, omega, T)
+    y_split = osv.split_solution(A, b, omega, T)[0]
+    assert np.linalg.norm(y_aug - y_split) <= 1e-12 * np.linalg.norm(y_split)
+
+
+def test_gmres_routes_match_sparse_lu():
+    # the GMRES branches (forward and explicit-transpose adjoint) against
+    # SuperLU on the same systems, with their true residuals reported
+    wl, inp = _medium(9, seed=2, n_spheres=4)
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    omega = 2 * math.pi * 0.1
+    b = wk.source_vector(wl, omega, 0.3)
+    z_lu, r_lu = osv.stationary_with_residual(A, b, omega, method="splu")
+    z_gm, r_gm = osv.stationary_with_residual(A, b, omega, method="gmres")
+    assert r_lu < 1e-14 and r_gm < 1e-12
+    assert np.linalg.norm(z_gm - z_lu) <= 1e-12 * np.linalg.norm(z_lu)
+    a = og.flux_seed(z_lu, wl.N, 5)
+    lam_lu = og._adjoint_solve(A, a, omega, "splu")
+    lam_gm = og._adjoint_solve(A, a, omega, "gmres")
+    At = A.T.toarray() + 1j * omega * np.eye(wl.n)
+    assert np.linalg.norm(At @ lam_lu - a) <= 1e-13 * np.linalg.norm(a)
+    assert np.linalg.norm(lam_gm - lam_lu) <= 1e-12 * np.linalg.norm(lam_lu)
+
+
+def test_gmres_route_raises_when_target_is_missed():
+    wl, inp = _medium(2, seed=2, n_spheres=1)
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    import scipy.sparse as sp
+    As = (A.astype(np.complex128) + 0.3j * sp.identity(wl.n)).tocsr()
+    b = wk.random_state(wl.n, 1).astype(np.complex128)
+    x, res = osv.shifted_solve(As, b, "gmres", rtol=1e-13)
+    assert res < 1e-12
+    with pytest.raises(RuntimeError, match="did not converge"):
+        osv.shifted_solve(As, b, "gmres", rtol=1e-30)
