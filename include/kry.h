@@ -35,7 +35,9 @@
  *
  * Errors.  Every int-returning function returns 0 on success or one of the
  * negative KRY_E* codes; kry_last_error() then describes the failure.
- * No C++ exception crosses this interface.
+ * No C++ exception crosses this interface: a host allocation failure
+ * inside the library returns KRY_ENOMEM, any other host exception
+ * KRY_EINVAL.
  */
 #ifndef KRY_H
 #define KRY_H
@@ -146,7 +148,11 @@ typedef struct {
   double kernel_flops[KRY_K_CLASSES];
 } kry_stats;
 
-/* Create a context for the grid and per-cell materials.
+/* Create a context for the grid and per-cell materials: the operator
+ * A = M^{-1} (S + K) of the semi-discrete Maxwell system (Section 2.1,
+ * equation (ode) and the block form of the operator after it: M holds the
+ * permittivity and permeability, S the conductivity, K the curl pair; here
+ * the 3D Yee curl with the same per-cell sigma on all six components).
  * eps, mu, sigma: device arrays of nx*ny*nz doubles (C order, x fastest).
  * mu may be NULL (mu = 1 everywhere), sigma may be NULL (sigma = 0).
  * eps > 0, mu > 0, sigma >= 0 and all finite, else KRY_EINVAL.
@@ -239,7 +245,8 @@ typedef struct {
 } kry_tune;
 
 /* Time the operator kernel the solver runs (the s-step basis stencil when
- * opts.s_step > 1, else the stencil fused with the first Gram-Schmidt
+ * opts.s_step > 1, which is the FP64 stencil on the FP64 work block under
+ * either storage type, else the stencil fused with the first Gram-Schmidt
  * dots), and the update and dot kernels of one one-step Arnoldi step with
  * `cnt` basis vectors (0: krylov_dim / 2), for every launch shape on this
  * context's grid and workspace; apply the fastest per kernel class, and

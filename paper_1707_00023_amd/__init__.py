@@ -77,9 +77,17 @@ class KryTune(ctypes.Structure):
 
 
 class KryError(RuntimeError):
-    def __init__(self, code, msg):
+    def __init__(self, code, msg, stats=None):
         super().__init__(f"{_CODES.get(code, code)}: {msg}")
         self.code = code
+        self.stats = stats
+
+
+class NotConverged(KryError):
+    """KRY_ENOCONV: a restart limit was reached.  The outputs of the call hold
+    the library's best estimate; ``stats`` holds its residual statistics.
+    Pass allow_noconv=True to a solver method to get the estimate back
+    instead of this exception."""
 
 
 _lib = None
@@ -213,10 +221,13 @@ class Solver:
         except Exception:
             pass
 
-    def _check(self, rc, allow_noconv=False):
+    def _check(self, rc, allow_noconv=False, stats=None):
         if rc == KRY_OK or (allow_noconv and rc == KRY_ENOCONV):
             return rc
-        raise KryError(rc, self._lib.kry_last_error(self._ctx).decode())
+        msg = self._lib.kry_last_error(self._ctx).decode()
+        if rc == KRY_ENOCONV:
+            raise NotConverged(rc, msg or "restart limit reached", stats)
+        raise KryError(rc, msg, stats)
 
     def _vecs(self, x, dtype):
         import torch
@@ -307,15 +318,15 @@ class Solver:
             self._check(rc)
         return V, H.T.copy(), rc
 
-    def expv(self, t: float, v):
+    def expv(self, t: float, v, allow_noconv: bool = False):
         """e^{-tA} v for each row of v."""
         import torch
         v = self._vecs(v, torch.float64)
         y = torch.empty_like(v)
         st = KryStats()
         rc = self._lib.kry_expv(self._ctx, float(t), _ptr(v), _ptr(y), v.shape[0], ctypes.byref(st))
-        self._check(rc, allow_noconv=True)
         self.last_stats = st.as_dict()
+        self._check(rc, allow_noconv, self.last_stats)
         return y
 
     def _omega_b(self, omegas, b, b_per_omega):
@@ -332,7 +343,8 @@ class Solver:
             nsrc = b.shape[0]
         return om, b, nw, nsrc
 
-    def stationary(self, omegas: Sequence[float], b, b_per_omega: bool = False):
+    def stationary(self, omegas: Sequence[float], b, b_per_omega: bool = False,
+                   allow_noconv: bool = False):
         """z = (A + i w I)^-1 b; returns complex128 (n_omega * n_src, n)."""
         import torch
         om, b, nw, nsrc = self._omega_b(omegas, b, b_per_omega)
@@ -340,11 +352,12 @@ class Solver:
         st = KryStats()
         rc = self._lib.kry_stationary(self._ctx, om.ctypes.data_as(ctypes.c_void_p), nw, nsrc,
                                       _ptr(b), int(bool(b_per_omega)), _ptr(z), ctypes.byref(st))
-        self._check(rc, allow_noconv=True)
         self.last_stats = st.as_dict()
+        self._check(rc, allow_noconv, self.last_stats)
         return z
 
-    def solve_multifreq(self, omegas: Sequence[float], b, T: float, b_per_omega: bool = False):
+    def solve_multifreq(self, omegas: Sequence[float], b, T: float, b_per_omega: bool = False,
+                        allow_noconv: bool = False):
         """y(T) for every (omega, source) column; float64 (n_omega * n_src, n)."""
         import torch
         om, b, nw, nsrc = self._omega_b(omegas, b, b_per_omega)
@@ -353,12 +366,12 @@ class Solver:
         rc = self._lib.kry_solve_multifreq(self._ctx, om.ctypes.data_as(ctypes.c_void_p), nw, nsrc,
                                            _ptr(b), int(bool(b_per_omega)), float(T), _ptr(y),
                                            ctypes.byref(st))
-        self._check(rc, allow_noconv=True)
         self.last_stats = st.as_dict()
+        self._check(rc, allow_noconv, self.last_stats)
         return y
 
     def grad(self, omegas: Sequence[float], b, plane_k: int, b_per_omega: bool = False,
-             loss_only: bool = False):
+             loss_only: bool = False, allow_noconv: bool = False):
         """(L, dL/d eps) of the period-averaged flux through plane z = plane_k.
 
         b: complex128 (1, n) shared source or (n_omega, n) per-omega sources.
@@ -375,8 +388,8 @@ class Solver:
         rc = self._lib.kry_grad(self._ctx, om.ctypes.data_as(ctypes.c_void_p), nw, _ptr(b),
                                 int(bool(b_per_omega)), int(plane_k), ctypes.byref(loss),
                                 None if g is None else _ptr(g), ctypes.byref(st))
-        self._check(rc, allow_noconv=True)
         self.last_stats = st.as_dict()
+        self._check(rc, allow_noconv, self.last_stats)
         return loss.value, g
 
 
@@ -388,9 +401,14 @@ def _flux_function():
 
         @staticmethod
         def forward(ctx, eps, sigma, b, omegas, plane_k, opts, b_per_omega):
+            # the forward and adjoint solves must both converge: an
+            # unconverged adjoint would hand autograd a wrong gradient, so
+            # KRY_ENOCONV raises NotConverged here
             solver = Solver(eps.detach(), None, sigma, opts)
-            L, g = solver.grad(omegas, b, plane_k, b_per_omega)
-            solver.close()
+            try:
+                L, g = solver.grad(omegas, b, plane_k, b_per_omega)
+            finally:
+                solver.close()
             ctx.save_for_backward(g)
             return torch.tensor(L, dtype=torch.float64, device=eps.device)
 

@@ -726,9 +726,11 @@ bool finite_all(const std::vector<double>& a) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int kry_create(const kry_grid* grid, const double* eps, const double* mu, const double* sigma,
+void api_destroy(kry_ctx* c);
+
+int api_create(const kry_grid* grid, const double* eps, const double* mu, const double* sigma,
                const kry_opts* opts, kry_ctx** out) {
   kry_ctx* c = nullptr;
   if (!grid || !eps || !opts || !out) return fail(nullptr, KRY_EINVAL, "null argument");
@@ -806,7 +808,7 @@ int kry_create(const kry_grid* grid, const double* eps, const double* mu, const 
   if (hipMemcpy(c->d_mat, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMalloc(&c->d_scal, sizeof(double) * 4) != hipSuccess ||
       hipHostMalloc(&c->h_scal, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess) {
-    kry_destroy(c);
+    api_destroy(c);
     return fail(nullptr, KRY_EHIP, "device setup failed");
   }
   c->mats.inv_eps = c->d_mat;
@@ -818,7 +820,7 @@ int kry_create(const kry_grid* grid, const double* eps, const double* mu, const 
   return KRY_OK;
 }
 
-void kry_destroy(kry_ctx* c) {
+void api_destroy(kry_ctx* c) {
   if (!c) return;
   hipFree(c->d_mat);
   hipFree(c->V);
@@ -846,11 +848,11 @@ void kry_destroy(kry_ctx* c) {
   delete c;
 }
 
-const char* kry_last_error(const kry_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+const char* api_last_error(const kry_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
-int64_t kry_size(const kry_ctx* c) { return c ? c->n : 0; }
+int64_t api_size(const kry_ctx* c) { return c ? c->n : 0; }
 
-int kry_apply(kry_ctx* c, const double* v, double* w, int32_t ncols) {
+int api_apply(kry_ctx* c, const double* v, double* w, int32_t ncols) {
   if (!c || !v || !w || ncols < 0) return fail(c, KRY_EINVAL, "invalid argument");
   for (int k = 0; k < ncols; ++k)
     KRY_HIP(kry::launch_stencil(kry::F64, v + (size_t)k * c->n, w + (size_t)k * c->n, nullptr, 0, 0,
@@ -858,7 +860,7 @@ int kry_apply(kry_ctx* c, const double* v, double* w, int32_t ncols) {
   return KRY_OK;
 }
 
-int kry_apply_f32(kry_ctx* c, const float* v, float* w, int32_t ncols) {
+int api_apply_f32(kry_ctx* c, const float* v, float* w, int32_t ncols) {
   if (!c || !v || !w || ncols < 0) return fail(c, KRY_EINVAL, "invalid argument");
   for (int k = 0; k < ncols; ++k)
     KRY_HIP(kry::launch_stencil(kry::F32, v + (size_t)k * c->n, w + (size_t)k * c->n, nullptr, 0, 0,
@@ -866,7 +868,7 @@ int kry_apply_f32(kry_ctx* c, const float* v, float* w, int32_t ncols) {
   return KRY_OK;
 }
 
-int kry_arnoldi(kry_ctx* c, const double* v, int32_t m, void* V_out, double* H_out, double* beta_out) {
+int api_arnoldi(kry_ctx* c, const double* v, int32_t m, void* V_out, double* H_out, double* beta_out) {
   if (!c || !v || !V_out || !H_out || !beta_out) return fail(c, KRY_EINVAL, "null argument");
   treset(c);
   if (m < 1 || m + 2 > kry::kMaxCoef) return fail(c, KRY_EINVAL, "invalid m");
@@ -886,7 +888,7 @@ int kry_arnoldi(kry_ctx* c, const double* v, int32_t m, void* V_out, double* H_o
   return me;
 }
 
-int kry_expv(kry_ctx* c, double t, const double* v, double* y, int32_t ncols, kry_stats* st) {
+int api_expv(kry_ctx* c, double t, const double* v, double* y, int32_t ncols, kry_stats* st) {
   if (!c || !v || !y || ncols < 0) return fail(c, KRY_EINVAL, "invalid argument");
   if (!(t >= 0.0) || !std::isfinite(t)) return fail(c, KRY_EINVAL, "invalid time");
   if (st) std::memset(st, 0, sizeof(*st));
@@ -921,7 +923,7 @@ int kry_expv(kry_ctx* c, double t, const double* v, double* y, int32_t ncols, kr
   return status;
 }
 
-}  // extern "C"
+}  // namespace
 
 namespace {
 
@@ -929,7 +931,7 @@ namespace {
 // data from b_col): z_k = (A + i w_k)^{-1} b for the listed shifts, stored
 // in Z columns 2*zcolk[k] (Re) and 2*zcolk[k]+1 (Im).
 int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, double tol_rel,
-                 double bn, kry_stats* st);
+                 double bn, kry_stats* st, double* max_res, bool correct);
 int cnorm(kry_ctx* c, const double* x, double* out);
 
 // spare >= 0: a free Z pair; once every shift reports convergence, its
@@ -1000,9 +1002,12 @@ int stationary_group(kry_ctx* c, const double* b_col, const std::vector<double>&
     rc = solve(std::vector<int>{k}, true);
     if (rc) return rc;
   }
-  if (spare >= 0 && status == KRY_OK) {  // shifts reported converged
+  if (spare >= 0) {
+    // every shift's true residual goes into the statistics; shifts of a
+    // group that reported convergence are corrected where it misses
+    const bool correct = status == KRY_OK;
     for (int k = 0; k < nw; ++k) {
-      rc = refine_shift(c, b_col, omegas[k], zcolk[k], spare, tol_rel, bnorm, st);
+      rc = refine_shift(c, b_col, omegas[k], zcolk[k], spare, tol_rel, bnorm, st, max_res, correct);
       if (rc == KRY_ENOCONV) status = rc;
       else if (rc) return rc;
     }
@@ -1010,10 +1015,21 @@ int stationary_group(kry_ctx* c, const double* b_col, const std::vector<double>&
   return status;
 }
 
-// r = b - (A + i w) z_k; where |r|_M > 2 tol_rel |b|_M, solve (A + i w) d = r
-// into the spare pair and add d to z_k.
+// True residual r = b - (A + i w) z_k, |r|_M / |b|_M folded into *max_res.
+// With `correct`, where |r|_M > 2 tol_rel |b|_M: solve (A + i w) d = r into
+// the spare pair, z_k += d, and take the true residual again (the statistics
+// then hold the residual of the returned z, never an estimate); KRY_ENOCONV
+// if it still misses 2 tol_rel.
+int true_residual(kry_ctx* c, const double* bcol, double w, int zk, kry_stats* st, double* rn) {
+  KRY_HIP(kry::launch_stencil_cols(c->st, zcol(c, 2 * zk), slot(c, 1), c->ldv, 2, c->g, c->mats, c->stream));
+  KRY_HIP(kry::launch_shift_residual(c->st, bcol, zcol(c, 2 * zk), zcol(c, 2 * zk + 1), slot(c, 1), slot(c, 2),
+                                     w, c->d_r, c->n, c->stream));
+  if (st) st->matvecs_stationary += 2;
+  return cnorm(c, c->d_r, rn);
+}
+
 int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, double tol_rel,
-                 double bn, kry_stats* st) {
+                 double bn, kry_stats* st, double* max_res, bool correct) {
   if (!c->d_r) {  // the residual vector (complex, n entries)
     if (hipMalloc(&c->d_r, sizeof(double) * 2 * c->n) != hipSuccess) {
       c->d_r = nullptr;
@@ -1021,14 +1037,14 @@ int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, do
       return fail(c, KRY_ENOMEM, "cannot allocate the residual vector");
     }
   }
-  KRY_HIP(kry::launch_stencil_cols(c->st, zcol(c, 2 * zk), slot(c, 1), c->ldv, 2, c->g, c->mats, c->stream));
-  KRY_HIP(kry::launch_shift_residual(c->st, bcol, zcol(c, 2 * zk), zcol(c, 2 * zk + 1), slot(c, 1), slot(c, 2),
-                                     w, c->d_r, c->n, c->stream));
-  if (st) st->matvecs_stationary += 2;
+  if (!(bn > 0.0)) return KRY_OK;
   double rn = 0.0;
-  int rc = cnorm(c, c->d_r, &rn);
+  int rc = true_residual(c, bcol, w, zk, st, &rn);
   if (rc) return rc;
-  if (!(rn > 2.0 * tol_rel * bn)) return KRY_OK;
+  if (!correct || !(rn > 2.0 * tol_rel * bn)) {
+    *max_res = std::max(*max_res, rn / bn);
+    return KRY_OK;
+  }
   if (c->opts.verbose)
     std::fprintf(stderr, "[kry] shift omega = %.6f: true relative residual %.3e, corrected\n", w, rn / bn);
   double lr = 0.0, rn2 = 0.0;
@@ -1040,7 +1056,13 @@ int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, do
   KRY_HIP(kry::launch_combine(c->st, zcol(c, 2 * spare), c->ldv, 2, c->d_Y, 2, zcol(c, 2 * zk), c->ldv, nullptr,
                               1, c->g, c->stream));
   KRY_HIP(hipStreamSynchronize(c->stream));
-  return status;
+  rc = true_residual(c, bcol, w, zk, st, &rn);
+  if (rc) return rc;
+  *max_res = std::max(*max_res, rn / bn);
+  if (c->opts.verbose)
+    std::fprintf(stderr, "[kry] shift omega = %.6f: true relative residual %.3e after the correction\n", w,
+                 rn / bn);
+  return rn > 2.0 * tol_rel * bn ? KRY_ENOCONV : KRY_OK;
 }
 
 // |x|_M for a complex interleaved FP64 device vector x (slot 0 as staging).
@@ -1211,7 +1233,10 @@ int for_each_group(kry_ctx* c, const double* omegas, int n_omega, int n_src, con
           double res = 0.0;
           rc = stationary_from(c, bcol, omegas[k], om_a, hist_a, tol_s, st, &res, &bn);
           *max_res = std::max(*max_res, res);
-          if (rc == KRY_OK) rc = refine_shift(c, bcol, omegas[k], 0, 1, tol_s, bn, st);
+          if (rc == KRY_OK || rc == KRY_ENOCONV) {
+            const int r2 = refine_shift(c, bcol, omegas[k], 0, 1, tol_s, bn, st, max_res, rc == KRY_OK);
+            if (r2 != KRY_OK) rc = r2;
+          }
         }
         if (rc == KRY_ENOCONV) status = rc;
         else if (rc) return rc;
@@ -1999,9 +2024,9 @@ int solve_blocked(kry_ctx* c, const double* omegas, int n_omega, int n_src, cons
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int kry_stationary(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src, const double* b,
+int api_stationary(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src, const double* b,
                    int32_t b_per_omega, double* z, kry_stats* st) {
   int rc = check_multifreq_args(c, omegas, n_omega, n_src, b);
   if (rc) return rc;
@@ -2058,7 +2083,7 @@ int kry_stationary(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_
   return rc;
 }
 
-int kry_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src,
+int api_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src,
                         const double* b, int32_t b_per_omega, double T, double* yT, kry_stats* st) {
   int rc = check_multifreq_args(c, omegas, n_omega, n_src, b);
   if (rc) return rc;
@@ -2142,11 +2167,11 @@ int kry_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
   return rc;
 }
 
-}  // extern "C"
+}  // namespace
 
-extern "C" {
+namespace {
 
-int kry_grad(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
+int api_grad(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
              int32_t b_per_omega, int32_t plane_k, double* loss, double* dL_deps, kry_stats* st) {
   int rc = check_multifreq_args(c, omegas, n_omega, 1, b);
   if (rc) return rc;
@@ -2254,11 +2279,11 @@ int kry_grad(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
   return status;
 }
 
-}  // extern "C"
+}  // namespace
 
-extern "C" {
+namespace {
 
-int kry_block_arnoldi(kry_ctx* c, const double* V0, int32_t p, int32_t mb, void* V_out,
+int api_block_arnoldi(kry_ctx* c, const double* V0, int32_t p, int32_t mb, void* V_out,
                       double* H_out) {
   if (!c || !V0 || !V_out || !H_out) return fail(c, KRY_EINVAL, "null argument");
   if (p < 1 || p > 128 || mb < 1 || (mb + 1) * p > 4096) return fail(c, KRY_EINVAL, "invalid p or mb");
@@ -2283,11 +2308,11 @@ int kry_block_arnoldi(kry_ctx* c, const double* V0, int32_t p, int32_t mb, void*
   return mbe;
 }
 
-}  // extern "C"
+}  // namespace
 
-extern "C" {
+namespace {
 
-int kry_set_tune(kry_ctx* c, const kry_tune* t) {
+int api_set_tune(kry_ctx* c, const kry_tune* t) {
   if (!c || !t) return fail(c, KRY_EINVAL, "null argument");
   auto ok = [](int v) { return v == 1 || v == 2 || v == 4; };
   if (!ok(t->cpt_stencil) || !ok(t->cpt_update) || !ok(t->cpt_dots))
@@ -2299,7 +2324,7 @@ int kry_set_tune(kry_ctx* c, const kry_tune* t) {
   return KRY_OK;
 }
 
-int kry_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {
+int api_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {
   if (!c || !out) return fail(c, KRY_EINVAL, "null argument");
   const int m = c->opts.krylov_dim;
   if (cnt <= 0) cnt = std::max(1, m / 2);
@@ -2318,6 +2343,19 @@ int kry_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {
   const kry::DevGrid saved = c->g;
   void* U = slot(c, c->mcap + 1);
   void* X = slot(c, c->mcap + 2);
+  // the s-step Arnoldi builds its basis blocks with the FP64 stencil on an
+  // FP64 work block under either storage type (FP32 storage with m > 112
+  // runs one step per sweep, in the storage type)
+  const bool ca_f64 = c->opts.s_step > 1 && !(c->st == kry::F32 && m > 112);
+  void *U64 = U, *P64 = slot(c, cnt), *X64 = X;
+  if (ca_f64 && c->st == kry::F32) {
+    rc = ensure_sblock(c, 3);
+    if (rc) return rc;
+    KRY_HIP(hipMemsetAsync(c->SB, 0, (size_t)3 * c->ldv * sizeof(double), c->stream));
+    U64 = c->SB;
+    P64 = c->SB + c->ldv;
+    X64 = c->SB + 2 * c->ldv;
+  }
   const int cpts[3] = {1, 2, 4};
   auto time_us = [&](auto&& launch) -> double {
     double best = 1e300;
@@ -2337,9 +2375,9 @@ int kry_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {
     // the operator kernel the solver runs: the s-step basis stencil, or the
     // stencil fused with the Gram-Schmidt dots of the one-step Arnoldi
     out->us_stencil[k] = time_us([&]() {
-      if (c->opts.s_step > 1)
-        return kry::launch_stencil_axpby(c->st, U, slot(c, cnt), X, 2.0 / c->rho, 0.0, 1.0, c->g,
-                                         c->mats, c->stream);
+      if (ca_f64)
+        return kry::launch_stencil_axpby(kry::F64, U64, P64, X64, 2.0 / c->rho, 0.0, 1.0, c->g, c->mats,
+                                         c->stream);
       return kry::launch_stencil_lag(c->st, U, X, c->V, c->ldv, cnt, c->g, c->mats, c->partials, c->stream);
     });
     out->us_update[k] = time_us([&]() {
@@ -2364,7 +2402,107 @@ int kry_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {
   out->cpt_dots = pick(out->us_dots);
   c->g = saved;
   KRY_HIP(hipStreamSynchronize(c->stream));
-  return kry_set_tune(c, out);
+  return api_set_tune(c, out);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Exported entry points.  Every body runs inside `guarded`, so no C++
+// exception (a host allocation failure in a std::vector, std::string or
+// std::map, or any other) crosses the C interface: it becomes KRY_ENOMEM or
+// KRY_EINVAL with a message in kry_last_error.
+namespace {
+
+void note(kry_ctx* c, const char* msg) noexcept {
+  try {
+    if (c) c->err = msg; else g_create_err = msg;
+  } catch (...) {
+  }
+}
+
+template <typename F>
+int guarded(kry_ctx* c, F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    note(c, "host allocation failed");
+    return KRY_ENOMEM;
+  } catch (const std::exception& e) {
+    note(c, e.what());
+    return KRY_EINVAL;
+  } catch (...) {
+    note(c, "unexpected host exception");
+    return KRY_EINVAL;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int kry_create(const kry_grid* grid, const double* eps, const double* mu, const double* sigma,
+               const kry_opts* opts, kry_ctx** out) {
+  return guarded(nullptr, [&] { return api_create(grid, eps, mu, sigma, opts, out); });
+}
+
+void kry_destroy(kry_ctx* c) {
+  try {
+    api_destroy(c);
+  } catch (...) {
+  }
+}
+
+const char* kry_last_error(const kry_ctx* c) { return api_last_error(c); }
+
+int64_t kry_size(const kry_ctx* c) { return api_size(c); }
+
+int kry_apply(kry_ctx* c, const double* v, double* w, int32_t ncols) {
+  return guarded(c, [&] { return api_apply(c, v, w, ncols); });
+}
+
+int kry_apply_f32(kry_ctx* c, const float* v, float* w, int32_t ncols) {
+  return guarded(c, [&] { return api_apply_f32(c, v, w, ncols); });
+}
+
+int kry_arnoldi(kry_ctx* c, const double* v, int32_t m, void* V_out, double* H_out, double* beta_out) {
+  return guarded(c, [&] { return api_arnoldi(c, v, m, V_out, H_out, beta_out); });
+}
+
+int kry_expv(kry_ctx* c, double t, const double* v, double* y, int32_t ncols, kry_stats* st) {
+  return guarded(c, [&] { return api_expv(c, t, v, y, ncols, st); });
+}
+
+int kry_stationary(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src, const double* b,
+                   int32_t b_per_omega, double* z, kry_stats* st) {
+  return guarded(c, [&] { return api_stationary(c, omegas, n_omega, n_src, b, b_per_omega, z, st); });
+}
+
+int kry_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src,
+                        const double* b, int32_t b_per_omega, double T, double* yT, kry_stats* st) {
+  return guarded(c, [&] {
+    return api_solve_multifreq(c, omegas, n_omega, n_src, b, b_per_omega, T, yT, st);
+  });
+}
+
+int kry_grad(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
+             int32_t b_per_omega, int32_t plane_k, double* loss, double* dL_deps, kry_stats* st) {
+  return guarded(c, [&] {
+    return api_grad(c, omegas, n_omega, b, b_per_omega, plane_k, loss, dL_deps, st);
+  });
+}
+
+int kry_block_arnoldi(kry_ctx* c, const double* V0, int32_t p, int32_t mb, void* V_out,
+                      double* H_out) {
+  return guarded(c, [&] { return api_block_arnoldi(c, V0, p, mb, V_out, H_out); });
+}
+
+int kry_set_tune(kry_ctx* c, const kry_tune* t) {
+  return guarded(c, [&] { return api_set_tune(c, t); });
+}
+
+int kry_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {
+  return guarded(c, [&] { return api_autotune(c, cnt, out); });
 }
 
 }  // extern "C"

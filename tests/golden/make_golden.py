@@ -9,6 +9,11 @@ shifted solve and does not use Corollary 3.
 
     python tests/golden/make_golden.py c2        # ~1 h on one CPU core
     python tests/golden/make_golden.py c3        # 4 of the 256 columns
+    python tests/golden/make_golden.py grad16    # 16^3 flux gradient, ~1 min
+
+grad16 stores the oracle's whole gradient vector dL/d eps (4096 cells) and
+the loss for GRAD16, a 16^3 medium with two frequencies: both shifted solves
+and both explicit-transpose adjoint solves by SuperLU (n = 24576).
 """
 from __future__ import annotations
 
@@ -31,6 +36,31 @@ N_PROJ = 4
 SAMPLE_SEED = 20170630
 # columns (omega index, theta index) evaluated for the batched workload
 SUBSETS = {"c3": [(0, 0), (15, 3), (31, 7), (16, 5)]}
+
+
+def grad16_workload():
+    """16^3, two frequencies, flux plane 12 (outside the 2-cell layer at
+    14..15), Ex source at k = 3, 24 random spheres; one shared source."""
+    return wk.small(16, seed=41, n_spheres=24, layer=2, radius=(1.0, 2.0),
+                    omegas=(2 * np.pi * 0.09, 2 * np.pi * 0.11), src_k=3,
+                    flux_plane=12, tol=1e-12, krylov_dim=40)
+
+
+def make_grad16():
+    from oracle import grad as og
+    wl = grad16_workload()
+    inp = wk.generate(wl)
+    b = wk.source_vector(wl, wl.omegas[0], 0.0)
+    b_cols = np.stack([b] * len(wl.omegas), axis=1)
+    t0 = time.time()
+    L, g = og.loss_and_grad(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, wl.flux_plane)
+    dt = time.time() - t0
+    out = {"workload": wl.name, "N": wl.N, "omegas": list(wl.omegas), "plane_k": wl.flux_plane,
+           "route": "SuperLU shifted and explicit-transpose adjoint solves",
+           "loss": float(L), "grad": g.reshape(-1).tolist(), "oracle_seconds": dt}
+    with open(os.path.join(HERE, "grad16_oracle.json"), "w") as f:
+        json.dump(out, f)
+    print(f"grad16 L={L:.12e} |g|={np.linalg.norm(g):.6e} {dt:.1f}s", flush=True)
 
 
 def sample_spec(n):
@@ -72,4 +102,7 @@ def main(cfg_name: str):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1])
+    if sys.argv[1] == "grad16":
+        make_grad16()
+    else:
+        main(sys.argv[1])
