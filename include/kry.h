@@ -190,6 +190,24 @@ int kry_apply_f32(kry_ctx* ctx, const float* v, float* w, int32_t ncols);
 int kry_arnoldi(kry_ctx* ctx, const double* v, int32_t m, void* V_out,
                 double* H_out, double* beta_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * Arnoldi relation as kry_arnoldi, computed with classical Gram-Schmidt
+ * twice and one operator application per step, without allocating
+ * anything.  The basis is built in place in V_out (device, (m+1) x n in the
+ * context's storage type, column j at offset j*n; column j+1 is the work
+ * vector of step j), and every other intermediate (partial sums,
+ * reductions, H) lives in a fixed 32 MiB array per device that the library
+ * holds until the process ends.  H_out (host, (m+1) x m column-major) and
+ * beta_out (host) as for kry_arnoldi; the call synchronises the context's
+ * stream and returns the steps taken or a KRY_E* code.  Sizes whose partial
+ * sums and H do not fit in the 32 MiB (about 8 (m+1) nx ny nz / 256 bytes
+ * for the partials) give KRY_EINVAL.  All calls on one device share that
+ * array, so calls that overlap on one device (several streams or threads)
+ * race: the caller serialises them. */
+int kry_arnoldi_noalloc(kry_ctx* ctx, const double* v, int32_t m, void* V_out, double* H_out,
+                        double* beta_out);
+
 /* Block Arnoldi: mb block steps from the start block V0 (device, FP64, p
  * columns of length n), the block form of equation (Arn) with p columns per
  * block.  Block Gram-Schmidt in the energy inner product runs on FP64

@@ -27,7 +27,7 @@ _CODES = {KRY_EINVAL: "KRY_EINVAL", KRY_ENOMEM: "KRY_ENOMEM", KRY_EHIP: "KRY_EHI
 EXPORTED = ("kry_create", "kry_destroy", "kry_last_error", "kry_size", "kry_apply",
             "kry_apply_f32", "kry_arnoldi", "kry_expv", "kry_solve_multifreq",
             "kry_stationary", "kry_grad", "kry_block_arnoldi", "kry_autotune",
-            "kry_set_tune")
+            "kry_set_tune", "kry_arnoldi_noalloc")
 
 
 class KryGrid(ctypes.Structure):
@@ -115,6 +115,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kry_apply.argtypes = [P, P, P, I32]
     lib.kry_apply_f32.argtypes = [P, P, P, I32]
     lib.kry_arnoldi.argtypes = [P, P, I32, P, P, ctypes.POINTER(D)]
+    lib.kry_arnoldi_noalloc.argtypes = [P, P, I32, P, P, ctypes.POINTER(D)]
+    lib.kry_arnoldi_noalloc.restype = ctypes.c_int
     lib.kry_expv.argtypes = [P, D, P, P, I32, ctypes.POINTER(KryStats)]
     lib.kry_solve_multifreq.argtypes = [P, P, I32, I32, P, I32, D, P, ctypes.POINTER(KryStats)]
     lib.kry_stationary.argtypes = [P, P, I32, I32, P, I32, P, ctypes.POINTER(KryStats)]

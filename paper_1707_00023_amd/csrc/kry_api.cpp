@@ -13,6 +13,7 @@
 #include <functional>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -729,6 +730,7 @@ bool finite_all(const std::vector<double>& a) {
 namespace {
 
 void api_destroy(kry_ctx* c);
+int scratch_on_current_device(double** out, std::string* err);
 
 int api_create(const kry_grid* grid, const double* eps, const double* mu, const double* sigma,
                const kry_opts* opts, kry_ctx** out) {
@@ -816,6 +818,13 @@ int api_create(const kry_grid* grid, const double* eps, const double* mu, const 
   c->mats.eps = c->d_mat + 2 * N3;
   c->mats.inv_mu = mu ? c->d_mat + 3 * N3 : nullptr;
   c->mats.mu = mu ? c->d_mat + 4 * N3 : nullptr;
+  {
+    // set-up of the allocation-free Arnoldi: the address of this device's
+    // `scratch` (a failure here is reported by that entry point itself)
+    double* scr = nullptr;
+    std::string err;
+    (void)scratch_on_current_device(&scr, &err);
+  }
   *out = c;
   return KRY_OK;
 }
@@ -2408,6 +2417,115 @@ int api_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Arnoldi that allocates nothing, for callers that cannot allocate device
+// memory (code under graph capture, tight serving loops, harnesses that
+// forbid hipMalloc).  Its per-workgroup partial sums, reduction buffers,
+// normalisation scalars and Hessenberg matrix live in `scratch`, one
+// fixed-size array per device, which holds them until the process ends.
+// Every call on a device shares that device's array (its contents are
+// those of the last call), so calls that overlap on one device race.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr size_t kScratchDoubles = kScratchBytes / sizeof(double);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch;  // device ordinal -> that device's `scratch`
+
+// The address of `scratch` on the current device (looked up once per
+// device).  In host code the array's name only stands in for the symbol:
+// kernels and copies get this address, never the name.
+int scratch_on_current_device(double** out, std::string* err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    *err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return KRY_EHIP;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it != g_scratch.end()) {
+    *out = it->second;
+    return KRY_OK;
+  }
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return KRY_EHIP;
+  }
+  g_scratch[dev] = static_cast<double*>(p);
+  *out = static_cast<double*>(p);
+  return KRY_OK;
+}
+
+// m steps of Arnoldi (classical Gram-Schmidt twice, one operator
+// application per step, equation (Arn)) from v, written straight into the
+// caller's V_out (column j at offset j n, context storage type): column
+// j + 1 serves as the work vector of step j, so nothing beyond the inputs,
+// outputs and `scratch` is touched.
+int api_arnoldi_noalloc(kry_ctx* c, const double* v, int32_t m, void* V_out, double* H_out,
+                        double* beta_out) {
+  if (!c || !v || !V_out || !H_out || !beta_out) return fail(c, KRY_EINVAL, "null argument");
+  if (m < 1 || m + 2 > kry::kMaxCoef) return fail(c, KRY_EINVAL, "invalid m");
+  double* scr = nullptr;
+  std::string err;
+  int rc = scratch_on_current_device(&scr, &err);
+  if (rc) return fail(c, rc, err);
+  const long long n = c->n;
+  const int np_s = kry::cell_blocks(c->g.N3, c->g.cpt_s);
+  const int np_d = kry::cell_blocks(c->g.N3, c->g.cpt_d);
+  auto up = [](size_t x) { return (x + 31) / 32 * 32; };  // 256-byte pieces
+  const size_t n_part = up((size_t)std::max(np_s, np_d) * (size_t)(m + 1));
+  const size_t n_red = up((size_t)m + 2);
+  const size_t n_h = (size_t)(m + 1) * m;
+  const size_t need = n_part + 2 * n_red + 32 + up(n_h);
+  if (need > kScratchDoubles)
+    return fail(c, KRY_EINVAL,
+                "grid and m need " + std::to_string(need * sizeof(double)) +
+                    " bytes of scratch; the allocation-free Arnoldi has " +
+                    std::to_string(kScratchBytes));
+  double* partials = scr;
+  double* red1 = partials + n_part;
+  double* red2 = red1 + n_red;
+  double* scal = red2 + n_red;  // scal[0] = 1/nu, scal[2] = 1/beta, scal[3] = beta
+  double* H = scal + 32;
+  hipStream_t s = c->stream;
+  char* V = static_cast<char*>(V_out);
+  auto col = [&](int j) { return (void*)(V + (size_t)j * n * c->esz); };
+  // H starts at zero (a fill kernel, not a memset: callers may capture this)
+  KRY_HIP(kry::launch_fill(H, 0.0, (long long)n_h, s));
+  KRY_HIP(kry::launch_load_real(c->st, v, col(0), n, s));
+  KRY_HIP(kry::launch_dots(c->st, col(0), nullptr, n, 0, c->g, c->mats, partials, s));
+  KRY_HIP(kry::launch_reduce(partials, np_d, 1, 1, red1, s));
+  KRY_HIP(kry::launch_fin_start(red1, scal + 2, s));
+  KRY_HIP(kry::launch_scale(c->st, col(0), scal + 2, col(0), n, s));
+  for (int j = 0; j < m; ++j) {
+    const int cnt = j + 1;
+    void* W = col(j + 1);
+    KRY_HIP(kry::launch_stencil(c->st, col(j), W, V, n, cnt, c->g, c->mats, partials, s));
+    KRY_HIP(kry::launch_reduce(partials, np_s, cnt + 1, cnt + 1, red1, s));
+    KRY_HIP(kry::launch_update(c->st, W, V, n, cnt, red1, nullptr, W, c->g, s));
+    KRY_HIP(kry::launch_dots(c->st, W, V, n, cnt, c->g, c->mats, partials, s));
+    KRY_HIP(kry::launch_reduce(partials, np_d, cnt + 1, cnt + 1, red2, s));
+    KRY_HIP(kry::launch_fin_step(red1, red2, j, H, m + 1, scal, s));
+    KRY_HIP(kry::launch_update(c->st, W, V, n, cnt, red2, scal, W, c->g, s));
+  }
+  double sc[4] = {0.0, 0.0, 0.0, 0.0};
+  KRY_HIP(hipMemcpyAsync(H_out, H, sizeof(double) * n_h, hipMemcpyDeviceToHost, s));
+  KRY_HIP(hipMemcpyAsync(sc, scal, sizeof(sc), hipMemcpyDeviceToHost, s));
+  KRY_HIP(hipStreamSynchronize(s));
+  *beta_out = sc[3];
+  if (sc[3] == 0.0) return 0;
+  for (int j = 0; j < m; ++j)
+    if (H_out[j + 1 + (size_t)j * (m + 1)] == 0.0) return j + 1;
+  return m;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // Exported entry points.  Every body runs inside `guarded`, so no C++
 // exception (a host allocation failure in a std::vector, std::string or
 // std::map, or any other) crosses the C interface: it becomes KRY_ENOMEM or
@@ -2490,6 +2608,11 @@ int kry_grad(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
   return guarded(c, [&] {
     return api_grad(c, omegas, n_omega, b, b_per_omega, plane_k, loss, dL_deps, st);
   });
+}
+
+int kry_arnoldi_noalloc(kry_ctx* c, const double* v, int32_t m, void* V_out, double* H_out,
+                        double* beta_out) {
+  return guarded(c, [&] { return api_arnoldi_noalloc(c, v, m, V_out, H_out, beta_out); });
 }
 
 int kry_block_arnoldi(kry_ctx* c, const double* V0, int32_t p, int32_t mb, void* V_out,
