@@ -113,6 +113,14 @@ typedef struct {
                            extrapolation, in omega, of the same source's
                            solutions at up to three earlier frequencies of
                            the call, and only the correction is solved    */
+  int32_t transient_continuation; /* 1: the transient of each column after
+                           the first of a source is continued from the
+                           previous column of that source (equation
+                           (4diff), steps 4-6 of Fig. alg:spl1):
+                           y_hat_next(T) = y_hat(T) + e^{-TA} (Im z_next -
+                           Im z), each column's accumulated error estimate
+                           kept within its own budget (a column starts a
+                           new chain otherwise)                           */
 } kry_opts;
 
 /* Kernel classes reported by the per-kernel timing. */
@@ -244,6 +252,27 @@ int kry_expv(kry_ctx* ctx, double t, const double* v, double* y,
 int kry_solve_multifreq(kry_ctx* ctx, const double* omegas, int32_t n_omega,
                         int32_t n_src, const double* b, int32_t b_per_omega,
                         double T, double* yT, kry_stats* stats);
+
+/* y(T) of problem (1) for every (w, source) pair by the residual-restarted
+ * Krylov method for the inhomogeneous problem (Section 3, restarting in
+ * Krylov dimension: equation (rst), Corollary 2 and the algorithm of
+ * Fig. alg:rst, regular Krylov variant), with no shifted solve: each real
+ * source part (Re b driven by sin(w t), Im b by cos(w t)) gets one sequence
+ * of krylov_dim-step Arnoldi bases, shared by every w that drives it (the
+ * bases do not depend on the time function, Corollary 2); per w the
+ * projected problem (equation (corr2)) is solved on [0, T] with its source
+ * sampled on a fine time grid, y(T) += V_m u(T), and the next restart
+ * starts from v_{m+1} with the sampled residual function
+ * -h_{m+1,m} e_m^T u(t) as its source (Lemma 1).  A w stops once the
+ * integral over [0, T] of its residual norm, which bounds the energy-norm
+ * error of y(T), is below tol/2 |y(T)|_M.  Arguments as for
+ * kry_solve_multifreq; stats: matvecs_transient and steps_transient count
+ * the operator applications and restarts, max_err_estimate the largest
+ * residual integral relative to |y(T)|_M.  KRY_ENOCONV after max_restarts
+ * restarts (outputs hold the current approximation). */
+int kry_solve_restarted(kry_ctx* ctx, const double* omegas, int32_t n_omega, int32_t n_src,
+                        const double* b, int32_t b_per_omega, double T, double* yT,
+                        kry_stats* stats);
 
 /* Time-harmonic fields only: z_w = (A + i w I)^{-1} b for every column, the
  * vector z_stat of Corollary 3.  Same argument conventions as

@@ -27,7 +27,7 @@ _CODES = {KRY_EINVAL: "KRY_EINVAL", KRY_ENOMEM: "KRY_ENOMEM", KRY_EHIP: "KRY_EHI
 EXPORTED = ("kry_create", "kry_destroy", "kry_last_error", "kry_size", "kry_apply",
             "kry_apply_f32", "kry_arnoldi", "kry_expv", "kry_solve_multifreq",
             "kry_stationary", "kry_grad", "kry_block_arnoldi", "kry_autotune",
-            "kry_set_tune", "kry_arnoldi_noalloc")
+            "kry_set_tune", "kry_arnoldi_noalloc", "kry_solve_restarted")
 
 
 class KryGrid(ctypes.Structure):
@@ -43,7 +43,7 @@ class KryOpts(ctypes.Structure):
                 ("timing", ctypes.c_int32), ("block_steps", ctypes.c_int32),
                 ("block_steps_transient", ctypes.c_int32), ("verbose", ctypes.c_int32),
                 ("orth", ctypes.c_int32), ("s_step", ctypes.c_int32),
-                ("omega_continuation", ctypes.c_int32)]
+                ("omega_continuation", ctypes.c_int32), ("transient_continuation", ctypes.c_int32)]
 
 
 class KryStats(ctypes.Structure):
@@ -120,6 +120,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kry_expv.argtypes = [P, D, P, P, I32, ctypes.POINTER(KryStats)]
     lib.kry_solve_multifreq.argtypes = [P, P, I32, I32, P, I32, D, P, ctypes.POINTER(KryStats)]
     lib.kry_stationary.argtypes = [P, P, I32, I32, P, I32, P, ctypes.POINTER(KryStats)]
+    lib.kry_solve_restarted.argtypes = [P, P, I32, I32, P, I32, D, P, ctypes.POINTER(KryStats)]
     lib.kry_grad.argtypes = [P, P, I32, P, I32, I32, ctypes.POINTER(D), P,
                              ctypes.POINTER(KryStats)]
     lib.kry_block_arnoldi.argtypes = [P, P, I32, I32, P, P]
@@ -129,7 +130,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kry_set_tune.argtypes = [P, ctypes.POINTER(KryTune)]
     lib.kry_set_tune.restype = ctypes.c_int
     for name in ("kry_apply", "kry_apply_f32", "kry_arnoldi", "kry_expv",
-                 "kry_solve_multifreq", "kry_stationary", "kry_grad"):
+                 "kry_solve_multifreq", "kry_stationary", "kry_grad", "kry_solve_restarted"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -163,6 +164,9 @@ class Options:
     # per-frequency sources: start each shifted solve from the extrapolation
     # of the same source's solutions at earlier frequencies of the call
     omega_continuation: bool = False
+    # continue each column's transient from the previous column of the same
+    # source: e^{-TA} is applied to the difference of the two Im z only
+    transient_continuation: bool = False
 
 
 class Solver:
@@ -197,7 +201,8 @@ class Solver:
                             opts.block_steps_transient, int(bool(opts.verbose)),
                             1 if opts.orth == "cgs2" else 0,
                             int(opts.s_step if opts.s_step is not None else DEFAULT_S_STEP),
-                            int(bool(opts.omega_continuation)))
+                            int(bool(opts.omega_continuation)),
+                            int(bool(opts.transient_continuation)))
         self.storage = opts.storage
         ctx = ctypes.c_void_p()
         rc = lib.kry_create(ctypes.byref(self.grid), _ptr(e),
@@ -366,6 +371,21 @@ class Solver:
         y = torch.empty((nw * nsrc, self.n), dtype=torch.float64, device=self.device)
         st = KryStats()
         rc = self._lib.kry_solve_multifreq(self._ctx, om.ctypes.data_as(ctypes.c_void_p), nw, nsrc,
+                                           _ptr(b), int(bool(b_per_omega)), float(T), _ptr(y),
+                                           ctypes.byref(st))
+        self.last_stats = st.as_dict()
+        self._check(rc, allow_noconv, self.last_stats)
+        return y
+
+    def solve_restarted(self, omegas: Sequence[float], b, T: float, b_per_omega: bool = False,
+                        allow_noconv: bool = False):
+        """y(T) for every (omega, source) column by the residual-restarted
+        Krylov method (no shifted solve); same conventions as solve_multifreq."""
+        import torch
+        om, b, nw, nsrc = self._omega_b(omegas, b, b_per_omega)
+        y = torch.empty((nw * nsrc, self.n), dtype=torch.float64, device=self.device)
+        st = KryStats()
+        rc = self._lib.kry_solve_restarted(self._ctx, om.ctypes.data_as(ctypes.c_void_p), nw, nsrc,
                                            _ptr(b), int(bool(b_per_omega)), float(T), _ptr(y),
                                            ctypes.byref(st))
         self.last_stats = st.as_dict()

@@ -16,6 +16,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kry_dense.h"
@@ -67,6 +68,10 @@ struct kry_ctx {
   // the residual of an extrapolated start (complex interleaved FP64)
   void* Zh = nullptr;
   int zh_cap = 0;
+  // transient continuation: per source, Im z of the chain's last column and
+  // its y_hat(T) (2 vectors each, storage type)
+  void* TC = nullptr;
+  int tc_cap = 0;
   // FP64 work block of the s-step Arnoldi under FP32 storage
   double* SB = nullptr;
   int sb_cap = 0;
@@ -843,6 +848,7 @@ void api_destroy(kry_ctx* c) {
   hipFree(c->d_colmap);
   hipFree(c->Z);
   hipFree(c->Zh);
+  hipFree(c->TC);
   hipFree(c->d_r);
   hipFree(c->SB);
   drop_graphs(c);
@@ -1025,16 +1031,36 @@ int stationary_group(kry_ctx* c, const double* b_col, const std::vector<double>&
 }
 
 // True residual r = b - (A + i w) z_k, |r|_M / |b|_M folded into *max_res.
-// With `correct`, where |r|_M > 2 tol_rel |b|_M: solve (A + i w) d = r into
-// the spare pair, z_k += d, and take the true residual again (the statistics
-// then hold the residual of the returned z, never an estimate); KRY_ENOCONV
-// if it still misses 2 tol_rel.
-int true_residual(kry_ctx* c, const double* bcol, double w, int zk, kry_stats* st, double* rn) {
+// With `correct`, where |r|_M misses the acceptance level: solve
+// (A + i w) d = r into the spare pair, z_k += d, and take the true residual
+// again (the statistics then hold the residual of the returned z, never an
+// estimate); KRY_ENOCONV if it still misses.  The acceptance level is
+// 2 tol_rel |b|_M, but never below what the storage type can represent:
+// rounding z (and A z) to the storage precision u alone moves the residual
+// by up to u (|A z|_M + w |z|_M), so the level is at least 8 times that
+// (it matters for FP32 storage at tight tolerances).
+// *floor receives that rounding level.
+int true_residual(kry_ctx* c, const double* bcol, double w, int zk, kry_stats* st, double* rn,
+                  double* floor) {
   KRY_HIP(kry::launch_stencil_cols(c->st, zcol(c, 2 * zk), slot(c, 1), c->ldv, 2, c->g, c->mats, c->stream));
   KRY_HIP(kry::launch_shift_residual(c->st, bcol, zcol(c, 2 * zk), zcol(c, 2 * zk + 1), slot(c, 1), slot(c, 2),
                                      w, c->d_r, c->n, c->stream));
   if (st) st->matvecs_stationary += 2;
-  return cnorm(c, c->d_r, rn);
+  int rc = cnorm(c, c->d_r, rn);
+  if (rc) return rc;
+  double az2 = 0.0, z2 = 0.0;
+  std::vector<double> d;
+  for (int part = 0; part < 2; ++part) {
+    rc = host_dots(c, slot(c, 1 + part), nullptr, 0, d);
+    if (rc) return rc;
+    az2 += d[0];
+    rc = host_dots(c, zcol(c, 2 * zk + part), nullptr, 0, d);
+    if (rc) return rc;
+    z2 += d[0];
+  }
+  const double u = c->st == kry::F32 ? 0x1p-24 : 0x1p-53;
+  *floor = u * (std::sqrt(std::max(az2, 0.0)) + w * std::sqrt(std::max(z2, 0.0)));
+  return KRY_OK;
 }
 
 int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, double tol_rel,
@@ -1047,10 +1073,11 @@ int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, do
     }
   }
   if (!(bn > 0.0)) return KRY_OK;
-  double rn = 0.0;
-  int rc = true_residual(c, bcol, w, zk, st, &rn);
+  double rn = 0.0, fl = 0.0;
+  int rc = true_residual(c, bcol, w, zk, st, &rn, &fl);
   if (rc) return rc;
-  if (!correct || !(rn > 2.0 * tol_rel * bn)) {
+  const double accept = std::max(2.0 * tol_rel * bn, 8.0 * fl);
+  if (!correct || !(rn > accept)) {
     *max_res = std::max(*max_res, rn / bn);
     return KRY_OK;
   }
@@ -1065,13 +1092,13 @@ int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, do
   KRY_HIP(kry::launch_combine(c->st, zcol(c, 2 * spare), c->ldv, 2, c->d_Y, 2, zcol(c, 2 * zk), c->ldv, nullptr,
                               1, c->g, c->stream));
   KRY_HIP(hipStreamSynchronize(c->stream));
-  rc = true_residual(c, bcol, w, zk, st, &rn);
+  rc = true_residual(c, bcol, w, zk, st, &rn, &fl);
   if (rc) return rc;
   *max_res = std::max(*max_res, rn / bn);
   if (c->opts.verbose)
     std::fprintf(stderr, "[kry] shift omega = %.6f: true relative residual %.3e after the correction\n", w,
                  rn / bn);
-  return rn > 2.0 * tol_rel * bn ? KRY_ENOCONV : KRY_OK;
+  return rn > std::max(2.0 * tol_rel * bn, 8.0 * fl) ? KRY_ENOCONV : KRY_OK;
 }
 
 // |x|_M for a complex interleaved FP64 device vector x (slot 0 as staging).
@@ -2124,6 +2151,24 @@ int api_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
     }
     return rc;
   }
+  // transient continuation (equation (4diff)): per source, a chain whose
+  // last column left Im z and y_hat(T) in TC and an accumulated error
+  // estimate acc (absolute, energy norm)
+  const bool tcont = c->opts.transient_continuation != 0 && T > 0.0;
+  std::vector<double> chain_acc(n_src, -1.0);  // < 0: no chain yet
+  if (tcont && (!c->TC || c->tc_cap < 2 * n_src)) {
+    hipFree(c->TC);
+    c->TC = nullptr;
+    c->tc_cap = 0;
+    const size_t bytes = (size_t)2 * n_src * c->ldv * c->esz;
+    if (hipMalloc(&c->TC, bytes) != hipSuccess) {
+      c->TC = nullptr;
+      (void)hipGetLastError();
+      return fail(c, KRY_ENOMEM, "cannot allocate transient continuation workspace");
+    }
+    c->tc_cap = 2 * n_src;
+  }
+  auto tcv = [&](int i) { return (void*)((char*)c->TC + (size_t)i * c->ldv * c->esz); };
   rc = for_each_group(
       c, omegas, n_omega, n_src, b, b_per_omega, 0.05 * tol, st, &max_res,
       [&](int col, double w, int zk, double bnorm) -> int {
@@ -2132,8 +2177,10 @@ int api_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
         void* zre = zcol(c, 2 * zk);
         void* zim = zcol(c, 2 * zk + 1);
         double* out = yT + (size_t)col * c->n;
+        const int src = col % n_src;
         if (bnorm == 0.0) {
           KRY_HIP(hipMemsetAsync(out, 0, sizeof(double) * c->n, c->stream));
+          if (tcont) chain_acc[src] = -1.0;
           return KRY_OK;
         }
         // |Im(e^{iwT} z)|_M from <re,re>, <re,im>, <im,im>
@@ -2147,14 +2194,40 @@ int api_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
         const double yt2 = sn * sn * nre + cs * cs * nim + 2.0 * sn * cs * xri;
         const double ynorm = std::sqrt(std::max(yt2, 0.0));
         const double scale = std::max(ynorm, 1e-300);
-        // transient: y_hat(0) = Im z
-        KRY_HIP(hipMemcpyAsync(slot(c, 0), zim, c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
         double err = 0.0;
         int status = KRY_OK;
-        if (T > 0.0) {
-          r = expv_slot0(c, T, 0.15 * tol * scale, 0.15 * tol * scale, st, &err);
+        const double budget = 0.3 * tol * scale;  // steps + dropped remainder
+        if (tcont && chain_acc[src] >= 0.0 && budget - chain_acc[src] >= 0.25 * budget) {
+          // w(0) = Im z - Im z_prev, y_hat(T) = y_hat_prev(T) + e^{-TA} w(0)
+          const double room = budget - chain_acc[src];
+          const double Ym[2] = {-1.0, 1.0};
+          KRY_HIP(hipMemcpyAsync(slot(c, 0), zim, c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
+          KRY_HIP(hipMemcpyAsync(c->d_Y, Ym, sizeof(Ym), hipMemcpyHostToDevice, c->stream));
+          KRY_HIP(kry::launch_combine(c->st, tcv(2 * src), c->ldv, 1, c->d_Y, 1, slot(c, 0), c->ldv, nullptr, 1,
+                                      c->g, c->stream));
+          r = expv_slot0(c, T, 0.25 * room, 0.25 * room, st, &err);
           if (r == KRY_ENOCONV) status = r;
           else if (r) return r;
+          // (the exponential used d_Y for its own coefficients: upload +1 again)
+          KRY_HIP(hipMemcpyAsync(c->d_Y, Ym + 1, sizeof(double), hipMemcpyHostToDevice, c->stream));
+          KRY_HIP(kry::launch_combine(c->st, tcv(2 * src + 1), c->ldv, 1, c->d_Y, 1, slot(c, 0), c->ldv,
+                                      nullptr, 1, c->g, c->stream));
+          err += chain_acc[src];
+        } else {
+          // transient: y_hat(0) = Im z (a new chain when continuing)
+          KRY_HIP(hipMemcpyAsync(slot(c, 0), zim, c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
+          if (T > 0.0) {
+            const double part = tcont ? 0.25 * budget : 0.5 * budget;
+            r = expv_slot0(c, T, part, part, st, &err);
+            if (r == KRY_ENOCONV) status = r;
+            else if (r) return r;
+          }
+        }
+        if (tcont) {  // this column closes the chain: keep Im z and y_hat(T)
+          chain_acc[src] = err;
+          KRY_HIP(hipMemcpyAsync(tcv(2 * src), zim, c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
+          KRY_HIP(hipMemcpyAsync(tcv(2 * src + 1), slot(c, 0), c->ldv * c->esz, hipMemcpyDeviceToDevice,
+                                 c->stream));
         }
         max_err = std::max(max_err, err / scale);
         KRY_HIP(kry::launch_assemble(c->st, zre, zim, slot(c, 0), sn, cs, out, c->n, c->stream));
@@ -2417,6 +2490,236 @@ int api_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Residual-restarted Krylov method for the inhomogeneous problem (Section 3,
+// restarting in Krylov dimension: equation (rst), Corollary 2 and the
+// algorithm of Fig. alg:rst, regular Krylov variant).  For a real source
+// vector g driven by a time function alpha(t), m Arnoldi steps from g give
+// V_{m+1}, H; the projected problem u' = -H_m u + alpha(t) beta e_1 (equation
+// (corr2)) is solved on [0, T] for every time function that drives g; the
+// update y(T) += V_m u(T) follows (equation (upd1)); the residual is
+// alpha_hat(t) v_{m+1} with alpha_hat = -h_{m+1,m} e_m^T u(t) (Lemma 1), so
+// the next restart starts from g = v_{m+1} with the source alpha_hat, the
+// same vector for every time function (Corollary 2: the bases are shared by
+// all frequencies of one source).  Each alpha_hat is sampled and stored on
+// [0, T] (step (2b) of the algorithm) at the Gauss nodes of a uniform time
+// grid, fine enough that the polynomial through a step's nodes represents
+// it to rounding; a time function stops once the integral of its residual
+// norm over [0, T], which bounds the error of y(T) in the energy norm (A is
+// dissipative in it), is below its share of tol |y(T)|_M (step (2c)).
+// A complex source b contributes Im(e^{i w t} b) = sin(w t) Re b +
+// cos(w t) Im b: two real parts, each with its own sequence of bases.
+
+constexpr int kRstNodes = 8;  // Gauss nodes per time step of the sampled sources
+
+// Run fn(c) for c in [0, n) on up to `threads` host threads.
+template <typename F>
+void parallel_columns(int n, F&& fn) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nth = std::min(n, std::min(hw, 16));
+  if (nth <= 1) {
+    for (int k = 0; k < n; ++k) fn(k);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t)
+    pool.emplace_back([&, t]() {
+      for (int k = t; k < n; k += nth) fn(k);
+    });
+  for (auto& th : pool) th.join();
+}
+
+struct RstColumn {
+  int out;     // output column (Z column of the accumulated y(T))
+  double w;    // angular frequency
+  int phase;   // 0: sin(w t) (real part of b), 1: cos(w t) (imaginary part)
+  double share;  // fraction of the column's error budget given to this part
+  std::vector<double> fin, fout;  // samples of the current and the next source
+  bool active = true;
+  double resint = 0.0;
+};
+
+// One real source part in slot 0 (unnormalised) and the time functions that
+// drive it; y(T) accumulates into the Z columns of `cols`.
+int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const std::vector<double>& gx,
+             const std::vector<double>& gw, kry_stats* st, double* max_err) {
+  const int m = c->opts.krylov_dim;
+  const int q = kRstNodes;
+  const double dt = T / nt;
+  const int ldh = m + 1;
+  for (auto& cl : cols) {
+    cl.fin.resize((size_t)nt * q);
+    cl.fout.assign((size_t)nt * q, 0.0);
+    for (int j = 0; j < nt; ++j)
+      for (int i = 0; i < q; ++i) {
+        const double t = (j + gx[i]) * dt;
+        cl.fin[(size_t)j * q + i] = cl.phase == 0 ? std::sin(cl.w * t) : std::cos(cl.w * t);
+      }
+  }
+  const int maxcyc = c->opts.max_restarts > 0 ? c->opts.max_restarts : 100000;
+  int rc = ensure_y(c, m + 1, (int)cols.size());
+  if (rc) return rc;
+  kry::RstProp P;
+  std::vector<int> act, cmap;
+  std::vector<double> uT, Yh;
+  int status = KRY_ENOCONV;
+  for (int cyc = 0; cyc < maxcyc; ++cyc) {
+    double beta = 0.0;
+    int me = 0;
+    rc = arnoldi(c, m, &beta, &me);
+    if (rc) return rc;
+    if (st) { st->matvecs_transient += m; st->steps_transient += 1; }
+    if (me == 0) {  // the source vector vanished: nothing left
+      status = KRY_OK;
+      break;
+    }
+    const double hnext = me < m ? 0.0 : c->h_H[m + (size_t)(m - 1) * ldh];
+    kry::rst_prepare(me, c->h_H, ldh, q, dt, gx.data(), &P);
+    act.clear();
+    for (int k = 0; k < (int)cols.size(); ++k)
+      if (cols[k].active) act.push_back(k);
+    const int na = (int)act.size();
+    uT.assign((size_t)me * na, 0.0);
+    parallel_columns(na, [&](int a) {
+      RstColumn& cl = cols[act[a]];
+      const double* fi = cl.fin.data();
+      double* fo = cl.fout.data();
+      kry::rst_march(P, nt, 1, beta, hnext, gw.data(), &fi, &fo, &uT[(size_t)a * me], &cl.resint);
+    });
+    // y(T) += V_m u(T) for every active time function, one sweep of the basis
+    Yh.assign((size_t)me * na, 0.0);
+    cmap.assign(na, 0);
+    for (int a = 0; a < na; ++a) {
+      for (int i = 0; i < me; ++i) Yh[i + (size_t)a * me] = uT[(size_t)a * me + i];
+      cmap[a] = cols[act[a]].out;
+    }
+    KRY_HIP(hipMemcpyAsync(c->d_Y, Yh.data(), sizeof(double) * Yh.size(), hipMemcpyHostToDevice, c->stream));
+    KRY_HIP(hipMemcpyAsync(c->d_colmap, cmap.data(), sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
+    hipEvent_t e = tbeg(c);
+    KRY_HIP(kry::launch_combine(c->st, c->V, c->ldv, me, c->d_Y, na, c->Z, c->ldv, c->d_colmap, 1, c->g,
+                                c->stream));
+    tend(c, e, KRY_K_COMBINE, vbytes(c) * (me + 2.0 * na));
+    // residual integral against the column's share of tol |y(T)|_M
+    bool any = false;
+    for (int a = 0; a < na; ++a) {
+      RstColumn& cl = cols[act[a]];
+      std::vector<double> d;
+      rc = host_dots(c, zcol(c, cl.out), nullptr, 0, d);
+      if (rc) return rc;
+      const double yn = std::sqrt(std::max(d[0], 0.0));
+      const double rel = yn > 0.0 ? cl.resint / yn : (cl.resint > 0.0 ? INFINITY : 0.0);
+      if (cl.resint <= cl.share * c->opts.tol * yn || me < m) {
+        cl.active = false;
+        *max_err = std::max(*max_err, rel);
+      } else {
+        any = true;
+        cl.fin.swap(cl.fout);
+      }
+    }
+    if (c->opts.verbose && (cyc + 1) % 5 == 0)
+      std::fprintf(stderr, "[kry] restarted inhomogeneous Krylov: restart %d, %d time functions active\n",
+                   cyc + 1, (int)std::count_if(cols.begin(), cols.end(), [](const RstColumn& x) { return x.active; }));
+    if (!any) {
+      status = KRY_OK;
+      break;
+    }
+    // next start vector g = v_{m+1} (energy norm 1)
+    KRY_HIP(hipMemcpyAsync(slot(c, 0), slot(c, m), c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
+  }
+  if (status == KRY_ENOCONV) {
+    for (auto& cl : cols) {
+      if (!cl.active) continue;
+      std::vector<double> d;
+      rc = host_dots(c, zcol(c, cl.out), nullptr, 0, d);
+      if (rc) return rc;
+      const double yn = std::sqrt(std::max(d[0], 0.0));
+      *max_err = std::max(*max_err, yn > 0.0 ? cl.resint / yn : INFINITY);
+    }
+    fail(c, KRY_ENOCONV, "restart limit reached in the restarted inhomogeneous Krylov method");
+  }
+  return status;
+}
+
+int api_solve_restarted(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src, const double* b,
+                        int32_t b_per_omega, double T, double* yT, kry_stats* st) {
+  int rc = check_multifreq_args(c, omegas, n_omega, n_src, b);
+  if (rc) return rc;
+  if (!yT) return fail(c, KRY_EINVAL, "null output");
+  if (!(T >= 0.0) || !std::isfinite(T)) return fail(c, KRY_EINVAL, "invalid T");
+  if (st) std::memset(st, 0, sizeof(*st));
+  treset(c);
+  const double t0 = now_ms();
+  const int m = c->opts.krylov_dim;
+  rc = ensure_basis(c, m);
+  if (rc) return rc;
+  const int ncols = n_omega * n_src;
+  rc = ensure_z(c, (ncols + 1) / 2);
+  if (rc) return rc;
+  for (int k = 0; k < ncols; ++k) KRY_HIP(hipMemsetAsync(zcol(c, k), 0, c->ldv * c->esz, c->stream));
+  int status = KRY_OK;
+  double max_err = 0.0;
+  if (T > 0.0) {
+    // time grid: the projected matrices and the sources carry frequencies
+    // up to rho (the curl part's imaginary extent) plus the largest w; a
+    // step of 0.5 / that bandwidth makes the degree-7 interpolant through 8
+    // Gauss nodes exact to about 1e-12 relative
+    double wmax = 0.0;
+    for (int k = 0; k < n_omega; ++k) wmax = std::max(wmax, omegas[k]);
+    const int nt = std::max(1, (int)std::ceil(T * (c->rho + wmax) / 0.5));
+    std::vector<double> gx(kRstNodes), gw(kRstNodes);
+    kry::gauss_legendre01(kRstNodes, gx.data(), gw.data());
+    // one group of time functions per (source, part)
+    const int ngroups = b_per_omega ? ncols : n_src;
+    for (int gi = 0; gi < ngroups; ++gi) {
+      const double* bcol = b + (size_t)gi * 2 * c->n;
+      double nrm2[2] = {0.0, 0.0};
+      for (int part = 0; part < 2; ++part) {
+        KRY_HIP(kry::launch_load_complex(c->st, bcol, part, slot(c, 0), c->n, c->stream));
+        std::vector<double> d;
+        rc = host_dots(c, slot(c, 0), nullptr, 0, d);
+        if (rc) return rc;
+        nrm2[part] = d[0];
+      }
+      const int parts = (nrm2[0] > 0.0) + (nrm2[1] > 0.0);
+      for (int part = 0; part < 2; ++part) {
+        if (!(nrm2[part] > 0.0)) continue;
+        std::vector<RstColumn> cols;
+        if (b_per_omega) {
+          RstColumn cl;
+          cl.out = gi;
+          cl.w = omegas[gi / n_src];
+          cl.phase = part;
+          cl.share = 0.5 / parts;
+          cols.push_back(std::move(cl));
+        } else {
+          for (int k = 0; k < n_omega; ++k) {
+            RstColumn cl;
+            cl.out = k * n_src + gi;
+            cl.w = omegas[k];
+            cl.phase = part;
+            cl.share = 0.5 / parts;
+            cols.push_back(std::move(cl));
+          }
+        }
+        KRY_HIP(kry::launch_load_complex(c->st, bcol, part, slot(c, 0), c->n, c->stream));
+        rc = rst_part(c, cols, T, nt, gx, gw, st, &max_err);
+        if (rc == KRY_ENOCONV) status = rc;
+        else if (rc) return rc;
+      }
+    }
+  }
+  for (int k = 0; k < ncols; ++k)
+    KRY_HIP(kry::launch_store_real(c->st, zcol(c, k), yT + (size_t)k * c->n, c->n, c->stream));
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  if (st) {
+    st->max_err_estimate = max_err;
+    st->ms_total = st->ms_transient = now_ms() - t0;
+    st->converged = status == KRY_OK;
+    texport(c, st);
+  }
+  return status;
+}
+
+// ---------------------------------------------------------------------------
 // Arnoldi that allocates nothing, for callers that cannot allocate device
 // memory (code under graph capture, tight serving loops, harnesses that
 // forbid hipMalloc).  Its per-workgroup partial sums, reduction buffers,
@@ -2600,6 +2903,13 @@ int kry_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
                         const double* b, int32_t b_per_omega, double T, double* yT, kry_stats* st) {
   return guarded(c, [&] {
     return api_solve_multifreq(c, omegas, n_omega, n_src, b, b_per_omega, T, yT, st);
+  });
+}
+
+int kry_solve_restarted(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src,
+                        const double* b, int32_t b_per_omega, double T, double* yT, kry_stats* st) {
+  return guarded(c, [&] {
+    return api_solve_restarted(c, omegas, n_omega, n_src, b, b_per_omega, T, yT, st);
   });
 }
 

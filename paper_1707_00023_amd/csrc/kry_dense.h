@@ -146,3 +146,38 @@ void stack_coef(int M, int s, const double* C, const double* Rinv, double* K);
 void stack_coef_full(int M, int s, const double* C, const double* F, double* K);
 
 }  // namespace kry
+
+namespace kry {
+
+// Gauss-Legendre rule with q points on [0, 1]: nodes x (increasing) and
+// weights w (summing to 1), by Newton's method on the Legendre polynomial.
+void gauss_legendre01(int q, double* x, double* w);
+
+// Propagators of the projected problem u' = -H u + f(t) e_1 (H m x m) over
+// one time step of length dt, for a source f known at the q nodes dt x_i
+// of the step (interpolated by the degree q-1 polynomial through them):
+//   u(dt)        = E u(0) + W f,            E = e^{-dt H},  W  m x q,
+//   e_m^T u(s_i) = El[i] u(0) + Wl[i] f,    El q x m,       Wl q x q,
+// with s_i = dt x_i.  The polynomial part is exact: the integrals of
+// e^{-(tau-s)H} e_1 against the monomials (s/dt)^r come from one
+// exponential of the augmented matrix [[-H, e_1 e_1^T], [0, J]] (J the
+// q x q shift) per node, and the Lagrange weights from the inverse of the
+// Vandermonde matrix of the nodes.  All row-major except E, W
+// (column-major).
+struct RstProp {
+  int m = 0, q = 0;
+  double dt = 0.0;
+  std::vector<double> E, W, El, Wl;
+};
+void rst_prepare(int m, const double* H, int ldh, int q, double dt, const double* x, RstProp* P);
+
+// March ncol projected problems u_c' = -H u_c + beta f_c(t) e_1, u_c(0) = 0,
+// over nt steps of P.dt: f_c is given by its samples fin[c][j q + i] at
+// t = j dt + dt x_i; writes the samples of the new residual source
+// fout[c][j q + i] = -hnext e_m^T u_c(t) at the same times, u_c(nt dt)
+// into uT (m x ncol column-major), and the integral of |fout| over the
+// interval (Gauss rule with weights dt w_i) into resint[c].
+void rst_march(const RstProp& P, int nt, int ncol, double beta, double hnext, const double* w,
+               const double* const* fin, double* const* fout, double* uT, double* resint);
+
+}  // namespace kry

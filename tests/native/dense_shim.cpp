@@ -1,5 +1,7 @@
 // Test-only C wrappers around the host small-dense routines of libkry.
+#include <algorithm>
 #include <complex>
+#include <vector>
 
 #include "../../paper_1707_00023_amd/csrc/kry_dense.h"
 
@@ -91,4 +93,31 @@ double t_choose_step_block(int K, int q, int g, const double* H, int ldh, const 
                            double tau_try, const double* rate, int Ks, double* U, double* err) {
   return kry::choose_step_block(K, q, g, H, ldh, U0, tau_try, rate, Ks, U, err);
 }
+
+void t_gauss_legendre01(int q, double* x, double* w) { kry::gauss_legendre01(q, x, w); }
+
+void t_rst_prepare(int m, const double* H, int ldh, int q, double dt, const double* x, double* E,
+                   double* W, double* El, double* Wl) {
+  kry::RstProp P;
+  kry::rst_prepare(m, H, ldh, q, dt, x, &P);
+  std::copy(P.E.begin(), P.E.end(), E);
+  std::copy(P.W.begin(), P.W.end(), W);
+  std::copy(P.El.begin(), P.El.end(), El);
+  std::copy(P.Wl.begin(), P.Wl.end(), Wl);
 }
+
+// fin, fout: ncol x (nt q) row-major
+void t_rst_march(int m, const double* H, int ldh, int q, double dt, const double* x, const double* w,
+                 int nt, int ncol, double beta, double hnext, const double* fin, double* fout, double* uT,
+                 double* resint) {
+  kry::RstProp P;
+  kry::rst_prepare(m, H, ldh, q, dt, x, &P);
+  std::vector<const double*> fi(ncol);
+  std::vector<double*> fo(ncol);
+  for (int c = 0; c < ncol; ++c) {
+    fi[c] = fin + (size_t)c * nt * q;
+    fo[c] = fout + (size_t)c * nt * q;
+  }
+  kry::rst_march(P, nt, ncol, beta, hnext, w, fi.data(), fo.data(), uT, resint);
+}
+}  // extern "C"

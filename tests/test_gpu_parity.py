@@ -585,6 +585,95 @@ def test_grad_c4_full_size_against_difference_solves():
     assert err <= 1e-5
 
 
+# ------------------------------------------------ transient continuation --
+
+@pytest.mark.parametrize("per_omega", [False, True])
+def test_transient_continuation_matches_oracle(per_omega):
+    # six neighbouring frequencies (a scan): each column's transient after
+    # the first is continued from the previous column's (equation (4diff));
+    # every column against the oracle's augmented-matrix route at 1e-8, and
+    # fewer transient operator applications than the plain transients
+    _announce(f"transient continuation (per-omega sources {per_omega})")
+    wl = wk.small(12, seed=34, n_spheres=5, layer=2, T=90.0)
+    inp = wk.generate(wl)
+    om = [2 * math.pi * f for f in np.linspace(0.095, 0.105, 6)]
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    if per_omega:
+        B = np.stack([wk.source_vector(wl, w, 0.25) for w in om])
+        refs = [osv.augmented_solution(A, B[k], w, wl.T) for k, w in enumerate(om)]
+    else:
+        B = wk.source_vector(wl, om[0], 0.0)[None, :]
+        refs = [osv.augmented_solution(A, B[0], w, wl.T) for w in om]
+    mv = {}
+    for tc in (False, True):
+        s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-10, transient_continuation=tc)
+        y = s.solve_multifreq(om, _t(B), wl.T, b_per_omega=per_omega).cpu().numpy()
+        mv[tc] = s.last_stats["matvecs_transient"]
+        assert s.last_stats["converged"] == 1
+        s.close()
+        for k in range(len(om)):
+            assert _rel(y[k], refs[k]) <= 1e-8
+    _announce(f"transient operator applications: plain {mv[False]}, continued {mv[True]}")
+    assert mv[True] < mv[False]
+
+
+# ------------------------------------------ restarted inhomogeneous Krylov --
+
+@pytest.mark.parametrize("m", [30, 64])
+def test_restarted_inhomogeneous_c1_matches_oracle(m):
+    # c1 (16^3, T = 200, tol 1e-10) by the residual-restarted method, with no
+    # shifted solve, against the oracle's split solution (SuperLU and
+    # expm_multiply)
+    wl = wk.C1
+    _announce(f"restarted inhomogeneous Krylov c1, m = {m}")
+    inp = wk.generate(wl)
+    b = wk.source_vector(wl, wl.omegas[0], 0.0)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=m, tol=wl.tol)
+    y = s.solve_restarted(wl.omegas, _t(b[None, :]), wl.T).cpu().numpy()[0]
+    st = s.last_stats
+    _announce(f"restarted c1 m={m}: {st['steps_transient']} restarts, {st['matvecs_transient']} "
+              f"operator applications, {st['ms_total']:.0f} ms, error estimate {st['max_err_estimate']:.2e}")
+    s.close()
+    assert st["converged"] == 1 and st["max_err_estimate"] <= 0.5 * wl.tol
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    y_or = osv.split_solution(A, b, wl.omegas[0], wl.T)[0]
+    assert _rel(y, y_or) <= 1e-8
+
+
+def test_restarted_inhomogeneous_shared_and_per_omega_sources():
+    # 10^3, three frequencies, T = 60: a complex source shared by all of them
+    # (one sequence of bases per real part serves every frequency) and
+    # per-frequency oblique sources, against the oracle's augmented-matrix
+    # route per column
+    _announce("restarted inhomogeneous Krylov, several frequencies and sources")
+    wl = wk.small(10, seed=33, n_spheres=4, layer=2, T=60.0)
+    inp = wk.generate(wl)
+    om = [2 * math.pi * f for f in (0.09, 0.1, 0.115)]
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=40, tol=1e-10)
+    srcs = [wk.source_vector(wl, om[0], 0.35), wk.source_vector(wl, om[1], 0.0)]
+    y = s.solve_restarted(om, _t(np.stack(srcs)), wl.T).cpu().numpy()
+    st = s.last_stats
+    assert st["converged"] == 1
+    for k, w in enumerate(om):
+        for si, bs in enumerate(srcs):
+            ref = osv.augmented_solution(A, bs, w, wl.T)
+            assert _rel(y[k * len(srcs) + si], ref) <= 1e-8
+    B = np.stack([wk.source_vector(wl, w, 0.2) for w in om])
+    y = s.solve_restarted(om, _t(B), wl.T, b_per_omega=True).cpu().numpy()
+    for k, w in enumerate(om):
+        assert _rel(y[k], osv.augmented_solution(A, B[k], w, wl.T)) <= 1e-8
+    # a restart cap returns the current approximation with KRY_ENOCONV
+    s.close()
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=10, tol=1e-10, max_restarts=2)
+    kry = _kry()
+    with pytest.raises(kry.NotConverged):
+        s.solve_restarted(om, _t(np.stack(srcs)), wl.T)
+    y = s.solve_restarted(om, _t(np.stack(srcs)), wl.T, allow_noconv=True)
+    assert torch.isfinite(y).all() and s.last_stats["max_err_estimate"] > 1e-10
+    s.close()
+
+
 # ------------------------------------------------------------ error paths --
 
 def test_noconv_returns_best_estimate_and_true_residual():

@@ -502,3 +502,73 @@ def test_group_shifts(lib):
         gid = np.zeros(n, dtype=np.int32)
         ng = lib.t_group_shifts(n, P(w), 5, ctypes.c_double(0.1), P(gid))
         _groups_valid(w, gid, ng, 5, 0.1)
+
+
+# --- the projected problem of the residual-restarted inhomogeneous method --
+
+def test_gauss_legendre_rule(lib):
+    for q in (1, 4, 8, 13):
+        x, w = np.zeros(q), np.zeros(q)
+        lib.t_gauss_legendre01(q, P(x), P(w))
+        xr, wr = np.polynomial.legendre.leggauss(q)
+        assert np.abs(x - 0.5 * (xr + 1)).max() < 1e-15
+        assert np.abs(w - 0.5 * wr).max() < 1e-15
+
+
+def _stable_hessenberg(m, seed):
+    # an Arnoldi matrix of a dissipative operator (skew plus small positive
+    # diagonal), the kind of H the restarted method projects on
+    rng = np.random.default_rng(seed)
+    n = 4 * m
+    S = rng.standard_normal((n, n))
+    A = (S - S.T) / np.sqrt(n) * 3.0 + np.diag(rng.uniform(0.0, 0.3, n))
+    V = np.zeros((n, m + 1))
+    H = np.zeros((m + 1, m))
+    v = rng.standard_normal(n)
+    V[:, 0] = v / np.linalg.norm(v)
+    for j in range(m):
+        x = A @ V[:, j]
+        for _ in range(2):
+            h = V[:, :j + 1].T @ x
+            x -= V[:, :j + 1] @ h
+            H[:j + 1, j] += h
+        H[j + 1, j] = np.linalg.norm(x)
+        V[:, j + 1] = x / H[j + 1, j]
+    return H
+
+
+@pytest.mark.parametrize("m,q,dt", [(12, 8, 0.1), (40, 8, 0.12)])
+def test_rst_march_matches_exact_projected_solution(lib, m, q, dt):
+    # u' = -H u + beta f(t) e_1 with f = sin(w t) (column 0) and cos(w t)
+    # (column 1), sampled at the Gauss nodes of each step: u(T) and the new
+    # residual source -h e_m^T u(t) against the exact solution from one
+    # exponential of the augmented matrix [[-H, beta e1, 0], [0, 0, w],
+    # [0, -w, 0]] (the source as the output of a rotation)
+    Hb = _stable_hessenberg(m, 3)
+    H = np.asfortranarray(Hb[:m, :m])
+    h = Hb[m, m - 1]
+    om, beta, nt = 0.7, 1.3, 50
+    x, w = np.zeros(q), np.zeros(q)
+    lib.t_gauss_legendre01(q, P(x), P(w))
+    t = (np.arange(nt)[:, None] * dt + dt * x[None, :]).reshape(-1)
+    fin = np.ascontiguousarray(np.stack([np.sin(om * t), np.cos(om * t)]))
+    fout = np.zeros_like(fin)
+    uT = np.zeros((2, m))
+    resint = np.zeros(2)
+    lib.t_rst_march(m, P(H), m, q, ctypes.c_double(dt), P(x), P(w), nt, 2, ctypes.c_double(beta),
+                    ctypes.c_double(h), P(fin), P(fout), P(uT), P(resint))
+    G = np.zeros((m + 2, m + 2))
+    G[:m, :m] = -H
+    G[0, m] = beta
+    G[m, m + 1] = om
+    G[m + 1, m] = -om
+    T = nt * dt
+    for c, p0 in ((0, [0.0, 1.0]), (1, [1.0, 0.0])):  # (sin, cos) and (cos, -sin) outputs
+        xi0 = np.concatenate([np.zeros(m), p0])
+        uex = (sla.expm(T * G) @ xi0)[:m]
+        assert np.linalg.norm(uT[c] - uex) <= 1e-11 * np.linalg.norm(uex)
+        for k in (0, 7, len(t) // 2, len(t) - 1):
+            ut = (sla.expm(t[k] * G) @ xi0)[:m]
+            assert abs(fout[c, k] + h * ut[-1]) <= 1e-11 * max(1.0, abs(h * ut[-1]))
+    # the residual integral is the Gauss rule of |fout| over [0, T]
+    assert np.allclose(resint, (np.abs(fout).reshape(2, nt, q) * (dt * w)).sum(axis=(1, 2)), rtol=1e-13)
