@@ -274,6 +274,20 @@ int kry_solve_restarted(kry_ctx* ctx, const double* omegas, int32_t n_omega, int
                         const double* b, int32_t b_per_omega, double T, double* yT,
                         kry_stats* stats);
 
+/* y(T) of problem (1) for every (w, source) pair by splitting off the
+ * source term (equation (split2)): with a subinterval dT of `periods`
+ * periods 2 pi / w of the source, the zero-start solution w2 over [0, dT]
+ * is the same on every subinterval, so y(k dT) = e^{-dT A} y((k-1) dT) +
+ * w2(dT) for k = 1..floor(T / dT), and a remainder r takes y(T) =
+ * e^{-r A} y + w2(r).  w2 comes from the restarted method of
+ * kry_solve_restarted on the window (no shifted solve), the steps from the
+ * time-restarted exponential of kry_expv.  Each column is solved on its
+ * own.  Arguments as for kry_solve_multifreq; every w must be > 0
+ * (KRY_EINVAL otherwise); periods >= 1. */
+int kry_solve_split2(kry_ctx* ctx, const double* omegas, int32_t n_omega, int32_t n_src,
+                     const double* b, int32_t b_per_omega, double T, int32_t periods, double* yT,
+                     kry_stats* stats);
+
 /* Time-harmonic fields only: z_w = (A + i w I)^{-1} b for every column, the
  * vector z_stat of Corollary 3.  Same argument conventions as
  * kry_solve_multifreq; z: device, complex interleaved FP64,

@@ -27,7 +27,7 @@ _CODES = {KRY_EINVAL: "KRY_EINVAL", KRY_ENOMEM: "KRY_ENOMEM", KRY_EHIP: "KRY_EHI
 EXPORTED = ("kry_create", "kry_destroy", "kry_last_error", "kry_size", "kry_apply",
             "kry_apply_f32", "kry_arnoldi", "kry_expv", "kry_solve_multifreq",
             "kry_stationary", "kry_grad", "kry_block_arnoldi", "kry_autotune",
-            "kry_set_tune", "kry_arnoldi_noalloc", "kry_solve_restarted")
+            "kry_set_tune", "kry_arnoldi_noalloc", "kry_solve_restarted", "kry_solve_split2")
 
 
 class KryGrid(ctypes.Structure):
@@ -121,6 +121,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kry_solve_multifreq.argtypes = [P, P, I32, I32, P, I32, D, P, ctypes.POINTER(KryStats)]
     lib.kry_stationary.argtypes = [P, P, I32, I32, P, I32, P, ctypes.POINTER(KryStats)]
     lib.kry_solve_restarted.argtypes = [P, P, I32, I32, P, I32, D, P, ctypes.POINTER(KryStats)]
+    lib.kry_solve_split2.argtypes = [P, P, I32, I32, P, I32, D, I32, P, ctypes.POINTER(KryStats)]
     lib.kry_grad.argtypes = [P, P, I32, P, I32, I32, ctypes.POINTER(D), P,
                              ctypes.POINTER(KryStats)]
     lib.kry_block_arnoldi.argtypes = [P, P, I32, I32, P, P]
@@ -130,7 +131,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kry_set_tune.argtypes = [P, ctypes.POINTER(KryTune)]
     lib.kry_set_tune.restype = ctypes.c_int
     for name in ("kry_apply", "kry_apply_f32", "kry_arnoldi", "kry_expv",
-                 "kry_solve_multifreq", "kry_stationary", "kry_grad", "kry_solve_restarted"):
+                 "kry_solve_multifreq", "kry_stationary", "kry_grad", "kry_solve_restarted",
+                 "kry_solve_split2"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -388,6 +390,21 @@ class Solver:
         rc = self._lib.kry_solve_restarted(self._ctx, om.ctypes.data_as(ctypes.c_void_p), nw, nsrc,
                                            _ptr(b), int(bool(b_per_omega)), float(T), _ptr(y),
                                            ctypes.byref(st))
+        self.last_stats = st.as_dict()
+        self._check(rc, allow_noconv, self.last_stats)
+        return y
+
+    def solve_split2(self, omegas: Sequence[float], b, T: float, periods: int = 1,
+                     b_per_omega: bool = False, allow_noconv: bool = False):
+        """y(T) for every (omega, source) column by source splitting over
+        subintervals of `periods` source periods; conventions as solve_multifreq."""
+        import torch
+        om, b, nw, nsrc = self._omega_b(omegas, b, b_per_omega)
+        y = torch.empty((nw * nsrc, self.n), dtype=torch.float64, device=self.device)
+        st = KryStats()
+        rc = self._lib.kry_solve_split2(self._ctx, om.ctypes.data_as(ctypes.c_void_p), nw, nsrc,
+                                        _ptr(b), int(bool(b_per_omega)), float(T), int(periods),
+                                        _ptr(y), ctypes.byref(st))
         self.last_stats = st.as_dict()
         self._check(rc, allow_noconv, self.last_stats)
         return y

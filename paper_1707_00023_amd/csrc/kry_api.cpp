@@ -2529,38 +2529,97 @@ void parallel_columns(int n, F&& fn) {
 }
 
 struct RstColumn {
-  int out;     // output column (Z column of the accumulated y(T))
-  double w;    // angular frequency
-  int phase;   // 0: sin(w t) (real part of b), 1: cos(w t) (imaginary part)
+  int out;       // output column (Z column of the accumulated y(T))
+  double w;      // angular frequency
+  double ca, cb; // time function ca sin(w t) + cb cos(w t)
   double share;  // fraction of the column's error budget given to this part
-  std::vector<double> fin, fout;  // samples of the current and the next source
   bool active = true;
   double resint = 0.0;
 };
 
+// |Z column|_M for every listed column, with one synchronisation.
+int zcol_norms(kry_ctx* c, const std::vector<int>& zc, std::vector<double>& out) {
+  const int nparts = kry::cell_blocks(c->g.N3, c->g.cpt_d);
+  const int nz = (int)zc.size();
+  out.assign(nz, 0.0);
+  if (nz == 0) return KRY_OK;
+  double* part = nullptr;
+  double* red = nullptr;
+  if (hipMalloc(&part, sizeof(double) * (size_t)nparts * nz) != hipSuccess ||
+      hipMalloc(&red, sizeof(double) * nz) != hipSuccess) {
+    hipFree(part);
+    (void)hipGetLastError();
+    return fail(c, KRY_ENOMEM, "cannot allocate column norm workspace");
+  }
+  Defer<std::function<void()>> fr{[&]() {
+    hipFree(part);
+    hipFree(red);
+  }};
+  for (int k = 0; k < nz; ++k) {
+    KRY_HIP(kry::launch_dots(c->st, zcol(c, zc[k]), nullptr, c->ldv, 0, c->g, c->mats,
+                             part + (size_t)k * nparts, c->stream));
+    KRY_HIP(kry::launch_reduce(part + (size_t)k * nparts, nparts, 1, 1, red + k, c->stream));
+  }
+  KRY_HIP(hipMemcpyAsync(out.data(), red, sizeof(double) * nz, hipMemcpyDeviceToHost, c->stream));
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  for (auto& v : out) v = std::sqrt(std::max(v, 0.0));
+  return KRY_OK;
+}
+
 // One real source part in slot 0 (unnormalised) and the time functions that
-// drive it; y(T) accumulates into the Z columns of `cols`.
+// drive it; y(T) accumulates into the Z columns of `cols`.  The sampled
+// sources of every time function live in two device buffers (current and
+// next restart); the projected problems are marched on the GPU, one wave per
+// time function (on the host for Krylov dimensions above 64).
 int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const std::vector<double>& gx,
              const std::vector<double>& gw, kry_stats* st, double* max_err) {
   const int m = c->opts.krylov_dim;
   const int q = kRstNodes;
   const double dt = T / nt;
   const int ldh = m + 1;
-  for (auto& cl : cols) {
-    cl.fin.resize((size_t)nt * q);
-    cl.fout.assign((size_t)nt * q, 0.0);
+  const int nc = (int)cols.size();
+  const bool gpu = m <= kry::rst_march_max_m();
+  const size_t ldf = (size_t)nt * q;
+  std::vector<double> f0((size_t)nc * ldf);
+  for (int k = 0; k < nc; ++k)
     for (int j = 0; j < nt; ++j)
       for (int i = 0; i < q; ++i) {
         const double t = (j + gx[i]) * dt;
-        cl.fin[(size_t)j * q + i] = cl.phase == 0 ? std::sin(cl.w * t) : std::cos(cl.w * t);
+        f0[(size_t)k * ldf + (size_t)j * q + i] =
+            cols[k].ca * std::sin(cols[k].w * t) + cols[k].cb * std::cos(cols[k].w * t);
       }
+  // device buffers: samples (2 nc ldf), packed propagators E, W, El, Wl and
+  // the Gauss weights, u(T) per time function, residual integrals, index map
+  const size_t npk = (size_t)m * m + 2 * (size_t)m * q + (size_t)q * q + q;
+  double *dF = nullptr, *dP = nullptr, *dU = nullptr, *dR = nullptr;
+  int* dMap = nullptr;
+  Defer<std::function<void()>> free_bufs{[&]() {
+    hipFree(dF);
+    hipFree(dP);
+    hipFree(dU);
+    hipFree(dR);
+    hipFree(dMap);
+  }};
+  std::vector<double> hF[2];
+  if (gpu) {
+    if (hipMalloc(&dF, sizeof(double) * 2 * nc * ldf) != hipSuccess || hipMalloc(&dP, sizeof(double) * npk) != hipSuccess ||
+        hipMalloc(&dU, sizeof(double) * (size_t)m * nc) != hipSuccess || hipMalloc(&dR, sizeof(double) * nc) != hipSuccess ||
+        hipMalloc(&dMap, sizeof(int) * nc) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, KRY_ENOMEM, "cannot allocate the sampled sources of the restarted method");
+    }
+    KRY_HIP(hipMemcpyAsync(dF, f0.data(), sizeof(double) * f0.size(), hipMemcpyHostToDevice, c->stream));
+  } else {
+    hF[0] = f0;
+    hF[1].assign(f0.size(), 0.0);
   }
   const int maxcyc = c->opts.max_restarts > 0 ? c->opts.max_restarts : 100000;
-  int rc = ensure_y(c, m + 1, (int)cols.size());
+  int rc = ensure_y(c, m + 1, nc);
   if (rc) return rc;
   kry::RstProp P;
   std::vector<int> act, cmap;
-  std::vector<double> uT, Yh;
+  std::vector<double> uT, Yh, pk(npk), rs;
+  int cur = 0;
   int status = KRY_ENOCONV;
   for (int cyc = 0; cyc < maxcyc; ++cyc) {
     double beta = 0.0;
@@ -2575,46 +2634,65 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
     const double hnext = me < m ? 0.0 : c->h_H[m + (size_t)(m - 1) * ldh];
     kry::rst_prepare(me, c->h_H, ldh, q, dt, gx.data(), &P);
     act.clear();
-    for (int k = 0; k < (int)cols.size(); ++k)
+    for (int k = 0; k < nc; ++k)
       if (cols[k].active) act.push_back(k);
     const int na = (int)act.size();
-    uT.assign((size_t)me * na, 0.0);
-    parallel_columns(na, [&](int a) {
-      RstColumn& cl = cols[act[a]];
-      const double* fi = cl.fin.data();
-      double* fo = cl.fout.data();
-      kry::rst_march(P, nt, 1, beta, hnext, gw.data(), &fi, &fo, &uT[(size_t)a * me], &cl.resint);
-    });
-    // y(T) += V_m u(T) for every active time function, one sweep of the basis
-    Yh.assign((size_t)me * na, 0.0);
     cmap.assign(na, 0);
-    for (int a = 0; a < na; ++a) {
-      for (int i = 0; i < me; ++i) Yh[i + (size_t)a * me] = uT[(size_t)a * me + i];
-      cmap[a] = cols[act[a]].out;
+    for (int a = 0; a < na; ++a) cmap[a] = cols[act[a]].out;
+    rs.assign(na, 0.0);
+    const double* Ydev = c->d_Y;
+    if (gpu) {
+      double* p = pk.data();
+      std::copy(P.E.begin(), P.E.end(), p);
+      std::copy(P.W.begin(), P.W.end(), p + (size_t)me * me);
+      std::copy(P.El.begin(), P.El.end(), p + (size_t)me * me + (size_t)me * q);
+      std::copy(P.Wl.begin(), P.Wl.end(), p + (size_t)me * me + 2 * (size_t)me * q);
+      std::copy(gw.begin(), gw.end(), p + (size_t)me * me + 2 * (size_t)me * q + (size_t)q * q);
+      const double* dE = dP;
+      const double* dW = dP + (size_t)me * me;
+      const double* dEl = dW + (size_t)me * q;
+      const double* dWl = dEl + (size_t)q * me;
+      const double* dgw = dWl + (size_t)q * q;
+      KRY_HIP(hipMemcpyAsync(dP, pk.data(), sizeof(double) * npk, hipMemcpyHostToDevice, c->stream));
+      KRY_HIP(hipMemcpyAsync(dMap, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
+      KRY_HIP(kry::launch_rst_march(me, q, nt, na, dE, dW, dEl, dWl, dgw, beta, hnext, dt, dMap,
+                                    dF + (size_t)cur * nc * ldf, dF + (size_t)(cur ^ 1) * nc * ldf, (long long)ldf,
+                                    dU, dR, c->stream));
+      KRY_HIP(hipMemcpyAsync(rs.data(), dR, sizeof(double) * na, hipMemcpyDeviceToHost, c->stream));
+      Ydev = dU;
+    } else {
+      uT.assign((size_t)me * na, 0.0);
+      parallel_columns(na, [&](int a) {
+        const double* fi = hF[cur].data() + (size_t)act[a] * ldf;
+        double* fo = hF[cur ^ 1].data() + (size_t)act[a] * ldf;
+        kry::rst_march(P, nt, 1, beta, hnext, gw.data(), &fi, &fo, &uT[(size_t)a * me], &rs[a]);
+      });
+      KRY_HIP(hipMemcpyAsync(c->d_Y, uT.data(), sizeof(double) * uT.size(), hipMemcpyHostToDevice, c->stream));
     }
-    KRY_HIP(hipMemcpyAsync(c->d_Y, Yh.data(), sizeof(double) * Yh.size(), hipMemcpyHostToDevice, c->stream));
+    // y(T) += V_m u(T) for every active time function, one sweep of the basis
     KRY_HIP(hipMemcpyAsync(c->d_colmap, cmap.data(), sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
     hipEvent_t e = tbeg(c);
-    KRY_HIP(kry::launch_combine(c->st, c->V, c->ldv, me, c->d_Y, na, c->Z, c->ldv, c->d_colmap, 1, c->g,
+    KRY_HIP(kry::launch_combine(c->st, c->V, c->ldv, me, Ydev, na, c->Z, c->ldv, c->d_colmap, 1, c->g,
                                 c->stream));
     tend(c, e, KRY_K_COMBINE, vbytes(c) * (me + 2.0 * na));
     // residual integral against the column's share of tol |y(T)|_M
     bool any = false;
+    std::vector<double> yns;
+    rc = zcol_norms(c, cmap, yns);  // synchronises: rs is on the host now
+    if (rc) return rc;
     for (int a = 0; a < na; ++a) {
       RstColumn& cl = cols[act[a]];
-      std::vector<double> d;
-      rc = host_dots(c, zcol(c, cl.out), nullptr, 0, d);
-      if (rc) return rc;
-      const double yn = std::sqrt(std::max(d[0], 0.0));
+      cl.resint = rs[a];
+      const double yn = yns[a];
       const double rel = yn > 0.0 ? cl.resint / yn : (cl.resint > 0.0 ? INFINITY : 0.0);
       if (cl.resint <= cl.share * c->opts.tol * yn || me < m) {
         cl.active = false;
         *max_err = std::max(*max_err, rel);
       } else {
         any = true;
-        cl.fin.swap(cl.fout);
       }
     }
+    cur ^= 1;
     if (c->opts.verbose && (cyc + 1) % 5 == 0)
       std::fprintf(stderr, "[kry] restarted inhomogeneous Krylov: restart %d, %d time functions active\n",
                    cyc + 1, (int)std::count_if(cols.begin(), cols.end(), [](const RstColumn& x) { return x.active; }));
@@ -2626,16 +2704,267 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
     KRY_HIP(hipMemcpyAsync(slot(c, 0), slot(c, m), c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
   }
   if (status == KRY_ENOCONV) {
+    std::vector<int> zc;
+    std::vector<double> yns;
+    for (auto& cl : cols)
+      if (cl.active) zc.push_back(cl.out);
+    rc = zcol_norms(c, zc, yns);
+    if (rc) return rc;
+    int a = 0;
     for (auto& cl : cols) {
       if (!cl.active) continue;
-      std::vector<double> d;
-      rc = host_dots(c, zcol(c, cl.out), nullptr, 0, d);
-      if (rc) return rc;
-      const double yn = std::sqrt(std::max(d[0], 0.0));
+      const double yn = yns[a++];
       *max_err = std::max(*max_err, yn > 0.0 ? cl.resint / yn : INFINITY);
     }
     fail(c, KRY_ENOCONV, "restart limit reached in the restarted inhomogeneous Krylov method");
   }
+  return status;
+}
+
+// Zero-start solution over [0, Tw] of y' = -A y + Im(e^{i w t} b) for one
+// complex source column by the restarted method, into Z column zout; each
+// real part stops at tol_rel / 2 (per part) of its |y(Tw)|_M.  *rel_err
+// receives the largest residual integral relative to |y(Tw)|_M.
+int rst_window(kry_ctx* c, const double* bcol, double w, double Tw, int zout, double tol_rel,
+               kry_stats* st, double* rel_err) {
+  KRY_HIP(hipMemsetAsync(zcol(c, zout), 0, c->ldv * c->esz, c->stream));
+  *rel_err = 0.0;
+  if (!(Tw > 0.0)) return KRY_OK;
+  const int nt = std::max(1, (int)std::ceil(Tw * (c->rho + w) / 0.5));
+  std::vector<double> gx(kRstNodes), gw(kRstNodes);
+  kry::gauss_legendre01(kRstNodes, gx.data(), gw.data());
+  double nrm2[2] = {0.0, 0.0};
+  for (int part = 0; part < 2; ++part) {
+    KRY_HIP(kry::launch_load_complex(c->st, bcol, part, slot(c, 0), c->n, c->stream));
+    std::vector<double> d;
+    int rc = host_dots(c, slot(c, 0), nullptr, 0, d);
+    if (rc) return rc;
+    nrm2[part] = d[0];
+  }
+  const int parts = (nrm2[0] > 0.0) + (nrm2[1] > 0.0);
+  int status = KRY_OK;
+  for (int part = 0; part < 2; ++part) {
+    if (!(nrm2[part] > 0.0)) continue;
+    std::vector<RstColumn> cols{RstColumn{zout, w, part == 0 ? 1.0 : 0.0, part == 0 ? 0.0 : 1.0,
+                                          0.5 / parts * tol_rel / c->opts.tol}};
+    KRY_HIP(kry::launch_load_complex(c->st, bcol, part, slot(c, 0), c->n, c->stream));
+    const int rc = rst_part(c, cols, Tw, nt, gx, gw, st, rel_err);
+    if (rc == KRY_ENOCONV) status = rc;
+    else if (rc) return rc;
+  }
+  return status;
+}
+
+// Source splitting (equation (split2)): for a subinterval length dT that is
+// a whole number of periods of the source, the zero-start solution w2 over
+// [0, dT] is the same on every subinterval, so with y_0 = 0
+//   y(k dT) = e^{-dT A} y((k-1) dT) + w2(dT),   k = 1..N,  N = floor(T / dT),
+// and a remainder r = T - N dT takes y(T) = e^{-r A} y(N dT) + w2(r) (the
+// source restarts in phase at N dT).  w2 comes from the restarted method on
+// the short window (no shifted solve); the homogeneous steps are the
+// time-restarted exponential.  Error budget (energy norm, A dissipative, so
+// e^{-tA} does not amplify): the error of w2 enters N times, so w2 is
+// solved to tol / (4 N) of its norm; each of the N - 1 steps gets
+// tol |y| / (4 N); the remainder's pieces tol / 4 each.
+int api_solve_split2(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src, const double* b,
+                     int32_t b_per_omega, double T, int32_t periods, double* yT, kry_stats* st) {
+  int rc = check_multifreq_args(c, omegas, n_omega, n_src, b);
+  if (rc) return rc;
+  if (!yT) return fail(c, KRY_EINVAL, "null output");
+  if (!(T >= 0.0) || !std::isfinite(T)) return fail(c, KRY_EINVAL, "invalid T");
+  if (periods < 1) return fail(c, KRY_EINVAL, "periods per subinterval must be >= 1");
+  for (int k = 0; k < n_omega; ++k)
+    if (!(omegas[k] > 0.0)) return fail(c, KRY_EINVAL, "source splitting needs w > 0 (a period)");
+  if (st) std::memset(st, 0, sizeof(*st));
+  treset(c);
+  const double t0 = now_ms();
+  const int m = c->opts.krylov_dim;
+  rc = ensure_basis(c, m);
+  if (rc) return rc;
+  rc = ensure_z(c, 2);  // Z columns: 0 = w2(dT), 1 = saved y(N dT), 2 = w2(r)
+  if (rc) return rc;
+  rc = ensure_y(c, m + 1, 1);
+  if (rc) return rc;
+  const double tol = c->opts.tol;
+  const double one = 1.0;
+  int status = KRY_OK;
+  double max_err = 0.0;
+  const int ncols = n_omega * n_src;
+  auto add_z = [&](int zc) -> int {  // slot 0 += Z column zc
+    KRY_HIP(hipMemcpyAsync(c->d_Y, &one, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    KRY_HIP(kry::launch_combine(c->st, zcol(c, zc), c->ldv, 1, c->d_Y, 1, slot(c, 0), c->ldv, nullptr, 1, c->g,
+                                c->stream));
+    KRY_HIP(hipStreamSynchronize(c->stream));
+    return KRY_OK;
+  };
+  auto mnorm = [&](const void* x, double* out) -> int {
+    std::vector<double> d;
+    const int r = host_dots(c, x, nullptr, 0, d);
+    *out = std::sqrt(std::max(d.empty() ? 0.0 : d[0], 0.0));
+    return r;
+  };
+  for (int col = 0; col < ncols; ++col) {
+    const double w = omegas[col / n_src];
+    const double* bcol = b + (size_t)(b_per_omega ? col : col % n_src) * 2 * c->n;
+    const double period = 2.0 * M_PI / w;
+    const double dT = periods * period;
+    int N = (int)std::floor(T / dT * (1.0 + 1e-13));
+    double r = T - N * dT;
+    if (r < 1e-12 * std::max(T, 1.0)) r = 0.0;
+    double err_abs = 0.0;
+    KRY_HIP(hipMemsetAsync(slot(c, 0), 0, c->ldv * c->esz, c->stream));
+    if (N >= 1) {
+      double rel_w2 = 0.0, nw2 = 0.0;
+      rc = rst_window(c, bcol, w, dT, 0, tol / (4.0 * N), st, &rel_w2);
+      if (rc == KRY_ENOCONV) status = rc;
+      else if (rc) return rc;
+      rc = mnorm(zcol(c, 0), &nw2);
+      if (rc) return rc;
+      err_abs += N * rel_w2 * nw2;
+      KRY_HIP(hipMemcpyAsync(slot(c, 0), zcol(c, 0), c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
+      for (int k = 2; k <= N; ++k) {
+        double yn = 0.0, e = 0.0;
+        rc = mnorm(slot(c, 0), &yn);
+        if (rc) return rc;
+        if (yn > 0.0) {
+          const double a = tol * yn / (4.0 * N);
+          rc = expv_slot0(c, dT, 0.5 * a, 0.5 * a, st, &e);
+          if (rc == KRY_ENOCONV) status = rc;
+          else if (rc) return rc;
+          err_abs += e;
+        }
+        rc = add_z(0);
+        if (rc) return rc;
+        if (c->opts.verbose && k % 10 == 0)
+          std::fprintf(stderr, "[kry] source splitting: subinterval %d of %d\n", k, N);
+      }
+    }
+    if (r > 0.0) {
+      KRY_HIP(hipMemcpyAsync(zcol(c, 1), slot(c, 0), c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
+      double rel_r = 0.0, nwr = 0.0;
+      rc = rst_window(c, bcol, w, r, 2, 0.25 * tol, st, &rel_r);
+      if (rc == KRY_ENOCONV) status = rc;
+      else if (rc) return rc;
+      rc = mnorm(zcol(c, 2), &nwr);
+      if (rc) return rc;
+      err_abs += rel_r * nwr;
+      KRY_HIP(hipMemcpyAsync(slot(c, 0), zcol(c, 1), c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
+      double yn = 0.0, e = 0.0;
+      rc = mnorm(slot(c, 0), &yn);
+      if (rc) return rc;
+      if (yn > 0.0) {
+        rc = expv_slot0(c, r, 0.125 * tol * yn, 0.125 * tol * yn, st, &e);
+        if (rc == KRY_ENOCONV) status = rc;
+        else if (rc) return rc;
+        err_abs += e;
+      }
+      rc = add_z(2);
+      if (rc) return rc;
+    }
+    double yT_norm = 0.0;
+    rc = mnorm(slot(c, 0), &yT_norm);
+    if (rc) return rc;
+    max_err = std::max(max_err, yT_norm > 0.0 ? err_abs / yT_norm : 0.0);
+    KRY_HIP(kry::launch_store_real(c->st, slot(c, 0), yT + (size_t)col * c->n, c->n, c->stream));
+  }
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  if (st) {
+    st->max_err_estimate = max_err;
+    st->ms_total = st->ms_transient = now_ms() - t0;
+    st->converged = status == KRY_OK;
+    texport(c, st);
+  }
+  return status;
+}
+
+// Per-column sources b_c (b_per_omega): a real basis {s_j} of the span of
+// all Re b_c, Im b_c in the energy inner product, by a pivoted Householder
+// QR of their non-zero rows scaled by sqrt(M) (truncated where the pivot
+// falls below 1e-4 tol of the largest column), so that b_c = sum_j
+// (x_cj + i y_cj) s_j and the source of column c is sum_j [x_cj sin(w_c t) +
+// y_cj cos(w_c t)] s_j.  Each s_j then drives one time function per column,
+// and its sequence of bases serves all of them (Corollary 2): r sequences
+// instead of two per column.  Column c's error budget is split evenly over
+// the s_j it uses.  *used = 0 (and nothing solved) when the sources are not
+// compressible: too many non-zero rows for the host factorisation, or a
+// rank above 3/4 of the two real parts per column.
+int rst_compressed(kry_ctx* c, const double* omegas, int n_omega, int n_src, const double* b, double T, int nt,
+                   const std::vector<double>& gx, const std::vector<double>& gw, kry_stats* st, double* max_err,
+                   int* used) {
+  *used = 0;
+  const int ncols = n_omega * n_src;
+  const long long n = c->n;
+  int rc = ensure_weights(c);
+  if (rc) return rc;
+  unsigned char* dmask = nullptr;
+  int* didx = nullptr;
+  double* dC = nullptr;
+  void* SRC = nullptr;
+  Defer<std::function<void()>> fr{[&]() {
+    hipFree(dmask);
+    hipFree(didx);
+    hipFree(dC);
+    hipFree(SRC);
+  }};
+  if (hipMalloc(&dmask, (size_t)n) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, KRY_ENOMEM, "cannot allocate the source row mask");
+  }
+  KRY_HIP(kry::launch_nonzero_rows(b, ncols, n, dmask, c->stream));
+  std::vector<unsigned char> mask((size_t)n);
+  KRY_HIP(hipMemcpyAsync(mask.data(), dmask, (size_t)n, hipMemcpyDeviceToHost, c->stream));
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  std::vector<int> idx;
+  for (long long e = 0; e < n; ++e)
+    if (mask[e]) idx.push_back((int)e);
+  const int nr = (int)idx.size();
+  const int q = 2 * ncols;
+  if (nr == 0 || (double)nr * q > (double)(1 << 26)) return KRY_OK;  // empty, or above 512 MB
+  if (hipMalloc(&didx, sizeof(int) * nr) != hipSuccess || hipMalloc(&dC, sizeof(double) * (size_t)nr * q) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, KRY_ENOMEM, "cannot allocate the source compression workspace");
+  }
+  KRY_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int) * nr, hipMemcpyHostToDevice, c->stream));
+  KRY_HIP(kry::launch_gather_rows(b, ncols, n, didx, nr, c->d_w, dC, c->stream));
+  std::vector<double> C((size_t)nr * q), Q((size_t)nr * q), Rf((size_t)q * q);
+  KRY_HIP(hipMemcpyAsync(C.data(), dC, sizeof(double) * C.size(), hipMemcpyDeviceToHost, c->stream));
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  const int r = kry::qr_pivoted(nr, q, C.data(), 1e-4 * c->opts.tol, Q.data(), Rf.data());
+  if (r < 1 || 4 * r > 3 * q) return KRY_OK;
+  if (c->opts.verbose)
+    std::fprintf(stderr, "[kry] %d per-column sources share %d real source vectors (%d non-zero rows)\n", ncols, r,
+                 nr);
+  // the basis vectors s_j, in the storage type
+  const size_t vb = (size_t)c->ldv * c->esz;
+  if (hipMalloc(&SRC, vb * r) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, KRY_ENOMEM, "cannot allocate the compressed sources");
+  }
+  KRY_HIP(hipMemsetAsync(SRC, 0, vb * r, c->stream));
+  KRY_HIP(hipMemcpyAsync(dC, Q.data(), sizeof(double) * (size_t)nr * r, hipMemcpyHostToDevice, c->stream));
+  KRY_HIP(kry::launch_scatter_basis(c->st, dC, nr, r, didx, c->d_w, SRC, c->ldv, c->stream));
+  // sequences used per column (non-zero coefficients)
+  std::vector<int> uses(ncols, 0);
+  for (int j = 0; j < r; ++j)
+    for (int k = 0; k < ncols; ++k)
+      if (Rf[(size_t)j * q + 2 * k] != 0.0 || Rf[(size_t)j * q + 2 * k + 1] != 0.0) ++uses[k];
+  int status = KRY_OK;
+  for (int j = 0; j < r; ++j) {
+    std::vector<RstColumn> cols;
+    for (int k = 0; k < ncols; ++k) {
+      const double x = Rf[(size_t)j * q + 2 * k], y = Rf[(size_t)j * q + 2 * k + 1];
+      if (x == 0.0 && y == 0.0) continue;
+      cols.push_back(RstColumn{k, omegas[k / n_src], x, y, 0.5 / std::max(uses[k], 1)});
+    }
+    if (cols.empty()) continue;
+    KRY_HIP(hipMemcpyAsync(slot(c, 0), (char*)SRC + vb * j, vb, hipMemcpyDeviceToDevice, c->stream));
+    rc = rst_part(c, cols, T, nt, gx, gw, st, max_err);
+    if (rc == KRY_ENOCONV) status = rc;
+    else if (rc) return rc;
+    if (c->opts.verbose)
+      std::fprintf(stderr, "[kry] compressed source %d of %d done\n", j + 1, r);
+  }
+  *used = 1;
   return status;
 }
 
@@ -2667,8 +2996,18 @@ int api_solve_restarted(kry_ctx* c, const double* omegas, int32_t n_omega, int32
     const int nt = std::max(1, (int)std::ceil(T * (c->rho + wmax) / 0.5));
     std::vector<double> gx(kRstNodes), gw(kRstNodes);
     kry::gauss_legendre01(kRstNodes, gx.data(), gw.data());
+    // per-column sources: try one real basis of all of them (the sequences
+    // of bases then serve every column, Corollary 2)
+    bool done = false;
+    if (b_per_omega && ncols >= 2) {
+      int used = 0;
+      rc = rst_compressed(c, omegas, n_omega, n_src, b, T, nt, gx, gw, st, &max_err, &used);
+      if (rc == KRY_ENOCONV) status = rc;
+      else if (rc) return rc;
+      done = used != 0;
+    }
     // one group of time functions per (source, part)
-    const int ngroups = b_per_omega ? ncols : n_src;
+    const int ngroups = done ? 0 : (b_per_omega ? ncols : n_src);
     for (int gi = 0; gi < ngroups; ++gi) {
       const double* bcol = b + (size_t)gi * 2 * c->n;
       double nrm2[2] = {0.0, 0.0};
@@ -2682,23 +3021,13 @@ int api_solve_restarted(kry_ctx* c, const double* omegas, int32_t n_omega, int32
       const int parts = (nrm2[0] > 0.0) + (nrm2[1] > 0.0);
       for (int part = 0; part < 2; ++part) {
         if (!(nrm2[part] > 0.0)) continue;
+        const double ca = part == 0 ? 1.0 : 0.0, cb = part == 0 ? 0.0 : 1.0;
         std::vector<RstColumn> cols;
         if (b_per_omega) {
-          RstColumn cl;
-          cl.out = gi;
-          cl.w = omegas[gi / n_src];
-          cl.phase = part;
-          cl.share = 0.5 / parts;
-          cols.push_back(std::move(cl));
+          cols.push_back(RstColumn{gi, omegas[gi / n_src], ca, cb, 0.5 / parts});
         } else {
-          for (int k = 0; k < n_omega; ++k) {
-            RstColumn cl;
-            cl.out = k * n_src + gi;
-            cl.w = omegas[k];
-            cl.phase = part;
-            cl.share = 0.5 / parts;
-            cols.push_back(std::move(cl));
-          }
+          for (int k = 0; k < n_omega; ++k)
+            cols.push_back(RstColumn{k * n_src + gi, omegas[k], ca, cb, 0.5 / parts});
         }
         KRY_HIP(kry::launch_load_complex(c->st, bcol, part, slot(c, 0), c->n, c->stream));
         rc = rst_part(c, cols, T, nt, gx, gw, st, &max_err);
@@ -2910,6 +3239,13 @@ int kry_solve_restarted(kry_ctx* c, const double* omegas, int32_t n_omega, int32
                         const double* b, int32_t b_per_omega, double T, double* yT, kry_stats* st) {
   return guarded(c, [&] {
     return api_solve_restarted(c, omegas, n_omega, n_src, b, b_per_omega, T, yT, st);
+  });
+}
+
+int kry_solve_split2(kry_ctx* c, const double* omegas, int32_t n_omega, int32_t n_src, const double* b,
+                     int32_t b_per_omega, double T, int32_t periods, double* yT, kry_stats* st) {
+  return guarded(c, [&] {
+    return api_solve_split2(c, omegas, n_omega, n_src, b, b_per_omega, T, periods, yT, st);
   });
 }
 

@@ -161,4 +161,29 @@ hipError_t launch_grad_acc(Storage st, const void* zre, const void* zim, const v
                            const void* xim, const double* b, double w, double* g, long long N3,
                            hipStream_t s);
 
+// Projected problems of the residual-restarted inhomogeneous method
+// (kry_rst.hip): for each of ncol time functions a (stored as column
+// c = cmap[a], or a when cmap is null), march u' = -H u + beta f_c(t) e_1,
+// u(0) = 0, over nt steps of length dt with the step propagators E (m x m),
+// W (m x q) (column-major), El (q x m), Wl (q x q) (row-major) and the
+// sampled sources fin[c ldf + j q + i]; writes the next residual source
+// samples fout (same layout), u(nt dt) into uT[a m + .] and the Gauss-rule
+// integral of |fout_c| (node weights gw, times dt) into resint[a].  All
+// device pointers.  m <= rst_march_max_m(), q = 8, ldf >= nt q.
+// Source compression for the restarted method (kry_rst.hip): mask[e] = 1
+// where any of ncols complex interleaved columns of b (stride 2n doubles) is
+// non-zero; C (nr x 2 ncols, column-major) = the energy-scaled real and
+// imaginary parts sqrt(w) b at the rows idx; out_j (stride ld, zero
+// elsewhere beforehand) = Q[:, j] / sqrt(w) scattered back to the rows idx.
+hipError_t launch_nonzero_rows(const double* b, int ncols, long long n, unsigned char* mask, hipStream_t s);
+hipError_t launch_gather_rows(const double* b, int ncols, long long n, const int* idx, int nr, const double* w,
+                              double* C, hipStream_t s);
+hipError_t launch_scatter_basis(Storage st, const double* Q, int nr, int r, const int* idx, const double* w,
+                                void* out, long long ld, hipStream_t s);
+int rst_march_max_m();
+hipError_t launch_rst_march(int m, int q, int nt, int ncol, const double* E, const double* W,
+                            const double* El, const double* Wl, const double* gw, double beta,
+                            double hnext, double dt, const int* cmap, const double* fin, double* fout,
+                            long long ldf, double* uT, double* resint, hipStream_t s);
+
 }  // namespace kry

@@ -619,8 +619,9 @@ def test_transient_continuation_matches_oracle(per_omega):
 
 # ------------------------------------------ restarted inhomogeneous Krylov --
 
-@pytest.mark.parametrize("m", [30, 64])
+@pytest.mark.parametrize("m", [30, 64, 80])
 def test_restarted_inhomogeneous_c1_matches_oracle(m):
+    # m <= 64: projected problems marched on the GPU; m = 80: on the host
     # c1 (16^3, T = 200, tol 1e-10) by the residual-restarted method, with no
     # shifted solve, against the oracle's split solution (SuperLU and
     # expm_multiply)
@@ -672,6 +673,62 @@ def test_restarted_inhomogeneous_shared_and_per_omega_sources():
     y = s.solve_restarted(om, _t(np.stack(srcs)), wl.T, allow_noconv=True)
     assert torch.isfinite(y).all() and s.last_stats["max_err_estimate"] > 1e-10
     s.close()
+
+
+def test_restarted_per_column_sources_share_a_compressed_basis():
+    # 5 frequencies x 3 oblique angles, one source per column (the batched
+    # recipe at 10^3): the sources are spanned by a few real vectors, each of
+    # which drives one time function per column, so a handful of sequences
+    # of bases serve all 15 columns; every column against the oracle, and
+    # fewer restarts than two sequences per column
+    _announce("restarted method, per-column sources through a compressed basis")
+    wl = wk.small(10, seed=36, n_spheres=4, layer=2, T=50.0)
+    inp = wk.generate(wl)
+    om = [2 * math.pi * f for f in np.linspace(0.09, 0.11, 5)]
+    th = [0.0, 0.2, 0.45]
+    B = np.stack([wk.source_vector(wl, w, t) for w in om for t in th])
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=40, tol=1e-10)
+    y = s.solve_restarted(om, _t(B), wl.T, b_per_omega=True).cpu().numpy()
+    st = s.last_stats
+    assert st["converged"] == 1
+    for k, w in enumerate(om):
+        for i in range(len(th)):
+            col = k * len(th) + i
+            assert _rel(y[col], osv.augmented_solution(A, B[col], w, wl.T)) <= 1e-8
+    restarts_shared = st["steps_transient"]
+    one = 0
+    for col in (0, 7, 14):  # columns solved alone: two sequences each (Re and Im)
+        s.solve_restarted([om[col // 3]], _t(B[col:col + 1]), wl.T, b_per_omega=True)
+        one += s.last_stats["steps_transient"]
+    s.close()
+    _announce(f"restarts: 15 columns together {restarts_shared}, 3 columns alone {one}")
+    assert restarts_shared < 5 * one
+
+
+# ------------------------------------------------------- source splitting --
+
+@pytest.mark.parametrize("T,periods", [(60.0, 1), (65.0, 2)])
+def test_source_splitting_matches_oracle(T, periods):
+    # equation (split2): y(k dT) = e^{-dT A} y((k-1) dT) + w2(dT) over
+    # subintervals of whole periods, w2 from the restarted method on one
+    # window, plus a remainder window where T is not a whole number of
+    # subintervals (both frequencies at T = 65, the second one at T = 60);
+    # a complex shared source, every column against the oracle's
+    # augmented-matrix route
+    _announce(f"source splitting T={T} periods={periods}")
+    wl = wk.small(10, seed=35, n_spheres=4, layer=2)
+    inp = wk.generate(wl)
+    om = [2 * math.pi * 0.1, 2 * math.pi * 0.113]
+    b = wk.source_vector(wl, om[0], 0.3)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=40, tol=1e-10)
+    y = s.solve_split2(om, _t(b[None, :]), T, periods=periods).cpu().numpy()
+    st = s.last_stats
+    s.close()
+    assert st["converged"] == 1
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    for k, w in enumerate(om):
+        assert _rel(y[k], osv.augmented_solution(A, b, w, T)) <= 1e-8
 
 
 # ------------------------------------------------------------ error paths --
