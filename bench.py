@@ -130,8 +130,13 @@ def compare_batched(args, wl, inp, dev):
     workload at one incidence angle (per-frequency oblique sources).
     plain: every column on its own; continuation: the columns solved in
     frequency order, each shifted solve starting from the extrapolation of
-    the earlier frequencies' solutions; block: the columns sharing one
-    block Krylov space (block width, block steps)."""
+    the earlier frequencies' solutions (continuation_transient: the
+    transients continued too, equation (4diff)); block: the columns sharing
+    one block Krylov space (block width, block steps); restarted: the
+    residual-restarted method with every column's source expressed in one
+    shared real basis, whose sequences of bases serve all columns.
+    --theta-index -1 takes every angle of each frequency (columns = the
+    frequencies times the angles)."""
     import numpy as np
     import torch
 
@@ -141,24 +146,32 @@ def compare_batched(args, wl, inp, dev):
     eps = torch.as_tensor(inp.eps, device=dev)
     sig = torch.as_tensor(inp.sigma, device=dev)
     ks = list(range(args.omega_index, min(args.omega_index + args.columns, len(wl.omegas))))
-    om = [wl.omegas[k] for k in ks]
-    th = float(inp.thetas[args.theta_index])
-    B = torch.as_tensor(np.stack([wk.source_vector(wl, w, th) for w in om]), device=dev)
+    if args.theta_index < 0:  # every angle of each frequency
+        om = [wl.omegas[k] for k in ks for _ in inp.thetas]
+        ths = [float(t) for _ in ks for t in inp.thetas]
+    else:
+        om = [wl.omegas[k] for k in ks]
+        ths = [float(inp.thetas[args.theta_index])] * len(om)
+    th = ths[0] if args.theta_index >= 0 else "all"
+    B = torch.as_tensor(np.stack([wk.source_vector(wl, w, t) for w, t in zip(om, ths)]), device=dev)
     out = {"metric": "batched vs plain time to solution (same columns, same tol)",
            "workload": wl.name, "columns": len(om), "omegas": om, "theta": th, "T": wl.T,
            "tol": wl.tol}
     ys = {}
     all_modes = {"plain": {}, "continuation": {"omega_continuation": True},
-                 "block": {"block_width": args.block_width, "block_steps": args.block_steps}}
+                 "continuation_transient": {"omega_continuation": True, "transient_continuation": True},
+                 "block": {"block_width": args.block_width, "block_steps": args.block_steps},
+                 "restarted": {}}
     names = ["plain"] + [m for m in args.batched_modes.split(",") if m in all_modes and m != "plain"]
     modes = [(m, all_modes[m]) for m in names]
     for name, extra in modes:
         s = kry.Solver(eps, None, sig, kry.Options(krylov_dim=wl.krylov_dim, tol=wl.tol, timing=True,
                                                    s_step=args.s_step, verbose=args.verbose,
                                                    **extra))
+        solve = s.solve_restarted if name == "restarted" else s.solve_multifreq
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        y = s.solve_multifreq(om, B, wl.T, b_per_omega=True)
+        y = solve(om, B, wl.T, b_per_omega=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st = s.last_stats
@@ -198,12 +211,14 @@ def precision_compare(args, wl, inp, dev):
     out = {"metric": "FP32-storage error vs FP64 GPU run, per omega", "workload": wl.name,
            "n": wl.n, "omegas": om, "T": wl.T, "krylov_dim": wl.krylov_dim}
     ys = {}
+    out["method"] = args.method
     for name, storage, tol in (("f32", "f32", wl.tol), ("f64", "f64", 1e-8)):
         s = kry.Solver(eps, None, sig, kry.Options(storage=storage, krylov_dim=wl.krylov_dim,
                                                    tol=tol, verbose=True, s_step=args.s_step_cli))
+        solve = s.solve_restarted if args.method == "restarted" else s.solve_multifreq
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        y = s.solve_multifreq(om, b, wl.T)
+        y = solve(om, b, wl.T)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st = s.last_stats
@@ -230,6 +245,38 @@ def precision_compare(args, wl, inp, dev):
         out["rel_err_vs_single_f64"] = ref
     out["speedup_f32_over_f64"] = out["f64"]["s"] / out["f32"]["s"]
     print(json.dumps(out), flush=True)
+
+
+def other_methods(solver, wl, b, per_omega, split_stats, args):
+    """The paper's other routes to the same y(T), each timed once on the same
+    workload and solver after the split steps: the residual-restarted Krylov
+    method (no shifted solve) and source splitting over subintervals of
+    whole periods.  Reported with their relative difference from the split
+    result of the last timed step (both are checked against the oracle in
+    the tests)."""
+    import torch
+    y_split = solver.solve_multifreq(wl.omegas, b, wl.T, b_per_omega=per_omega)
+    out = {}
+    runs = [("restarted", lambda: solver.solve_restarted(wl.omegas, b, wl.T, b_per_omega=per_omega)),
+            ("split2", lambda: solver.solve_split2(wl.omegas, b, wl.T, periods=args.split2_periods,
+                                                   b_per_omega=per_omega))]
+    for name, fn in runs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = solver.last_stats
+        d = torch.linalg.norm(y - y_split, dim=1) / torch.linalg.norm(y_split, dim=1)
+        out[name] = {"s": dt, "matvecs": st["matvecs_stationary"] + st["matvecs_transient"],
+                     "restarts_or_steps": st["steps_transient"],
+                     "err_estimate": st["max_err_estimate"],
+                     "max_rel_diff_vs_split": float(d.max()),
+                     "speedup_vs_split": (split_stats["ms_total"] / 1e3) / dt}
+        print(f"[bench] {name}: {dt:.2f} s", file=sys.stderr, flush=True)
+    if name == "split2":
+        out["split2"]["periods_per_subinterval"] = args.split2_periods
+    return out
 
 
 def main():
@@ -260,6 +307,9 @@ def main():
                     help="FP32-storage solve of the first --n-omega frequencies against an "
                          "FP64 solve of the same columns on the GPU")
     ap.add_argument("--n-omega", type=int, default=2)
+    ap.add_argument("--method", default="split", choices=["split", "restarted"],
+                    help="precision compare: the split solver (Corollary 3) or the "
+                         "residual-restarted method")
     ap.add_argument("--single-ref", type=int, default=0,
                     help="precision compare: also solve the first K frequencies one at a time "
                          "in FP64 and report both runs' errors against them")
@@ -267,6 +317,10 @@ def main():
                     help="precision compare: index of the first frequency")
     ap.add_argument("--s-step", type=int, default=None,
                     help="s-step Arnoldi block size (default: the library binding's default)")
+    ap.add_argument("--no-methods", action="store_true",
+                    help="skip the one-off timings of the restarted method and source splitting")
+    ap.add_argument("--split2-periods", type=int, default=5,
+                    help="source splitting: periods of the source per subinterval")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="after the timed steps, one device copy of 1 GiB each way (the "
                          "reference dispatch that scales HBM counters to bytes)")
@@ -382,6 +436,15 @@ def main():
         "max_residual": last["max_residual"],
         "max_err_estimate": last["max_err_estimate"],
     }
+    # curl + Arnoldi together: operator, Gram, update and combination kernels
+    agg = [i for i, k in enumerate(kry.KERNEL_CLASSES) if kms[i] > 0]
+    agg_ms = float(sum(kms[i] for i in agg))
+    agg_b = float(sum(kb[i] for i in agg))
+    out["curl_arnoldi"] = {"gbs": agg_b / (agg_ms * 1e-3) / 1e9 if agg_ms > 0 else 0.0,
+                           "frac": agg_b / (agg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if agg_ms > 0 else 0.0,
+                           "ms_per_step": agg_ms / args.steps, "kernels": [kry.KERNEL_CLASSES[i] for i in agg]}
+    if not args.no_methods:
+        out["methods"] = other_methods(solver, wl, b, per_omega, stats[-1], args)
     if calib is not None:
         out["calibration_copy"] = calib
     if not args.no_cpu_baseline:

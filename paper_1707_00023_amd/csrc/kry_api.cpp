@@ -2535,6 +2535,7 @@ struct RstColumn {
   double share;  // fraction of the column's error budget given to this part
   bool active = true;
   double resint = 0.0;
+  double ynorm = 0.0;  // |y(T)|_M of the output column at the last check
 };
 
 // |Z column|_M for every listed column, with one synchronisation.
@@ -2675,15 +2676,28 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
     KRY_HIP(kry::launch_combine(c->st, c->V, c->ldv, me, Ydev, na, c->Z, c->ldv, c->d_colmap, 1, c->g,
                                 c->stream));
     tend(c, e, KRY_K_COMBINE, vbytes(c) * (me + 2.0 * na));
-    // residual integral against the column's share of tol |y(T)|_M
+    // residual integral against the column's share of tol |y(T)|_M.  The
+    // output norms (a sweep over every active column) are refreshed only
+    // when some residual integral is within 16 times of its threshold at
+    // the last norms (or none are known yet); until then no time function
+    // can stop.
     bool any = false;
+    KRY_HIP(hipStreamSynchronize(c->stream));  // rs is on the host now
+    bool near = false;
+    for (int a = 0; a < na; ++a) {
+      const RstColumn& cl = cols[act[a]];
+      near |= !(cl.ynorm > 0.0) || rs[a] <= 16.0 * cl.share * c->opts.tol * cl.ynorm;
+    }
     std::vector<double> yns;
-    rc = zcol_norms(c, cmap, yns);  // synchronises: rs is on the host now
-    if (rc) return rc;
+    if (near || me < m) {
+      rc = zcol_norms(c, cmap, yns);
+      if (rc) return rc;
+    }
     for (int a = 0; a < na; ++a) {
       RstColumn& cl = cols[act[a]];
       cl.resint = rs[a];
-      const double yn = yns[a];
+      if (!yns.empty()) cl.ynorm = yns[a];
+      const double yn = cl.ynorm;
       const double rel = yn > 0.0 ? cl.resint / yn : (cl.resint > 0.0 ? INFINITY : 0.0);
       if (cl.resint <= cl.share * c->opts.tol * yn || me < m) {
         cl.active = false;

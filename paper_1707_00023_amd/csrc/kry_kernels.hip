@@ -609,21 +609,30 @@ __global__ void k_scale(const T* __restrict__ x, const double* __restrict__ s, T
 // out_last instead, never accumulated; out_last may be one of the V_i (a
 // thread reads every V_i at its cells before writing them), so then all
 // columns must be in one workgroup row (ncol <= CC).
+// Block b covers cell chunk i and column chunk k with b = ((i / 8) ncc + k)
+// 8 + i mod 8: every column chunk of a cell chunk runs on the XCD that the
+// dispatcher assigns to b mod 8 = i mod 8, at nearby dispatch times, so the
+// basis entries of the chunk come from HBM once and from that XCD's L2 for
+// the other column chunks.
 template <typename T, int CC>
 __global__ __launch_bounds__(kBlock) void k_combine(const T* V, long long ldv, int m,
                                                     const double* __restrict__ Y, int ncol,
                                                     T* out, long long ldo,
                                                     const int* __restrict__ colmap, int accumulate,
-                                                    T* out_last, long long N3) {
+                                                    T* out_last, long long N3, int ncc, int gx) {
   extern __shared__ double sY[];  // m * CC
-  const int c0 = blockIdx.y * CC;
+  const int bt = blockIdx.x >> 3;
+  const int kchunk = bt % ncc;
+  const int ichunk = (bt / ncc) * 8 + (blockIdx.x & 7);
+  if (ichunk >= gx) return;
+  const int c0 = kchunk * CC;
   const int nc = min(CC, ncol - c0);
   for (int t = threadIdx.x; t < m * CC; t += kBlock) {
     const int i = t / CC, cc = t % CC;
     sY[t] = (cc < nc) ? Y[i + (long long)(c0 + cc) * m] : 0.0;
   }
   __syncthreads();
-  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long c = (long long)ichunk * kBlock + threadIdx.x;
   if (c >= N3) return;
   double acc[CC][6];
 #pragma unroll
@@ -1037,15 +1046,17 @@ static hipError_t combine_t(const void* V, long long ldv, int m, const double* Y
   constexpr int CC = 8;
   if (out_last && ncol > CC) return hipErrorInvalidValue;
   const unsigned gx = blocks_for(g.N3);
+  const unsigned g8 = (gx + 7) / 8 * 8;
   if (ncol == 1) {
     const size_t shm = sizeof(double) * (size_t)m;
-    hipLaunchKernelGGL((k_combine<T, 1>), dim3(gx, 1), dim3(kBlock), shm, s, (const T*)V, ldv, m, Y,
-                       ncol, (T*)out, ldo, colmap, accumulate, (T*)out_last, g.N3);
+    hipLaunchKernelGGL((k_combine<T, 1>), dim3(g8), dim3(kBlock), shm, s, (const T*)V, ldv, m, Y,
+                       ncol, (T*)out, ldo, colmap, accumulate, (T*)out_last, g.N3, 1, (int)gx);
   } else {
+    const int ncc = (ncol + CC - 1) / CC;
     const size_t shm = sizeof(double) * (size_t)m * CC;
-    hipLaunchKernelGGL((k_combine<T, CC>), dim3(gx, (ncol + CC - 1) / CC), dim3(kBlock), shm, s,
+    hipLaunchKernelGGL((k_combine<T, CC>), dim3(g8 * ncc), dim3(kBlock), shm, s,
                        (const T*)V, ldv, m, Y, ncol, (T*)out, ldo, colmap, accumulate, (T*)out_last,
-                       g.N3);
+                       g.N3, ncc, (int)gx);
   }
   return hipGetLastError();
 }
