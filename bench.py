@@ -146,16 +146,13 @@ def compare_batched(args, wl, inp, dev):
     eps = torch.as_tensor(inp.eps, device=dev)
     sig = torch.as_tensor(inp.sigma, device=dev)
     ks = list(range(args.omega_index, min(args.omega_index + args.columns, len(wl.omegas))))
-    if args.theta_index < 0:  # every angle of each frequency
-        om = [wl.omegas[k] for k in ks for _ in inp.thetas]
-        ths = [float(t) for _ in ks for t in inp.thetas]
-    else:
-        om = [wl.omegas[k] for k in ks]
-        ths = [float(inp.thetas[args.theta_index])] * len(om)
-    th = ths[0] if args.theta_index >= 0 else "all"
-    B = torch.as_tensor(np.stack([wk.source_vector(wl, w, t) for w, t in zip(om, ths)]), device=dev)
+    om = [wl.omegas[k] for k in ks]
+    # one source per (frequency, angle): column (k, s) at k * n_angles + s
+    angles = [float(t) for t in inp.thetas] if args.theta_index < 0 else [float(inp.thetas[args.theta_index])]
+    th = angles[0] if args.theta_index >= 0 else "all"
+    B = torch.as_tensor(np.stack([wk.source_vector(wl, w, t) for w in om for t in angles]), device=dev)
     out = {"metric": "batched vs plain time to solution (same columns, same tol)",
-           "workload": wl.name, "columns": len(om), "omegas": om, "theta": th, "T": wl.T,
+           "workload": wl.name, "columns": B.shape[0], "omegas": om, "theta": th, "T": wl.T,
            "tol": wl.tol}
     ys = {}
     all_modes = {"plain": {}, "continuation": {"omega_continuation": True},
@@ -176,7 +173,7 @@ def compare_batched(args, wl, inp, dev):
         dt = time.perf_counter() - t0
         st = s.last_stats
         ys[name] = y.cpu().numpy()
-        out[name] = {"s": dt, "s_per_column": dt / len(om),
+        out[name] = {"s": dt, "s_per_column": dt / B.shape[0],
                      "stationary_s": st["ms_stationary"] / 1e3, "transient_s": st["ms_transient"] / 1e3,
                      "matvecs_stationary": st["matvecs_stationary"],
                      "matvecs_transient": st["matvecs_transient"],

@@ -1076,6 +1076,10 @@ int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, do
   double rn = 0.0, fl = 0.0;
   int rc = true_residual(c, bcol, w, zk, st, &rn, &fl);
   if (rc) return rc;
+  if (!std::isfinite(rn) || !std::isfinite(fl)) {
+    *max_res = INFINITY;
+    return fail(c, KRY_ENOCONV, "non-finite shifted solution");
+  }
   const double accept = std::max(2.0 * tol_rel * bn, 8.0 * fl);
   if (!correct || !(rn > accept)) {
     *max_res = std::max(*max_res, rn / bn);
@@ -1094,7 +1098,8 @@ int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, do
   KRY_HIP(hipStreamSynchronize(c->stream));
   rc = true_residual(c, bcol, w, zk, st, &rn, &fl);
   if (rc) return rc;
-  *max_res = std::max(*max_res, rn / bn);
+  *max_res = std::max(*max_res, std::isfinite(rn) ? rn / bn : INFINITY);
+  if (!std::isfinite(rn)) return fail(c, KRY_ENOCONV, "non-finite shifted solution");
   if (c->opts.verbose)
     std::fprintf(stderr, "[kry] shift omega = %.6f: true relative residual %.3e after the correction\n", w,
                  rn / bn);
@@ -1255,7 +1260,11 @@ int for_each_group(kry_ctx* c, const double* omegas, int n_omega, int n_src, con
         const int col = k * n_src + s;
         const double* bcol = b + (size_t)col * 2 * c->n;
         double bn = 0.0;
-        const int q = cont ? std::min(k, kQ) : 0;
+        int q = cont ? std::min(k, kQ) : 0;
+        // extrapolation nodes must be distinct frequencies
+        for (int a = k - q; a < k && q > 0; ++a)
+          for (int b2 = a + 1; b2 <= k; ++b2)
+            if (std::abs(omegas[a] - omegas[b2]) <= 1e-12 * std::max(std::abs(omegas[b2]), 1.0)) q = 0;
         if (q == 0) {
           rc = stationary_group(c, bcol, std::vector<double>{omegas[k]}, std::vector<int>{0}, tol_s,
                                 st, max_res, &bn, 1);
@@ -2693,6 +2702,11 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
       rc = zcol_norms(c, cmap, yns);
       if (rc) return rc;
     }
+    for (int a = 0; a < na; ++a)
+      if (!std::isfinite(rs[a])) {
+        *max_err = INFINITY;
+        return fail(c, KRY_ENOCONV, "non-finite residual in the restarted inhomogeneous Krylov method");
+      }
     for (int a = 0; a < na; ++a) {
       RstColumn& cl = cols[act[a]];
       cl.resint = rs[a];

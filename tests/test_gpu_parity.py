@@ -617,6 +617,25 @@ def test_transient_continuation_matches_oracle(per_omega):
     assert mv[True] < mv[False]
 
 
+def test_continuation_with_coincident_frequencies():
+    # per-column sources with a frequency that repeats along one chain: the
+    # extrapolation in omega needs distinct nodes, so such a column starts
+    # from zero; every column stays finite and matches the oracle
+    _announce("continuation with coincident frequencies")
+    wl = wk.small(8, seed=37, n_spheres=3, layer=2, T=40.0)
+    inp = wk.generate(wl)
+    om = [2 * math.pi * 0.1, 2 * math.pi * 0.1, 2 * math.pi * 0.104, 2 * math.pi * 0.104]
+    B = np.stack([wk.source_vector(wl, w, 0.1 * k) for k, w in enumerate(om)])
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-10, omega_continuation=True,
+                transient_continuation=True)
+    y = s.solve_multifreq(om, _t(B), wl.T, b_per_omega=True).cpu().numpy()
+    s.close()
+    assert np.isfinite(y).all()
+    for k, w in enumerate(om):
+        assert _rel(y[k], osv.augmented_solution(A, B[k], w, wl.T)) <= 1e-8
+
+
 # ------------------------------------------ restarted inhomogeneous Krylov --
 
 @pytest.mark.parametrize("m", [30, 64, 80])
