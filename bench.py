@@ -159,7 +159,8 @@ def compare_batched(args, wl, inp, dev):
                  "continuation_transient": {"omega_continuation": True, "transient_continuation": True},
                  "block": {"block_width": args.block_width, "block_steps": args.block_steps},
                  "restarted": {}}
-    names = ["plain"] + [m for m in args.batched_modes.split(",") if m in all_modes and m != "plain"]
+    names = ([] if args.skip_plain else ["plain"]) + [m for m in args.batched_modes.split(",")
+                                                        if m in all_modes and m != "plain"]
     modes = [(m, all_modes[m]) for m in names]
     for name, extra in modes:
         s = kry.Solver(eps, None, sig, kry.Options(krylov_dim=wl.krylov_dim, tol=wl.tol, timing=True,
@@ -182,10 +183,27 @@ def compare_batched(args, wl, inp, dev):
                                  if st["kernel_launches"][i] > 0}}
         print(f"[bench] {name}: {dt:.1f} s", file=sys.stderr, flush=True)
         s.close()
-    for name in names[1:]:
+    for name in names:
+        if name == "plain" or "plain" not in ys:
+            continue
         d = np.linalg.norm(ys[name] - ys["plain"], axis=1) / np.linalg.norm(ys["plain"], axis=1)
         out[name]["max_rel_diff_vs_plain"] = float(d.max())
         out[name]["speedup_vs_plain"] = out["plain"]["s"] / out[name]["s"]
+    if wl.name.startswith("c3") and args.golden_check:
+        # the stored oracle columns that fall among the solved ones
+        g = json.load(open(os.path.join(ROOT, "tests", "golden", "c3_yT_samples.json")))
+        idx = np.asarray(g["indices"])
+        checks = []
+        for col in g["columns"]:
+            if col["omega_index"] not in ks or (args.theta_index >= 0 and col["theta_index"] != args.theta_index):
+                continue
+            k = ks.index(col["omega_index"]) * len(angles) + (col["theta_index"] if args.theta_index < 0 else 0)
+            for name in names:
+                yv = ys[name][k]
+                checks.append({"mode": name, "omega_index": col["omega_index"], "theta_index": col["theta_index"],
+                               "sampled_rel_err": float(np.linalg.norm(yv[idx] - np.asarray(col["values"]))
+                                                        / np.linalg.norm(col["values"]))})
+        out["oracle_columns"] = checks
     print(json.dumps(out), flush=True)
 
 
@@ -297,6 +315,11 @@ def main():
                          "(continuation, block)")
     ap.add_argument("--theta-index", type=int, default=0,
                     help="with --compare-batched: incidence angle index of the columns")
+    ap.add_argument("--skip-plain", action="store_true",
+                    help="with --compare-batched: time only the listed modes")
+    ap.add_argument("--golden-check", action="store_true",
+                    help="with --compare-batched on the batched workload: compare the solved "
+                         "columns that have stored oracle values")
     ap.add_argument("--block-width", type=int, default=16)
     ap.add_argument("--block-steps", type=int, default=16)
     ap.add_argument("--no-autotune", action="store_true")

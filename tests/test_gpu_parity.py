@@ -442,6 +442,68 @@ def test_batched_c3_against_oracle_samples():
             assert abs(p @ y[k] - pr) <= 4e-8 * nrm
 
 
+def _check_c2_samples(y, label):
+    gold = json.load(open(GOLD_C2))
+    col = gold["columns"][0]
+    idx = np.asarray(gold["indices"])
+    ref = np.asarray(col["values"])
+    nrm = col["norm2"]
+    err = float(np.linalg.norm(y[idx] - ref) / np.linalg.norm(ref))
+    _announce(f"{label}: sampled rel err {err:.2e}")
+    assert err <= 1e-8
+    assert abs(np.linalg.norm(y) - nrm) <= 1e-8 * nrm
+    import sys
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    from make_golden import projection_vector
+    for k, p in enumerate(col["projections"]):
+        assert abs(projection_vector(y.size, k) @ y - p) <= 4e-8 * nrm
+
+
+@pytest.mark.parametrize("method", ["restarted", "split2"])
+def test_other_methods_c2_against_oracle_samples(method):
+    # the 128^3 workload (T = 500, tol 1e-8) by the residual-restarted method
+    # and by source splitting (5 periods per subinterval), no shifted solve
+    wl = wk.C2
+    _announce(f"c2 128^3 (full size) by {method}")
+    inp = wk.generate(wl)
+    b = _t(wk.source_vector(wl, wl.omegas[0], 0.0)[None, :])
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=wl.tol)
+    t0 = time.time()
+    if method == "restarted":
+        y = s.solve_restarted(wl.omegas, b, wl.T)
+    else:
+        y = s.solve_split2(wl.omegas, b, wl.T, periods=5)
+    y = y.cpu().numpy()[0]
+    _announce(f"c2 {method} {time.time() - t0:.2f}s stats={s.last_stats}")
+    s.close()
+    _check_c2_samples(y, f"c2 {method}")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLD_C3), reason="c3 oracle samples not generated")
+def test_batched_c3_all_columns_restarted_against_oracle_samples():
+    """The batched workload as configured: all 256 columns (32 frequencies x
+    8 angles, one oblique source each) solved together by the restarted
+    method through one compressed basis of the sources; the 4 columns with
+    stored oracle samples compared."""
+    wl = wk.C3
+    _announce("batched c3 96^3, all 256 columns, restarted method")
+    gold = json.load(open(GOLD_C3))
+    inp = wk.generate(wl)
+    nth = len(inp.thetas)
+    B = np.stack([wk.source_vector(wl, w, float(t)) for w in wl.omegas for t in inp.thetas])
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=wl.tol)
+    t0 = time.time()
+    y = s.solve_restarted(list(wl.omegas), _t(B), wl.T, b_per_omega=True)
+    _announce(f"c3 all columns {time.time() - t0:.2f}s stats={s.last_stats}")
+    s.close()
+    idx = np.asarray(gold["indices"])
+    for col in gold["columns"]:
+        yk = y[col["omega_index"] * nth + col["theta_index"]].cpu().numpy()
+        ref = np.asarray(col["values"])
+        assert np.linalg.norm(yk[idx] - ref) <= 1e-8 * np.linalg.norm(ref)
+        assert abs(np.linalg.norm(yk) - col["norm2"]) <= 1e-8 * col["norm2"]
+
+
 # ---------------------------------------------------------- differentiation --
 
 @pytest.mark.parametrize("cont", [False, True])
