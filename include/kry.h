@@ -315,6 +315,18 @@ typedef struct {
  * Krylov workspace (no solve may be in progress on the stream). */
 int kry_autotune(kry_ctx* ctx, int32_t cnt, kry_tune* out);
 
+/* Choose the s-step block size (opts.s_step) by measurement: one restart
+ * cycle of krylov_dim Arnoldi steps, the cycle every solver runs, from a
+ * fixed pseudo-random start vector, for each of the ncand candidates cand[i]
+ * (0 or 1: one operator application per Gram-Schmidt step; 2..64: s-step
+ * blocks); after a warm-up cycle (which sets the Newton shifts, as in a
+ * solve) the best of three cycles counts, and a candidate whose blocks trip
+ * the conditioning guard pays for its fallback.  The fastest candidate is
+ * applied to the context and written to *best; us[i] (host) receives each
+ * candidate's cycle time in microseconds.  1 <= ncand <= 16.  Overwrites the
+ * context's Krylov workspace (no solve may be in progress on the stream). */
+int kry_autotune_sstep(kry_ctx* ctx, const int32_t* cand, int32_t ncand, int32_t* best, double* us);
+
 /* Apply a previously measured launch-shape choice (cpt_* fields of *t). */
 int kry_set_tune(kry_ctx* ctx, const kry_tune* t);
 

@@ -27,7 +27,8 @@ _CODES = {KRY_EINVAL: "KRY_EINVAL", KRY_ENOMEM: "KRY_ENOMEM", KRY_EHIP: "KRY_EHI
 EXPORTED = ("kry_create", "kry_destroy", "kry_last_error", "kry_size", "kry_apply",
             "kry_apply_f32", "kry_arnoldi", "kry_expv", "kry_solve_multifreq",
             "kry_stationary", "kry_grad", "kry_block_arnoldi", "kry_autotune",
-            "kry_set_tune", "kry_arnoldi_noalloc", "kry_solve_restarted", "kry_solve_split2")
+            "kry_set_tune", "kry_arnoldi_noalloc", "kry_solve_restarted", "kry_solve_split2",
+            "kry_autotune_sstep")
 
 
 class KryGrid(ctypes.Structure):
@@ -130,6 +131,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kry_autotune.restype = ctypes.c_int
     lib.kry_set_tune.argtypes = [P, ctypes.POINTER(KryTune)]
     lib.kry_set_tune.restype = ctypes.c_int
+    lib.kry_autotune_sstep.argtypes = [P, P, I32, ctypes.POINTER(I32), P]
+    lib.kry_autotune_sstep.restype = ctypes.c_int
     for name in ("kry_apply", "kry_apply_f32", "kry_arnoldi", "kry_expv",
                  "kry_solve_multifreq", "kry_stationary", "kry_grad", "kry_solve_restarted",
                  "kry_solve_split2"):
@@ -278,32 +281,50 @@ class Solver:
             self._check(rc)
         return V, H.T.copy(), beta.value, rc
 
-    def autotune(self, cache: Optional[str] = None, cnt: int = 0):
-        """Choose the kernels' launch shapes by timing them on this grid.
+    def autotune(self, cache: Optional[str] = None, cnt: int = 0,
+                 s_candidates: Optional[Sequence[int]] = None):
+        """Choose the kernels' launch shapes, and with `s_candidates` the
+        s-step block size, by timing them on this grid.
 
         With `cache` (a JSON path) a measured choice is reused for the same
-        grid, storage, Krylov dimension and GPU architecture, and new
-        measurements are added to it.  Returns the choice as a dict.
+        grid, storage, Krylov dimension, block width and GPU architecture,
+        and new measurements are added to it.  Returns the choice as a dict.
         """
         import json
+        import numpy as np
         import torch
         arch = getattr(torch.cuda.get_device_properties(self.device), "gcnArchName", "gpu")
         key = (f"{self.grid.nx}x{self.grid.ny}x{self.grid.nz}-{self.storage}-"
-               f"m{self.opts.krylov_dim}-c{cnt}-{arch}")
+               f"m{self.opts.krylov_dim}-p{self.opts.block_width}-c{cnt}-{arch}")
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as f:
                 table = json.load(f)
+
+        def tune_s(cands):
+            cand = np.ascontiguousarray(np.asarray(cands, dtype=np.int32))
+            us = np.zeros(cand.size)
+            best = ctypes.c_int32()
+            self._check(self._lib.kry_autotune_sstep(self._ctx, cand.ctypes.data_as(ctypes.c_void_p),
+                                                      int(cand.size), ctypes.byref(best),
+                                                      us.ctypes.data_as(ctypes.c_void_p)))
+            return int(best.value), [float(x) for x in us]
+
         t = KryTune()
-        if key in table:
+        if key in table and (s_candidates is None or "s_step" in table[key]):
             e = table[key]
             t.cpt_stencil, t.cpt_update, t.cpt_dots = e["cpt_stencil"], e["cpt_update"], e["cpt_dots"]
             self._check(self._lib.kry_set_tune(self._ctx, ctypes.byref(t)))
+            if s_candidates is not None:
+                tune_s([e["s_step"]])  # applies the cached block size
             return dict(e, cached=True)
         self._check(self._lib.kry_autotune(self._ctx, int(cnt), ctypes.byref(t)))
         e = {"cpt_stencil": t.cpt_stencil, "cpt_update": t.cpt_update, "cpt_dots": t.cpt_dots,
              "us_stencil": list(t.us_stencil), "us_update": list(t.us_update),
              "us_dots": list(t.us_dots)}
+        if s_candidates is not None:
+            e["s_step"], e["us_cycle"] = tune_s(s_candidates)
+            e["s_candidates"] = [int(x) for x in s_candidates]
         if cache:
             table[key] = e
             d = os.path.dirname(os.path.abspath(cache))

@@ -38,6 +38,7 @@ struct kry_ctx {
 
   // Krylov workspace: slots 0..mcap hold the basis, slot mcap+1 the work vector.
   int mcap = 0;
+  int vextra = 0;  // work slots after the basis in the allocation
   void* V = nullptr;
   double* partials = nullptr;
   double* d_red1 = nullptr;
@@ -210,7 +211,9 @@ void drop_graphs(kry_ctx* c) {
 }
 
 int ensure_basis(kry_ctx* c, int m) {
-  if (m <= c->mcap && c->V) return KRY_OK;
+  const int need_extra = c->st == kry::F64 ? std::max(2, std::min(c->opts.s_step, std::max(m, c->mcap))) : 2;
+  if (m <= c->mcap && c->V && need_extra <= c->vextra) return KRY_OK;
+  m = std::max(m, c->mcap);
   drop_graphs(c);
   if (m + 2 > kry::kMaxCoef) return fail(c, KRY_ENOMEM, "krylov_dim too large");
   hipFree(c->V);
@@ -227,6 +230,7 @@ int ensure_basis(kry_ctx* c, int m) {
   // slots 0..m: basis; m+1: candidate / work vector; m+2: operator output
   // (an s-step block uses slots m+1..m+s as its work block)
   const int extra = c->st == kry::F64 ? std::max(2, std::min(c->opts.s_step, m)) : 2;
+  c->vextra = 0;
   const size_t vbytes = (size_t)(m + 1 + extra) * c->ldv * c->esz;
   if (hipMalloc(&c->V, vbytes) != hipSuccess) {
     c->V = nullptr;
@@ -241,6 +245,7 @@ int ensure_basis(kry_ctx* c, int m) {
   KRY_HIP(hipMalloc(&c->d_H, sizeof(double) * (size_t)(m + 1) * m));
   KRY_HIP(hipHostMalloc(&c->h_H, sizeof(double) * (size_t)(m + 1) * m, hipHostMallocDefault));
   c->mcap = m;
+  c->vextra = extra;
   return KRY_OK;
 }
 
@@ -3186,6 +3191,55 @@ int api_arnoldi_noalloc(kry_ctx* c, const double* v, int32_t m, void* V_out, dou
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// s-step block size by measurement: one restart cycle of krylov_dim steps,
+// the cycle every solver here runs, from a fixed pseudo-random start vector,
+// per candidate s.  A warm-up cycle sets the Newton shifts (Ritz values of
+// the first cycle, as in a solve) and the best of three further cycles is
+// kept; a candidate whose basis blocks trip the conditioning guard pays for
+// its fallback in its own time.
+namespace {
+
+int api_autotune_sstep(kry_ctx* c, const int32_t* cand, int32_t ncand, int32_t* best, double* us) {
+  if (!c || !cand || !best || !us || ncand < 1 || ncand > 16) return fail(c, KRY_EINVAL, "invalid argument");
+  for (int i = 0; i < ncand; ++i)
+    if (cand[i] < 0 || cand[i] > 64) return fail(c, KRY_EINVAL, "s candidates must be in 0..64");
+  const int m = c->opts.krylov_dim;
+  const int32_t saved = c->opts.s_step;
+  int bi = -1;
+  for (int i = 0; i < ncand; ++i) {
+    c->opts.s_step = cand[i];
+    int rc = ensure_basis(c, m);
+    if (rc) {
+      c->opts.s_step = saved;
+      return rc;
+    }
+    treset(c);
+    double t_best = 1e300;
+    for (int rep = 0; rep < 4; ++rep) {
+      KRY_HIP(kry::launch_fill_hash(slot(c, 0), c->st, c->n, 20170630u, c->stream));
+      const double t0 = now_ms();
+      double beta = 0.0;
+      int me = 0;
+      rc = arnoldi(c, m, &beta, &me);
+      if (rc) {
+        c->opts.s_step = saved;
+        return rc;
+      }
+      KRY_HIP(hipStreamSynchronize(c->stream));
+      if (rep > 0) t_best = std::min(t_best, now_ms() - t0);
+    }
+    us[i] = 1e3 * t_best;
+    if (bi < 0 || us[i] < us[bi]) bi = i;
+  }
+  c->opts.s_step = cand[bi];
+  treset(c);
+  *best = cand[bi];
+  return KRY_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // Exported entry points.  Every body runs inside `guarded`, so no C++
 // exception (a host allocation failure in a std::vector, std::string or
 // std::map, or any other) crosses the C interface: it becomes KRY_ENOMEM or
@@ -3296,6 +3350,10 @@ int kry_block_arnoldi(kry_ctx* c, const double* V0, int32_t p, int32_t mb, void*
 
 int kry_set_tune(kry_ctx* c, const kry_tune* t) {
   return guarded(c, [&] { return api_set_tune(c, t); });
+}
+
+int kry_autotune_sstep(kry_ctx* c, const int32_t* cand, int32_t ncand, int32_t* best, double* us) {
+  return guarded(c, [&] { return api_autotune_sstep(c, cand, ncand, best, us); });
 }
 
 int kry_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {

@@ -180,6 +180,8 @@ hipError_t launch_gather_rows(const double* b, int ncols, long long n, const int
                               double* C, hipStream_t s);
 hipError_t launch_scatter_basis(Storage st, const double* Q, int nr, int r, const int* idx, const double* w,
                                 void* out, long long ld, hipStream_t s);
+// p[0:n] = pseudo-random values in [-1/2, 1/2) from a hash of the index.
+hipError_t launch_fill_hash(void* p, Storage st, long long n, unsigned seed, hipStream_t s);
 int rst_march_max_m();
 hipError_t launch_rst_march(int m, int q, int nt, int ncol, const double* E, const double* W,
                             const double* El, const double* Wl, const double* gw, double beta,

@@ -8,8 +8,8 @@
 // e_m^T u at the nodes):
 //   fout[j q + i] = -hnext (El[i] u + Wl[i] a)      (the next residual source)
 //   u            <- E u + W a.
-// Lane r owns row r of u and keeps row r of E and W in registers; u and a
-// live in LDS, double-buffered, so one barrier per step suffices.
+// Lane r owns u_r and keeps row r of E and W (and, for r < q, of El and Wl)
+// in registers; u and a reach the other lanes by lane broadcasts.
 #include "kry_internal.h"
 
 namespace kry {
@@ -19,6 +19,18 @@ namespace {
 constexpr int kRstM = 64;  // largest projected dimension of the GPU march
 constexpr int kRstQ = 8;   // nodes per time step
 
+// Value of lane `lane` of v, in every lane (lane must be wave-uniform).
+__device__ __forceinline__ double bcast(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// One wave per time function.  Lane r holds u_r and rows r of E and W;
+// lanes r < q also row r of El and Wl.  u and the step's source samples
+// reach every lane by lane broadcasts, so the wave needs neither LDS nor a
+// barrier; four partial sums per dot break the chain of dependent FMAs.
 __global__ __launch_bounds__(64) void k_rst_march(int m, int nt, const double* __restrict__ E,
                                                   const double* __restrict__ W,
                                                   const double* __restrict__ El,
@@ -28,58 +40,67 @@ __global__ __launch_bounds__(64) void k_rst_march(int m, int nt, const double* _
                                                   const double* __restrict__ fin,
                                                   double* __restrict__ fout, long long ldf,
                                                   double* __restrict__ uT, double* __restrict__ resint) {
-  __shared__ double su[2][kRstM];
-  __shared__ double sa[2][kRstQ];
-  __shared__ double sEl[kRstM][kRstQ];  // El transposed: [k][node]
-  __shared__ double sWl[kRstQ][kRstQ];
   const int r = threadIdx.x;
   const int col = cmap ? cmap[blockIdx.x] : (int)blockIdx.x;
   const double* fi = fin + (long long)col * ldf;
   double* fo = fout + (long long)col * ldf;
-  double er[kRstM], wr[kRstQ];
+  double er[kRstM], el[kRstM], wr[kRstQ], wl[kRstQ];
 #pragma unroll
-  for (int k = 0; k < kRstM; ++k) er[k] = (r < m && k < m) ? E[r + (long long)k * m] : 0.0;
+  for (int k = 0; k < kRstM; ++k) {
+    er[k] = (r < m && k < m) ? E[r + (long long)k * m] : 0.0;
+    el[k] = (r < kRstQ && k < m) ? El[(long long)r * m + k] : 0.0;
+  }
 #pragma unroll
-  for (int l = 0; l < kRstQ; ++l) wr[l] = r < m ? W[r + (long long)l * m] : 0.0;
-  for (int k = 0; k < m; ++k)
-    if (r < kRstQ) sEl[k][r] = El[(long long)r * m + k];
-  if (r < kRstQ)
-#pragma unroll
-    for (int l = 0; l < kRstQ; ++l) sWl[r][l] = Wl[r * kRstQ + l];
-  su[0][r] = 0.0;
-  if (r < kRstQ) sa[0][r] = nt > 0 ? beta * fi[r] : 0.0;
+  for (int l = 0; l < kRstQ; ++l) {
+    wr[l] = r < m ? W[r + (long long)l * m] : 0.0;
+    wl[l] = r < kRstQ ? Wl[r * kRstQ + l] : 0.0;
+  }
   const double wnode = r < kRstQ ? gw[r] : 0.0;
+  double u = 0.0;
+  double anext = (r < kRstQ && nt > 0) ? beta * fi[r] : 0.0;
   double racc = 0.0;
-  __syncthreads();
   for (int j = 0; j < nt; ++j) {
-    const int cur = j & 1, nxt = cur ^ 1;
-    // next step's source samples into the other buffer
-    if (r < kRstQ) sa[nxt][r] = (j + 1 < nt) ? beta * fi[(long long)(j + 1) * kRstQ + r] : 0.0;
-    const double* u = su[cur];
-    const double* a = sa[cur];
-    if (r < kRstQ) {
-      double v = 0.0;
-      for (int k = 0; k < m; ++k) v += sEl[k][r] * u[k];
+    const double acur = anext;
+    if (r < kRstQ && j + 1 < nt) anext = beta * fi[(long long)(j + 1) * kRstQ + r];
+    double a[kRstQ];
 #pragma unroll
-      for (int l = 0; l < kRstQ; ++l) v += sWl[r][l] * a[l];
-      const double f = -hnext * v;
+    for (int l = 0; l < kRstQ; ++l) a[l] = bcast(acur, l);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRstM; k += 4) {
+      const double u0 = bcast(u, k), u1 = bcast(u, k + 1), u2 = bcast(u, k + 2), u3 = bcast(u, k + 3);
+      s0 += er[k] * u0;
+      s1 += er[k + 1] * u1;
+      s2 += er[k + 2] * u2;
+      s3 += er[k + 3] * u3;
+      t0 += el[k] * u0;
+      t1 += el[k + 1] * u1;
+      t2 += el[k + 2] * u2;
+      t3 += el[k + 3] * u3;
+    }
+    double sa = 0.0, ta = 0.0;
+#pragma unroll
+    for (int l = 0; l < kRstQ; ++l) {
+      sa += wr[l] * a[l];
+      ta += wl[l] * a[l];
+    }
+    if (r < kRstQ) {
+      const double f = -hnext * (((t0 + t1) + (t2 + t3)) + ta);
       fo[(long long)j * kRstQ + r] = f;
       racc += wnode * fabs(f);
     }
-    double un = 0.0;
-#pragma unroll
-    for (int k = 0; k < kRstM; ++k) un += er[k] * u[k];
-#pragma unroll
-    for (int l = 0; l < kRstQ; ++l) un += wr[l] * a[l];
-    su[nxt][r] = r < m ? un : 0.0;
-    __syncthreads();
+    u = r < m ? ((s0 + s1) + (s2 + s3)) + sa : 0.0;
   }
-  if (r < m) uT[(long long)blockIdx.x * m + r] = su[nt & 1][r];
+  if (r < m) uT[(long long)blockIdx.x * m + r] = u;
   // integral of |fout|: the q node lanes' sums (Gauss weights times dt)
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) racc += __shfl_xor(racc, off, 64);
   if (r == 0) resint[blockIdx.x] = dt * racc;
 }
+
+}  // namespace
+
+namespace {
 
 // mask[e] = 1 where any of the ncols complex interleaved columns of b
 // (stride 2 n doubles) is non-zero at entry e.
@@ -147,6 +168,34 @@ hipError_t launch_scatter_basis(Storage st, const double* Q, int nr, int r, cons
     hipLaunchKernelGGL(k_scatter_basis<double>, grid, dim3(256), 0, s, Q, nr, r, idx, w, (double*)out, ld);
   else
     hipLaunchKernelGGL(k_scatter_basis<float>, grid, dim3(256), 0, s, Q, nr, r, idx, w, (float*)out, ld);
+  return hipGetLastError();
+}
+
+namespace {
+
+// Pseudo-random values in [-1/2, 1/2) from an integer hash of the index (a
+// fixed, reproducible vector for timing runs).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_hash(T* __restrict__ p, long long n, unsigned seed) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  unsigned h = (unsigned)i * 2654435761u ^ seed;
+  h ^= h >> 16;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  h *= 3266489917u;
+  h ^= h >> 16;
+  p[i] = T((double)h * (1.0 / 4294967296.0) - 0.5);
+}
+
+}  // namespace
+
+hipError_t launch_fill_hash(void* p, Storage st, long long n, unsigned seed, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (st == F64)
+    hipLaunchKernelGGL(k_fill_hash<double>, grid, dim3(256), 0, s, (double*)p, n, seed);
+  else
+    hipLaunchKernelGGL(k_fill_hash<float>, grid, dim3(256), 0, s, (float*)p, n, seed);
   return hipGetLastError();
 }
 

@@ -1021,3 +1021,15 @@ def test_autotune_choice_and_results(tmp_path):
     s2 = _solver(inp.eps, None, inp.sigma, krylov_dim=32, tol=1e-9)
     t2 = s2.autotune(cache=cache)
     assert t2["cached"] and t2["cpt_update"] == t["cpt_update"]
+    # the s-step block size: one timed restart cycle per candidate, the
+    # fastest applied; the solve with it agrees with the default one
+    s3 = _solver(inp.eps, None, inp.sigma, krylov_dim=32, tol=1e-9)
+    cache_s = str(tmp_path / "tune_s.json")
+    t3 = s3.autotune(cache=cache_s, s_candidates=(0, 8, 16, 32))
+    _announce(f"autotune with s: {t3}")
+    assert t3["s_step"] in (0, 8, 16, 32) and all(x > 0 for x in t3["us_cycle"])
+    y3 = s3.solve_multifreq(wl.omegas, b, wl.T).cpu().numpy()
+    assert _rel(y3, y0) <= 1e-8
+    s4 = _solver(inp.eps, None, inp.sigma, krylov_dim=32, tol=1e-9)
+    t4 = s4.autotune(cache=cache_s, s_candidates=(0, 8, 16, 32))
+    assert t4["cached"] and t4["s_step"] == t3["s_step"]
