@@ -479,6 +479,52 @@ def test_other_methods_c2_against_oracle_samples(method):
     _check_c2_samples(y, f"c2 {method}")
 
 
+def test_c2_three_routes_agree_on_the_whole_field():
+    # the 128^3 workload by the split (Corollary 3), the residual-restarted
+    # method and source splitting: three routes that share no step beyond
+    # the operator and Arnoldi kernels; each is pinned to the stored oracle
+    # samples elsewhere, here their whole 12.6M-entry fields agree
+    wl = wk.C2
+    _announce("c2 128^3: split, restarted and source splitting on the whole field")
+    inp = wk.generate(wl)
+    b = _t(wk.source_vector(wl, wl.omegas[0], 0.0)[None, :])
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=wl.tol)
+    y1 = s.solve_multifreq(wl.omegas, b, wl.T)[0]
+    y2 = s.solve_restarted(wl.omegas, b, wl.T)[0]
+    y3 = s.solve_split2(wl.omegas, b, wl.T, periods=5)[0]
+    s.close()
+    n1 = float(torch.linalg.norm(y1))
+    d12 = float(torch.linalg.norm(y1 - y2)) / n1
+    d13 = float(torch.linalg.norm(y1 - y3)) / n1
+    _announce(f"c2 whole field: split vs restarted {d12:.2e}, split vs source splitting {d13:.2e}")
+    # each route stops at relative error tol = 1e-8, so two of them differ by
+    # at most twice that
+    assert d12 <= 2e-8 and d13 <= 2e-8
+
+
+def test_sstep_basis_orthogonality_at_full_size():
+    # s-step Arnoldi (s = 16, one Gram-Schmidt pass where the block's
+    # condition estimate allows) on the 128^3 medium from its plane source,
+    # m = 64: the basis is M-orthonormal to 1e-10 and satisfies the Arnoldi
+    # relation at full size, where the skipped second passes happen
+    wl = wk.C2
+    _announce("s-step basis orthogonality at 128^3")
+    inp = wk.generate(wl)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=64, tol=1e-8, s_step=16)
+    v = _t(wk.source_vector(wl, wl.omegas[0], 0.0).real)
+    V, H, beta, steps = s.arnoldi(v, 64)
+    assert steps == 64
+    w = _t(op.material_weights(inp.eps, inp.mu))
+    G = (V * w) @ V.T
+    orth = float((G - torch.eye(65, dtype=G.dtype, device=G.device)).abs().max())
+    AV = s.apply(V[:64].contiguous())
+    Ht = torch.as_tensor(H, device=V.device)
+    rel = float(torch.linalg.norm(AV - Ht.T @ V) / torch.linalg.norm(AV))
+    s.close()
+    _announce(f"128^3 s-step basis: max |V^T M V - I| {orth:.2e}, Arnoldi relation {rel:.2e}")
+    assert orth <= 1e-10 and rel <= 1e-12
+
+
 @pytest.mark.skipif(not os.path.exists(GOLD_C3), reason="c3 oracle samples not generated")
 def test_batched_c3_all_columns_restarted_against_oracle_samples():
     """The batched workload as configured: all 256 columns (32 frequencies x
