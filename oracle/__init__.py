@@ -22,9 +22,14 @@ What it computes, following the paper (arXiv 1707.00023):
   field through a z-plane and its exact gradient with respect to per-cell
   permittivity (the paper is silent on gradients; the reading is documented
   in the design notes), plus brute-force central differences.
+* ``transient_grad`` -- the instantaneous flux of the whole solution at a
+  finite time T (time-harmonic part minus the transient of equation
+  (y_homo)) and its gradient w.r.t. per-cell permittivity by forward
+  differentiation (library solves and the Frechet derivative of the matrix
+  exponential), plus central differences.
 
 Readings of the paper where it is silent or 2D-only (3D Yee staggering,
 zero-ghost boundary, damping scaling sigma/eps, angular omega, minus sign of
 the split) are listed in the design notes and restated in each docstring.
 """
-from . import operator, solve, grad, krylov  # noqa: F401
+from . import operator, solve, grad, krylov, transient_grad  # noqa: F401

@@ -440,3 +440,103 @@ def test_gmres_route_raises_when_target_is_missed():
     assert res < 1e-12
     with pytest.raises(RuntimeError, match="did not converge"):
         osv.shifted_solve(As, b, "gmres", rtol=1e-30)
+
+
+# --- the flux at a finite time T and its forward-mode gradient -------------
+
+def _tflux_case(N, kf, omegas, seed=21):
+    wl = wk.small(N, seed=seed, n_spheres=1, layer=1, radius=(0.8, 1.4), omegas=omegas, src_k=0)
+    inp = wk.generate(wl)
+    b_cols = np.stack([wk.source_vector(wl, w, 0.0) for w in wl.omegas], axis=1)
+    return wl, inp, b_cols
+
+
+def test_instantaneous_flux_hand_cases():
+    # 3^3 grid, plane kf = 1: the z-component of E x H for a real field,
+    # Ex Hy - Ey Hx, with H averaged over the planes below (k = 0) and above
+    # (k = 1) the E plane
+    from oracle import transient_grad as tg
+    N, kf = 3, 1
+
+    def state(**entries):
+        y = np.zeros((6, N, N, N))
+        for name, (k, val) in entries.items():
+            y[wk.COMPONENTS.index(name), k, 2, 0] = val
+        return y.reshape(-1)
+
+    assert tg.flux_real(state(Ex=(1, 1.0), Hy=(0, 2.0)), N, kf) == pytest.approx(1.0, abs=1e-15)
+    assert tg.flux_real(state(Ex=(1, 3.0), Hy=(1, 2.0)), N, kf) == pytest.approx(3.0, abs=1e-15)
+    assert tg.flux_real(state(Ey=(1, 1.0), Hx=(1, 2.0)), N, kf) == pytest.approx(-1.0, abs=1e-15)
+    assert tg.flux_real(state(Ey=(1, -1.0), Hx=(0, 4.0)), N, kf) == pytest.approx(2.0, abs=1e-15)
+    assert tg.flux_real(state(Ex=(1, 1.0), Hy=(2, 5.0)), N, kf) == 0.0
+    assert tg.flux_real(state(Ez=(1, 1.0), Hx=(1, 5.0), Hy=(0, 3.0)), N, kf) == 0.0
+
+
+def test_instantaneous_flux_averages_to_the_harmonic_flux():
+    # over one period the instantaneous flux of Im(e^{i w t} z) averages to
+    # the period-averaged flux 1/2 Re(Ex conj(Hy) - Ey conj(Hx)) (the flux is
+    # quadratic, so four equispaced phases average it exactly)
+    from oracle import transient_grad as tg
+    rng = np.random.default_rng(8)
+    N, kf, w = 4, 2, 0.7
+    z = rng.standard_normal(6 * N ** 3) + 1j * rng.standard_normal(6 * N ** 3)
+    per = 2 * math.pi / w
+    avg = np.mean([tg.flux_real(np.imag(np.exp(1j * w * j * per / 4) * z), N, kf) for j in range(4)])
+    assert avg == pytest.approx(og.flux(z, N, kf), rel=1e-13)
+    # and its derivative is the one central differences give (F is quadratic)
+    y = rng.standard_normal(6 * N ** 3)
+    d = rng.standard_normal(6 * N ** 3)
+    fd = (tg.flux_real(y + d, N, kf) - tg.flux_real(y - d, N, kf)) / 2
+    assert tg.flux_real_grad(y, N, kf) @ d == pytest.approx(fd, rel=1e-12)
+
+
+def test_expm_derivative_routes_against_differences():
+    # the block identity route (expm_multiply on a 2n system) and scipy's
+    # dense Frechet derivative against central differences of e^{-T(A + h dA)} v
+    from oracle import transient_grad as tg
+    wl, inp = _medium(4, seed=6)
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    d_eps = np.random.default_rng(2).standard_normal(inp.eps.shape)
+    dA = tg._dA(A, inp.eps, d_eps)
+    v = wk.random_state(wl.n, 5)
+    T, h = 6.0, 1e-5
+    fd = (osv.expv(A + h * dA, T, v) - osv.expv(A - h * dA, T, v)) / (2 * h)
+    dense = tg.expm_derivative(A, dA, T, v, "dense")
+    sparse = tg.expm_derivative(A, dA, T, v, "sparse")
+    assert np.linalg.norm(dense - fd) <= 1e-8 * np.linalg.norm(fd)
+    assert np.linalg.norm(sparse - dense) <= 1e-11 * np.linalg.norm(dense)
+    # the perturbation changes only the E rows: a change of the H rows'
+    # weights (mu) is not what d eps means
+    assert np.abs(dA[: 3 * inp.eps.size].toarray()).max() == 0.0
+
+
+def test_transient_flux_gradient_matches_fd_every_cell():
+    from oracle import transient_grad as tg
+    N, kf, T = 3, 2, 7.0
+    wl, inp, b_cols = _tflux_case(N, kf, (2 * math.pi * 0.1,))
+    g = tg.grad(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, kf, T)
+    cells = [(i, j, k) for k in range(N) for j in range(N) for i in range(N)]
+    fd = tg.fd_grad(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, kf, T, cells, h=1e-5)
+    gv = np.array([g[k, j, i] for (i, j, k) in cells])
+    assert np.linalg.norm(gv - fd) <= 1e-7 * np.linalg.norm(fd)
+    # the transient matters here: dropping it changes the gradient
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    y, z = tg.field_at_T(A, b_cols[:, 0], wl.omegas[0], T)
+    assert np.linalg.norm(osv.expv(A, T, np.imag(z))) > 0.1 * np.linalg.norm(y)
+
+
+def test_transient_flux_directional_derivative_routes():
+    # per-cell gradient, dense and block-identity directional derivatives on
+    # two frequencies agree, and all vanish at T = 0 (y(0) = 0)
+    from oracle import transient_grad as tg
+    N, kf, T = 3, 1, 5.0
+    wl, inp, b_cols = _tflux_case(N, kf, (2 * math.pi * 0.09, 2 * math.pi * 0.11), seed=4)
+    g = tg.grad(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, kf, T)
+    d = np.random.default_rng(3).standard_normal(inp.eps.shape)
+    dd = tg.directional(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, kf, T, d, "dense")
+    ds = tg.directional(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, kf, T, d, "sparse")
+    assert dd == pytest.approx(float((g * d).sum()), rel=1e-11)
+    assert ds == pytest.approx(dd, rel=1e-11)
+    assert tg.loss(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, kf, 0.0) == pytest.approx(0.0, abs=1e-15)
+    assert tg.directional(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, kf, 0.0, d) == \
+        pytest.approx(0.0, abs=1e-14)
