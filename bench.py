@@ -262,6 +262,43 @@ def precision_compare(args, wl, inp, dev):
     print(json.dumps(out), flush=True)
 
 
+def grad_transient_bench(args, wl, inp, dev):
+    """Gradient of the flux of the field at time T (transient included) on
+    the gradient workload's medium and frequencies, timed once after one
+    untimed run, beside the time-averaged gradient of the same workload."""
+    import torch
+
+    import paper_1707_00023_amd as kry
+    import workloads as wk
+
+    eps = torch.as_tensor(inp.eps, device=dev)
+    sig = torch.as_tensor(inp.sigma, device=dev)
+    b = torch.as_tensor(wk.source_vector(wl, wl.omegas[0], 0.0)[None, :], device=dev)
+    kf = wl.flux_plane
+    s = kry.Solver(eps, None, sig, kry.Options(krylov_dim=wl.krylov_dim, tol=wl.tol, timing=True,
+                                               s_step=args.s_step))
+    out = {"metric": "finite-time flux gradient, time to solution", "workload": wl.name,
+           "n": wl.n, "omegas": list(wl.omegas), "plane_k": kf, "T": args.grad_transient,
+           "krylov_dim": wl.krylov_dim, "tol": wl.tol}
+    for name, fn in (("time_averaged", lambda: s.grad(wl.omegas, b, kf)),
+                     ("finite_time", lambda: s.grad_transient(wl.omegas, b, kf, args.grad_transient))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L, g = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = s.last_stats
+        out[name] = {"s": dt, "loss": L, "grad_norm": float(torch.linalg.norm(g)),
+                     "matvecs_stationary": st["matvecs_stationary"],
+                     "matvecs_transient": st["matvecs_transient"],
+                     "steps_transient": st["steps_transient"],
+                     "ms_stationary": st["ms_stationary"], "ms_transient": st["ms_transient"]}
+        print(f"[bench] gradient {name}: {dt:.2f} s", file=sys.stderr, flush=True)
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
 def other_methods(solver, wl, b, per_omega, split_stats, args):
     """The paper's other routes to the same y(T), each timed once on the same
     workload and solver after the split steps: the residual-restarted Krylov
@@ -341,6 +378,9 @@ def main():
                     help="skip the one-off timings of the restarted method and source splitting")
     ap.add_argument("--split2-periods", type=int, default=5,
                     help="source splitting: periods of the source per subinterval")
+    ap.add_argument("--grad-transient", type=float, default=None, metavar="T",
+                    help="time the gradient of the flux of the field at time T (transient "
+                         "included) on the gradient workload (use with --workload c4)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="after the timed steps, one device copy of 1 GiB each way (the "
                          "reference dispatch that scales HBM counters to bytes)")
@@ -368,6 +408,9 @@ def main():
         return
     if args.precision_compare:
         precision_compare(args, wl, inp, dev)
+        return
+    if args.grad_transient is not None:
+        grad_transient_bench(args, wl, inp, dev)
         return
     eps = torch.as_tensor(inp.eps, device=dev)
     sig = torch.as_tensor(inp.sigma, device=dev)

@@ -350,6 +350,34 @@ int kry_grad(kry_ctx* ctx, const double* omegas, int32_t n_omega, const double* 
              int32_t b_per_omega, int32_t plane_k, double* loss, double* dL_deps,
              kry_stats* stats);
 
+/* Flux at a finite time T, the transient included, and its gradient w.r.t.
+ * per-cell permittivity.  The field is the whole solution of Corollary 3,
+ * y_w(T) = Im(e^{i w T} z_w) - e^{-T A} Im z_w (equation (split1); the
+ * transient solves the homogeneous problem (y_homo)), and the loss is its
+ * instantaneous Poynting flux through the plane z = plane_k, summed over the
+ * frequencies:
+ *     L = sum_w sum_{i,j} [Ex Hy_bar - Ey Hx_bar](y_w(T)),
+ * Hy_bar, Hx_bar the means of the H planes plane_k - 1 and plane_k (the
+ * paper computes no gradients).  With g = dF/dy(T), dL/d eps has a term
+ * through z (one adjoint shifted solve per frequency, right-hand side
+ * e^{i w T} g - e^{-T A^T} g, by the identity A^T = M P A P M^{-1}) and a
+ * term through e^{-TA}, the Frechet derivative of the exponential: the
+ * integral over [0, T] of e^{-(T-s)A^T} g against (dA) e^{-sA} Im z.  Both
+ * transients (forward from Im z, adjoint from P M^{-1} g) run by restarts
+ * in time with the start vector of every step kept; each step's Krylov
+ * basis is regenerated once from it, and the integral over every interval
+ * where a forward and an adjoint step overlap is a small matrix of the two
+ * projected problems, integrated by Gauss-Legendre panels on the host, and
+ * applied per cell on the GPU.
+ * Arguments as for kry_grad, plus T >= 0 (host).  Workspace allocated per
+ * call: 2 (m + 3) vectors of the storage type, 3 FP64 n-vectors, and one
+ * checkpoint vector per time step of each transient.  Targets: shifted
+ * residuals opts.tol relative; each transient's error below opts.tol
+ * relative to its start vector.  stats may be NULL. */
+int kry_grad_transient(kry_ctx* ctx, const double* omegas, int32_t n_omega, const double* b,
+                       int32_t b_per_omega, int32_t plane_k, double T, double* loss,
+                       double* dL_deps, kry_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

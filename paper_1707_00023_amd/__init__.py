@@ -28,7 +28,7 @@ EXPORTED = ("kry_create", "kry_destroy", "kry_last_error", "kry_size", "kry_appl
             "kry_apply_f32", "kry_arnoldi", "kry_expv", "kry_solve_multifreq",
             "kry_stationary", "kry_grad", "kry_block_arnoldi", "kry_autotune",
             "kry_set_tune", "kry_arnoldi_noalloc", "kry_solve_restarted", "kry_solve_split2",
-            "kry_autotune_sstep")
+            "kry_autotune_sstep", "kry_grad_transient")
 
 
 class KryGrid(ctypes.Structure):
@@ -125,6 +125,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kry_solve_split2.argtypes = [P, P, I32, I32, P, I32, D, I32, P, ctypes.POINTER(KryStats)]
     lib.kry_grad.argtypes = [P, P, I32, P, I32, I32, ctypes.POINTER(D), P,
                              ctypes.POINTER(KryStats)]
+    lib.kry_grad_transient.argtypes = [P, P, I32, P, I32, I32, D, ctypes.POINTER(D), P,
+                                       ctypes.POINTER(KryStats)]
     lib.kry_block_arnoldi.argtypes = [P, P, I32, I32, P, P]
     lib.kry_block_arnoldi.restype = ctypes.c_int
     lib.kry_autotune.argtypes = [P, I32, ctypes.POINTER(KryTune)]
@@ -135,7 +137,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kry_autotune_sstep.restype = ctypes.c_int
     for name in ("kry_apply", "kry_apply_f32", "kry_arnoldi", "kry_expv",
                  "kry_solve_multifreq", "kry_stationary", "kry_grad", "kry_solve_restarted",
-                 "kry_solve_split2"):
+                 "kry_solve_split2", "kry_grad_transient"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -452,6 +454,31 @@ class Solver:
         self._check(rc, allow_noconv, self.last_stats)
         return loss.value, g
 
+    def grad_transient(self, omegas: Sequence[float], b, plane_k: int, T: float,
+                       b_per_omega: bool = False, loss_only: bool = False,
+                       allow_noconv: bool = False):
+        """(L, dL/d eps) of the instantaneous flux through plane z = plane_k of
+        the whole field at time T (time-harmonic part minus the transient).
+
+        b: complex128 (1, n) shared source or (n_omega, n) per-omega sources.
+        Returns the loss (float) and dL/d eps as a float64 (nz, ny, nx) tensor.
+        """
+        import torch
+        om, b, nw, nsrc = self._omega_b(omegas, b, b_per_omega)
+        if nsrc != 1:
+            raise ValueError("one source per frequency (or one shared source)")
+        g = None if loss_only else torch.empty((self.grid.nz, self.grid.ny, self.grid.nx),
+                                               dtype=torch.float64, device=self.device)
+        loss = ctypes.c_double()
+        st = KryStats()
+        rc = self._lib.kry_grad_transient(self._ctx, om.ctypes.data_as(ctypes.c_void_p), nw, _ptr(b),
+                                          int(bool(b_per_omega)), int(plane_k), float(T),
+                                          ctypes.byref(loss), None if g is None else _ptr(g),
+                                          ctypes.byref(st))
+        self.last_stats = st.as_dict()
+        self._check(rc, allow_noconv, self.last_stats)
+        return loss.value, g
+
 
 def _flux_function():
     import torch
@@ -485,3 +512,36 @@ def flux_loss(eps, sigma, b, omegas, plane_k, opts: Optional[Options] = None,
     """Differentiable transmitted power (torch.autograd) w.r.t. per-cell eps."""
     return _flux_function().apply(eps, sigma, b, omegas, plane_k, opts or Options(),
                                   b_per_omega)
+
+
+def _flux_at_function():
+    import torch
+
+    class FluxAtT(torch.autograd.Function):
+        """L(eps) = instantaneous flux of the field at time T; backward by the
+        adjoint of the shifted solves and of the exponential."""
+
+        @staticmethod
+        def forward(ctx, eps, sigma, b, omegas, plane_k, T, opts, b_per_omega):
+            solver = Solver(eps.detach(), None, sigma, opts)
+            try:
+                L, g = solver.grad_transient(omegas, b, plane_k, T, b_per_omega)
+            finally:
+                solver.close()
+            ctx.save_for_backward(g)
+            return torch.tensor(L, dtype=torch.float64, device=eps.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (g,) = ctx.saved_tensors
+            return grad_out * g, None, None, None, None, None, None, None
+
+    return FluxAtT
+
+
+def flux_loss_at(eps, sigma, b, omegas, plane_k, T, opts: Optional[Options] = None,
+                 b_per_omega: bool = False):
+    """Differentiable flux of the field at time T (transient included),
+    w.r.t. per-cell eps."""
+    return _flux_at_function().apply(eps, sigma, b, omegas, plane_k, T, opts or Options(),
+                                     b_per_omega)

@@ -664,7 +664,49 @@ int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> 
 // dissipative in that norm, so e^{-sA} does not amplify it), and the total
 // stays below abstol.  Once |y_hat(t)|_M <= drop the remainder is dropped
 // (e^{-(T-t)A} cannot increase it).
-int expv_slot0(kry_ctx* c, double T, double abstol, double drop, kry_stats* st, double* err_est) {
+// With `tr`, every step's start vector is kept (checkpoint) with its start
+// time, length and basis size, for a later pass that regenerates the step's
+// Krylov basis from it (the gradient through the exponential).
+struct ExpvTrace {
+  void* ck = nullptr;  // device: checkpoint j at ck + j ldv (storage type)
+  int cap = 0;
+  std::vector<double> t0, tau, hnorm;  // per step; hnorm = |H|_1 of its basis
+  ExpvTrace() = default;
+  ExpvTrace(const ExpvTrace&) = delete;
+  ExpvTrace& operator=(const ExpvTrace&) = delete;
+  ~ExpvTrace() { hipFree(ck); }
+  int steps() const { return (int)t0.size(); }
+  void clear() { t0.clear(), tau.clear(), hnorm.clear(); }
+};
+
+void* trace_ck(kry_ctx* c, const ExpvTrace* tr, int j) {
+  return (char*)tr->ck + (size_t)j * c->ldv * c->esz;
+}
+
+// Copy slot 0 into checkpoint tr->steps(), growing the buffer as needed.
+int trace_push(kry_ctx* c, ExpvTrace* tr) {
+  const int j = tr->steps();
+  if (j >= tr->cap) {
+    const int cap = std::max(8, 2 * tr->cap);
+    void* nb = nullptr;
+    if (hipMalloc(&nb, (size_t)cap * c->ldv * c->esz) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, KRY_ENOMEM, "cannot allocate checkpoints of the exponential");
+    }
+    if (j > 0)
+      KRY_HIP(hipMemcpyAsync(nb, tr->ck, (size_t)j * c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
+    KRY_HIP(hipStreamSynchronize(c->stream));
+    hipFree(tr->ck);
+    tr->ck = nb;
+    tr->cap = cap;
+  }
+  KRY_HIP(hipMemcpyAsync(trace_ck(c, tr, j), slot(c, 0), c->ldv * c->esz, hipMemcpyDeviceToDevice,
+                         c->stream));
+  return KRY_OK;
+}
+
+int expv_slot0(kry_ctx* c, double T, double abstol, double drop, kry_stats* st, double* err_est,
+               ExpvTrace* tr = nullptr) {
   const int m = c->opts.krylov_dim;
   int rc = ensure_basis(c, m);
   if (rc) return rc;
@@ -680,6 +722,10 @@ int expv_slot0(kry_ctx* c, double T, double abstol, double drop, kry_stats* st, 
   int steps = 0;
   while (t < T) {
     if (steps >= maxsteps) { *err_est = err; return KRY_ENOCONV; }
+    if (tr) {
+      rc = trace_push(c, tr);
+      if (rc) return rc;
+    }
     double beta = 0.0;
     int me = 0;
     rc = arnoldi(c, m, &beta, &me);
@@ -715,6 +761,17 @@ int expv_slot0(kry_ctx* c, double T, double abstol, double drop, kry_stats* st, 
       if (t + tau > T * (1.0 - 1e-15)) tau = tmax;
     }
     err += step_err;
+    if (tr) {
+      double hn = 0.0;
+      for (int j = 0; j < me; ++j) {
+        double col = 0.0;
+        for (int i = 0; i <= std::min(j + 1, me - 1); ++i) col += std::abs(c->h_H[i + (size_t)j * ldh]);
+        hn = std::max(hn, col);
+      }
+      tr->t0.push_back(t);
+      tr->tau.push_back(tau);
+      tr->hnorm.push_back(hn);
+    }
     if (c->opts.verbose && steps % 20 == 0)
       std::fprintf(stderr, "[kry] exponential step %d: t = %.4g of %.4g\n", steps, t + tau, T);
     KRY_HIP(hipMemcpyAsync(c->d_Y, u.data(), sizeof(double) * me, hipMemcpyHostToDevice, c->stream));
@@ -1897,7 +1954,9 @@ int transient_steps(kry_ctx* c) {
   return c->opts.block_steps_transient > 0 ? c->opts.block_steps_transient : 32;
 }
 
-int expv_slot0(kry_ctx* c, double T, double abstol, double drop, kry_stats* st, double* err_est);
+struct ExpvTrace;
+int expv_slot0(kry_ctx* c, double T, double abstol, double drop, kry_stats* st, double* err_est,
+               ExpvTrace* tr);
 
 // Transients for a group of g columns: X (slots at xs, g columns) holds
 // Im z_k; e^{-T A} X by restarts in time with block Arnoldi, left in X.
@@ -2369,6 +2428,385 @@ int api_grad(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
   if (st) {
     st->max_residual = max_res;
     st->ms_stationary = st->ms_total = now_ms() - t0;
+    st->converged = status == KRY_OK;
+    texport(c, st);
+  }
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// Gradient of the flux at a finite time T, the transient included.
+//
+// L = sum_w F(y_w(T)), F the instantaneous Poynting flux of the real field
+// y_w(T) = Im(e^{iwT} z) - x(T) through plane k_f (Corollary 3, with
+// x(s) = e^{-sA} Im z the transient of equation (y_homo)).  With
+// g = dF/dy(T) and r0 = P M^-1 g (P = +1 on H rows, -1 on E rows), the
+// identity A^T = M P A P M^-1 gives e^{-tA^T} g = M P r(t) with
+// r(t) = e^{-tA} r0, so the adjoint transient runs on A itself, and
+//   dL/d eps_c = sum_E Im(lam (A z)) / eps_c              (through z)
+//              + sum_E int_0^T r(T - s) (A x(s)) ds        (through e^{-TA})
+// with (A^T + i w) lam = e^{iwT} g - M P r(T), solved as the forward
+// system (A + i w) x = sin(wT) r0 + i (r(T) - cos(wT) r0), lam = -i M P x.
+// The second term is the Frechet derivative of the exponential.  Both
+// transients run by restarts in time with their start vectors kept; the
+// integral is taken over every interval where one forward step (basis V,
+// x(s) = V u(s), A x(s) = V Hbar u(s)) and one backward step (basis W,
+// r(T - s) = W w(T - s)) overlap, each basis regenerated once from its
+// checkpoint: it is sum_ij V_i C_ij W_j per entry with C = Hbar int u w^T ds,
+// a small matrix integrated on the host by Gauss-Legendre panels fine
+// enough for the bases' norms.
+
+// One regenerated basis and the propagators of the panel grid's node gaps.
+struct GapBasis {
+  int me = 0;  // Arnoldi steps (0: the start vector was zero)
+  int nv = 0;  // basis vectors in A V_me = V_nv Hbar (me + 1, or me on an invariant subspace)
+  double beta = 0.0;
+  std::vector<double> H;               // me x me, column-major
+  std::vector<double> Hb;              // nv x me, column-major
+  std::vector<std::vector<double>> D;  // e^{-gap_g H} per distinct gap
+};
+
+int regen_basis(kry_ctx* c, const ExpvTrace* tr, int j, void* dst, const std::vector<double>& gaps,
+                GapBasis* b, kry_stats* st) {
+  const int m = c->opts.krylov_dim;
+  const int ldh = m + 1;
+  KRY_HIP(hipMemcpyAsync(slot(c, 0), trace_ck(c, tr, j), c->ldv * c->esz, hipMemcpyDeviceToDevice,
+                         c->stream));
+  double beta = 0.0;
+  int me = 0;
+  int rc = arnoldi(c, m, &beta, &me);
+  if (rc) return rc;
+  if (st) st->matvecs_transient += me;
+  b->me = me;
+  b->beta = beta;
+  b->nv = me == m ? m + 1 : me;
+  if (me == 0) return KRY_OK;
+  KRY_HIP(hipMemcpyAsync(dst, slot(c, 0), (size_t)b->nv * c->ldv * c->esz, hipMemcpyDeviceToDevice,
+                         c->stream));
+  b->H.assign((size_t)me * me, 0.0);
+  b->Hb.assign((size_t)b->nv * me, 0.0);
+  for (int q = 0; q < me; ++q)
+    for (int i = 0; i < b->nv; ++i) {
+      const double h = c->h_H[i + (size_t)q * ldh];
+      b->Hb[i + (size_t)q * b->nv] = h;
+      if (i < me) b->H[i + (size_t)q * me] = h;
+    }
+  b->D.assign(gaps.size(), {});
+  std::vector<double> X((size_t)me * me);
+  for (size_t g = 0; g < gaps.size(); ++g) {
+    for (size_t i = 0; i < X.size(); ++i) X[i] = -gaps[g] * b->H[i];
+    b->D[g].resize((size_t)me * me);
+    kry::expm(me, X.data(), b->D[g].data());
+  }
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  return KRY_OK;
+}
+
+// beta e^{-h H} e_1 (length me).
+std::vector<double> exp_e1(const GapBasis& b, double h) {
+  const int me = b.me;
+  std::vector<double> X((size_t)me * me), E((size_t)me * me), u(me);
+  for (size_t i = 0; i < X.size(); ++i) X[i] = -h * b.H[i];
+  kry::expm(me, X.data(), E.data());
+  for (int i = 0; i < me; ++i) u[i] = b.beta * E[i];
+  return u;
+}
+
+void matvec(int me, const std::vector<double>& D, const std::vector<double>& x, std::vector<double>& y) {
+  y.assign(me, 0.0);
+  for (int q = 0; q < me; ++q) {
+    const double xq = x[q];
+    const double* col = D.data() + (size_t)q * me;
+    for (int i = 0; i < me; ++i) y[i] += col[i] * xq;
+  }
+}
+
+// The Frechet term over [0, T] from the two traces; V and W: device buffers
+// of m + 1 vectors each, dC: (m + 1) x frechet_cols() doubles.
+int frechet_term(kry_ctx* c, double T, const ExpvTrace& trf, const ExpvTrace& trb, void* Vb, void* Wb,
+                 double* dC, double* g, kry_stats* st) {
+  const int Kf = trf.steps(), Kb = trb.steps();
+  if (Kf == 0 || Kb == 0 || !(T > 0.0)) return KRY_OK;
+  // forward steps cover s in [t_k, t_k + tau_k); backward steps sigma in
+  // (sigma_l, sigma_l + tau_l], i.e. s in [T - sigma_l - tau_l, T - sigma_l)
+  const double fend = trf.t0[Kf - 1] + trf.tau[Kf - 1];
+  const double bend = trb.t0[Kb - 1] + trb.tau[Kb - 1];
+  const double lo = std::max(0.0, T - bend), hi = std::min(T, fend);
+  if (!(hi > lo)) return KRY_OK;
+  // panel grid: 8-point Gauss-Legendre panels of width delta, with delta
+  // times the sum of the two bases' norms at most 2.5 (the integrand's
+  // frequencies are sums of eigenvalues of the two projected matrices)
+  constexpr int Q = 8;
+  double hmax_f = 0.0, hmax_b = 0.0;
+  for (double h : trf.hnorm) hmax_f = std::max(hmax_f, h);
+  for (double h : trb.hnorm) hmax_b = std::max(hmax_b, h);
+  const double den = std::max(hmax_f + hmax_b, 1e-300);
+  const long long P = std::max(1LL, (long long)std::ceil(T * den / 2.5));
+  if (P > (1LL << 26)) return fail(c, KRY_EINVAL, "time horizon too long for the gradient's panel grid");
+  const double delta = T / (double)P;
+  double xq[Q], wq[Q];
+  kry::gauss_legendre01(Q, xq, wq);
+  auto node = [&](long long id) { return ((double)(id / Q) + xq[id % Q]) * delta; };
+  auto first_at_or_after = [&](double a) {
+    long long id = std::max(0LL, (long long)std::floor(a / delta) - 1) * Q;
+    while (id < P * Q && node(id) < a) ++id;
+    return id;
+  };
+  // distinct gaps between consecutive nodes: within a panel (x_{q+1} - x_q)
+  // delta, and across panels (1 - x_{Q-1} + x_0) delta; gap index of the
+  // step from node id to id + 1 is gidx[id % Q]
+  std::vector<double> gaps;
+  int gidx[Q];
+  for (int q = 0; q < Q; ++q) {
+    const double gv = q < Q - 1 ? (xq[q + 1] - xq[q]) * delta : (1.0 - xq[Q - 1] + xq[0]) * delta;
+    int found = -1;
+    for (size_t k = 0; k < gaps.size(); ++k)
+      if (std::abs(gaps[k] - gv) <= 1e-13 * delta) found = (int)k;
+    if (found < 0) {
+      found = (int)gaps.size();
+      gaps.push_back(gv);
+    }
+    gidx[q] = found;
+  }
+  // breakpoints of the overlap
+  std::vector<double> bp = {lo, hi};
+  for (int k = 0; k < Kf; ++k)
+    if (trf.t0[k] > lo && trf.t0[k] < hi) bp.push_back(trf.t0[k]);
+  for (int l = 0; l < Kb; ++l) {
+    const double sb = T - trb.t0[l];
+    if (sb > lo && sb < hi) bp.push_back(sb);
+  }
+  std::sort(bp.begin(), bp.end());
+  const int fcols = kry::frechet_cols();
+  const int m = c->opts.krylov_dim;
+  GapBasis bf, bb;
+  int kcur = -1, lcur = -1;
+  long long fid = 0;  // node at which uf is evaluated
+  std::vector<double> uf, tmp;
+  long long wlo = 0;  // first node id held in wn
+  std::vector<std::vector<double>> wn;
+  std::vector<double> S, C, Cc((size_t)(m + 1) * fcols);
+  for (size_t ib = 0; ib + 1 < bp.size(); ++ib) {
+    const double a = bp[ib], b = bp[ib + 1];
+    if (!(b - a > 1e-14 * T)) continue;
+    const double mid = 0.5 * (a + b);
+    // forward step containing mid; backward step whose s-range contains mid
+    int k = (int)(std::upper_bound(trf.t0.begin(), trf.t0.end(), mid) - trf.t0.begin()) - 1;
+    if (k < 0 || mid >= trf.t0[k] + trf.tau[k]) continue;
+    int l = -1;
+    for (int q = 0; q < Kb; ++q)
+      if (T - trb.t0[q] - trb.tau[q] <= mid && mid < T - trb.t0[q]) { l = q; break; }
+    if (l < 0) continue;
+    if (k != kcur) {
+      int rc = regen_basis(c, &trf, k, Vb, gaps, &bf, st);
+      if (rc) return rc;
+      kcur = k;
+      fid = first_at_or_after(trf.t0[k]);
+      if (bf.me > 0 && fid < P * Q) uf = exp_e1(bf, node(fid) - trf.t0[k]);
+    }
+    if (l != lcur) {
+      int rc = regen_basis(c, &trb, l, Wb, gaps, &bb, st);
+      if (rc) return rc;
+      lcur = l;
+      wn.clear();
+      if (bb.me > 0) {
+        // nodes of s in [top - tau_l, top), padded by a rounding margin (the
+        // breakpoints are T - sigma_l, computed apart)
+        const double top = T - trb.t0[l];  // sigma = sigma_l
+        const double pad = 1e-12 * T;
+        const long long idb = first_at_or_after(std::max(0.0, top - trb.tau[l] - pad));
+        const long long idt = first_at_or_after(top + pad) - 1;
+        if (idt >= idb) {
+          wlo = idb;
+          wn.assign((size_t)(idt - idb + 1), {});
+          wn.back() = exp_e1(bb, top - node(idt));
+          for (long long id = idt - 1; id >= idb; --id)
+            matvec(bb.me, bb.D[gidx[id % Q]], wn[(size_t)(id + 1 - wlo)], wn[(size_t)(id - wlo)]);
+        }
+      }
+    }
+    if (bf.me == 0 || bb.me == 0 || wn.empty()) continue;
+    const long long id0 = first_at_or_after(a), id1 = first_at_or_after(b);
+    if (id1 <= id0) continue;
+    // S = sum over the nodes of weight * u w^T (me_f x me_b, column-major)
+    S.assign((size_t)bf.me * bb.me, 0.0);
+    while (fid < id0) {  // the overlap may begin inside the forward step
+      matvec(bf.me, bf.D[gidx[fid % Q]], uf, tmp);
+      uf.swap(tmp);
+      ++fid;
+    }
+    for (long long id = id0; id < id1; ++id) {
+      if (id < wlo || id - wlo >= (long long)wn.size()) return fail(c, KRY_EINVAL, "node outside the adjoint step");
+      const std::vector<double>& wv = wn[(size_t)(id - wlo)];
+      const double wt = wq[id % Q] * delta;
+      for (int j = 0; j < bb.me; ++j) {
+        const double wj = wt * wv[j];
+        double* Sj = S.data() + (size_t)j * bf.me;
+        for (int i = 0; i < bf.me; ++i) Sj[i] += uf[i] * wj;
+      }
+      matvec(bf.me, bf.D[gidx[id % Q]], uf, tmp);
+      uf.swap(tmp);
+      ++fid;
+    }
+    // C = Hbar S (nv_f x me_b), then the device accumulation per chunk of
+    // 64 columns of W
+    C.assign((size_t)bf.nv * bb.me, 0.0);
+    for (int j = 0; j < bb.me; ++j)
+      for (int q = 0; q < bf.me; ++q) {
+        const double sq = S[q + (size_t)j * bf.me];
+        if (sq == 0.0) continue;
+        const double* hc = bf.Hb.data() + (size_t)q * bf.nv;
+        double* cj = C.data() + (size_t)j * bf.nv;
+        for (int i = 0; i < bf.nv; ++i) cj[i] += hc[i] * sq;
+      }
+    for (int j0 = 0; j0 < bb.me; j0 += fcols) {
+      const int nw = std::min(fcols, bb.me - j0);
+      std::fill(Cc.begin(), Cc.end(), 0.0);
+      for (int i = 0; i < bf.nv; ++i)
+        for (int jj = 0; jj < nw; ++jj) Cc[(size_t)i * fcols + jj] = C[i + (size_t)(j0 + jj) * bf.nv];
+      KRY_HIP(hipMemcpyAsync(dC, Cc.data(), sizeof(double) * (size_t)bf.nv * fcols, hipMemcpyHostToDevice,
+                             c->stream));
+      KRY_HIP(kry::launch_frechet_acc(c->st, Vb, bf.nv, (char*)Wb + (size_t)j0 * c->ldv * c->esz, nw, dC,
+                                      c->ldv, c->g.N3, g, c->stream));
+      KRY_HIP(hipStreamSynchronize(c->stream));  // Cc is reused
+    }
+  }
+  return KRY_OK;
+}
+
+int api_grad_transient(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
+                       int32_t b_per_omega, int32_t plane_k, double T, double* loss, double* dL_deps,
+                       kry_stats* st) {
+  int rc = check_multifreq_args(c, omegas, n_omega, 1, b);
+  if (rc) return rc;
+  if (!loss) return fail(c, KRY_EINVAL, "null output");
+  if (plane_k < 1 || plane_k > c->g.nz - 1) return fail(c, KRY_EINVAL, "plane_k out of range");
+  if (!(T >= 0.0) || !std::isfinite(T)) return fail(c, KRY_EINVAL, "invalid T");
+  if (st) std::memset(st, 0, sizeof(*st));
+  treset(c);
+  const double t0 = now_ms();
+  const int m = c->opts.krylov_dim;
+  rc = ensure_basis(c, m);
+  if (rc) return rc;
+  // Z pairs: forward solutions 0..n_omega-1, the adjoint solution n_omega,
+  // refinement scratch n_omega + 1 (and n_omega for the forward group)
+  rc = ensure_z(c, n_omega + 2);
+  if (rc) return rc;
+  const long long n = c->n, N3 = c->g.N3;
+  const long long N2 = (long long)c->g.nx * c->g.ny;
+  const int nfb = (int)((N2 + kry::kBlock - 1) / kry::kBlock);
+  const size_t vb = c->ldv * c->esz;
+  double* rhs = nullptr;   // adjoint right-hand side, complex interleaved
+  double* ybuf = nullptr;  // y(T), FP64
+  double* fpart = nullptr;
+  double* dC = nullptr;
+  void* work = nullptr;    // r0, r(T), then the two regenerated bases
+  const int fcols = kry::frechet_cols();
+  const bool grad = dL_deps != nullptr;
+  const int wvecs = grad ? 2 + 2 * (m + 1) : 0;
+  if (hipMalloc(&ybuf, sizeof(double) * n) != hipSuccess ||
+      hipMalloc(&fpart, sizeof(double) * nfb) != hipSuccess ||
+      (grad && (hipMalloc(&rhs, sizeof(double) * 2 * n) != hipSuccess ||
+                hipMalloc(&dC, sizeof(double) * (size_t)(m + 1) * fcols) != hipSuccess ||
+                hipMalloc(&work, (size_t)wvecs * vb) != hipSuccess))) {
+    hipFree(ybuf), hipFree(fpart), hipFree(rhs), hipFree(dC), hipFree(work);
+    (void)hipGetLastError();
+    return fail(c, KRY_ENOMEM, "cannot allocate the gradient workspace");
+  }
+  Defer<std::function<void()>> free_ws{[&]() {
+    hipFree(ybuf), hipFree(fpart), hipFree(rhs), hipFree(dC), hipFree(work);
+  }};
+  auto wv = [&](int i) { return (void*)((char*)work + (size_t)i * vb); };
+  int status = KRY_OK;
+  double max_res = 0.0, max_err = 0.0;
+  const double tol = c->opts.tol;
+  std::vector<double> om(omegas, omegas + n_omega);
+  if (!b_per_omega) {
+    std::vector<int> zc(n_omega);
+    for (int k = 0; k < n_omega; ++k) zc[k] = k;
+    double bn = 0.0;
+    rc = stationary_group(c, b, om, zc, tol, st, &max_res, &bn, n_omega);
+    if (rc == KRY_ENOCONV) status = rc;
+    else if (rc) return rc;
+  } else {
+    for (int k = 0; k < n_omega; ++k) {
+      double bn = 0.0;
+      rc = stationary_group(c, b + (size_t)k * 2 * n, std::vector<double>{om[k]}, std::vector<int>{k}, tol,
+                            st, &max_res, &bn, n_omega);
+      if (rc == KRY_ENOCONV) status = rc;
+      else if (rc) return rc;
+    }
+  }
+  const double t_stat = now_ms();
+  if (grad) KRY_HIP(hipMemsetAsync(dL_deps, 0, sizeof(double) * N3, c->stream));
+  double L = 0.0;
+  std::vector<double> hp(nfb), d;
+  ExpvTrace trf, trb;
+  for (int k = 0; k < n_omega; ++k) {
+    const double w = om[k];
+    const double sn = std::sin(w * T), cs = std::cos(w * T);
+    void* zre = zcol(c, 2 * k);
+    void* zim = zcol(c, 2 * k + 1);
+    // forward transient x(s) = e^{-sA} Im z, start vectors kept
+    rc = host_dots(c, zim, nullptr, 0, d);
+    if (rc) return rc;
+    const double vn = std::sqrt(std::max(d[0], 0.0));
+    KRY_HIP(hipMemcpyAsync(slot(c, 0), zim, vb, hipMemcpyDeviceToDevice, c->stream));
+    trf.clear();
+    double err = 0.0;
+    if (vn > 0.0 && T > 0.0) {
+      rc = expv_slot0(c, T, 0.5 * tol * vn, 0.25 * tol * vn, st, &err, grad ? &trf : nullptr);
+      if (rc == KRY_ENOCONV) status = rc;
+      else if (rc) return rc;
+      max_err = std::max(max_err, err / vn);
+    }
+    // y(T) = Im(e^{iwT} z) - x(T), its flux and the adjoint start r0
+    KRY_HIP(kry::launch_assemble(c->st, zre, zim, slot(c, 0), sn, cs, ybuf, n, c->stream));
+    if (grad) KRY_HIP(hipMemsetAsync(wv(0), 0, vb, c->stream));
+    int nb = 0;
+    KRY_HIP(kry::launch_flux_inst(c->st, ybuf, plane_k, c->g, c->mats, fpart, grad ? wv(0) : nullptr, &nb,
+                                  c->stream));
+    KRY_HIP(hipMemcpyAsync(hp.data(), fpart, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
+    KRY_HIP(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < nb; ++i) L += hp[i];
+    if (!grad) continue;
+    rc = host_dots(c, wv(0), nullptr, 0, d);
+    if (rc) return rc;
+    const double rn = std::sqrt(std::max(d[0], 0.0));
+    if (!(rn > 0.0)) continue;  // F does not depend on y here: no gradient from this frequency
+    // backward transient r(sigma) = e^{-sigma A} r0, start vectors kept
+    KRY_HIP(hipMemcpyAsync(slot(c, 0), wv(0), vb, hipMemcpyDeviceToDevice, c->stream));
+    trb.clear();
+    if (T > 0.0) {
+      double err2 = 0.0;
+      rc = expv_slot0(c, T, 0.5 * tol * rn, 0.25 * tol * rn, st, &err2, &trb);
+      if (rc == KRY_ENOCONV) status = rc;
+      else if (rc) return rc;
+      max_err = std::max(max_err, err2 / rn);
+    }
+    KRY_HIP(hipMemcpyAsync(wv(1), slot(c, 0), vb, hipMemcpyDeviceToDevice, c->stream));
+    // adjoint shifted solve and the terms through z
+    KRY_HIP(kry::launch_adj_rhs(c->st, wv(0), wv(1), sn, cs, rhs, n, c->stream));
+    double bn = 0.0;
+    rc = stationary_group(c, rhs, std::vector<double>{w}, std::vector<int>{n_omega}, tol, st, &max_res, &bn,
+                          n_omega + 1);
+    if (rc == KRY_ENOCONV) status = rc;
+    else if (rc) return rc;
+    const double* bk = b_per_omega ? b + (size_t)k * 2 * n : b;
+    KRY_HIP(kry::launch_grad_acc(c->st, zre, zim, zcol(c, 2 * n_omega), zcol(c, 2 * n_omega + 1), bk, w,
+                                 dL_deps, N3, c->stream));
+    // the term through e^{-TA}
+    rc = frechet_term(c, T, trf, trb, wv(2), wv(2 + m + 1), dC, dL_deps, st);
+    if (rc) return rc;
+  }
+  KRY_HIP(hipStreamSynchronize(c->stream));
+  *loss = L;
+  if (st) {
+    st->max_residual = max_res;
+    st->max_err_estimate = max_err;
+    st->ms_total = now_ms() - t0;
+    st->ms_stationary = t_stat - t0;
+    st->ms_transient = st->ms_total - st->ms_stationary;
     st->converged = status == KRY_OK;
     texport(c, st);
   }
@@ -3335,6 +3773,14 @@ int kry_grad(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
              int32_t b_per_omega, int32_t plane_k, double* loss, double* dL_deps, kry_stats* st) {
   return guarded(c, [&] {
     return api_grad(c, omegas, n_omega, b, b_per_omega, plane_k, loss, dL_deps, st);
+  });
+}
+
+int kry_grad_transient(kry_ctx* c, const double* omegas, int32_t n_omega, const double* b,
+                       int32_t b_per_omega, int32_t plane_k, double T, double* loss, double* dL_deps,
+                       kry_stats* st) {
+  return guarded(c, [&] {
+    return api_grad_transient(c, omegas, n_omega, b, b_per_omega, plane_k, T, loss, dL_deps, st);
   });
 }
 

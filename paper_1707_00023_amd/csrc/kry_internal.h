@@ -188,4 +188,21 @@ hipError_t launch_rst_march(int m, int q, int nt, int ncol, const double* E, con
                             double hnext, double dt, const int* cmap, const double* fin, double* fout,
                             long long ldf, double* uT, double* resint, hipStream_t s);
 
+// Gradient of the flux at a finite time T (kry_adjoint.hip).
+// F = sum over plane kf of Ex Hy_bar - Ey Hx_bar for the real FP64 field y
+// (per-workgroup partial sums, *nblk of them) and, if r0 != nullptr, the
+// adjoint start vector r0 = P M^-1 dF/dy at its six entries per plane cell
+// (r0 zero elsewhere beforehand; storage type).
+hipError_t launch_flux_inst(Storage st, const double* y, int kf, const DevGrid& g, const DevMats& m,
+                            double* partials, void* r0, int* nblk, hipStream_t s);
+// rhs = sn r0 + i (rT - cs r0) (complex interleaved FP64).
+hipError_t launch_adj_rhs(Storage st, const void* r0, const void* rT, double sn, double cs, double* rhs,
+                          long long n, hipStream_t s);
+// g[c] += sum over the E rows p of cell c of sum_{i < nv, j < nw}
+// V_i[p] C[i][j] W_j[p], C row-major with row stride frechet_cols();
+// nw <= frechet_cols().  V, W: storage type, stride ld.
+int frechet_cols();
+hipError_t launch_frechet_acc(Storage st, const void* V, int nv, const void* W, int nw, const double* C,
+                              long long ld, long long N3, double* g, hipStream_t s);
+
 }  // namespace kry

@@ -10,10 +10,18 @@ shifted solve and does not use Corollary 3.
     python tests/golden/make_golden.py c2        # ~1 h on one CPU core
     python tests/golden/make_golden.py c3        # 4 of the 256 columns
     python tests/golden/make_golden.py grad16    # 16^3 flux gradient, ~1 min
+    python tests/golden/make_golden.py tgrad     # flux at time T: 5^3 gradient, 15^3 directions
 
 grad16 stores the oracle's whole gradient vector dL/d eps (4096 cells) and
 the loss for GRAD16, a 16^3 medium with two frequencies: both shifted solves
 and both explicit-transpose adjoint solves by SuperLU (n = 24576).
+
+tgrad stores, for the flux of the whole field at a finite time T (transient
+included), the oracle's per-cell gradient on a 5^3 medium (forward
+derivatives with dense LU and scipy's Frechet derivative of expm) and, on a
+15^3 medium, the loss and three directional derivatives along seeded random
+permittivity changes (SuperLU solves, expm_multiply for the exponential and
+for its Frechet derivative through the 2n block identity).
 """
 from __future__ import annotations
 
@@ -63,6 +71,49 @@ def make_grad16():
     print(f"grad16 L={L:.12e} |g|={np.linalg.norm(g):.6e} {dt:.1f}s", flush=True)
 
 
+def tgrad_workloads():
+    """(small, medium, T, directions): the 5^3 and 15^3 media of the
+    finite-time flux gradient, two frequencies, one shared Ex source."""
+    om = (2 * np.pi * 0.09, 2 * np.pi * 0.11)
+    w5 = wk.small(5, seed=52, n_spheres=2, layer=1, radius=(0.8, 1.4), omegas=om, src_k=1,
+                  flux_plane=3, tol=1e-12, krylov_dim=30)
+    w15 = wk.small(15, seed=53, n_spheres=12, layer=2, radius=(1.0, 2.0), omegas=om, src_k=3,
+                   flux_plane=11, tol=1e-12, krylov_dim=40)
+    return w5, w15, 12.0, 3
+
+
+def tgrad_direction(N, k):
+    return np.random.default_rng(SAMPLE_SEED + 100 + k).standard_normal((N, N, N))
+
+
+def make_tgrad():
+    from oracle import transient_grad as tg
+    w5, w15, T, ndir = tgrad_workloads()
+    out = {"T": T}
+    for tag, wl in (("small", w5), ("medium", w15)):
+        inp = wk.generate(wl)
+        b = wk.source_vector(wl, wl.omegas[0], 0.0)
+        b_cols = np.stack([b] * len(wl.omegas), axis=1)
+        t0 = time.time()
+        L = tg.loss(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, wl.flux_plane, T)
+        rec = {"workload": wl.name, "N": wl.N, "omegas": list(wl.omegas), "plane_k": wl.flux_plane,
+               "loss": float(L)}
+        if tag == "small":
+            g = tg.grad(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, wl.flux_plane, T)
+            rec["grad"] = g.reshape(-1).tolist()
+            rec["route"] = "dense LU and expm_frechet, one forward derivative per cell"
+        else:
+            rec["directional"] = [
+                tg.directional(inp.eps, inp.mu, inp.sigma, b_cols, wl.omegas, wl.flux_plane, T,
+                               tgrad_direction(wl.N, k)) for k in range(ndir)]
+            rec["route"] = "SuperLU, expm_multiply and the 2n block identity"
+        rec["oracle_seconds"] = time.time() - t0
+        out[tag] = rec
+        print(f"tgrad {tag} L={L:.12e} {rec['oracle_seconds']:.1f}s", flush=True)
+    with open(os.path.join(HERE, "tgrad_oracle.json"), "w") as f:
+        json.dump(out, f)
+
+
 def sample_spec(n):
     rng = np.random.default_rng(SAMPLE_SEED)
     idx = np.sort(rng.choice(n, size=min(N_SAMPLES, n), replace=False))
@@ -104,5 +155,7 @@ def main(cfg_name: str):
 if __name__ == "__main__":
     if sys.argv[1] == "grad16":
         make_grad16()
+    elif sys.argv[1] == "tgrad":
+        make_tgrad()
     else:
         main(sys.argv[1])

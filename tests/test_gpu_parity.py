@@ -693,6 +693,121 @@ def test_grad_c4_full_size_against_difference_solves():
     assert err <= 1e-5
 
 
+# ------------------------------------- flux at a finite time T (NEXT-3) --
+
+def _tgrad_ref():
+    import sys
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    from make_golden import tgrad_direction, tgrad_workloads
+    with open(os.path.join(ROOT, "tests", "golden", "tgrad_oracle.json")) as f:
+        ref = json.load(f)
+    return ref, tgrad_workloads(), tgrad_direction
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(ROOT, "tests", "golden", "tgrad_oracle.json")),
+                    reason="finite-time gradient oracle values not generated")
+def test_grad_transient_5cube_full_vector_against_oracle():
+    # the whole gradient (125 cells, two frequencies, T = 12) of the flux of
+    # the field at time T against the oracle's per-cell forward derivatives
+    # (dense LU and the Frechet derivative of expm), and the loss
+    ref, (w5, _, T, _), _ = _tgrad_ref()
+    r = ref["small"]
+    _announce(f"finite-time flux gradient 5^3 vs oracle, T = {T}")
+    inp = wk.generate(w5)
+    b = wk.source_vector(w5, w5.omegas[0], 0.0)
+    assert list(w5.omegas) == r["omegas"] and w5.flux_plane == r["plane_k"] and T == ref["T"]
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=w5.krylov_dim, tol=1e-12)
+    L, g = s.grad_transient(w5.omegas, _t(b[None, :]), w5.flux_plane, T)
+    st = s.last_stats
+    s.close()
+    go = np.asarray(r["grad"])
+    err = _rel(g.cpu().numpy().reshape(-1), go)
+    _announce(f"5^3: loss {L:.10e} (oracle {r['loss']:.10e}), gradient rel err {err:.2e}, stats {st}")
+    assert abs(L - r["loss"]) <= 1e-9 * abs(r["loss"])
+    assert err <= 1e-8
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(ROOT, "tests", "golden", "tgrad_oracle.json")),
+                    reason="finite-time gradient oracle values not generated")
+def test_grad_transient_15cube_directional_against_oracle():
+    # 15^3 (3375 cells: 14 workgroups, a ragged last one): the loss and the
+    # gradient along three seeded random permittivity changes against the
+    # oracle's forward derivatives (SuperLU, expm_multiply, 2n block identity)
+    ref, (_, w15, T, ndir), direction = _tgrad_ref()
+    r = ref["medium"]
+    _announce(f"finite-time flux gradient 15^3, directional vs oracle, T = {T}")
+    inp = wk.generate(w15)
+    b = wk.source_vector(w15, w15.omegas[0], 0.0)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=w15.krylov_dim, tol=1e-12)
+    L, g = s.grad_transient(w15.omegas, _t(b[None, :]), w15.flux_plane, T)
+    s.close()
+    g = g.cpu().numpy()
+    assert abs(L - r["loss"]) <= 1e-9 * abs(r["loss"])
+    gnorm = np.linalg.norm(g)
+    for k in range(ndir):
+        d = direction(w15.N, k)
+        dd = float((g * d).sum())
+        _announce(f"15^3 direction {k}: {dd:.10e} (oracle {r['directional'][k]:.10e})")
+        assert abs(dd - r["directional"][k]) <= 1e-8 * gnorm * np.linalg.norm(d)
+
+
+def test_grad_transient_full_size_directional_differences():
+    # the 64^3 medium of the gradient workload, two of its frequencies,
+    # T = 60: the adjoint gradient along two random permittivity changes
+    # against central differences of the loss.  The losses carry ~3e-11 of
+    # relative error (solves to 1e-12 relative residual), which a step of
+    # 1e-5 turns into ~5e-6 of the directional derivative; the step 1e-4
+    # (eps ~ 2.5) keeps that and the O(h^2) truncation near 1e-7
+    wl = wk.C4
+    N, kf, T, h = wl.N, wl.flux_plane, 60.0, 1e-4
+    om = list(wl.omegas[::4])
+    _announce(f"finite-time flux gradient 64^3, T = {T}, directional central differences")
+    inp = wk.generate(wl)
+    b = _t(wk.source_vector(wl, wl.omegas[0], 0.0)[None, :])
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=1e-12)
+    t0 = time.time()
+    L, g = s.grad_transient(om, b, kf, T)
+    _announce(f"64^3 finite-time gradient {time.time() - t0:.1f}s L={L:.6e} stats={s.last_stats}")
+    s.close()
+    g = g.cpu().numpy()
+    rng = np.random.default_rng(77)
+    for k in range(2):
+        d = rng.standard_normal(inp.eps.shape)
+        Ls = []
+        for sgn in (1.0, -1.0):
+            sp = _solver(inp.eps + sgn * h * d, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=1e-12)
+            Ls.append(sp.grad_transient(om, b, kf, T, loss_only=True)[0])
+            sp.close()
+        fd = (Ls[0] - Ls[1]) / (2 * h)
+        dd = float((g * d).sum())
+        _announce(f"64^3 direction {k}: adjoint {dd:.10e}, central differences {fd:.10e}")
+        assert abs(dd - fd) <= 1e-5 * abs(fd)
+
+
+def test_grad_transient_edges_and_autograd():
+    kry = _kry()
+    wl = wk.small(8, seed=31, n_spheres=3, layer=2, radius=(0.8, 1.5), src_k=1)
+    inp = wk.generate(wl)
+    b = _t(wk.source_vector(wl, wl.omegas[0], 0.0)[None, :])
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-12)
+    # T = 0: y(0) = 0, so the loss and its gradient vanish
+    L0, g0 = s.grad_transient(wl.omegas, b, 5, 0.0)
+    assert L0 == 0.0 and float(g0.abs().max()) == 0.0
+    with pytest.raises(kry.KryError):
+        s.grad_transient(wl.omegas, b, 5, -1.0)
+    with pytest.raises(kry.KryError):
+        s.grad_transient(wl.omegas, b, 0, 5.0)
+    L, g = s.grad_transient(wl.omegas, b, 5, 9.0)
+    s.close()
+    # through torch.autograd: the backward hands the adjoint gradient back
+    eps = _t(inp.eps).requires_grad_(True)
+    out = kry.flux_loss_at(eps, _t(inp.sigma), b, wl.omegas, 5, 9.0,
+                           kry.Options(krylov_dim=30, tol=1e-12))
+    out.backward()
+    assert abs(float(out) - L) <= 1e-13 * abs(L)
+    assert float((eps.grad - g).abs().max()) <= 1e-12 * float(g.abs().max())
+
+
 # ------------------------------------------------ transient continuation --
 
 @pytest.mark.parametrize("per_omega", [False, True])
