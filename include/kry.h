@@ -156,6 +156,26 @@ typedef struct {
   double kernel_flops[KRY_K_CLASSES];
 } kry_stats;
 
+/* Per-column record of the last kry_solve_multifreq call on a context (the
+ * single-vector path; other calls leave no records).  The metrics the paper
+ * reports per run (residuals, restarts in time, the decay of |y_hat(t)|
+ * that makes the split pay, Fig. `normy`), per output column. */
+typedef struct {
+  double omega;
+  int32_t source;              /* source index; column = omega index * n_src + source */
+  int32_t converged;           /* 1 if the column's shifted solve and transient met their targets */
+  int64_t matvecs_stationary;  /* of the column's shifted-solve group (shared by its columns) */
+  int64_t matvecs_transient;   /* this column's transient */
+  int64_t steps_transient;     /* this column's restarts in time */
+  double residual;             /* true relative shifted residual |b - (A + i w) z|_M / |b|_M of
+                                  the returned z; NaN where the path does not compute it */
+  double err_estimate;         /* transient error bound / |Im(e^{iwT} z)|_M */
+  double harmonic_norm;        /* |Im(e^{iwT} z)|_M (time-harmonic part at T) */
+  double ms_transient;         /* wall time of this column's transient and assembly */
+  int32_t series_len;          /* samples in the column's |y_hat(t)| series */
+  int32_t pad_;
+} kry_col_stats;
+
 /* Create a context for the grid and per-cell materials: the operator
  * A = M^{-1} (S + K) of the semi-discrete Maxwell system (Section 2.1,
  * equation (ode) and the block form of the operator after it: M holds the
@@ -349,6 +369,18 @@ int kry_set_tune(kry_ctx* ctx, const kry_tune* t);
 int kry_grad(kry_ctx* ctx, const double* omegas, int32_t n_omega, const double* b,
              int32_t b_per_omega, int32_t plane_k, double* loss, double* dL_deps,
              kry_stats* stats);
+
+/* Record of column `col` of the last kry_solve_multifreq call (single-vector
+ * path).  KRY_EINVAL if the last call left no record for col.  out: host. */
+int kry_column_stats(const kry_ctx* ctx, int32_t col, kry_col_stats* out);
+
+/* The |y_hat(t)|_M series of column `col` of the last kry_solve_multifreq
+ * call: sample k is the start of the k-th restart in time of the transient
+ * (t[k], |y_hat(t[k])|_M, and ms[k], the wall time of that restart), then a
+ * last sample at the end (t = T or the time the remainder was dropped,
+ * ms = 0).  Writes min(cap, len) samples into the host arrays (any may be
+ * NULL) and returns len, the series' length, or a negative error code. */
+int kry_norm_series(const kry_ctx* ctx, int32_t col, double* t, double* norm, double* ms, int32_t cap);
 
 /* Flux at a finite time T, the transient included, and its gradient w.r.t.
  * per-cell permittivity.  The field is the whole solution of Corollary 3,

@@ -28,7 +28,7 @@ EXPORTED = ("kry_create", "kry_destroy", "kry_last_error", "kry_size", "kry_appl
             "kry_apply_f32", "kry_arnoldi", "kry_expv", "kry_solve_multifreq",
             "kry_stationary", "kry_grad", "kry_block_arnoldi", "kry_autotune",
             "kry_set_tune", "kry_arnoldi_noalloc", "kry_solve_restarted", "kry_solve_split2",
-            "kry_autotune_sstep", "kry_grad_transient")
+            "kry_autotune_sstep", "kry_grad_transient", "kry_column_stats", "kry_norm_series")
 
 
 class KryGrid(ctypes.Structure):
@@ -62,6 +62,18 @@ class KryStats(ctypes.Structure):
             v = getattr(self, f)
             out[f] = list(v) if hasattr(v, "__len__") else v
         return out
+
+
+class KryColStats(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("source", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("matvecs_stationary", ctypes.c_int64), ("matvecs_transient", ctypes.c_int64),
+                ("steps_transient", ctypes.c_int64), ("residual", ctypes.c_double),
+                ("err_estimate", ctypes.c_double), ("harmonic_norm", ctypes.c_double),
+                ("ms_transient", ctypes.c_double), ("series_len", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
 
 
 DEFAULT_S_STEP = 16
@@ -127,6 +139,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                              ctypes.POINTER(KryStats)]
     lib.kry_grad_transient.argtypes = [P, P, I32, P, I32, I32, D, ctypes.POINTER(D), P,
                                        ctypes.POINTER(KryStats)]
+    lib.kry_column_stats.argtypes = [P, I32, ctypes.POINTER(KryColStats)]
+    lib.kry_column_stats.restype = ctypes.c_int
+    lib.kry_norm_series.argtypes = [P, I32, P, P, P, I32]
+    lib.kry_norm_series.restype = ctypes.c_int
     lib.kry_block_arnoldi.argtypes = [P, P, I32, I32, P, P]
     lib.kry_block_arnoldi.restype = ctypes.c_int
     lib.kry_autotune.argtypes = [P, I32, ctypes.POINTER(KryTune)]
@@ -453,6 +469,27 @@ class Solver:
         self.last_stats = st.as_dict()
         self._check(rc, allow_noconv, self.last_stats)
         return loss.value, g
+
+    def column_stats(self, col: int):
+        """Per-column record of the last solve_multifreq call (single-vector
+        path): frequency, source, operator applications of its shifted-solve
+        group and of its transient, restarts in time, true shifted residual,
+        transient error estimate, |Im(e^{iwT} z)|_M, wall time."""
+        out = KryColStats()
+        self._check(self._lib.kry_column_stats(self._ctx, int(col), ctypes.byref(out)))
+        return out.as_dict()
+
+    def norm_series(self, col: int):
+        """(t, |y_hat(t)|_M, ms per restart) of column col's transient in the
+        last solve_multifreq call, as numpy arrays (the last sample is T)."""
+        import numpy as np
+        n = self._lib.kry_norm_series(self._ctx, int(col), None, None, None, 0)
+        if n < 0:
+            self._check(n)
+        t, nrm, ms = (np.zeros(n) for _ in range(3))
+        self._lib.kry_norm_series(self._ctx, int(col), t.ctypes.data_as(ctypes.c_void_p),
+                                  nrm.ctypes.data_as(ctypes.c_void_p), ms.ctypes.data_as(ctypes.c_void_p), n)
+        return t, nrm, ms
 
     def grad_transient(self, omegas: Sequence[float], b, plane_k: int, T: float,
                        b_per_omega: bool = False, loss_only: bool = False,

@@ -104,6 +104,18 @@ struct kry_ctx {
   double k_bytes[KRY_K_CLASSES] = {};
   double k_flops[KRY_K_CLASSES] = {};
 
+  // per-column record of the last kry_solve_multifreq call (single-vector path)
+  struct ColRecord {
+    kry_col_stats s{};
+    std::vector<double> t, norm, ms;  // |y_hat(t)|_M series
+  };
+  std::vector<ColRecord> cols;
+  // true relative residual of each Z pair after its last check (NaN: none)
+  std::vector<double> zres;
+  // operator applications and status of the last shifted-solve group
+  long long grp_mv = 0;
+  int grp_status = 0;
+
   std::string err;
 };
 
@@ -670,13 +682,16 @@ int multishift(kry_ctx* c, const std::vector<double>& omegas, std::vector<cplx> 
 struct ExpvTrace {
   void* ck = nullptr;  // device: checkpoint j at ck + j ldv (storage type)
   int cap = 0;
-  std::vector<double> t0, tau, hnorm;  // per step; hnorm = |H|_1 of its basis
+  bool keep_ck = true;  // false: record the norm series only
+  std::vector<double> t0, tau, hnorm;  // per accepted step; hnorm = |H|_1 of its basis
+  // every restart: its start time, |y_hat|_M there and its wall time (ms)
+  std::vector<double> s_t, s_beta, s_ms;
   ExpvTrace() = default;
   ExpvTrace(const ExpvTrace&) = delete;
   ExpvTrace& operator=(const ExpvTrace&) = delete;
   ~ExpvTrace() { hipFree(ck); }
   int steps() const { return (int)t0.size(); }
-  void clear() { t0.clear(), tau.clear(), hnorm.clear(); }
+  void clear() { t0.clear(), tau.clear(), hnorm.clear(), s_t.clear(), s_beta.clear(), s_ms.clear(); }
 };
 
 void* trace_ck(kry_ctx* c, const ExpvTrace* tr, int j) {
@@ -722,7 +737,8 @@ int expv_slot0(kry_ctx* c, double T, double abstol, double drop, kry_stats* st, 
   int steps = 0;
   while (t < T) {
     if (steps >= maxsteps) { *err_est = err; return KRY_ENOCONV; }
-    if (tr) {
+    const double tstep = tr ? now_ms() : 0.0;
+    if (tr && tr->keep_ck) {
       rc = trace_push(c, tr);
       if (rc) return rc;
     }
@@ -731,11 +747,20 @@ int expv_slot0(kry_ctx* c, double T, double abstol, double drop, kry_stats* st, 
     rc = arnoldi(c, m, &beta, &me);
     if (rc) return rc;
     ++steps;
+    if (tr) {
+      tr->s_t.push_back(t);
+      tr->s_beta.push_back(beta);
+      tr->s_ms.push_back(0.0);
+    }
     if (st) { st->matvecs_transient += m; st->steps_transient += 1; }
-    if (me == 0) break;  // y_hat(t) = 0
+    if (me == 0) {  // y_hat(t) = 0
+      if (tr) tr->s_ms.back() = now_ms() - tstep;
+      break;
+    }
     if (beta <= drop) {  // remainder below the drop threshold
       KRY_HIP(hipMemsetAsync(slot(c, 0), 0, c->ldv * c->esz, c->stream));
       err += beta;
+      if (tr) tr->s_ms.back() = now_ms() - tstep;
       break;
     }
     const double tmax = T - t;
@@ -781,6 +806,7 @@ int expv_slot0(kry_ctx* c, double T, double abstol, double drop, kry_stats* st, 
     tend(c, e, KRY_K_COMBINE, vbytes(c) * (me + 1.0));
     KRY_HIP(hipStreamSynchronize(c->stream));
     t += tau;
+    if (tr) tr->s_ms.back() = now_ms() - tstep;
   }
   *err_est = err;
   return KRY_OK;
@@ -1020,8 +1046,10 @@ int stationary_group(kry_ctx* c, const double* b_col, const std::vector<double>&
                      const std::vector<int>& zcolk, double tol_rel, kry_stats* st, double* max_res,
                      double* bnorm_out, int spare = -1) {
   const int nw = (int)omegas.size();
+  if ((int)c->zres.size() < c->zcap) c->zres.resize(c->zcap, NAN);
   for (int k = 0; k < nw; ++k) {
     KRY_HIP(hipMemsetAsync(zcol(c, 2 * zcolk[k]), 0, 2 * c->ldv * c->esz, c->stream));
+    if (zcolk[k] < (int)c->zres.size()) c->zres[zcolk[k]] = NAN;
   }
   // norms of Re b and Im b
   std::vector<double> d;
@@ -1143,6 +1171,7 @@ int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, do
     return fail(c, KRY_ENOCONV, "non-finite shifted solution");
   }
   const double accept = std::max(2.0 * tol_rel * bn, 8.0 * fl);
+  if (zk < (int)c->zres.size()) c->zres[zk] = rn / bn;
   if (!correct || !(rn > accept)) {
     *max_res = std::max(*max_res, rn / bn);
     return KRY_OK;
@@ -1160,6 +1189,7 @@ int refine_shift(kry_ctx* c, const double* bcol, double w, int zk, int spare, do
   KRY_HIP(hipStreamSynchronize(c->stream));
   rc = true_residual(c, bcol, w, zk, st, &rn, &fl);
   if (rc) return rc;
+  if (zk < (int)c->zres.size()) c->zres[zk] = rn / bn;
   *max_res = std::max(*max_res, std::isfinite(rn) ? rn / bn : INFINITY);
   if (!std::isfinite(rn)) return fail(c, KRY_ENOCONV, "non-finite shifted solution");
   if (c->opts.verbose)
@@ -1297,7 +1327,10 @@ int for_each_group(kry_ctx* c, const double* omegas, int n_omega, int n_src, con
     for (int k = 0; k < n_omega; ++k) zc[k] = k;
     for (int s = 0; s < n_src; ++s) {
       double bn = 0.0;
+      const long long mv0 = st ? st->matvecs_stationary : 0;
       rc = stationary_group(c, b + (size_t)s * 2 * c->n, om, zc, tol_s, st, max_res, &bn, n_omega);
+      c->grp_mv = (st ? st->matvecs_stationary : 0) - mv0;
+      c->grp_status = rc;
       if (rc == KRY_ENOCONV) status = rc;
       else if (rc) return rc;
       for (int k = 0; k < n_omega; ++k) {
@@ -1327,6 +1360,7 @@ int for_each_group(kry_ctx* c, const double* omegas, int n_omega, int n_src, con
         for (int a = k - q; a < k && q > 0; ++a)
           for (int b2 = a + 1; b2 <= k; ++b2)
             if (std::abs(omegas[a] - omegas[b2]) <= 1e-12 * std::max(std::abs(omegas[b2]), 1.0)) q = 0;
+        const long long mv0 = st ? st->matvecs_stationary : 0;
         if (q == 0) {
           rc = stationary_group(c, bcol, std::vector<double>{omegas[k]}, std::vector<int>{0}, tol_s,
                                 st, max_res, &bn, 1);
@@ -1345,6 +1379,8 @@ int for_each_group(kry_ctx* c, const double* omegas, int n_omega, int n_src, con
             if (r2 != KRY_OK) rc = r2;
           }
         }
+        c->grp_mv = (st ? st->matvecs_stationary : 0) - mv0;
+        c->grp_status = rc;
         if (rc == KRY_ENOCONV) status = rc;
         else if (rc) return rc;
         rc = each(col, omegas[k], 0, bn);
@@ -2198,8 +2234,11 @@ int api_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
   if (rc) return rc;
   if (!yT) return fail(c, KRY_EINVAL, "null output");
   if (!(T >= 0.0) || !std::isfinite(T)) return fail(c, KRY_EINVAL, "invalid T");
-  if (st) std::memset(st, 0, sizeof(*st));
+  kry_stats st_local;
+  if (!st) st = &st_local;  // the per-column records need the counters
+  std::memset(st, 0, sizeof(*st));
   treset(c);
+  c->cols.clear();
   const double t0 = now_ms();
   double max_res = 0.0, max_err = 0.0;
   double t_trans = 0.0;
@@ -2242,6 +2281,9 @@ int api_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
     c->tc_cap = 2 * n_src;
   }
   auto tcv = [&](int i) { return (void*)((char*)c->TC + (size_t)i * c->ldv * c->esz); };
+  c->cols.assign((size_t)n_omega * n_src, kry_ctx::ColRecord{});
+  ExpvTrace tr;  // the norm series of each column's transient
+  tr.keep_ck = false;
   rc = for_each_group(
       c, omegas, n_omega, n_src, b, b_per_omega, 0.05 * tol, st, &max_res,
       [&](int col, double w, int zk, double bnorm) -> int {
@@ -2251,6 +2293,14 @@ int api_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
         void* zim = zcol(c, 2 * zk + 1);
         double* out = yT + (size_t)col * c->n;
         const int src = col % n_src;
+        kry_col_stats& rec = c->cols[col].s;
+        rec.omega = w;
+        rec.source = src;
+        rec.matvecs_stationary = c->grp_mv;
+        rec.residual = zk < (int)c->zres.size() ? c->zres[zk] : NAN;
+        rec.converged = c->grp_status == KRY_OK;
+        const long long mvt0 = st->matvecs_transient, sst0 = st->steps_transient;
+        tr.clear();
         if (bnorm == 0.0) {
           KRY_HIP(hipMemsetAsync(out, 0, sizeof(double) * c->n, c->stream));
           if (tcont) chain_acc[src] = -1.0;
@@ -2278,7 +2328,7 @@ int api_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
           KRY_HIP(hipMemcpyAsync(c->d_Y, Ym, sizeof(Ym), hipMemcpyHostToDevice, c->stream));
           KRY_HIP(kry::launch_combine(c->st, tcv(2 * src), c->ldv, 1, c->d_Y, 1, slot(c, 0), c->ldv, nullptr, 1,
                                       c->g, c->stream));
-          r = expv_slot0(c, T, 0.25 * room, 0.25 * room, st, &err);
+          r = expv_slot0(c, T, 0.25 * room, 0.25 * room, st, &err, &tr);
           if (r == KRY_ENOCONV) status = r;
           else if (r) return r;
           // (the exponential used d_Y for its own coefficients: upload +1 again)
@@ -2291,7 +2341,7 @@ int api_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
           KRY_HIP(hipMemcpyAsync(slot(c, 0), zim, c->ldv * c->esz, hipMemcpyDeviceToDevice, c->stream));
           if (T > 0.0) {
             const double part = tcont ? 0.25 * budget : 0.5 * budget;
-            r = expv_slot0(c, T, part, part, st, &err);
+            r = expv_slot0(c, T, part, part, st, &err, &tr);
             if (r == KRY_ENOCONV) status = r;
             else if (r) return r;
           }
@@ -2303,8 +2353,26 @@ int api_solve_multifreq(kry_ctx* c, const double* omegas, int32_t n_omega, int32
                                  c->stream));
         }
         max_err = std::max(max_err, err / scale);
+        // the series' last sample: |y_hat(T)|_M of the returned transient
+        std::vector<double> dn;
+        r = host_dots(c, slot(c, 0), nullptr, 0, dn);
+        if (r) return r;
         KRY_HIP(kry::launch_assemble(c->st, zre, zim, slot(c, 0), sn, cs, out, c->n, c->stream));
         KRY_HIP(hipStreamSynchronize(c->stream));
+        auto& cr = c->cols[col];
+        cr.t = tr.s_t;
+        cr.norm = tr.s_beta;
+        cr.ms = tr.s_ms;
+        cr.t.push_back(T);
+        cr.norm.push_back(std::sqrt(std::max(dn[0], 0.0)));
+        cr.ms.push_back(0.0);
+        rec.matvecs_transient = st->matvecs_transient - mvt0;
+        rec.steps_transient = st->steps_transient - sst0;
+        rec.err_estimate = err / scale;
+        rec.harmonic_norm = ynorm;
+        rec.converged = rec.converged && status == KRY_OK;
+        rec.series_len = (int32_t)cr.t.size();
+        rec.ms_transient = now_ms() - t1;
         t_trans += now_ms() - t1;
         return status;
       });
@@ -3041,10 +3109,15 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
         f0[(size_t)k * ldf + (size_t)j * q + i] =
             cols[k].ca * std::sin(cols[k].w * t) + cols[k].cb * std::cos(cols[k].w * t);
       }
-  // device buffers: samples (2 nc ldf), packed propagators E, W, El, Wl and
-  // the Gauss weights, u(T) per time function, residual integrals, index map
-  const size_t npk = (size_t)m * m + 2 * (size_t)m * q + (size_t)q * q + q;
-  double *dF = nullptr, *dP = nullptr, *dU = nullptr, *dR = nullptr;
+  // device buffers: samples (2 nc ldf), packed propagators E, W, El, Wl,
+  // the Gauss weights and E^L, u(T) per time function, residual integrals,
+  // index map, and the chunk states of the parallel-in-time march (chunks of
+  // L steps, L ~ sqrt(nt / 2): a chain of about 2 L + nt / L dependent steps)
+  const int Lc = std::max(16, (int)std::ceil(std::sqrt(nt / 2.0)));
+  const bool chunked = gpu && Lc < nt;
+  const size_t npk = 2 * (size_t)m * m + 2 * (size_t)m * q + (size_t)q * q + q;
+  const long long nwork = chunked ? kry::rst_march_work(m, nt, nc, Lc) : 0;
+  double *dF = nullptr, *dP = nullptr, *dU = nullptr, *dR = nullptr, *dWk = nullptr;
   int* dMap = nullptr;
   Defer<std::function<void()>> free_bufs{[&]() {
     hipFree(dF);
@@ -3052,12 +3125,14 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
     hipFree(dU);
     hipFree(dR);
     hipFree(dMap);
+    hipFree(dWk);
   }};
   std::vector<double> hF[2];
   if (gpu) {
     if (hipMalloc(&dF, sizeof(double) * 2 * nc * ldf) != hipSuccess || hipMalloc(&dP, sizeof(double) * npk) != hipSuccess ||
         hipMalloc(&dU, sizeof(double) * (size_t)m * nc) != hipSuccess || hipMalloc(&dR, sizeof(double) * nc) != hipSuccess ||
-        hipMalloc(&dMap, sizeof(int) * nc) != hipSuccess) {
+        hipMalloc(&dMap, sizeof(int) * nc) != hipSuccess ||
+        (nwork > 0 && hipMalloc(&dWk, sizeof(double) * nwork) != hipSuccess)) {
       (void)hipGetLastError();
       return fail(c, KRY_ENOMEM, "cannot allocate the sampled sources of the restarted method");
     }
@@ -3101,16 +3176,24 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
       std::copy(P.El.begin(), P.El.end(), p + (size_t)me * me + (size_t)me * q);
       std::copy(P.Wl.begin(), P.Wl.end(), p + (size_t)me * me + 2 * (size_t)me * q);
       std::copy(gw.begin(), gw.end(), p + (size_t)me * me + 2 * (size_t)me * q + (size_t)q * q);
+      double* pEL = p + (size_t)me * me + 2 * (size_t)me * q + (size_t)q * q + q;
+      if (chunked) {  // E^L = e^{-L dt H} for the carry between chunks
+        std::vector<double> X((size_t)me * me);
+        for (int jj = 0; jj < me; ++jj)
+          for (int ii = 0; ii < me; ++ii) X[ii + (size_t)jj * me] = -(double)Lc * dt * c->h_H[ii + (size_t)jj * ldh];
+        kry::expm(me, X.data(), pEL);
+      }
       const double* dE = dP;
       const double* dW = dP + (size_t)me * me;
       const double* dEl = dW + (size_t)me * q;
       const double* dWl = dEl + (size_t)q * me;
       const double* dgw = dWl + (size_t)q * q;
+      const double* dEL = dgw + q;
       KRY_HIP(hipMemcpyAsync(dP, pk.data(), sizeof(double) * npk, hipMemcpyHostToDevice, c->stream));
       KRY_HIP(hipMemcpyAsync(dMap, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
       KRY_HIP(kry::launch_rst_march(me, q, nt, na, dE, dW, dEl, dWl, dgw, beta, hnext, dt, dMap,
                                     dF + (size_t)cur * nc * ldf, dF + (size_t)(cur ^ 1) * nc * ldf, (long long)ldf,
-                                    dU, dR, c->stream));
+                                    dU, dR, c->stream, chunked ? Lc : 0, chunked ? dEL : nullptr, dWk));
       KRY_HIP(hipMemcpyAsync(rs.data(), dR, sizeof(double) * na, hipMemcpyDeviceToHost, c->stream));
       Ydev = dU;
     } else {
@@ -3724,6 +3807,26 @@ void kry_destroy(kry_ctx* c) {
 }
 
 const char* kry_last_error(const kry_ctx* c) { return api_last_error(c); }
+
+int kry_column_stats(const kry_ctx* c, int32_t col, kry_col_stats* out) {
+  if (!c || !out) return KRY_EINVAL;
+  if (col < 0 || col >= (int32_t)c->cols.size()) return KRY_EINVAL;
+  *out = c->cols[col].s;
+  return KRY_OK;
+}
+
+int kry_norm_series(const kry_ctx* c, int32_t col, double* t, double* norm, double* ms, int32_t cap) {
+  if (!c || cap < 0) return KRY_EINVAL;
+  if (col < 0 || col >= (int32_t)c->cols.size()) return KRY_EINVAL;
+  const auto& r = c->cols[col];
+  const int len = (int)r.t.size();
+  for (int k = 0; k < std::min(cap, len); ++k) {
+    if (t) t[k] = r.t[k];
+    if (norm) norm[k] = r.norm[k];
+    if (ms) ms[k] = r.ms[k];
+  }
+  return len;
+}
 
 int64_t kry_size(const kry_ctx* c) { return api_size(c); }
 

@@ -183,10 +183,16 @@ hipError_t launch_scatter_basis(Storage st, const double* Q, int nr, int r, cons
 // p[0:n] = pseudo-random values in [-1/2, 1/2) from a hash of the index.
 hipError_t launch_fill_hash(void* p, Storage st, long long n, unsigned seed, hipStream_t s);
 int rst_march_max_m();
+// Parallel-in-time form: with 1 <= L < nt, EL = E^L (m x m column-major,
+// device) and `work` of rst_march_work(m, nt, ncol, L) doubles (device),
+// the steps are scanned in chunks of L (local march, carry of the chunk
+// starts with EL, final march); otherwise one sequential march.
+long long rst_march_work(int m, int nt, int ncol, int L);
 hipError_t launch_rst_march(int m, int q, int nt, int ncol, const double* E, const double* W,
                             const double* El, const double* Wl, const double* gw, double beta,
                             double hnext, double dt, const int* cmap, const double* fin, double* fout,
-                            long long ldf, double* uT, double* resint, hipStream_t s);
+                            long long ldf, double* uT, double* resint, hipStream_t s, int L = 0,
+                            const double* EL = nullptr, double* work = nullptr);
 
 // Gradient of the flux at a finite time T (kry_adjoint.hip).
 // F = sum over plane kf of Ex Hy_bar - Ey Hx_bar for the real FP64 field y

@@ -1,6 +1,6 @@
 // Projected problems of the residual-restarted inhomogeneous Krylov method
 // on the GPU: the march of u' = -H u + beta f(t) e_1 over the sampled time
-// grid for many time functions at once (one wave per time function).
+// grid for many time functions at once.
 //
 // Per time step j (length dt, q Gauss nodes), with a = beta f at the step's
 // nodes and the step propagators of the restart (computed on the host from
@@ -8,6 +8,13 @@
 // e_m^T u at the nodes):
 //   fout[j q + i] = -hnext (El[i] u + Wl[i] a)      (the next residual source)
 //   u            <- E u + W a.
+// The recurrence is linear in u, so it is scanned in parallel over time:
+// the steps are cut into P chunks of L steps; every chunk is first marched
+// from u = 0 (its own contribution v_p), one wave per (chunk, time function);
+// then one wave per time function carries the chunk starts,
+// u_{p+1} = E^L u_p + v_p, with E^L = e^{-L dt H} from the host; then every
+// chunk is marched again from its start, writing the residual samples.
+// The chain of dependent steps is L + P + L long instead of P L.
 // Lane r owns u_r and keeps row r of E and W (and, for r < q, of El and Wl)
 // in registers; u and a reach the other lanes by lane broadcasts.
 #include "kry_internal.h"
@@ -27,11 +34,14 @@ __device__ __forceinline__ double bcast(double v, int lane) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// One wave per time function.  Lane r holds u_r and rows r of E and W;
-// lanes r < q also row r of El and Wl.  u and the step's source samples
-// reach every lane by lane broadcasts, so the wave needs neither LDS nor a
-// barrier; four partial sums per dot break the chain of dependent FMAs.
-__global__ __launch_bounds__(64) void k_rst_march(int m, int nt, const double* __restrict__ E,
+// One wave per (chunk p = blockIdx.x, time function a = blockIdx.y): the
+// steps [p L, min(nt, (p + 1) L)) from u = u0[a P + p] (zero if u0 is null).
+// OUT: also write the residual samples of those steps and the chunk's share
+// of the integral of |fout| into rpart[a P + p].  The end state goes to
+// uend[a P + p] (if given) and, for the last chunk, to uT[a].  Four partial
+// sums per dot break the chain of dependent FMAs.
+template <bool OUT>
+__global__ __launch_bounds__(64) void k_rst_march(int m, int nt, int L, const double* __restrict__ E,
                                                   const double* __restrict__ W,
                                                   const double* __restrict__ El,
                                                   const double* __restrict__ Wl,
@@ -39,63 +49,110 @@ __global__ __launch_bounds__(64) void k_rst_march(int m, int nt, const double* _
                                                   double hnext, double dt, const int* __restrict__ cmap,
                                                   const double* __restrict__ fin,
                                                   double* __restrict__ fout, long long ldf,
-                                                  double* __restrict__ uT, double* __restrict__ resint) {
+                                                  const double* __restrict__ u0, double* __restrict__ uend,
+                                                  double* __restrict__ uT, double* __restrict__ rpart) {
   const int r = threadIdx.x;
-  const int col = cmap ? cmap[blockIdx.x] : (int)blockIdx.x;
+  const int p = blockIdx.x, P = gridDim.x;
+  const int a = blockIdx.y;
+  const int col = cmap ? cmap[a] : a;
+  const long long slot = (long long)a * P + p;
   const double* fi = fin + (long long)col * ldf;
-  double* fo = fout + (long long)col * ldf;
+  double* fo = OUT ? fout + (long long)col * ldf : nullptr;
+  const int j0 = p * L;
+  const int j1 = min(nt, j0 + L);
   double er[kRstM], el[kRstM], wr[kRstQ], wl[kRstQ];
 #pragma unroll
   for (int k = 0; k < kRstM; ++k) {
     er[k] = (r < m && k < m) ? E[r + (long long)k * m] : 0.0;
-    el[k] = (r < kRstQ && k < m) ? El[(long long)r * m + k] : 0.0;
+    el[k] = (OUT && r < kRstQ && k < m) ? El[(long long)r * m + k] : 0.0;
   }
 #pragma unroll
   for (int l = 0; l < kRstQ; ++l) {
     wr[l] = r < m ? W[r + (long long)l * m] : 0.0;
-    wl[l] = r < kRstQ ? Wl[r * kRstQ + l] : 0.0;
+    wl[l] = (OUT && r < kRstQ) ? Wl[r * kRstQ + l] : 0.0;
   }
   const double wnode = r < kRstQ ? gw[r] : 0.0;
-  double u = 0.0;
-  double anext = (r < kRstQ && nt > 0) ? beta * fi[r] : 0.0;
+  double u = (u0 && r < m) ? u0[slot * m + r] : 0.0;
+  double anext = (r < kRstQ && j0 < j1) ? beta * fi[(long long)j0 * kRstQ + r] : 0.0;
   double racc = 0.0;
-  for (int j = 0; j < nt; ++j) {
+  for (int j = j0; j < j1; ++j) {
     const double acur = anext;
-    if (r < kRstQ && j + 1 < nt) anext = beta * fi[(long long)(j + 1) * kRstQ + r];
-    double a[kRstQ];
+    if (r < kRstQ && j + 1 < j1) anext = beta * fi[(long long)(j + 1) * kRstQ + r];
+    double av[kRstQ];
 #pragma unroll
-    for (int l = 0; l < kRstQ; ++l) a[l] = bcast(acur, l);
+    for (int l = 0; l < kRstQ; ++l) av[l] = bcast(acur, l);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
 #pragma unroll
     for (int k = 0; k < kRstM; k += 4) {
-      const double u0 = bcast(u, k), u1 = bcast(u, k + 1), u2 = bcast(u, k + 2), u3 = bcast(u, k + 3);
-      s0 += er[k] * u0;
+      const double u0k = bcast(u, k), u1 = bcast(u, k + 1), u2 = bcast(u, k + 2), u3 = bcast(u, k + 3);
+      s0 += er[k] * u0k;
       s1 += er[k + 1] * u1;
       s2 += er[k + 2] * u2;
       s3 += er[k + 3] * u3;
-      t0 += el[k] * u0;
-      t1 += el[k + 1] * u1;
-      t2 += el[k + 2] * u2;
-      t3 += el[k + 3] * u3;
+      if (OUT) {
+        t0 += el[k] * u0k;
+        t1 += el[k + 1] * u1;
+        t2 += el[k + 2] * u2;
+        t3 += el[k + 3] * u3;
+      }
     }
     double sa = 0.0, ta = 0.0;
 #pragma unroll
     for (int l = 0; l < kRstQ; ++l) {
-      sa += wr[l] * a[l];
-      ta += wl[l] * a[l];
+      sa += wr[l] * av[l];
+      if (OUT) ta += wl[l] * av[l];
     }
-    if (r < kRstQ) {
+    if (OUT && r < kRstQ) {
       const double f = -hnext * (((t0 + t1) + (t2 + t3)) + ta);
       fo[(long long)j * kRstQ + r] = f;
       racc += wnode * fabs(f);
     }
     u = r < m ? ((s0 + s1) + (s2 + s3)) + sa : 0.0;
   }
-  if (r < m) uT[(long long)blockIdx.x * m + r] = u;
-  // integral of |fout|: the q node lanes' sums (Gauss weights times dt)
+  if (uend && r < m) uend[slot * m + r] = u;
+  if (uT && p == P - 1 && r < m) uT[(long long)a * m + r] = u;
+  if (OUT) {
+    // the q node lanes' sums (Gauss weights times dt)
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) racc += __shfl_xor(racc, off, 64);
-  if (r == 0) resint[blockIdx.x] = dt * racc;
+    for (int off = 32; off > 0; off >>= 1) racc += __shfl_xor(racc, off, 64);
+    if (r == 0) rpart[slot] = dt * racc;
+  }
+}
+
+// One wave per time function: chunk starts u_0 = 0, u_{p+1} = EL u_p + v_p
+// (EL = E^L, column-major m x m), written to ustart[a P + p].
+__global__ __launch_bounds__(64) void k_rst_carry(int m, int P, const double* __restrict__ EL,
+                                                  const double* __restrict__ v, double* __restrict__ ustart) {
+  const int r = threadIdx.x;
+  const int a = blockIdx.x;
+  double er[kRstM];
+#pragma unroll
+  for (int k = 0; k < kRstM; ++k) er[k] = (r < m && k < m) ? EL[r + (long long)k * m] : 0.0;
+  double u = 0.0;
+  for (int p = 0; p < P; ++p) {
+    const long long slot = (long long)a * P + p;
+    if (r < m) ustart[slot * m + r] = u;
+    const double vp = r < m ? v[slot * m + r] : 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRstM; k += 4) {
+      s0 += er[k] * bcast(u, k);
+      s1 += er[k + 1] * bcast(u, k + 1);
+      s2 += er[k + 2] * bcast(u, k + 2);
+      s3 += er[k + 3] * bcast(u, k + 3);
+    }
+    u = r < m ? ((s0 + s1) + (s2 + s3)) + vp : 0.0;
+  }
+}
+
+// resint[a] = sum_p rpart[a P + p], in chunk order.
+__global__ __launch_bounds__(64) void k_rst_sum(int ncol, int P, const double* __restrict__ rpart,
+                                                double* __restrict__ resint) {
+  const int a = blockIdx.x * 64 + threadIdx.x;
+  if (a >= ncol) return;
+  double s = 0.0;
+  for (int p = 0; p < P; ++p) s += rpart[(long long)a * P + p];
+  resint[a] = s;
 }
 
 }  // namespace
@@ -201,14 +258,34 @@ hipError_t launch_fill_hash(void* p, Storage st, long long n, unsigned seed, hip
 
 int rst_march_max_m() { return kRstM; }
 
+long long rst_march_work(int m, int nt, int ncol, int L) {
+  if (L < 1 || L >= nt) return 0;
+  const long long P = (nt + L - 1) / L;
+  return 2LL * ncol * P * m + (long long)ncol * P;
+}
+
 hipError_t launch_rst_march(int m, int q, int nt, int ncol, const double* E, const double* W,
                             const double* El, const double* Wl, const double* gw, double beta,
                             double hnext, double dt, const int* cmap, const double* fin, double* fout,
-                            long long ldf, double* uT, double* resint, hipStream_t s) {
+                            long long ldf, double* uT, double* resint, hipStream_t s, int L,
+                            const double* EL, double* work) {
   if (m < 1 || m > kRstM || q != kRstQ || ncol < 1 || nt < 1 || ldf < (long long)nt * q)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rst_march, dim3(ncol), dim3(64), 0, s, m, nt, E, W, El, Wl, gw, beta, hnext, dt,
-                     cmap, fin, fout, ldf, uT, resint);
+  if (L < 1 || L >= nt || !EL || !work) {  // one chunk
+    hipLaunchKernelGGL(k_rst_march<true>, dim3(1, ncol), dim3(64), 0, s, m, nt, nt, E, W, El, Wl, gw, beta,
+                       hnext, dt, cmap, fin, fout, ldf, nullptr, nullptr, uT, resint);
+    return hipGetLastError();
+  }
+  const int P = (nt + L - 1) / L;
+  double* v = work;
+  double* ustart = v + (long long)ncol * P * m;
+  double* rpart = ustart + (long long)ncol * P * m;
+  hipLaunchKernelGGL(k_rst_march<false>, dim3(P, ncol), dim3(64), 0, s, m, nt, L, E, W, El, Wl, gw, beta,
+                     hnext, dt, cmap, fin, nullptr, ldf, nullptr, v, nullptr, nullptr);
+  hipLaunchKernelGGL(k_rst_carry, dim3(ncol), dim3(64), 0, s, m, P, EL, v, ustart);
+  hipLaunchKernelGGL(k_rst_march<true>, dim3(P, ncol), dim3(64), 0, s, m, nt, L, E, W, El, Wl, gw, beta,
+                     hnext, dt, cmap, fin, fout, ldf, ustart, nullptr, uT, rpart);
+  hipLaunchKernelGGL(k_rst_sum, dim3((ncol + 63) / 64), dim3(64), 0, s, ncol, P, rpart, resint);
   return hipGetLastError();
 }
 

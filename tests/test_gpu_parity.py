@@ -693,6 +693,45 @@ def test_grad_c4_full_size_against_difference_solves():
     assert err <= 1e-5
 
 
+# --------------------------------------------------- per-column records --
+
+def test_column_stats_and_norm_series():
+    # per-column records of a split solve: three frequencies of one source.
+    # The transient's |y_hat(t)|_M decays (A is dissipative in the energy
+    # norm), starts at |Im z|_M and ends at |e^{-TA} Im z|_M (oracle); the
+    # per-column operator applications add up to the call's totals
+    kry = _kry()
+    wl = wk.small(10, seed=12, n_spheres=4, layer=2, radius=(0.8, 1.5), src_k=1, T=30.0)
+    inp = wk.generate(wl)
+    om = [2 * math.pi * 0.09, 2 * math.pi * 0.1, 2 * math.pi * 0.11]
+    b = wk.source_vector(wl, om[0], 0.0)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=30, tol=1e-10)
+    s.solve_multifreq(om, _t(b[None, :]), wl.T)
+    tot = s.last_stats
+    A = op.assemble_A(inp.eps, inp.mu, inp.sigma)
+    w = op.material_weights(inp.eps, inp.mu)
+    mv = 0
+    for k, omega in enumerate(om):
+        cs = s.column_stats(k)
+        t, nrm, ms = s.norm_series(k)
+        mv += cs["matvecs_transient"]
+        assert cs["omega"] == omega and cs["source"] == 0 and cs["converged"] == 1
+        assert cs["matvecs_stationary"] == tot["matvecs_stationary"]  # one group
+        assert cs["residual"] <= 0.1 * 1e-10
+        assert cs["series_len"] == len(t) == cs["steps_transient"] + 1
+        z = osv.stationary(A, b, omega)
+        yh = osv.expv(A, wl.T, np.imag(z))
+        assert t[0] == 0.0 and t[-1] == wl.T and np.all(np.diff(t) > 0)
+        assert abs(nrm[0] - math.sqrt(np.imag(z) @ (w * np.imag(z)))) <= 1e-9 * nrm[0]
+        assert abs(nrm[-1] - math.sqrt(yh @ (w * yh))) <= 1e-9 * nrm[0]
+        assert np.all(np.diff(nrm) <= 1e-10 * nrm[0])
+        assert np.all(ms[:-1] > 0) and ms[-1] == 0.0
+    assert mv == tot["matvecs_transient"]
+    with pytest.raises(kry.KryError):
+        s.column_stats(3)
+    s.close()
+
+
 # ------------------------------------- flux at a finite time T (NEXT-3) --
 
 def _tgrad_ref():
