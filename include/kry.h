@@ -78,8 +78,11 @@ typedef struct {
   int32_t inner_product;/* 0: energy inner product (the only mode)         */
   void* stream;         /* hipStream_t; NULL = the null stream             */
   int32_t timing;       /* 1: time every launch of the main kernel classes
-                           with HIP events on the stream (adds a little
-                           overhead); results in kry_stats.kernel_*        */
+                           with HIP events on the stream (about 4% of a
+                           128^3 solve in host overhead); N > 1: time one
+                           launch in N (counted over all classes in launch
+                           order) and count every launch; 0: off.  Results
+                           in kry_stats.kernel_*                           */
   int32_t block_steps;  /* batched form: block Arnoldi steps per restart of
                            the shifted solves (0: max(2, krylov_dim / p)) */
   int32_t block_steps_transient; /* batched form: 0 = transients one
@@ -145,7 +148,7 @@ typedef struct {
   double ms_transient;
   double ms_total;
   int32_t converged;          /* 1 if every column met its target          */
-  /* filled when kry_opts.timing = 1 (else zero), per kernel class:
+  /* filled when kry_opts.timing >= 1 (else zero), per kernel class:
      summed HIP-event durations, launches, algorithmic bytes (each
      vector read or written once, materials once per cell) and
      algorithmic FP64 flops of the matrix-core products (2 per
@@ -154,6 +157,11 @@ typedef struct {
   int64_t kernel_launches[KRY_K_CLASSES];
   double kernel_bytes[KRY_K_CLASSES];
   double kernel_flops[KRY_K_CLASSES];
+  /* every launch of the class and its algorithmic bytes (the fields above
+     cover the timed launches: all of them with timing = 1, one in N with
+     timing = N)                                                        */
+  int64_t kernel_launches_all[KRY_K_CLASSES];
+  double kernel_bytes_all[KRY_K_CLASSES];
 } kry_stats;
 
 /* Per-column record of the last kry_solve_multifreq call on a context (the
@@ -323,12 +331,20 @@ int kry_stationary(kry_ctx* ctx, const double* omegas, int32_t n_omega,
 typedef struct {
   int32_t cpt_stencil, cpt_update, cpt_dots;
   double us_stencil[3], us_update[3], us_dots[3];
+  /* the s-step basis stencil: planes per workgroup of its z-marching form
+     (4, 8 or 16), or 0 for the cell-parallel form with cpt_stencil cells
+     per thread; us_stencil_zm: its times at 4, 8 and 16 planes (0 where
+     not timed)                                                          */
+  int32_t zm_stencil;
+  int32_t pad_;
+  double us_stencil_zm[3];
 } kry_tune;
 
 /* Time the operator kernel the solver runs (the s-step basis stencil when
  * opts.s_step > 1, which is the FP64 stencil on the FP64 work block under
- * either storage type, else the stencil fused with the first Gram-Schmidt
- * dots), and the update and dot kernels of one one-step Arnoldi step with
+ * either storage type, in its cell-parallel and its z-marching forms, else
+ * the stencil fused with the first Gram-Schmidt dots), and the update and
+ * dot kernels of one one-step Arnoldi step with
  * `cnt` basis vectors (0: krylov_dim / 2), for every launch shape on this
  * context's grid and workspace; apply the fastest per kernel class, and
  * report the choice and timings in *out (host).  Overwrites the context's

@@ -54,7 +54,8 @@ class KryStats(ctypes.Structure):
                 ("ms_stationary", ctypes.c_double), ("ms_transient", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("converged", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double * 6), ("kernel_launches", ctypes.c_int64 * 6),
-                ("kernel_bytes", ctypes.c_double * 6), ("kernel_flops", ctypes.c_double * 6)]
+                ("kernel_bytes", ctypes.c_double * 6), ("kernel_flops", ctypes.c_double * 6),
+                ("kernel_launches_all", ctypes.c_int64 * 6), ("kernel_bytes_all", ctypes.c_double * 6)]
 
     def as_dict(self):
         out = {}
@@ -86,7 +87,9 @@ KERNEL_CLASSES = ("operator", "gs_update", "gs_dots", "combine", "block_gram", "
 class KryTune(ctypes.Structure):
     _fields_ = [("cpt_stencil", ctypes.c_int32), ("cpt_update", ctypes.c_int32),
                 ("cpt_dots", ctypes.c_int32), ("us_stencil", ctypes.c_double * 3),
-                ("us_update", ctypes.c_double * 3), ("us_dots", ctypes.c_double * 3)]
+                ("us_update", ctypes.c_double * 3), ("us_dots", ctypes.c_double * 3),
+                ("zm_stencil", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("us_stencil_zm", ctypes.c_double * 3)]
 
 
 class KryError(RuntimeError):
@@ -174,7 +177,7 @@ class Options:
     krylov_dim: int = 30
     max_restarts: int = 0
     tol: float = 1e-8
-    timing: bool = False
+    timing: int = 0  # 1 (or True): every launch timed; N > 1: one launch in N
     orth: str = "delayed"       # "delayed" (two basis sweeps per step) or "cgs2"
     block_width: int = 0        # > 1: batched form, groups of block_width/2 columns
     use_graph: bool = False     # replay captured Arnoldi cycles (HIP graphs)
@@ -220,7 +223,7 @@ class Solver:
                             opts.max_restarts, opts.tol, opts.block_width,
                             int(bool(opts.use_graph)), 0,
                             _stream_ptr().value,
-                            int(bool(opts.timing)), opts.block_steps,
+                            int(opts.timing), opts.block_steps,
                             opts.block_steps_transient, int(bool(opts.verbose)),
                             1 if opts.orth == "cgs2" else 0,
                             int(opts.s_step if opts.s_step is not None else DEFAULT_S_STEP),
@@ -332,6 +335,7 @@ class Solver:
         if key in table and (s_candidates is None or "s_step" in table[key]):
             e = table[key]
             t.cpt_stencil, t.cpt_update, t.cpt_dots = e["cpt_stencil"], e["cpt_update"], e["cpt_dots"]
+            t.zm_stencil = e.get("zm_stencil", 0)
             self._check(self._lib.kry_set_tune(self._ctx, ctypes.byref(t)))
             if s_candidates is not None:
                 tune_s([e["s_step"]])  # applies the cached block size
@@ -339,7 +343,8 @@ class Solver:
         self._check(self._lib.kry_autotune(self._ctx, int(cnt), ctypes.byref(t)))
         e = {"cpt_stencil": t.cpt_stencil, "cpt_update": t.cpt_update, "cpt_dots": t.cpt_dots,
              "us_stencil": list(t.us_stencil), "us_update": list(t.us_update),
-             "us_dots": list(t.us_dots)}
+             "us_dots": list(t.us_dots), "zm_stencil": t.zm_stencil,
+             "us_stencil_zm": list(t.us_stencil_zm)}
         if s_candidates is not None:
             e["s_step"], e["us_cycle"] = tune_s(s_candidates)
             e["s_candidates"] = [int(x) for x in s_candidates]
@@ -350,6 +355,15 @@ class Solver:
             with open(cache, "w") as f:
                 json.dump(table, f, indent=1)
         return dict(e, cached=False)
+
+    def set_tune(self, cpt_stencil: int = 1, cpt_update: int = 1, cpt_dots: int = 1,
+                 zm_stencil: int = 0):
+        """Apply launch shapes: cells per thread of the operator, update and
+        dot kernels (1, 2 or 4), and the z-marching form of the s-step basis
+        stencil (planes per workgroup 4, 8 or 16; 0: cell-parallel)."""
+        t = KryTune()
+        t.cpt_stencil, t.cpt_update, t.cpt_dots, t.zm_stencil = cpt_stencil, cpt_update, cpt_dots, zm_stencil
+        self._check(self._lib.kry_set_tune(self._ctx, ctypes.byref(t)))
 
     def block_arnoldi(self, V0, mb: int):
         """(V ((mb+1) p, n), H ((mb+1) p, mb p) numpy, block steps) from the block V0 (p, n)."""

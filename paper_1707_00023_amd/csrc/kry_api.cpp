@@ -103,6 +103,11 @@ struct kry_ctx {
   long long k_launch[KRY_K_CLASSES] = {};
   double k_bytes[KRY_K_CLASSES] = {};
   double k_flops[KRY_K_CLASSES] = {};
+  // every launch of a class (timed or not) and its algorithmic bytes, and
+  // the count of timing opportunities (one in opts.timing is timed)
+  long long k_launch_all[KRY_K_CLASSES] = {};
+  double k_bytes_all[KRY_K_CLASSES] = {};
+  long long t_count = 0;
 
   // per-column record of the last kry_solve_multifreq call (single-vector path)
   struct ColRecord {
@@ -152,15 +157,20 @@ hipEvent_t take_event(kry_ctx* c) {
   return e;
 }
 
-// Record the start event of a timed launch (no-op unless timing is on).
+// Record the start event of a timed launch (no-op unless timing is on; with
+// opts.timing = N > 1 only one launch in N is timed).
 hipEvent_t tbeg(kry_ctx* c) {
-  if (!c->opts.timing) return nullptr;
+  if (c->opts.timing <= 0) return nullptr;
+  if (c->opts.timing > 1 && (c->t_count++ % c->opts.timing) != 0) return nullptr;
   hipEvent_t a = take_event(c);
   if (a) hipEventRecord(a, c->stream);
   return a;
 }
 
 void tend(kry_ctx* c, hipEvent_t a, int cls, double bytes, double flops = 0.0) {
+  if (c->opts.timing <= 0) return;
+  c->k_launch_all[cls] += 1;
+  c->k_bytes_all[cls] += bytes;
   if (!a) return;
   hipEvent_t b = take_event(c);
   if (!b) return;
@@ -191,8 +201,11 @@ void treset(kry_ctx* c) {
   c->s_eff = c->opts.s_step > 1 ? c->opts.s_step : 0;
   c->sh_alpha.clear();
   c->sh_q.clear();
-  for (int k = 0; k < KRY_K_CLASSES; ++k)
-    c->k_ms[k] = c->k_bytes[k] = c->k_flops[k] = 0.0, c->k_launch[k] = 0;
+  for (int k = 0; k < KRY_K_CLASSES; ++k) {
+    c->k_ms[k] = c->k_bytes[k] = c->k_flops[k] = c->k_bytes_all[k] = 0.0;
+    c->k_launch[k] = c->k_launch_all[k] = 0;
+  }
+  c->t_count = 0;
 }
 
 void texport(kry_ctx* c, kry_stats* st) {
@@ -203,6 +216,8 @@ void texport(kry_ctx* c, kry_stats* st) {
     st->kernel_launches[k] = c->k_launch[k];
     st->kernel_bytes[k] = c->k_bytes[k];
     st->kernel_flops[k] = c->k_flops[k];
+    st->kernel_launches_all[k] = c->k_launch_all[k];
+    st->kernel_bytes_all[k] = c->k_bytes_all[k];
   }
 }
 
@@ -2919,9 +2934,12 @@ int api_set_tune(kry_ctx* c, const kry_tune* t) {
   auto ok = [](int v) { return v == 1 || v == 2 || v == 4; };
   if (!ok(t->cpt_stencil) || !ok(t->cpt_update) || !ok(t->cpt_dots))
     return fail(c, KRY_EINVAL, "cells per thread must be 1, 2 or 4");
+  if (!(t->zm_stencil == 0 || t->zm_stencil == 4 || t->zm_stencil == 8 || t->zm_stencil == 16))
+    return fail(c, KRY_EINVAL, "z-marching planes must be 0, 4, 8 or 16");
   c->g.cpt_s = t->cpt_stencil;
   c->g.cpt_u = t->cpt_update;
   c->g.cpt_d = t->cpt_dots;
+  c->g.zm_s = t->zm_stencil;
   drop_graphs(c);  // captured launches carry the old shapes
   return KRY_OK;
 }
@@ -3002,6 +3020,32 @@ int api_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {
   out->cpt_stencil = pick(out->us_stencil);
   out->cpt_update = pick(out->us_update);
   out->cpt_dots = pick(out->us_dots);
+  // the z-marching form of the s-step basis stencil, 4, 8 and 16 planes
+  // per workgroup, against the best cell-parallel shape
+  out->zm_stencil = 0;
+  out->pad_ = 0;
+  for (int k = 0; k < 3; ++k) out->us_stencil_zm[k] = 0.0;
+  if (ca_f64) {
+    const int zms[3] = {4, 8, 16};
+    double best = 1e300;
+    for (int k = 0; k < 3; ++k) best = std::min(best, out->us_stencil[k]);
+    c->g.cpt_s = out->cpt_stencil;
+    for (int k = 0; k < 3; ++k) {
+      c->g.zm_s = zms[k];
+      out->us_stencil_zm[k] = time_us([&]() {
+        return kry::launch_stencil_axpby(kry::F64, U64, P64, X64, 2.0 / c->rho, 0.0, 1.0, c->g, c->mats,
+                                         c->stream);
+      });
+      if (out->us_stencil_zm[k] < 0) {
+        c->g = saved;
+        return fail(c, KRY_EHIP, "autotune launch failed");
+      }
+      if (out->us_stencil_zm[k] < best) {
+        best = out->us_stencil_zm[k];
+        out->zm_stencil = zms[k];
+      }
+    }
+  }
   c->g = saved;
   KRY_HIP(hipStreamSynchronize(c->stream));
   return api_set_tune(c, out);

@@ -14,6 +14,9 @@ struct DevGrid {
   // cells per thread (1, 2 or 4) of the operator kernels, the basis-update
   // kernels and the dot-product kernels (chosen by heuristic or autotuner)
   int cpt_s = 1, cpt_u = 1, cpt_d = 1;
+  // planes per workgroup of the z-marching basis stencil (4, 8 or 16; 0:
+  // the cell-parallel one with cpt_s cells per thread)
+  int zm_s = 0;
 };
 
 // Per-cell material data derived at context creation (all FP64, N3 each).

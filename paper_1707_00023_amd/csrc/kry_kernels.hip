@@ -231,6 +231,98 @@ __global__ __launch_bounds__(kBlock) void k_stencil_axpby(const T* __restrict__ 
   }
 }
 
+// The same step by z-marching columns of cells: a workgroup owns a 64 x 4
+// tile of (i, j) (one wave per row of 64 consecutive i: coalesced loads)
+// and KZ consecutive planes; each thread walks its (i, j) column up the
+// planes and keeps the z-neighbours in registers (H at k - 1 is the last
+// plane's own H, E at k + 1 becomes the next plane's own E), so v is read
+// once per plane plus one halo plane (Hx, Hy below, Ex, Ey above) per
+// chunk.  The x and y neighbours are read from the same or the adjacent
+// rows of the tile (cache hits).  No barriers: threads outside the grid
+// return at once.
+template <typename T, bool HAS_MU, int KZ>
+__global__ __launch_bounds__(kBlock) void k_stencil_axpby_zm(const T* __restrict__ v,
+                                                             const T* __restrict__ prev,
+                                                             T* __restrict__ out, double alpha,
+                                                             double gamma, double beta, DevGrid g,
+                                                             DevMats mt, int tiles_x, int tiles_y) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int tx = lb % tiles_x;
+  const int rest = lb / tiles_x;
+  const int ty = rest % tiles_y;
+  const int kc = rest / tiles_y;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int i = tx * 64 + (threadIdx.x & 63);
+  const int j = ty * 4 + (threadIdx.x >> 6);
+  if (i >= nx || j >= ny) return;
+  const int k0 = kc * KZ;
+  const int k1 = min(nz, k0 + KZ);
+  const long long N3 = g.N3;
+  const long long sy = nx, sz = (long long)nx * ny;
+  const T* Hx = v;
+  const T* Hy = v + N3;
+  const T* Hz = v + 2 * N3;
+  const T* Ex = v + 3 * N3;
+  const T* Ey = v + 4 * N3;
+  const T* Ez = v + 5 * N3;
+  const T z0 = T(0);
+  long long c = (long long)k0 * sz + (long long)j * nx + i;
+  T hxm = k0 > 0 ? Hx[c - sz] : z0;  // H at k - 1
+  T hym = k0 > 0 ? Hy[c - sz] : z0;
+  T ex = Ex[c], ey = Ey[c];           // E at k
+  for (int k = k0; k < k1; ++k, c += sz) {
+    const T ez = Ez[c];
+    const T exk = (k + 1 < nz) ? Ex[c + sz] : z0;
+    const T eyk = (k + 1 < nz) ? Ey[c + sz] : z0;
+    const T ex_j = (j + 1 < ny) ? Ex[c + sy] : z0;
+    const T ey_i = (i + 1 < nx) ? Ey[c + 1] : z0;
+    const T ez_i = (i + 1 < nx) ? Ez[c + 1] : z0;
+    const T ez_j = (j + 1 < ny) ? Ez[c + sy] : z0;
+    const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
+    const T hx_j = (j > 0) ? Hx[c - sy] : z0;
+    const T hy_i = (i > 0) ? Hy[c - 1] : z0;
+    const T hz_i = (i > 0) ? Hz[c - 1] : z0;
+    const T hz_j = (j > 0) ? Hz[c - sy] : z0;
+    const T cex = (ez_j - ez) - (eyk - ey);
+    const T cey = (exk - ex) - (ez_i - ez);
+    const T cez = (ey_i - ey) - (ex_j - ex);
+    const T chx = (hz - hz_j) - (hy - hym);
+    const T chy = (hx - hxm) - (hz - hz_i);
+    const T chz = (hy - hy_i) - (hx - hx_j);
+    const T ie = T(mt.inv_eps[c]);
+    const T sg = T(mt.sigma[c]);
+    T o[6];
+    if (HAS_MU) {
+      const T im = T(mt.inv_mu[c]);
+      const T se = T(mt.sigma[c] * mt.mu[c]);
+      o[0] = sg * hx + im * cex;
+      o[1] = sg * hy + im * cey;
+      o[2] = sg * hz + im * cez;
+      o[3] = ie * (se * ex - chx);
+      o[4] = ie * (se * ey - chy);
+      o[5] = ie * (se * ez - chz);
+    } else {
+      o[0] = sg * hx + cex;
+      o[1] = sg * hy + cey;
+      o[2] = sg * hz + cez;
+      o[3] = ie * (sg * ex - chx);
+      o[4] = ie * (sg * ey - chy);
+      o[5] = ie * (sg * ez - chz);
+    }
+    const T ctr[6] = {hx, hy, hz, ex, ey, ez};
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      double r = alpha * (double)o[p] + gamma * (double)ctr[p];
+      if (prev) r += beta * (double)prev[p * N3 + c];
+      out[p * N3 + c] = T(r);
+    }
+    hxm = hx;
+    hym = hy;
+    ex = exk;
+    ey = eyk;
+  }
+}
+
 // Pass A of a delayed-reorthogonalisation Arnoldi step.  For the candidate
 // u (orthogonalised once against V_0..cnt-1, neither reorthogonalised nor
 // normalised): x = A u, and in the same sweep the partial sums of
@@ -881,6 +973,23 @@ template <typename T>
 static hipError_t stencil_axpby_t(const void* v, const void* prev, void* out, double alpha,
                                   double gamma, double beta, const DevGrid& g, const DevMats& m,
                                   hipStream_t s) {
+  if (g.zm_s > 0) {  // z-marching columns, g.zm_s planes per workgroup
+    const int tiles_x = (g.nx + 63) / 64, tiles_y = (g.ny + 3) / 4;
+    const int kz = g.zm_s >= 16 ? 16 : (g.zm_s >= 8 ? 8 : 4);
+    const dim3 grid((unsigned)(tiles_x * tiles_y * ((g.nz + kz - 1) / kz))), blk(kBlock);
+    const T* vv = (const T*)v;
+    const T* pp = (const T*)prev;
+    T* oo = (T*)out;
+    const bool mu = m.inv_mu != nullptr;
+#define KRY_SZM(KZ)                                                                                      \
+  if (mu) hipLaunchKernelGGL((k_stencil_axpby_zm<T, true, KZ>), grid, blk, 0, s, vv, pp, oo, alpha, gamma, \
+                             beta, g, m, tiles_x, tiles_y);                                             \
+  else hipLaunchKernelGGL((k_stencil_axpby_zm<T, false, KZ>), grid, blk, 0, s, vv, pp, oo, alpha, gamma,   \
+                          beta, g, m, tiles_x, tiles_y);
+    if (kz == 16) { KRY_SZM(16) } else if (kz == 8) { KRY_SZM(8) } else { KRY_SZM(4) }
+#undef KRY_SZM
+    return hipGetLastError();
+  }
   const int cpt = g.cpt_s;
   const dim3 grid(cell_blocks(g.N3, cpt)), blk(kBlock);
   const T* vv = (const T*)v;

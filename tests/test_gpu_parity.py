@@ -152,6 +152,36 @@ def test_arnoldi_relation_and_orthogonality(m, orth, s_step):
     assert abs(math.sqrt(r @ (w * r)) - est) <= 1e-10 * max(est, 1e-300) + 1e-13 * beta
 
 
+@pytest.mark.parametrize("shape,with_mu,storage", [((67, 13, 23), True, "f64"), ((64, 8, 16), False, "f64"),
+                                                   ((130, 5, 37), False, "f32")])
+def test_zmarch_stencil_equals_cell_parallel(shape, with_mu, storage):
+    # the z-marching form of the s-step basis stencil (4, 8 and 16 planes per
+    # workgroup; ragged tiles in x, y and z) computes the same expressions in
+    # the same order as the cell-parallel one: the s-step Arnoldi bases and H
+    # agree bitwise
+    _announce(f"z-march stencil {shape} mu={with_mu} {storage}")
+    eps, mu, sig = _box(shape, 21, with_mu)
+    v = np.random.default_rng(5).standard_normal(6 * eps.size)
+    ref = None
+    for zm in (0, 4, 8, 16):
+        s = _solver(eps, mu, sig, krylov_dim=32, s_step=16, storage=storage)
+        s.set_tune(zm_stencil=zm)
+        V, H, beta, steps = s.arnoldi(_t(v), 32)
+        s.close()
+        if ref is None:
+            ref = (V.cpu().numpy(), H)
+            # and the basis is a Krylov basis of the oracle operator (the
+            # s-step Hessenberg algebra carries the block's conditioning:
+            # 1e-11 on these random boxes)
+            Vn = ref[0].astype(np.float64).T
+            mu_or = mu if mu is not None else np.ones(shape)
+            AV = np.stack([op.apply_A(eps, mu_or, sig, Vn[:, j]) for j in range(steps)], axis=1)
+            tol = 1e-11 if storage == "f64" else 2e-6
+            assert np.abs(AV - Vn @ H[:, :steps]).max() <= tol * np.abs(AV).max()
+        else:
+            assert np.array_equal(V.cpu().numpy(), ref[0]) and np.array_equal(H, ref[1])
+
+
 @pytest.mark.parametrize("m,s_step", [(32, 16), (30, 8), (64, 32)])
 def test_sstep_arnoldi_fp32_storage(m, s_step):
     # FP32 storage: the Chebyshev block and both Gram-Schmidt passes are
@@ -790,36 +820,79 @@ def test_grad_transient_15cube_directional_against_oracle():
         assert abs(dd - r["directional"][k]) <= 1e-8 * gnorm * np.linalg.norm(d)
 
 
+def _flux_real(y, N, kf):
+    """Instantaneous flux sum [Ex Hy_bar - Ey Hx_bar] of a real device field
+    through plane kf (H_bar the mean of the H planes kf - 1 and kf)."""
+    Y = y.view(6, N, N, N)
+    hx = 0.5 * (Y[0, kf - 1] + Y[0, kf])
+    hy = 0.5 * (Y[1, kf - 1] + Y[1, kf])
+    return float(torch.sum(Y[3, kf] * hy - Y[4, kf] * hx))
+
+
 def test_grad_transient_full_size_directional_differences():
     # the 64^3 medium of the gradient workload, two of its frequencies,
     # T = 60: the adjoint gradient along two random permittivity changes
-    # against central differences of the loss.  The losses carry ~3e-11 of
-    # relative error (solves to 1e-12 relative residual), which a step of
-    # 1e-5 turns into ~5e-6 of the directional derivative; the step 1e-4
-    # (eps ~ 2.5) keeps that and the O(h^2) truncation near 1e-7
+    # against central differences of the loss.  Two independent shifted
+    # solves differ by far more than their residual target (the systems are
+    # ill-conditioned near the cavity's resonances), so the perturbed z come
+    # from exact difference solves, z+- = z + d+- with (A+- + i w) d+- =
+    # -(A+- - A) z, which is (1 - eps / (eps +- h d)) (A z) on the E edges;
+    # the transients e^{-T A+-} Im z+- are computed on the perturbed media,
+    # and the flux of y+-(T) follows.  The loss still carries ~1e-9 of
+    # noise (the flux is a small sum of large plane products, and each
+    # transient's error is independent), which steps of 1e-5 turn into
+    # 2e-5 of the derivative whatever the transients' tolerance; so steps of
+    # 5e-4 and 1e-3 are taken and combined by Richardson extrapolation,
+    # (4 D(h) - D(2h)) / 3, which removes the O(h^2) truncation
     wl = wk.C4
-    N, kf, T, h = wl.N, wl.flux_plane, 60.0, 1e-4
+    N, kf, T, h = wl.N, wl.flux_plane, 60.0, 5e-4
     om = list(wl.omegas[::4])
+    n3 = N ** 3
     _announce(f"finite-time flux gradient 64^3, T = {T}, directional central differences")
     inp = wk.generate(wl)
     b = _t(wk.source_vector(wl, wl.omegas[0], 0.0)[None, :])
-    s = _solver(inp.eps, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=1e-12)
+    s = _solver(inp.eps, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=1e-13)
     t0 = time.time()
     L, g = s.grad_transient(om, b, kf, T)
     _announce(f"64^3 finite-time gradient {time.time() - t0:.1f}s L={L:.6e} stats={s.last_stats}")
-    s.close()
     g = g.cpu().numpy()
+    z = s.stationary(om, b)  # (2, n) complex
+    Az = torch.complex(s.apply(z.real.contiguous()), s.apply(z.imag.contiguous()))
+
+    def loss_of(zz, solver):
+        tot = 0.0
+        for q, w in enumerate(om):
+            yh = solver.expv(T, zz[q].imag.contiguous())[0]
+            y = torch.imag(np.exp(1j * w * T) * zz[q]) - yh
+            tot += _flux_real(y, N, kf)
+        return tot
+
+    # the flux written out here agrees with the library's loss
+    L0 = loss_of(z, s)
+    _announce(f"64^3 loss written out {L0:.12e}, library {L:.12e}")
+    assert abs(L0 - L) <= 1e-10 * abs(L)
+    s.close()
     rng = np.random.default_rng(77)
+    eps_t = _t(inp.eps.reshape(-1))
+    def loss_perturbed(e):
+        fac = 1.0 - eps_t / _t(e.reshape(-1))
+        rhs = torch.zeros_like(z)
+        for comp in (3, 4, 5):
+            rhs[:, comp * n3:(comp + 1) * n3] = fac * Az[:, comp * n3:(comp + 1) * n3]
+        sp = _solver(e, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=1e-13)
+        dz = sp.stationary(om, rhs, b_per_omega=True)
+        out = loss_of(z + dz, sp)
+        sp.close()
+        return out
+
     for k in range(2):
         d = rng.standard_normal(inp.eps.shape)
-        Ls = []
-        for sgn in (1.0, -1.0):
-            sp = _solver(inp.eps + sgn * h * d, None, inp.sigma, krylov_dim=wl.krylov_dim, tol=1e-12)
-            Ls.append(sp.grad_transient(om, b, kf, T, loss_only=True)[0])
-            sp.close()
-        fd = (Ls[0] - Ls[1]) / (2 * h)
+        D = [(loss_perturbed(inp.eps + a * h * d) - loss_perturbed(inp.eps - a * h * d)) / (2 * a * h)
+             for a in (1, 2)]
+        fd = (4 * D[0] - D[1]) / 3
         dd = float((g * d).sum())
-        _announce(f"64^3 direction {k}: adjoint {dd:.10e}, central differences {fd:.10e}")
+        _announce(f"64^3 direction {k}: adjoint {dd:.10e}, differences h {D[0]:.10e}, 2h {D[1]:.10e}, "
+                  f"extrapolated {fd:.10e}")
         assert abs(dd - fd) <= 1e-5 * abs(fd)
 
 
