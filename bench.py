@@ -378,6 +378,9 @@ def main():
                     help="skip the one-off timings of the restarted method and source splitting")
     ap.add_argument("--split2-periods", type=int, default=5,
                     help="source splitting: periods of the source per subinterval")
+    ap.add_argument("--host-blocks", action="store_true",
+                    help="finish each s-step block on the host (one synchronisation per "
+                         "Gram-Schmidt pass) instead of on the device")
     ap.add_argument("--timing-sample", type=int, default=7, metavar="N",
                     help="time one kernel launch in N with HIP events inside the timed steps "
                          "(1: every launch, which adds about 4%% of host overhead to a solve)")
@@ -419,7 +422,7 @@ def main():
     sig = torch.as_tensor(inp.sigma, device=dev)
     solver = kry.Solver(eps, None, sig, kry.Options(storage=wl.storage, krylov_dim=wl.krylov_dim,
                                                     tol=wl.tol, timing=args.timing_sample,
-                                                    s_step=args.s_step))
+                                                    s_step=args.s_step, host_blocks=args.host_blocks))
     tune = None if args.no_autotune else solver.autotune()
     cols = [wk.source_vector(wl, w, float(th)) for w in wl.omegas for th in inp.thetas]
     b = torch.as_tensor(np.stack(cols), device=dev)

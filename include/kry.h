@@ -124,6 +124,12 @@ typedef struct {
                            Im z), each column's accumulated error estimate
                            kept within its own budget (a column starts a
                            new chain otherwise)                           */
+  int32_t host_blocks;  /* s-step Arnoldi with FP64 storage: 0 = each block's
+                           Gram-Schmidt factors, checks and coefficients on
+                           the device, one host synchronisation per restart
+                           cycle (blocks the host would treat apart send
+                           the cycle to the host form); 1 = the host form,
+                           one synchronisation per Gram-Schmidt pass       */
 } kry_opts;
 
 /* Kernel classes reported by the per-kernel timing. */

@@ -44,7 +44,8 @@ class KryOpts(ctypes.Structure):
                 ("timing", ctypes.c_int32), ("block_steps", ctypes.c_int32),
                 ("block_steps_transient", ctypes.c_int32), ("verbose", ctypes.c_int32),
                 ("orth", ctypes.c_int32), ("s_step", ctypes.c_int32),
-                ("omega_continuation", ctypes.c_int32), ("transient_continuation", ctypes.c_int32)]
+                ("omega_continuation", ctypes.c_int32), ("transient_continuation", ctypes.c_int32),
+                ("host_blocks", ctypes.c_int32)]
 
 
 class KryStats(ctypes.Structure):
@@ -193,6 +194,9 @@ class Options:
     # continue each column's transient from the previous column of the same
     # source: e^{-TA} is applied to the difference of the two Im z only
     transient_continuation: bool = False
+    # s-step blocks finished on the host (one synchronisation per
+    # Gram-Schmidt pass) instead of on the device (one per restart cycle)
+    host_blocks: bool = False
 
 
 class Solver:
@@ -228,7 +232,8 @@ class Solver:
                             1 if opts.orth == "cgs2" else 0,
                             int(opts.s_step if opts.s_step is not None else DEFAULT_S_STEP),
                             int(bool(opts.omega_continuation)),
-                            int(bool(opts.transient_continuation)))
+                            int(bool(opts.transient_continuation)),
+                            int(bool(opts.host_blocks)))
         self.storage = opts.storage
         ctx = ctypes.c_void_p()
         rc = lib.kry_create(ctypes.byref(self.grid), _ptr(e),

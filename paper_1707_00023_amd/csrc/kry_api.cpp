@@ -86,6 +86,13 @@ struct kry_ctx {
   size_t gp_cap = 0;
   double* d_bc = nullptr;      // reduced Gram / coefficient matrices
   size_t bc_cap = 0;
+  // device finish of the s-step blocks: update coefficients, per-block
+  // stash of the Gram-Schmidt factors, per-block flags
+  double* d_K = nullptr;
+  double* d_stash = nullptr;
+  size_t stash_cap = 0;
+  int* d_flags = nullptr;
+  int flags_cap = 0;
 
   // captured Arnoldi cycles (one per cycle length), replayed on `stream`
   hipStream_t cstream = nullptr;  // private capture stream (default priority)
@@ -881,6 +888,7 @@ int api_create(const kry_grid* grid, const double* eps, const double* mu, const 
     if (mu) min_m = std::min(min_m, hm[i]);
   }
   if (opts->s_step < 0 || opts->s_step > 64) return fail(nullptr, KRY_EINVAL, "s_step out of range");
+  if (opts->host_blocks != 0 && opts->host_blocks != 1) return fail(nullptr, KRY_EINVAL, "invalid host_blocks");
   c = new (std::nothrow) kry_ctx();
   if (!c) return fail(nullptr, KRY_ENOMEM, "host allocation failed");
   c->g.nx = grid->nx;
@@ -954,6 +962,13 @@ void api_destroy(kry_ctx* c) {
   hipFree(c->TC);
   hipFree(c->d_r);
   hipFree(c->SB);
+  hipFree(c->BV);
+  hipFree(c->d_w);
+  hipFree(c->d_gp);
+  hipFree(c->d_bc);
+  hipFree(c->d_K);
+  hipFree(c->d_stash);
+  hipFree(c->d_flags);
   drop_graphs(c);
   if (c->cstream) hipStreamDestroy(c->cstream);
   for (auto& p : c->pending) {
@@ -1564,7 +1579,7 @@ const std::vector<double>& stack_coef(int M, int s, const std::vector<double>& C
   return K;
 }
 
-int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
+int arnoldi_ca_host(kry_ctx* c, int m, double* beta, int* m_eff) {
   const int s = c->s_eff;
   // largest accepted condition estimate |R|_F |R^-1|_F of a block's
   // triangular factor: rounding of the stored block reaches Hbar amplified
@@ -1575,6 +1590,9 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
   // skipped when the column-scaled estimate of cond(R1) puts that below
   // 1e-11 (u = 1.1e-16)
   const double one_pass_max = 300.0;
+  // ... and when no column lost all but 1e-6 of its squared norm to the
+  // projection (the Pythagorean Gram matrix keeps ~10 digits there)
+  const double one_pass_left = 1e-6;
   const int ldh = m + 1;
   hipStream_t st = c->stream;
   int rc = ensure_weights(c);
@@ -1685,10 +1703,16 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
       for (size_t i = 0; i < Rs.size(); ++i) f1 += Rs[i] * Rs[i], f2 += RI[i] * RI[i];
       return std::sqrt(f1 * f2);
     };
+    // the smallest share of a column's squared norm left after the
+    // projection: the projected Gram matrix comes from a difference, so a
+    // block mostly inside the basis (a nearly invariant space) loses digits
+    // there, and one pass is not enough however well conditioned R1 is
+    double left = 1.0;
+    for (int k = 0; k < ss; ++k) left = std::min(left, G[(size_t)k * ss + k] / std::max(nrm2[k], 1e-300));
     bool ok = kry::chol_upper(ss, G.data(), ref.data(), 1e-10, R1.data());
     // a well-conditioned block is final after one pass: written straight
     // into the basis slots in the storage type
-    const bool one = ok && (inplace || wide) && cond_est(R1) <= one_pass_max;
+    const bool one = ok && (inplace || wide) && left >= one_pass_left && cond_est(R1) <= one_pass_max;
     void* Tb = inplace ? S : Tb0;
     if (ok) {
       kry::inv_upper(ss, R1.data(), Ri.data());
@@ -1774,6 +1798,190 @@ int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
     }
   }
   return KRY_OK;
+}
+
+// The s-step cycle with every block finished on the device: the Gram
+// product, its reduction, the Cholesky factor, the condition checks and the
+// update coefficients (launch_sstep_fin), then the update, per pass; the
+// second pass's launches skip themselves (a device flag) when the first
+// pass was final.  The host waits once, at the end of the cycle, for the
+// blocks' factors and flags, and forms H with the same algebra as the host
+// path.  Any block that the host path would not take as is (a dependent or
+// too ill-conditioned block) sets *redo: the caller then runs the cycle on
+// the host path from the normalised start vector (slot 0).  FP64 storage,
+// blocks of at most 16 steps, M + s <= 256.
+bool dev_cycle_ok(kry_ctx* c, int m) {
+  const int s = c->s_eff;
+  return c->st == kry::F64 && s > 1 && s <= 16 && m + 1 <= 256 && !c->opts.host_blocks;
+}
+
+int arnoldi_ca_dev(kry_ctx* c, int m, double* beta, int* m_eff, bool* redo) {
+  *redo = false;
+  const int s = c->s_eff;
+  const double cond_max = 1e6, one_pass_max = 300.0, one_pass_left = 1e-6;
+  const int ldh = m + 1;
+  hipStream_t st = c->stream;
+  int rc = ensure_weights(c);
+  if (rc) return rc;
+  std::vector<double> d;
+  rc = host_dots(c, slot(c, 0), nullptr, 0, d);
+  if (rc) return rc;
+  double* H = c->h_H;
+  std::fill(H, H + (size_t)(m + 1) * m, 0.0);
+  const double b0 = std::sqrt(std::max(d[0], 0.0));
+  if (!(b0 > 0.0)) {
+    *beta = 0.0;
+    *m_eff = 0;
+    return KRY_OK;
+  }
+  KRY_HIP(kry::launch_fin_start(c->d_red1, c->d_scal + 2, st));
+  KRY_HIP(kry::launch_scale(c->st, slot(c, 0), c->d_scal + 2, slot(c, 0), c->n, st));
+  const double rho = c->rho;
+  const bool newton = (int)c->sh_alpha.size() >= s;
+  const int bs = newton ? s : std::min(s, 16);
+  std::vector<double> al(bs, 0.0), qq(bs, 0.0), sg(bs, 0.0);
+  for (int k = 0; k < bs; ++k) {
+    if (newton) {
+      al[k] = c->sh_alpha[k];
+      qq[k] = c->sh_q[k];
+      sg[k] = rho;
+    } else {
+      sg[k] = k == 0 ? rho : 0.5 * rho;
+      qq[k] = k == 0 ? 0.0 : 0.5 * rho;
+    }
+  }
+  // per-block stash offsets, workspace
+  std::vector<size_t> off;
+  size_t tot = 0, gp = 0, bc = 0;
+  int nblk = 0;
+  for (int j0 = 0; j0 < m; j0 += bs, ++nblk) {
+    const int ss = std::min(bs, m - j0), M = j0 + 1;
+    off.push_back(tot);
+    tot += (size_t)kry::sstep_stash_doubles(M, ss);
+    gp = std::max(gp, (size_t)kry::gram_splits(c->n, M + ss, ss) * (M + ss) * ss);
+    bc = std::max(bc, (size_t)(M + ss) * ss);
+  }
+  rc = ensure_gp(c, gp, bc);
+  if (rc) return rc;
+  if (!c->d_K) KRY_HIP(hipMalloc(&c->d_K, sizeof(double) * 256 * 16));
+  if (tot > c->stash_cap) {
+    hipFree(c->d_stash);
+    c->d_stash = nullptr;
+    KRY_HIP(hipMalloc(&c->d_stash, sizeof(double) * tot));
+    c->stash_cap = tot;
+  }
+  if (4 * nblk > c->flags_cap) {
+    hipFree(c->d_flags);
+    c->d_flags = nullptr;
+    KRY_HIP(hipMalloc(&c->d_flags, sizeof(int) * 4 * nblk));
+    c->flags_cap = 4 * nblk;
+  }
+  const double mb_axpby = mbytes(c, true) - 8.0 * c->g.N3;
+  const double vb = vbytes(c);
+  std::vector<std::vector<double>> Tms;
+  for (int j0 = 0, b = 0; j0 < m; j0 += bs, ++b) {
+    const int ss = std::min(bs, m - j0);
+    const int M = j0 + 1;
+    void* S = slot(c, j0 + 1);
+    auto tk = [&](int k) { return slot(c, j0 + k); };
+    std::vector<double> Tm((size_t)(ss + 1) * ss, 0.0);
+    for (int k = 0; k < ss; ++k) {
+      const bool prev = k > 0 && qq[k] != 0.0;
+      hipEvent_t e = tbeg(c);
+      KRY_HIP(kry::launch_stencil_axpby(kry::F64, tk(k), prev ? tk(k - 1) : nullptr, tk(k + 1), 1.0 / sg[k],
+                                        -al[k] / sg[k], prev ? qq[k] / sg[k] : 0.0, c->g, c->mats, st));
+      tend(c, e, KRY_K_STENCIL, vb * (prev ? 3.0 : 2.0) + mb_axpby);
+      Tm[(size_t)(k + 1) * ss + k] = sg[k];
+      Tm[(size_t)k * ss + k] = al[k];
+      if (prev) Tm[(size_t)(k - 1) * ss + k] = -qq[k];
+    }
+    Tms.push_back(std::move(Tm));
+    const int ns = kry::gram_splits(c->n, M + ss, ss);
+    double* stash = c->d_stash + off[b];
+    int* flags = c->d_flags + 4 * b;
+    const double gram_bytes = vb * (M + ss) + 8.0 * c->n;
+    const double gemm_bytes = vb * (M + ss) + vb * ss;
+    for (int pass = 1; pass <= 2; ++pass) {
+      const int* skip = pass == 2 ? flags + 1 : nullptr;
+      // the second pass's launches are timed only when they are known to run
+      hipEvent_t e = pass == 1 ? tbeg(c) : nullptr;
+      KRY_HIP(kry::launch_gram(kry::F64, slot(c, 0), M + ss, S, ss, c->ldv, c->d_w, c->n, c->d_gp, ns, st, S, M,
+                               -1, skip));
+      if (pass == 1) tend(c, e, KRY_K_GRAM, gram_bytes, 2.0 * c->n * (M + ss) * ss);
+      KRY_HIP(kry::launch_reduce(c->d_gp, ns, (M + ss) * ss, (M + ss) * ss, c->d_bc, st, skip));
+      KRY_HIP(kry::launch_sstep_fin(pass, M, ss, c->d_bc, c->d_K, stash, flags, one_pass_max, one_pass_left,
+                                    cond_max, st));
+      e = pass == 1 ? tbeg(c) : nullptr;
+      KRY_HIP(kry::launch_gemm_nn(kry::F64, slot(c, 0), M + ss, c->d_K, ss, S, c->ldv, c->n, 1.0, 0, st, S, M,
+                                  -1, -1, skip));
+      if (pass == 1) tend(c, e, KRY_K_GEMM, gemm_bytes, 2.0 * c->n * (M + ss) * ss);
+    }
+  }
+  std::vector<double> hs(tot);
+  std::vector<int> hf(4 * nblk);
+  KRY_HIP(hipMemcpyAsync(hs.data(), c->d_stash, sizeof(double) * tot, hipMemcpyDeviceToHost, st));
+  KRY_HIP(hipMemcpyAsync(hf.data(), c->d_flags, sizeof(int) * 4 * nblk, hipMemcpyDeviceToHost, st));
+  KRY_HIP(hipStreamSynchronize(st));
+  for (int b = 0; b < nblk; ++b) {
+    const int* f = hf.data() + 4 * b;
+    if (!f[0] || (!f[1] && (!f[2] || f[3]))) {
+      tresolve(c);
+      *beta = b0;
+      *redo = true;
+      return KRY_OK;
+    }
+  }
+  for (int j0 = 0, b = 0; j0 < m; j0 += bs, ++b) {
+    const int ss = std::min(bs, m - j0), M = j0 + 1;
+    const double* C1 = hs.data() + off[b];
+    const double* R1 = C1 + (size_t)M * ss;
+    const double* C2 = R1 + (size_t)ss * ss + ss + (size_t)ss * ss;
+    const double* R2 = C2 + (size_t)M * ss;
+    std::vector<double> C2h, R2h;
+    if (hf[4 * b + 1]) {  // final after one pass
+      C2h.assign((size_t)M * ss, 0.0);
+      R2h.assign((size_t)ss * ss, 0.0);
+      for (int a = 0; a < ss; ++a) R2h[(size_t)a * ss + a] = 1.0;
+      C2 = C2h.data();
+      R2 = R2h.data();
+    } else if (c->opts.timing > 0) {  // its second pass ran: count its launches
+      c->k_launch_all[KRY_K_GRAM] += 1;
+      c->k_bytes_all[KRY_K_GRAM] += vb * (M + ss) + 8.0 * c->n;
+      c->k_launch_all[KRY_K_GEMM] += 1;
+      c->k_bytes_all[KRY_K_GEMM] += vb * (M + 2.0 * ss);
+    }
+    kry::sstep_hessenberg_tm(j0, ss, Tms[b].data(), C1, C2, R1, R2, H, ldh);
+  }
+  tresolve(c);
+  *beta = b0;
+  *m_eff = m;
+  if (!newton) {
+    std::vector<double> re(m), im(m);
+    c->sh_alpha.assign(s, 0.0);
+    c->sh_q.assign(s, 0.0);
+    if (!kry::hess_eigvals(m, H, ldh, re.data(), im.data()) ||
+        kry::leja_steps(m, re.data(), im.data(), s, rho, c->sh_alpha.data(), c->sh_q.data()) < s) {
+      c->sh_alpha.clear();
+      c->sh_q.clear();
+    }
+  }
+  return KRY_OK;
+}
+
+int arnoldi_ca(kry_ctx* c, int m, double* beta, int* m_eff) {
+  if (dev_cycle_ok(c, m)) {
+    bool redo = false;
+    int rc = arnoldi_ca_dev(c, m, beta, m_eff, &redo);
+    if (rc || !redo) return rc;
+    // a block the host path treats apart: the cycle again on the host path
+    // from the normalised start vector
+    const double b0 = *beta;
+    double b1 = 0.0;
+    rc = arnoldi_ca_host(c, m, &b1, m_eff);
+    *beta = b0 * b1;
+    return rc;
+  }
+  return arnoldi_ca_host(c, m, beta, m_eff);
 }
 
 // Rank-revealing Cholesky QR, twice: Out[:p] = M-orthonormal basis of W[:p]

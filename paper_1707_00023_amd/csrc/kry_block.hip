@@ -126,8 +126,10 @@ __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int 
                                                    const T2* __restrict__ X2, int M,
                                                    const T2* __restrict__ Y, int N, long long ld,
                                                    const double* __restrict__ w, long long n,
-                                                   long long kchunk, double* __restrict__ partials) {
+                                                   long long kchunk, double* __restrict__ partials,
+                                                   const int* __restrict__ skip) {
   static_assert(!YSEG || MT > NT, "YSEG keeps Y in the first NT row tiles");
+  if (skip && *skip) return;  // (uniform: the whole grid skips)
   static_assert(YSEG || sizeof(T) == sizeof(T2), "mixed element types need the YSEG layout");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, kk = lane >> 4;
@@ -293,7 +295,9 @@ template <typename T, typename T2, typename TO, int EPT, int NO>
 __global__ __launch_bounds__(256) void k_gemm_cols(const T* X, int M1, const T2* X2, int M,
                                                    const double* __restrict__ C, int N,
                                                    TO* Out, long long ld, long long n,
-                                                   double alpha, int accumulate) {
+                                                   double alpha, int accumulate,
+                                                   const int* __restrict__ skip) {
+  if (skip && *skip) return;  // (uniform: the whole grid skips)
   extern __shared__ double sC[];  // M x NO
   for (int t = threadIdx.x; t < M * NO; t += 256) {
     const int k = t / NO, j = t % NO;
@@ -383,7 +387,7 @@ int gram_splits(long long n, int M, int N) {
 
 hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, long long ld,
                        const double* w, long long n, double* partials, int nsplit, hipStream_t s,
-                       const void* X2, int M1, int st2_) {
+                       const void* X2, int M1, int st2_, const int* skip) {
   const Storage st2 = st2_ < 0 ? st : (Storage)st2_;
   if (!X2) {  // one segment
     M1 = M;
@@ -404,7 +408,7 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
     const dim3 grid(wg, yseg ? 1 : (M + 16 * mt - 1) / (16 * mt));
 #define KRY_TALL_(T, T2, MT, NT, YS)                                                              \
   hipLaunchKernelGGL((k_gram_tall<T, T2, MT, NT, YS>), grid, dim3(256), 0, s, (const T*)X, M1,     \
-                     (const T2*)X2, M, (const T2*)Y, N, ld, w, n, kchunk, partials);
+                     (const T2*)X2, M, (const T2*)Y, N, ld, w, n, kchunk, partials, skip);
 #define KRY_TALL_NT(MT, NT)                             \
   if (yseg) {                                           \
     if constexpr (MT > NT) {                            \
@@ -442,7 +446,7 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
 #undef KRY_TALL_
     return hipGetLastError();
   }
-  if (st2 != st) return hipErrorInvalidValue;
+  if (st2 != st || skip) return hipErrorInvalidValue;  // (no skip flag in the wide form)
   long long kchunk = (n + nsplit - 1) / nsplit;
   kchunk = (kchunk + 15) / 16 * 16;
   const int nt = N >= 64 ? 4 : (N + 15) / 16;
@@ -466,7 +470,7 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
 
 hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int N, void* Out,
                           long long ld, long long n, double alpha, int accumulate, hipStream_t s,
-                          const void* X2, int M1, int st2_, int sto_) {
+                          const void* X2, int M1, int st2_, int sto_, const int* skip) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const Storage st2 = st2_ < 0 ? st : (Storage)st2_;
   const Storage sto = sto_ < 0 ? st : (Storage)sto_;
@@ -485,7 +489,7 @@ hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int
     const size_t lds = sizeof(double) * (wide ? 32 : 16) * (size_t)M;
 #define KRY_GCOLS_(T, T2, TO, EPT, NO)                                                             \
   hipLaunchKernelGGL((k_gemm_cols<T, T2, TO, EPT, NO>), grid, dim3(256), lds, s, (const T*)X, M1,   \
-                     (const T2*)X2, M, C, N, (TO*)Out, ld, n, alpha, accumulate);
+                     (const T2*)X2, M, C, N, (TO*)Out, ld, n, alpha, accumulate, skip);
 #define KRY_GCOLS(T, T2, TO)         \
   if (wide) {                        \
     KRY_GCOLS_(T, T2, TO, 1, 32)     \
@@ -509,7 +513,7 @@ hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int
 #undef KRY_GCOLS_
     return hipGetLastError();
   }
-  if (mixed) return hipErrorInvalidValue;
+  if (mixed || skip) return hipErrorInvalidValue;  // (no skip flag in the wide form)
   const int nt = N >= 64 ? 4 : (N + 15) / 16;
   const dim3 grid((unsigned)((n + 63) / 64), (N + 16 * nt - 1) / (16 * nt));
 #define KRY_GEMM(NT)                                                                          \

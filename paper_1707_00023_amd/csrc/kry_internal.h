@@ -80,9 +80,11 @@ hipError_t launch_update(Storage st, const void* w, const void* V, long long ldv
                          const double* coef, const double* scale, void* out,
                          const DevGrid& g, hipStream_t s);
 
-// out[q] = sum_p partials[p * stride + q] for q < cnt, fixed order.
+// out[q] = sum_p partials[p * stride + q] for q < cnt, fixed order.  With
+// skip != nullptr the launch does nothing when *skip (device) is non-zero
+// (likewise for launch_gram and launch_gemm_nn in their N <= 32 forms).
 hipError_t launch_reduce(const double* partials, int nparts, int stride, int cnt, double* out,
-                         hipStream_t s);
+                         hipStream_t s, const int* skip = nullptr);
 
 // scal[1] = sqrt(red[0]), scal[0] = 1/scal[1] (0 if scal[1] == 0).
 hipError_t launch_fin_start(const double* red, double* scal, hipStream_t s);
@@ -137,7 +139,7 @@ int gram_splits(long long n, int M, int N);
 // supported for st = F32, st2 = F64 with Y = X2 and N = M - M1 <= 16.
 hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, long long ld,
                        const double* w, long long n, double* partials, int nsplit, hipStream_t s,
-                       const void* X2 = nullptr, int M1 = 0, int st2 = -1);
+                       const void* X2 = nullptr, int M1 = 0, int st2 = -1, const int* skip = nullptr);
 // Out[:, :N] = (accumulate ? Out : 0) + alpha X[:, :M] C (C row-major M x N);
 // X in one or two segments as for launch_gram.  Out must not overlap X,
 // except for N <= 16 with M <= 256 and N <= 32 with M <= 128 (the
@@ -147,7 +149,22 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
 // with F64 in X2 and/or Out) for N <= 16, M <= 256 only.
 hipError_t launch_gemm_nn(Storage st, const void* X, int M, const double* C, int N, void* Out,
                           long long ld, long long n, double alpha, int accumulate, hipStream_t s,
-                          const void* X2 = nullptr, int M1 = 0, int st2 = -1, int sto = -1);
+                          const void* X2 = nullptr, int M1 = 0, int st2 = -1, int sto = -1,
+                          const int* skip = nullptr);
+// Device finish of one Gram-Schmidt pass of an s-step block (kry_sstep.hip;
+// one workgroup): from P = [V, S]^T M S ((M + s) x s row-major, reduced) it
+// forms the projected Gram matrix, its Cholesky factor R, the coefficients
+// K ((M + s) x s row-major) of the update [V, S] K = (S - V C) R^{-1}, and
+// stores C, R (and on pass 1 the squared column norms of S) in `stash` for
+// the Hessenberg algebra on the host; flags[0..3] = pass-1 factor valid,
+// pass 1 final (the second pass is skipped: flags[1] is the skip flag of the
+// pass-2 launches), pass-2 factor valid, basis too ill-conditioned.  A
+// failed factor leaves K = [0; I] (S unchanged) and the host redoes the
+// cycle.  s <= 16, M + s <= 256.
+int sstep_stash_doubles(int M, int s);
+hipError_t launch_sstep_fin(int pass, int M, int s, const double* P, double* K, double* stash,
+                            int* flags, double one_pass_max, double one_pass_left, double cond_max,
+                            hipStream_t st);
 // Energy weight of every entry (mu on H planes, eps on E planes).
 hipError_t launch_weights(const double* eps, const double* mu, double* w, long long N3,
                           hipStream_t s);

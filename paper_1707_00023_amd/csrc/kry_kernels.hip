@@ -652,7 +652,9 @@ __global__ __launch_bounds__(kBlock) void k_update(const T* w, const T* __restri
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ partials, int nparts,
-                                                   int stride, double* __restrict__ out) {
+                                                   int stride, double* __restrict__ out,
+                                                   const int* __restrict__ skip) {
+  if (skip && *skip) return;  // (uniform: the whole grid skips)
   const int q = blockIdx.x;
   double acc = 0.0;
   for (int p = threadIdx.x; p < nparts; p += kBlock) acc += partials[(long long)p * stride + q];
@@ -1120,8 +1122,8 @@ hipError_t launch_update(Storage st, const void* w, const void* V, long long ldv
 }
 
 hipError_t launch_reduce(const double* partials, int nparts, int stride, int cnt, double* out,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(cnt), dim3(kBlock), 0, s, partials, nparts, stride, out);
+                         hipStream_t s, const int* skip) {
+  hipLaunchKernelGGL(k_reduce, dim3(cnt), dim3(kBlock), 0, s, partials, nparts, stride, out, skip);
   return hipGetLastError();
 }
 

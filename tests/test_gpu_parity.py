@@ -182,6 +182,44 @@ def test_zmarch_stencil_equals_cell_parallel(shape, with_mu, storage):
             assert np.array_equal(V.cpu().numpy(), ref[0]) and np.array_equal(H, ref[1])
 
 
+@pytest.mark.parametrize("N,m,s_step", [(20, 64, 16), (16, 30, 8), (12, 48, 16)])
+def test_device_block_finish_matches_host(N, m, s_step):
+    # the s-step cycle with each block's Gram-Schmidt factors, checks and
+    # coefficients on the device (one synchronisation per cycle) against the
+    # host form of the same cycle: bases and H to rounding, and a solve
+    _announce(f"device block finish {N}^3 m={m} s={s_step}")
+    wl = wk.small(N, seed=N, n_spheres=6, layer=2)
+    inp = wk.generate(wl)
+    eps, sig = inp.eps, inp.sigma
+    shape = eps.shape
+    v = np.random.default_rng(8).standard_normal(6 * eps.size)
+    out = {}
+    for hb in (True, False):
+        s = _solver(eps, None, sig, krylov_dim=m, s_step=s_step, host_blocks=hb, tol=1e-10)
+        V, H, beta, steps = s.arnoldi(_t(v), m)
+        b = np.zeros(6 * eps.size, dtype=np.complex128)
+        b[3 * eps.size: 4 * eps.size] = np.random.default_rng(9).standard_normal(eps.size)
+        y = s.solve_multifreq([0.6, 0.65], _t(b[None, :]), 12.0).cpu().numpy()
+        out[hb] = (V.cpu().numpy(), H, beta, steps, y, s.last_stats)
+        s.close()
+    Vh, Hh, bh, sh, yh, sth = out[True]
+    Vd, Hd, bd, sd, yd, std_ = out[False]
+    assert sh == sd == m and abs(bh - bd) <= 1e-14 * bh
+    # both are M-orthonormal Krylov bases with the Arnoldi relation; the two
+    # forms round the small factors differently, and an s-step block passes
+    # the difference on amplified by its condition (up to 1e6 by the guard),
+    # so the bases themselves agree to 1e-6 here, the solves to 1e-9
+    w = op.material_weights(eps, np.ones(shape))
+    for V, H in ((Vh, Hh), (Vd, Hd)):
+        Vn = V.T
+        assert np.abs(Vn.T @ (w[:, None] * Vn) - np.eye(m + 1)).max() <= 1e-10
+        AV = np.stack([op.apply_A(eps, np.ones(shape), sig, Vn[:, j]) for j in range(m)], axis=1)
+        assert np.abs(AV - Vn @ H).max() <= 1e-11 * np.abs(AV).max()
+    assert np.abs(Vd - Vh).max() <= 1e-6 * np.abs(Vh).max()
+    assert np.abs(Hd - Hh).max() <= 1e-6 * np.abs(Hh).max()
+    assert _rel(yd, yh) <= 1e-9
+
+
 @pytest.mark.parametrize("m,s_step", [(32, 16), (30, 8), (64, 32)])
 def test_sstep_arnoldi_fp32_storage(m, s_step):
     # FP32 storage: the Chebyshev block and both Gram-Schmidt passes are
