@@ -97,6 +97,10 @@ struct kry_ctx {
   // captured Arnoldi cycles (one per cycle length), replayed on `stream`
   hipStream_t cstream = nullptr;  // private capture stream (default priority)
   std::map<int, hipGraphExec_t> graphs;
+  // the captured s-step cycle (device block finish) and what it was
+  // captured for (Krylov dimension, block size, basis steps)
+  hipGraphExec_t sstep_graph = nullptr;
+  std::vector<double> sstep_key;
 
   // optional per-kernel-class timing with HIP events
   struct Pending {
@@ -242,6 +246,9 @@ void* zcol(kry_ctx* c, int col) { return (char*)c->Z + (size_t)col * c->ldv * c-
 void drop_graphs(kry_ctx* c) {
   for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
   c->graphs.clear();
+  if (c->sstep_graph) hipGraphExecDestroy(c->sstep_graph);
+  c->sstep_graph = nullptr;
+  c->sstep_key.clear();
 }
 
 int ensure_basis(kry_ctx* c, int m) {
@@ -1482,6 +1489,7 @@ int ensure_block(kry_ctx* c, int slots) {
 }
 
 int ensure_gp(kry_ctx* c, size_t doubles, size_t bc) {
+  if (doubles > c->gp_cap || bc > c->bc_cap) drop_graphs(c);  // captured launches hold the old buffers
   if (doubles > c->gp_cap) {
     hipFree(c->d_gp);
     c->d_gp = nullptr;
@@ -1815,10 +1823,62 @@ bool dev_cycle_ok(kry_ctx* c, int m) {
   return c->st == kry::F64 && s > 1 && s <= 16 && m + 1 <= 256 && !c->opts.host_blocks;
 }
 
+// The launches of one device s-step cycle on `st` (from the normalisation
+// of the start vector to the last block's update); `timed`: record the
+// kernel-class events (never inside a graph capture).
+struct SstepPlan {
+  int m = 0, bs = 0, nblk = 0;
+  std::vector<double> al, qq, sg;
+  std::vector<size_t> off;
+  size_t tot = 0;
+};
+
+int enqueue_sstep_dev(kry_ctx* c, const SstepPlan& P, hipStream_t st, bool timed) {
+  const double cond_max = 1e6, one_pass_max = 300.0, one_pass_left = 1e-6;
+  const int m = P.m, bs = P.bs;
+  KRY_HIP(kry::launch_fin_start(c->d_red1, c->d_scal + 2, st));
+  KRY_HIP(kry::launch_scale(c->st, slot(c, 0), c->d_scal + 2, slot(c, 0), c->n, st));
+  const double mb_axpby = mbytes(c, true) - 8.0 * c->g.N3;
+  const double vb = vbytes(c);
+  for (int j0 = 0, b = 0; j0 < m; j0 += bs, ++b) {
+    const int ss = std::min(bs, m - j0);
+    const int M = j0 + 1;
+    void* S = slot(c, j0 + 1);
+    auto tk = [&](int k) { return slot(c, j0 + k); };
+    for (int k = 0; k < ss; ++k) {
+      const bool prev = k > 0 && P.qq[k] != 0.0;
+      hipEvent_t e = timed ? tbeg(c) : nullptr;
+      KRY_HIP(kry::launch_stencil_axpby(kry::F64, tk(k), prev ? tk(k - 1) : nullptr, tk(k + 1), 1.0 / P.sg[k],
+                                        -P.al[k] / P.sg[k], prev ? P.qq[k] / P.sg[k] : 0.0, c->g, c->mats, st));
+      if (timed) tend(c, e, KRY_K_STENCIL, vb * (prev ? 3.0 : 2.0) + mb_axpby);
+    }
+    const int ns = kry::gram_splits(c->n, M + ss, ss);
+    double* stash = c->d_stash + P.off[b];
+    int* flags = c->d_flags + 4 * b;
+    const double gram_bytes = vb * (M + ss) + 8.0 * c->n;
+    const double gemm_bytes = vb * (M + ss) + vb * ss;
+    for (int pass = 1; pass <= 2; ++pass) {
+      const int* skip = pass == 2 ? flags + 1 : nullptr;
+      // the second pass's launches are timed only when they are known to run
+      hipEvent_t e = (timed && pass == 1) ? tbeg(c) : nullptr;
+      KRY_HIP(kry::launch_gram(kry::F64, slot(c, 0), M + ss, S, ss, c->ldv, c->d_w, c->n, c->d_gp, ns, st, S, M,
+                               -1, skip));
+      if (timed && pass == 1) tend(c, e, KRY_K_GRAM, gram_bytes, 2.0 * c->n * (M + ss) * ss);
+      KRY_HIP(kry::launch_reduce(c->d_gp, ns, (M + ss) * ss, (M + ss) * ss, c->d_bc, st, skip));
+      KRY_HIP(kry::launch_sstep_fin(pass, M, ss, c->d_bc, c->d_K, stash, flags, one_pass_max, one_pass_left,
+                                    cond_max, st));
+      e = (timed && pass == 1) ? tbeg(c) : nullptr;
+      KRY_HIP(kry::launch_gemm_nn(kry::F64, slot(c, 0), M + ss, c->d_K, ss, S, c->ldv, c->n, 1.0, 0, st, S, M,
+                                  -1, -1, skip));
+      if (timed && pass == 1) tend(c, e, KRY_K_GEMM, gemm_bytes, 2.0 * c->n * (M + ss) * ss);
+    }
+  }
+  return KRY_OK;
+}
+
 int arnoldi_ca_dev(kry_ctx* c, int m, double* beta, int* m_eff, bool* redo) {
   *redo = false;
   const int s = c->s_eff;
-  const double cond_max = 1e6, one_pass_max = 300.0, one_pass_left = 1e-6;
   const int ldh = m + 1;
   hipStream_t st = c->stream;
   int rc = ensure_weights(c);
@@ -1834,92 +1894,99 @@ int arnoldi_ca_dev(kry_ctx* c, int m, double* beta, int* m_eff, bool* redo) {
     *m_eff = 0;
     return KRY_OK;
   }
-  KRY_HIP(kry::launch_fin_start(c->d_red1, c->d_scal + 2, st));
-  KRY_HIP(kry::launch_scale(c->st, slot(c, 0), c->d_scal + 2, slot(c, 0), c->n, st));
   const double rho = c->rho;
   const bool newton = (int)c->sh_alpha.size() >= s;
-  const int bs = newton ? s : std::min(s, 16);
-  std::vector<double> al(bs, 0.0), qq(bs, 0.0), sg(bs, 0.0);
+  SstepPlan P;
+  P.m = m;
+  P.bs = newton ? s : std::min(s, 16);
+  const int bs = P.bs;
+  P.al.assign(bs, 0.0);
+  P.qq.assign(bs, 0.0);
+  P.sg.assign(bs, 0.0);
   for (int k = 0; k < bs; ++k) {
     if (newton) {
-      al[k] = c->sh_alpha[k];
-      qq[k] = c->sh_q[k];
-      sg[k] = rho;
+      P.al[k] = c->sh_alpha[k];
+      P.qq[k] = c->sh_q[k];
+      P.sg[k] = rho;
     } else {
-      sg[k] = k == 0 ? rho : 0.5 * rho;
-      qq[k] = k == 0 ? 0.0 : 0.5 * rho;
+      P.sg[k] = k == 0 ? rho : 0.5 * rho;
+      P.qq[k] = k == 0 ? 0.0 : 0.5 * rho;
     }
   }
   // per-block stash offsets, workspace
-  std::vector<size_t> off;
-  size_t tot = 0, gp = 0, bc = 0;
-  int nblk = 0;
-  for (int j0 = 0; j0 < m; j0 += bs, ++nblk) {
+  size_t gp = 0, bc = 0;
+  std::vector<std::vector<double>> Tms;
+  for (int j0 = 0; j0 < m; j0 += bs, ++P.nblk) {
     const int ss = std::min(bs, m - j0), M = j0 + 1;
-    off.push_back(tot);
-    tot += (size_t)kry::sstep_stash_doubles(M, ss);
+    P.off.push_back(P.tot);
+    P.tot += (size_t)kry::sstep_stash_doubles(M, ss);
     gp = std::max(gp, (size_t)kry::gram_splits(c->n, M + ss, ss) * (M + ss) * ss);
     bc = std::max(bc, (size_t)(M + ss) * ss);
+    // A [t_0..t_{ss-1}] = [t_0..t_ss] Tm of the block's recurrence
+    std::vector<double> Tm((size_t)(ss + 1) * ss, 0.0);
+    for (int k = 0; k < ss; ++k) {
+      const bool prev = k > 0 && P.qq[k] != 0.0;
+      Tm[(size_t)(k + 1) * ss + k] = P.sg[k];
+      Tm[(size_t)k * ss + k] = P.al[k];
+      if (prev) Tm[(size_t)(k - 1) * ss + k] = -P.qq[k];
+    }
+    Tms.push_back(std::move(Tm));
   }
+  const int nblk = P.nblk;
   rc = ensure_gp(c, gp, bc);
   if (rc) return rc;
   if (!c->d_K) KRY_HIP(hipMalloc(&c->d_K, sizeof(double) * 256 * 16));
-  if (tot > c->stash_cap) {
+  if (P.tot > c->stash_cap) {
+    drop_graphs(c);
     hipFree(c->d_stash);
     c->d_stash = nullptr;
-    KRY_HIP(hipMalloc(&c->d_stash, sizeof(double) * tot));
-    c->stash_cap = tot;
+    KRY_HIP(hipMalloc(&c->d_stash, sizeof(double) * P.tot));
+    c->stash_cap = P.tot;
   }
   if (4 * nblk > c->flags_cap) {
+    drop_graphs(c);
     hipFree(c->d_flags);
     c->d_flags = nullptr;
     KRY_HIP(hipMalloc(&c->d_flags, sizeof(int) * 4 * nblk));
     c->flags_cap = 4 * nblk;
   }
-  const double mb_axpby = mbytes(c, true) - 8.0 * c->g.N3;
-  const double vb = vbytes(c);
-  std::vector<std::vector<double>> Tms;
-  for (int j0 = 0, b = 0; j0 < m; j0 += bs, ++b) {
-    const int ss = std::min(bs, m - j0);
-    const int M = j0 + 1;
-    void* S = slot(c, j0 + 1);
-    auto tk = [&](int k) { return slot(c, j0 + k); };
-    std::vector<double> Tm((size_t)(ss + 1) * ss, 0.0);
-    for (int k = 0; k < ss; ++k) {
-      const bool prev = k > 0 && qq[k] != 0.0;
-      hipEvent_t e = tbeg(c);
-      KRY_HIP(kry::launch_stencil_axpby(kry::F64, tk(k), prev ? tk(k - 1) : nullptr, tk(k + 1), 1.0 / sg[k],
-                                        -al[k] / sg[k], prev ? qq[k] / sg[k] : 0.0, c->g, c->mats, st));
-      tend(c, e, KRY_K_STENCIL, vb * (prev ? 3.0 : 2.0) + mb_axpby);
-      Tm[(size_t)(k + 1) * ss + k] = sg[k];
-      Tm[(size_t)k * ss + k] = al[k];
-      if (prev) Tm[(size_t)(k - 1) * ss + k] = -qq[k];
+  if (c->opts.use_graph && c->opts.timing <= 0) {
+    // one captured cycle per (m, block size, basis steps), replayed on the
+    // solver's stream for the cycles of a call that share its steps
+    std::vector<double> key = {(double)m, (double)bs, rho};
+    key.insert(key.end(), P.al.begin(), P.al.end());
+    key.insert(key.end(), P.qq.begin(), P.qq.end());
+    key.insert(key.end(), P.sg.begin(), P.sg.end());
+    if (!c->sstep_graph || key != c->sstep_key) {
+      if (c->sstep_graph) hipGraphExecDestroy(c->sstep_graph);
+      c->sstep_graph = nullptr;
+      c->sstep_key.clear();
+      if (!c->cstream) KRY_HIP(hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking));
+      hipGraph_t graph = nullptr;
+      KRY_HIP(hipStreamBeginCapture(c->cstream, hipStreamCaptureModeThreadLocal));
+      const int rc2 = enqueue_sstep_dev(c, P, c->cstream, false);
+      const hipError_t ec = hipStreamEndCapture(c->cstream, &graph);
+      if (rc2) {
+        if (graph) hipGraphDestroy(graph);
+        return rc2;
+      }
+      KRY_HIP(ec);
+      hipGraphExec_t exec = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      KRY_HIP(ei);
+      c->sstep_graph = exec;
+      c->sstep_key = key;
     }
-    Tms.push_back(std::move(Tm));
-    const int ns = kry::gram_splits(c->n, M + ss, ss);
-    double* stash = c->d_stash + off[b];
-    int* flags = c->d_flags + 4 * b;
-    const double gram_bytes = vb * (M + ss) + 8.0 * c->n;
-    const double gemm_bytes = vb * (M + ss) + vb * ss;
-    for (int pass = 1; pass <= 2; ++pass) {
-      const int* skip = pass == 2 ? flags + 1 : nullptr;
-      // the second pass's launches are timed only when they are known to run
-      hipEvent_t e = pass == 1 ? tbeg(c) : nullptr;
-      KRY_HIP(kry::launch_gram(kry::F64, slot(c, 0), M + ss, S, ss, c->ldv, c->d_w, c->n, c->d_gp, ns, st, S, M,
-                               -1, skip));
-      if (pass == 1) tend(c, e, KRY_K_GRAM, gram_bytes, 2.0 * c->n * (M + ss) * ss);
-      KRY_HIP(kry::launch_reduce(c->d_gp, ns, (M + ss) * ss, (M + ss) * ss, c->d_bc, st, skip));
-      KRY_HIP(kry::launch_sstep_fin(pass, M, ss, c->d_bc, c->d_K, stash, flags, one_pass_max, one_pass_left,
-                                    cond_max, st));
-      e = pass == 1 ? tbeg(c) : nullptr;
-      KRY_HIP(kry::launch_gemm_nn(kry::F64, slot(c, 0), M + ss, c->d_K, ss, S, c->ldv, c->n, 1.0, 0, st, S, M,
-                                  -1, -1, skip));
-      if (pass == 1) tend(c, e, KRY_K_GEMM, gemm_bytes, 2.0 * c->n * (M + ss) * ss);
-    }
+    KRY_HIP(hipGraphLaunch(c->sstep_graph, st));
+  } else {
+    rc = enqueue_sstep_dev(c, P, st, true);
+    if (rc) return rc;
   }
-  std::vector<double> hs(tot);
+  const double vb = vbytes(c);
+  std::vector<double> hs(P.tot);
   std::vector<int> hf(4 * nblk);
-  KRY_HIP(hipMemcpyAsync(hs.data(), c->d_stash, sizeof(double) * tot, hipMemcpyDeviceToHost, st));
+  KRY_HIP(hipMemcpyAsync(hs.data(), c->d_stash, sizeof(double) * P.tot, hipMemcpyDeviceToHost, st));
   KRY_HIP(hipMemcpyAsync(hf.data(), c->d_flags, sizeof(int) * 4 * nblk, hipMemcpyDeviceToHost, st));
   KRY_HIP(hipStreamSynchronize(st));
   for (int b = 0; b < nblk; ++b) {
@@ -1933,7 +2000,7 @@ int arnoldi_ca_dev(kry_ctx* c, int m, double* beta, int* m_eff, bool* redo) {
   }
   for (int j0 = 0, b = 0; j0 < m; j0 += bs, ++b) {
     const int ss = std::min(bs, m - j0), M = j0 + 1;
-    const double* C1 = hs.data() + off[b];
+    const double* C1 = hs.data() + P.off[b];
     const double* R1 = C1 + (size_t)M * ss;
     const double* C2 = R1 + (size_t)ss * ss + ss + (size_t)ss * ss;
     const double* R2 = C2 + (size_t)M * ss;

@@ -1312,6 +1312,37 @@ def test_graph_replay_matches_eager_bitwise():
     assert np.array_equal(H1, H2) and np.array_equal(V1.cpu().numpy(), V2.cpu().numpy())
 
 
+def test_sstep_cycle_graph_replay_matches_eager_bitwise():
+    # the s-step cycle with the device block finish, captured once per basis
+    # steps (a Chebyshev cycle, then the Newton cycles of each call) and
+    # replayed for every restart cycle: two solves (each recaptures for its
+    # own Newton steps) with an eager solve between them, and an Arnoldi
+    # call, all bitwise equal to the eager runs
+    _announce("s-step cycle graph replay vs eager")
+    wl = wk.small(32, seed=3, n_spheres=20, layer=3, T=30.0, krylov_dim=64, tol=1e-9)
+    inp = wk.generate(wl)
+    b = _t(wk.source_vector(wl, wl.omegas[0], 0.0)[None, :])
+    om = [wl.omegas[0], 1.1 * wl.omegas[0]]
+    eager = _solver(inp.eps, None, inp.sigma, krylov_dim=64, tol=1e-9, s_step=16)
+    graph = _solver(inp.eps, None, inp.sigma, krylov_dim=64, tol=1e-9, s_step=16, use_graph=True)
+    y_e = eager.solve_multifreq(om, b, wl.T).cpu().numpy()
+    outs = []
+    for rep in range(2):
+        outs.append(graph.solve_multifreq(om, b, wl.T).cpu().numpy())
+        eager.solve_multifreq(om, b, wl.T)
+    _announce(f"32^3 s-step graph: cycles {graph.last_stats['cycles_stationary']}, "
+              f"steps {graph.last_stats['steps_transient']}")
+    assert graph.last_stats["cycles_stationary"] > 3
+    for y in outs:
+        assert np.array_equal(y, y_e)
+    v = wk.random_state(wl.n, 3)
+    V1, H1, b1, s1 = eager.arnoldi(_t(v), 64)
+    V2, H2, b2, s2 = graph.arnoldi(_t(v), 64)
+    assert np.array_equal(H1, H2) and np.array_equal(V1.cpu().numpy(), V2.cpu().numpy())
+    eager.close()
+    graph.close()
+
+
 # --------------------------------------------------------------- autotuner --
 
 def test_autotune_choice_and_results(tmp_path):
