@@ -378,6 +378,9 @@ def main():
                     help="skip the one-off timings of the restarted method and source splitting")
     ap.add_argument("--split2-periods", type=int, default=5,
                     help="source splitting: periods of the source per subinterval")
+    ap.add_argument("--stencil-planes", type=int, default=None, choices=[0, 4, 8, 16],
+                    help="after the autotuner: force the basis stencil's form (0: cell-parallel, "
+                         "4/8/16: z-marching with that many planes per workgroup)")
     ap.add_argument("--host-blocks", action="store_true",
                     help="finish each s-step block on the host (one synchronisation per "
                          "Gram-Schmidt pass) instead of on the device")
@@ -424,6 +427,11 @@ def main():
                                                     tol=wl.tol, timing=args.timing_sample,
                                                     s_step=args.s_step, host_blocks=args.host_blocks))
     tune = None if args.no_autotune else solver.autotune()
+    if args.stencil_planes is not None:
+        t = tune or {"cpt_stencil": 1, "cpt_update": 1, "cpt_dots": 1}
+        solver.set_tune(t["cpt_stencil"], t["cpt_update"], t["cpt_dots"], args.stencil_planes)
+        if tune is not None:
+            tune = dict(tune, zm_stencil=args.stencil_planes, forced=True)
     cols = [wk.source_vector(wl, w, float(th)) for w in wl.omegas for th in inp.thetas]
     b = torch.as_tensor(np.stack(cols), device=dev)
     per_omega = wl.n_theta > 1

@@ -29,8 +29,11 @@ __global__ __launch_bounds__(256) void k_sstep_fin(int pass, int M, int s, const
                                                    double one_pass_left, double cond_max) {
   if (pass == 2 && flags[1]) return;  // final after pass 1 (uniform)
   __shared__ double G[kSS * kSS], R[kSS * kSS], Ri[kSS * kSS], ref[kSS], part1[256], part2[256];
+  __shared__ double Ps[256 * kSS];  // P staged once, read many times
   __shared__ int ok;
   const int t = threadIdx.x;
+  for (int e = t; e < (M + s) * s; e += 256) Ps[e] = P[e];
+  __syncthreads();
   // stash layout: C1 (M s), R1 (s s), |S_k|^2 (s), R1^{-1} (s s), C2 (M s), R2 (s s)
   double* C1 = stash;
   double* R1 = C1 + (long long)M * s;
@@ -42,12 +45,12 @@ __global__ __launch_bounds__(256) void k_sstep_fin(int pass, int M, int s, const
   double* Rst = pass == 1 ? R1 : R2;
   if (t < s * s) {
     const int a = t / s, b = t % s;
-    double g = P[(long long)(M + a) * s + b];
-    for (int k = 0; k < M; ++k) g -= P[(long long)k * s + a] * P[(long long)k * s + b];
+    double g = Ps[(M + a) * s + b];
+    for (int k = 0; k < M; ++k) g -= Ps[k * s + a] * Ps[k * s + b];
     G[a * kSS + b] = g;
   }
-  if (t < s) ref[t] = pass == 1 ? P[(long long)(M + t) * s + t] : 1.0;
-  for (int e = t; e < M * s; e += 256) Cst[e] = P[e];
+  if (t < s) ref[t] = pass == 1 ? Ps[(M + t) * s + t] : 1.0;
+  for (int e = t; e < M * s; e += 256) Cst[e] = Ps[e];
   if (t == 0) ok = 1;
   __syncthreads();
   if (pass == 1 && t < s) nrm[t] = ref[t];
@@ -120,16 +123,23 @@ __global__ __launch_bounds__(256) void k_sstep_fin(int pass, int M, int s, const
       v = (k >= M && k - M == b) ? 1.0 : 0.0;
     } else if (k < M) {
       double acc = 0.0;
-      for (int l = 0; l <= b; ++l) acc += P[(long long)k * s + l] * Ri[l * kSS + b];
+      for (int l = 0; l <= b; ++l) acc += Ps[k * s + l] * Ri[l * kSS + b];
       v = -acc;
     } else {
       v = Ri[(k - M) * kSS + b];
     }
     K[e] = v;
   }
+  // the two Frobenius sums: a tree over the 256 partial values
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      part1[t] += part1[t + h];
+      part2[t] += part2[t + h];
+    }
+    __syncthreads();
+  }
   if (t == 0) {
-    double f1 = 0.0, f2 = 0.0;
-    for (int i = 0; i < 256; ++i) f1 += part1[i], f2 += part2[i];
+    const double f1 = part1[0], f2 = part2[0];
     const double est = sqrt(f1 * f2);
     double left = 1.0;
     for (int k = 0; k < s; ++k) left = fmin(left, G[k * kSS + k] / fmax(ref[k], 1e-300));
