@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libkry.so")
 
-SOURCES = ["kry_kernels.hip", "kry_block.hip", "kry_rst.hip", "kry_adjoint.hip", "kry_sstep.hip",
+SOURCES = ["kry_kernels.hip", "kry_block.hip", "kry_rst.hip", "kry_adjoint.hip", "kry_sstep.hip", "kry_combine.hip",
            "kry_api.cpp", "kry_dense.cpp"]
 ARCH = os.environ.get("KRY_OFFLOAD_ARCH", "gfx950")
 

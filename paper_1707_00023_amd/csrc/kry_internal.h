@@ -214,6 +214,12 @@ hipError_t launch_rst_march(int m, int q, int nt, int ncol, const double* E, con
                             long long ldf, double* uT, double* resint, hipStream_t s, int L = 0,
                             const double* EL = nullptr, double* work = nullptr);
 
+// out_{cmap[j]} += sum_{k < m} V_k Y[k + j m] for j < ncol (cmap may be
+// nullptr: identity) on the matrix cores, the basis read once per 64
+// outputs (kry_combine.hip).  Out columns must be distinct and not in V.
+hipError_t launch_combine_mfma(Storage st, const void* V, long long ldv, int m, const double* Y, int ncol,
+                               void* out, long long ldo, const int* cmap, long long n, hipStream_t s);
+
 // Gradient of the flux at a finite time T (kry_adjoint.hip).
 // F = sum over plane kf of Ex Hy_bar - Ey Hx_bar for the real FP64 field y
 // (per-workgroup partial sums, *nblk of them) and, if r0 != nullptr, the
