@@ -3527,7 +3527,7 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
     // y(T) += V_m u(T) for every active time function, one sweep of the basis
     KRY_HIP(hipMemcpyAsync(c->d_colmap, cmap.data(), sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
     hipEvent_t e = tbeg(c);
-    if (na >= 32 && me <= 80)  // many outputs: on the matrix cores, the basis read once per 64 outputs
+    if (na >= 32 && me <= 80)  // many outputs: on the matrix cores, the basis read once per 32 outputs
       KRY_HIP(kry::launch_combine_mfma(c->st, c->V, c->ldv, me, Ydev, na, c->Z, c->ldv, c->d_colmap, c->n,
                                        c->stream));
     else

@@ -215,7 +215,7 @@ hipError_t launch_rst_march(int m, int q, int nt, int ncol, const double* E, con
                             const double* EL = nullptr, double* work = nullptr);
 
 // out_{cmap[j]} += sum_{k < m} V_k Y[k + j m] for j < ncol (cmap may be
-// nullptr: identity) on the matrix cores, the basis read once per 64
+// nullptr: identity) on the matrix cores, the basis read once per 32
 // outputs (kry_combine.hip).  Out columns must be distinct and not in V.
 hipError_t launch_combine_mfma(Storage st, const void* V, long long ldv, int m, const double* Y, int ncol,
                                void* out, long long ldo, const int* cmap, long long n, hipStream_t s);
