@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_128cube_traffic.md")
 # kernel class -> (kernel in the counter summary, source file it is built from)
-CLASS_KERNEL = {"block_gram": ("k_gram_tall", "kry_block.hip"),
+CLASS_KERNEL = {"block_gram": ("k_gram_step_lds", "kry_block.hip"),
                 "block_gemm": ("k_gemm_cols", "kry_block.hip"),
                 "operator": ("k_stencil_axpby", "kry_kernels.hip")}
 

@@ -220,6 +220,128 @@ __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int 
   }
 }
 
+// The Gram product of an s-step block in FP64 (the layout of k_gram_tall
+// with YSEG, N <= 16): partials[4 bx + wave][M x N] = [X; X2]^T diag(w) X2
+// over the elements the wave visits, with the loads regrouped through LDS.
+// In the MFMA operand layout every load instruction touches 16 columns at
+// 64 bytes each, and such narrow runs hold a plain read near 3.4-5.7 TB/s
+// on gfx950 where runs of 256 bytes or more reach 6.1-6.3 TB/s.  So per
+// step of 32 entries a wave loads each 16-column tile with four
+// instructions of 4 columns x 256 bytes (lane l: column 4 q + l / 16,
+// entries 2 (l % 16) and 2 (l % 16) + 1), writes the tile to its own LDS
+// slot [16][kLdsStride] and reads it back in the operand layout (lane
+// (i, kk): column i, entries 8 kk .. 8 kk + 7; the k = kk slot of the h-th
+// MFMA takes entry 8 kk + h).  The row stride 34 puts the 16-byte accesses
+// of eight consecutive lanes on distinct banks, on the write and the read
+// side.  A wave's LDS traffic stays in its own slot and in its own program
+// order, so no barrier is needed.  Tile 0 holds X2 (also the Y operand),
+// tiles 1.. the first segment; inactive columns read column 0 of their
+// segment (their rows and columns of the product are never stored).  The
+// waves of a workgroup take interleaved steps of its chunk (kchunk a
+// multiple of 128); a last partial step loads directly with masks.
+// grid (nsplit / 4).
+constexpr int kLdsStride = 34;
+constexpr int kStepLdsMaxTiles = 6;  // basis of up to 80 columns before the block
+template <int MT>
+__global__ __launch_bounds__(256) void k_gram_step_lds(const double* __restrict__ X, int M1,
+                                                       const double* __restrict__ X2, int N, long long ld,
+                                                       const double* __restrict__ w, long long n,
+                                                       long long kchunk, double* __restrict__ partials,
+                                                       const int* __restrict__ skip) {
+  if (skip && *skip) return;  // (uniform: the whole grid skips)
+  __shared__ double tiles[4][16 * kLdsStride];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int i = lane & 15, kk = lane >> 4;
+  double* slot = tiles[wave];
+  const long long e_begin = (long long)blockIdx.x * kchunk;
+  const long long e_end = min(n, e_begin + kchunk);
+  // column read by lane l in load instruction q of tile t: 4 q + l / 16
+  const double* lc[MT][4];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 4 * q + kk;
+      if (t == 0) {
+        lc[t][q] = X2 + (long long)(c < N ? c : 0) * ld;
+      } else {
+        const int r = 16 * (t - 1) + c;
+        lc[t][q] = X + (long long)(r < M1 ? r : 0) * ld;
+      }
+    }
+  v4d acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+  const long long es = e_begin + 32 * wave;
+  const long long nfull = e_end - es >= 32 ? (e_end - es - 32) / 128 + 1 : 0;
+  for (long long p = 0; p < nfull; ++p) {
+    const long long e0 = es + 128 * p;
+    double2 g[MT][4];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) g[t][q] = *reinterpret_cast<const double2*>(lc[t][q] + e0 + 2 * i);
+    double ww[8], yb[8];
+    {
+      const double4 a = *reinterpret_cast<const double4*>(w + e0 + 8 * kk);
+      const double4 b = *reinterpret_cast<const double4*>(w + e0 + 8 * kk + 4);
+      ww[0] = a.x; ww[1] = a.y; ww[2] = a.z; ww[3] = a.w;
+      ww[4] = b.x; ww[5] = b.y; ww[6] = b.z; ww[7] = b.w;
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        *reinterpret_cast<double2*>(slot + (4 * q + kk) * kLdsStride + 2 * i) = g[t][q];
+      double xa[8];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const double2 v = *reinterpret_cast<const double2*>(slot + i * kLdsStride + 8 * kk + 2 * h);
+        xa[2 * h] = v.x;
+        xa[2 * h + 1] = v.y;
+      }
+      if (t == 0) {
+#pragma unroll
+        for (int h = 0; h < 8; ++h) yb[h] = ww[h] * xa[h];
+      }
+#pragma unroll
+      for (int h = 0; h < 8; ++h) acc[t] = mfma16(xa[h], yb[h], acc[t]);
+    }
+  }
+  for (long long e0 = es + 128 * nfull; e0 < e_end; e0 += 128) {  // a partial step
+    const long long eb = e0 + 8 * kk;
+    double ww[8], yb[8];
+    load4(w, eb, e_end, *reinterpret_cast<double(*)[4]>(ww));
+    load4(w, eb + 4, e_end, *reinterpret_cast<double(*)[4]>(ww + 4));
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const double* col;
+      if (t == 0) col = X2 + (long long)(i < N ? i : 0) * ld;
+      else col = X + (long long)(16 * (t - 1) + i < M1 ? 16 * (t - 1) + i : 0) * ld;
+      double xa[8];
+      load4(col, eb, e_end, *reinterpret_cast<double(*)[4]>(xa));
+      load4(col, eb + 4, e_end, *reinterpret_cast<double(*)[4]>(xa + 4));
+      if (t == 0) {
+#pragma unroll
+        for (int h = 0; h < 8; ++h) yb[h] = ww[h] * xa[h];
+      }
+#pragma unroll
+      for (int h = 0; h < 8; ++h) acc[t] = mfma16(xa[h], yb[h], acc[t]);
+    }
+  }
+  const int M = M1 + N;
+  double* out = partials + ((long long)blockIdx.x * 4 + wave) * M * N;
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int vr = 4 * r + kk;
+      const int row = t == 0 ? (vr < N ? M1 + vr : M) : (16 * (t - 1) + vr < M1 ? 16 * (t - 1) + vr : M);
+      if (row < M && i < N) out[(long long)row * N + i] = acc[t][r];
+    }
+}
+
 // Out[:, j] = (accumulate ? Out[:, j] : 0) + alpha sum_k X[:, k] C[k][j] for
 // j < N (C row-major M x N, FP64).  Each wave computes 16 entries x 16 NT
 // columns (NT tiles of Out^T = C^T X^T): A = C^T (from C), B = X^T (16
@@ -405,6 +527,24 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
     if (st2 != st && !(yseg && st == F32 && st2 == F64)) return hipErrorInvalidValue;
     const int mt = yseg ? nt + (M1 + 15) / 16 : tall_mt(M);
     if (yseg && mt > 8) return hipErrorInvalidValue;
+    if (yseg && nt == 1 && st == F64 && st2 == F64 && mt <= kStepLdsMaxTiles) {
+      // the FP64 s-step block: loads regrouped through LDS
+      long long kc = (n + wg - 1) / wg;
+      kc = (kc + 127) / 128 * 128;
+#define KRY_STEP_LDS(MT)                                                                                  \
+  hipLaunchKernelGGL((k_gram_step_lds<MT>), dim3(wg), dim3(256), 0, s, (const double*)X, M1,             \
+                     (const double*)X2, N, ld, w, n, kc, partials, skip);
+      switch (mt) {
+        case 1: KRY_STEP_LDS(1) break;
+        case 2: KRY_STEP_LDS(2) break;
+        case 3: KRY_STEP_LDS(3) break;
+        case 4: KRY_STEP_LDS(4) break;
+        case 5: KRY_STEP_LDS(5) break;
+        default: KRY_STEP_LDS(6) break;
+      }
+#undef KRY_STEP_LDS
+      return hipGetLastError();
+    }
     const dim3 grid(wg, yseg ? 1 : (M + 16 * mt - 1) / (16 * mt));
 #define KRY_TALL_(T, T2, MT, NT, YS)                                                              \
   hipLaunchKernelGGL((k_gram_tall<T, T2, MT, NT, YS>), grid, dim3(256), 0, s, (const T*)X, M1,     \
