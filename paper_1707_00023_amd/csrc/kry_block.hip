@@ -239,11 +239,13 @@ __global__ __launch_bounds__(256) void k_gram_tall(const T* __restrict__ X, int 
 // segment (their rows and columns of the product are never stored).  The
 // waves of a workgroup take interleaved steps of its chunk (kchunk a
 // multiple of 128); a last partial step loads directly with masks.
-// grid (nsplit / 4).
+// T: element type of the first segment (FP32 storage keeps the block X2 in
+// FP64: its loads are then 8 bytes per lane, 4 columns x 128 bytes, and the
+// values enter the LDS tile as FP64).  grid (nsplit / 4).
 constexpr int kLdsStride = 34;
 constexpr int kStepLdsMaxTiles = 6;  // basis of up to 80 columns before the block
-template <int MT>
-__global__ __launch_bounds__(256) void k_gram_step_lds(const double* __restrict__ X, int M1,
+template <typename T, int MT>
+__global__ __launch_bounds__(256) void k_gram_step_lds(const T* __restrict__ X, int M1,
                                                        const double* __restrict__ X2, int N, long long ld,
                                                        const double* __restrict__ w, long long n,
                                                        long long kchunk, double* __restrict__ partials,
@@ -257,19 +259,18 @@ __global__ __launch_bounds__(256) void k_gram_step_lds(const double* __restrict_
   const long long e_begin = (long long)blockIdx.x * kchunk;
   const long long e_end = min(n, e_begin + kchunk);
   // column read by lane l in load instruction q of tile t: 4 q + l / 16
-  const double* lc[MT][4];
+  const double* lc2[4];
+  const T* lc[MT > 1 ? MT - 1 : 1][4];
 #pragma unroll
-  for (int t = 0; t < MT; ++t)
+  for (int q = 0; q < 4; ++q) {
+    const int c = 4 * q + kk;
+    lc2[q] = X2 + (long long)(c < N ? c : 0) * ld;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = 4 * q + kk;
-      if (t == 0) {
-        lc[t][q] = X2 + (long long)(c < N ? c : 0) * ld;
-      } else {
-        const int r = 16 * (t - 1) + c;
-        lc[t][q] = X + (long long)(r < M1 ? r : 0) * ld;
-      }
+    for (int t = 1; t < MT; ++t) {
+      const int r = 16 * (t - 1) + c;
+      lc[t - 1][q] = X + (long long)(r < M1 ? r : 0) * ld;
     }
+  }
   v4d acc[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
@@ -279,9 +280,18 @@ __global__ __launch_bounds__(256) void k_gram_step_lds(const double* __restrict_
     const long long e0 = es + 128 * p;
     double2 g[MT][4];
 #pragma unroll
-    for (int t = 0; t < MT; ++t)
+    for (int q = 0; q < 4; ++q) g[0][q] = *reinterpret_cast<const double2*>(lc2[q] + e0 + 2 * i);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) g[t][q] = *reinterpret_cast<const double2*>(lc[t][q] + e0 + 2 * i);
+    for (int t = 1; t < MT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if constexpr (sizeof(T) == 8) {
+          g[t][q] = *reinterpret_cast<const double2*>(lc[t - 1][q] + e0 + 2 * i);
+        } else {
+          const float2 f = *reinterpret_cast<const float2*>(lc[t - 1][q] + e0 + 2 * i);
+          g[t][q] = make_double2((double)f.x, (double)f.y);
+        }
+      }
     double ww[8], yb[8];
     {
       const double4 a = *reinterpret_cast<const double4*>(w + e0 + 8 * kk);
@@ -316,12 +326,16 @@ __global__ __launch_bounds__(256) void k_gram_step_lds(const double* __restrict_
     load4(w, eb + 4, e_end, *reinterpret_cast<double(*)[4]>(ww + 4));
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      const double* col;
-      if (t == 0) col = X2 + (long long)(i < N ? i : 0) * ld;
-      else col = X + (long long)(16 * (t - 1) + i < M1 ? 16 * (t - 1) + i : 0) * ld;
       double xa[8];
-      load4(col, eb, e_end, *reinterpret_cast<double(*)[4]>(xa));
-      load4(col, eb + 4, e_end, *reinterpret_cast<double(*)[4]>(xa + 4));
+      if (t == 0) {
+        const double* col = X2 + (long long)(i < N ? i : 0) * ld;
+        load4(col, eb, e_end, *reinterpret_cast<double(*)[4]>(xa));
+        load4(col, eb + 4, e_end, *reinterpret_cast<double(*)[4]>(xa + 4));
+      } else {
+        const T* col = X + (long long)(16 * (t - 1) + i < M1 ? 16 * (t - 1) + i : 0) * ld;
+        load4(col, eb, e_end, *reinterpret_cast<double(*)[4]>(xa));
+        load4(col, eb + 4, e_end, *reinterpret_cast<double(*)[4]>(xa + 4));
+      }
       if (t == 0) {
 #pragma unroll
         for (int h = 0; h < 8; ++h) yb[h] = ww[h] * xa[h];
@@ -527,13 +541,18 @@ hipError_t launch_gram(Storage st, const void* X, int M, const void* Y, int N, l
     if (st2 != st && !(yseg && st == F32 && st2 == F64)) return hipErrorInvalidValue;
     const int mt = yseg ? nt + (M1 + 15) / 16 : tall_mt(M);
     if (yseg && mt > 8) return hipErrorInvalidValue;
-    if (yseg && nt == 1 && st == F64 && st2 == F64 && mt <= kStepLdsMaxTiles) {
-      // the FP64 s-step block: loads regrouped through LDS
+    if (yseg && nt == 1 && st2 == F64 && mt <= kStepLdsMaxTiles) {
+      // the s-step block (FP64; the basis FP64 or FP32): loads regrouped
+      // through LDS
       long long kc = (n + wg - 1) / wg;
       kc = (kc + 127) / 128 * 128;
 #define KRY_STEP_LDS(MT)                                                                                  \
-  hipLaunchKernelGGL((k_gram_step_lds<MT>), dim3(wg), dim3(256), 0, s, (const double*)X, M1,             \
-                     (const double*)X2, N, ld, w, n, kc, partials, skip);
+  if (st == F64)                                                                                          \
+    hipLaunchKernelGGL((k_gram_step_lds<double, MT>), dim3(wg), dim3(256), 0, s, (const double*)X, M1,   \
+                       (const double*)X2, N, ld, w, n, kc, partials, skip);                              \
+  else                                                                                                    \
+    hipLaunchKernelGGL((k_gram_step_lds<float, MT>), dim3(wg), dim3(256), 0, s, (const float*)X, M1,     \
+                       (const double*)X2, N, ld, w, n, kc, partials, skip);
       switch (mt) {
         case 1: KRY_STEP_LDS(1) break;
         case 2: KRY_STEP_LDS(2) break;
