@@ -381,6 +381,8 @@ def main():
     ap.add_argument("--stencil-planes", type=int, default=None, choices=[0, 4, 8, 16],
                     help="after the autotuner: force the basis stencil's form (0: cell-parallel, "
                          "4/8/16: z-marching with that many planes per workgroup)")
+    ap.add_argument("--stencil-cells", type=int, default=None, choices=[1, 2, 4],
+                    help="after the autotuner: force the cell-parallel basis stencil's cells per thread")
     ap.add_argument("--host-blocks", action="store_true",
                     help="finish each s-step block on the host (one synchronisation per "
                          "Gram-Schmidt pass) instead of on the device")
@@ -427,11 +429,13 @@ def main():
                                                     tol=wl.tol, timing=args.timing_sample,
                                                     s_step=args.s_step, host_blocks=args.host_blocks))
     tune = None if args.no_autotune else solver.autotune()
-    if args.stencil_planes is not None:
-        t = tune or {"cpt_stencil": 1, "cpt_update": 1, "cpt_dots": 1}
-        solver.set_tune(t["cpt_stencil"], t["cpt_update"], t["cpt_dots"], args.stencil_planes)
+    if args.stencil_planes is not None or args.stencil_cells is not None:
+        t = tune or {"cpt_stencil": 1, "cpt_update": 1, "cpt_dots": 1, "zm_stencil": 0}
+        cells = args.stencil_cells if args.stencil_cells is not None else t["cpt_stencil"]
+        planes = args.stencil_planes if args.stencil_planes is not None else t.get("zm_stencil", 0)
+        solver.set_tune(cells, t["cpt_update"], t["cpt_dots"], planes)
         if tune is not None:
-            tune = dict(tune, zm_stencil=args.stencil_planes, forced=True)
+            tune = dict(tune, cpt_stencil=cells, zm_stencil=planes, forced=True)
     cols = [wk.source_vector(wl, w, float(th)) for w in wl.omegas for th in inp.thetas]
     b = torch.as_tensor(np.stack(cols), device=dev)
     per_omega = wl.n_theta > 1
