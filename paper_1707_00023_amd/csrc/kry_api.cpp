@@ -48,6 +48,11 @@ struct kry_ctx {
   double* d_H = nullptr;
   double* d_Y = nullptr;
   int* d_colmap = nullptr;
+  // column-norm workspace: partials (cn_cap doubles) and column indices
+  double* d_cnp = nullptr;
+  size_t cn_cap = 0;
+  int* d_cnc = nullptr;
+  int cnc_cap = 0;
   int ycap = 0;   // columns of d_Y
   int yrows = 0;  // rows of d_Y
   double* h_H = nullptr;     // pinned (mcap+1) x mcap
@@ -964,6 +969,8 @@ void api_destroy(kry_ctx* c) {
   hipFree(c->d_H);
   hipFree(c->d_Y);
   hipFree(c->d_colmap);
+  hipFree(c->d_cnp);
+  hipFree(c->d_cnc);
   hipFree(c->Z);
   hipFree(c->Zh);
   hipFree(c->TC);
@@ -3390,27 +3397,39 @@ struct RstColumn {
 
 // |Z column|_M for every listed column, with one synchronisation.
 int zcol_norms(kry_ctx* c, const std::vector<int>& zc, std::vector<double>& out) {
-  const int nparts = kry::cell_blocks(c->g.N3, c->g.cpt_d);
   const int nz = (int)zc.size();
   out.assign(nz, 0.0);
   if (nz == 0) return KRY_OK;
-  double* part = nullptr;
-  double* red = nullptr;
-  if (hipMalloc(&part, sizeof(double) * (size_t)nparts * nz) != hipSuccess ||
-      hipMalloc(&red, sizeof(double) * nz) != hipSuccess) {
-    hipFree(part);
-    (void)hipGetLastError();
-    return fail(c, KRY_ENOMEM, "cannot allocate column norm workspace");
+  // all columns in one launch, one reduction: partials and the index list
+  // in a workspace kept on the context (grown on demand; the reduction's
+  // results follow the partials)
+  const int nblk = kry::col_norm_blocks(c->g.N3);
+  const size_t need = (size_t)(nblk + 1) * nz;
+  if (need > c->cn_cap) {
+    hipFree(c->d_cnp);
+    c->d_cnp = nullptr;
+    c->cn_cap = 0;
+    if (hipMalloc(&c->d_cnp, sizeof(double) * need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, KRY_ENOMEM, "cannot allocate column norm workspace");
+    }
+    c->cn_cap = need;
   }
-  Defer<std::function<void()>> fr{[&]() {
-    hipFree(part);
-    hipFree(red);
-  }};
-  for (int k = 0; k < nz; ++k) {
-    KRY_HIP(kry::launch_dots(c->st, zcol(c, zc[k]), nullptr, c->ldv, 0, c->g, c->mats,
-                             part + (size_t)k * nparts, c->stream));
-    KRY_HIP(kry::launch_reduce(part + (size_t)k * nparts, nparts, 1, 1, red + k, c->stream));
+  if (nz > c->cnc_cap) {
+    hipFree(c->d_cnc);
+    c->d_cnc = nullptr;
+    c->cnc_cap = 0;
+    if (hipMalloc(&c->d_cnc, sizeof(int) * (size_t)nz) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, KRY_ENOMEM, "cannot allocate column norm workspace");
+    }
+    c->cnc_cap = nz;
   }
+  double* red = c->d_cnp + (size_t)nblk * nz;
+  KRY_HIP(hipMemcpyAsync(c->d_cnc, zc.data(), sizeof(int) * nz, hipMemcpyHostToDevice, c->stream));
+  KRY_HIP(kry::launch_col_norms(c->st, c->Z, c->ldv, c->d_cnc, nz, c->g.N3, c->mats.eps, c->mats.mu, c->d_cnp,
+                                c->stream));
+  KRY_HIP(kry::launch_reduce(c->d_cnp, nblk, nz, nz, red, c->stream));
   KRY_HIP(hipMemcpyAsync(out.data(), red, sizeof(double) * nz, hipMemcpyDeviceToHost, c->stream));
   KRY_HIP(hipStreamSynchronize(c->stream));
   for (auto& v : out) v = std::sqrt(std::max(v, 0.0));
@@ -3449,6 +3468,11 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
   const long long nwork = chunked ? kry::rst_march_work(m, nt, nc, Lc) : 0;
   double *dF = nullptr, *dP = nullptr, *dU = nullptr, *dR = nullptr, *dWk = nullptr;
   int* dMap = nullptr;
+  // pinned host staging of each restart's small transfers (propagators,
+  // residual integrals, active list, output map), so they queue behind the
+  // march and the combination without a host round trip in between; reused
+  // after the restart's stream synchronisation
+  void* hpin = nullptr;
   Defer<std::function<void()>> free_bufs{[&]() {
     hipFree(dF);
     hipFree(dP);
@@ -3456,7 +3480,18 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
     hipFree(dR);
     hipFree(dMap);
     hipFree(dWk);
+    if (hpin) hipHostFree(hpin);
   }};
+  if (hipHostMalloc(&hpin, sizeof(double) * (npk + nc) + sizeof(int) * 2 * (size_t)nc, hipHostMallocDefault) !=
+      hipSuccess) {
+    hpin = nullptr;
+    (void)hipGetLastError();
+    return fail(c, KRY_ENOMEM, "cannot allocate the restarted method's pinned staging");
+  }
+  double* h_pk = (double*)hpin;
+  double* h_rs = h_pk + npk;
+  int* h_act = (int*)(h_rs + nc);
+  int* h_cmap = h_act + nc;
   std::vector<double> hF[2];
   if (gpu) {
     if (hipMalloc(&dF, sizeof(double) * 2 * nc * ldf) != hipSuccess || hipMalloc(&dP, sizeof(double) * npk) != hipSuccess ||
@@ -3476,7 +3511,7 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
   if (rc) return rc;
   kry::RstProp P;
   std::vector<int> act, cmap;
-  std::vector<double> uT, Yh, pk(npk), rs;
+  std::vector<double> uT, Yh, rs;
   int cur = 0;
   int status = KRY_ENOCONV;
   for (int cyc = 0; cyc < maxcyc; ++cyc) {
@@ -3500,7 +3535,7 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
     rs.assign(na, 0.0);
     const double* Ydev = c->d_Y;
     if (gpu) {
-      double* p = pk.data();
+      double* p = h_pk;
       std::copy(P.E.begin(), P.E.end(), p);
       std::copy(P.W.begin(), P.W.end(), p + (size_t)me * me);
       std::copy(P.El.begin(), P.El.end(), p + (size_t)me * me + (size_t)me * q);
@@ -3519,12 +3554,13 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
       const double* dWl = dEl + (size_t)q * me;
       const double* dgw = dWl + (size_t)q * q;
       const double* dEL = dgw + q;
-      KRY_HIP(hipMemcpyAsync(dP, pk.data(), sizeof(double) * npk, hipMemcpyHostToDevice, c->stream));
-      KRY_HIP(hipMemcpyAsync(dMap, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
+      std::copy(act.begin(), act.end(), h_act);
+      KRY_HIP(hipMemcpyAsync(dP, h_pk, sizeof(double) * npk, hipMemcpyHostToDevice, c->stream));
+      KRY_HIP(hipMemcpyAsync(dMap, h_act, sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
       KRY_HIP(kry::launch_rst_march(me, q, nt, na, dE, dW, dEl, dWl, dgw, beta, hnext, dt, dMap,
                                     dF + (size_t)cur * nc * ldf, dF + (size_t)(cur ^ 1) * nc * ldf, (long long)ldf,
                                     dU, dR, c->stream, chunked ? Lc : 0, chunked ? dEL : nullptr, dWk));
-      KRY_HIP(hipMemcpyAsync(rs.data(), dR, sizeof(double) * na, hipMemcpyDeviceToHost, c->stream));
+      KRY_HIP(hipMemcpyAsync(h_rs, dR, sizeof(double) * na, hipMemcpyDeviceToHost, c->stream));
       Ydev = dU;
     } else {
       uT.assign((size_t)me * na, 0.0);
@@ -3536,7 +3572,8 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
       KRY_HIP(hipMemcpyAsync(c->d_Y, uT.data(), sizeof(double) * uT.size(), hipMemcpyHostToDevice, c->stream));
     }
     // y(T) += V_m u(T) for every active time function, one sweep of the basis
-    KRY_HIP(hipMemcpyAsync(c->d_colmap, cmap.data(), sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
+    std::copy(cmap.begin(), cmap.end(), h_cmap);
+    KRY_HIP(hipMemcpyAsync(c->d_colmap, h_cmap, sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
     hipEvent_t e = tbeg(c);
     if (na >= 32 && me <= 80)  // many outputs: on the matrix cores, the basis read once per 32 outputs
       KRY_HIP(kry::launch_combine_mfma(c->st, c->V, c->ldv, me, Ydev, na, c->Z, c->ldv, c->d_colmap, c->n,
@@ -3552,6 +3589,7 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
     // can stop.
     bool any = false;
     KRY_HIP(hipStreamSynchronize(c->stream));  // rs is on the host now
+    if (gpu) std::copy(h_rs, h_rs + na, rs.begin());
     bool near = false;
     for (int a = 0; a < na; ++a) {
       const RstColumn& cl = cols[act[a]];

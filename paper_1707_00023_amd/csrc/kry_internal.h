@@ -202,6 +202,13 @@ hipError_t launch_scatter_basis(Storage st, const double* Q, int nr, int r, cons
                                 void* out, long long ld, hipStream_t s);
 // p[0:n] = pseudo-random values in [-1/2, 1/2) from a hash of the index.
 hipError_t launch_fill_hash(void* p, Storage st, long long n, unsigned seed, hipStream_t s);
+// Squared energy norms of the columns cols[0..ncol) of Z (stride ldz):
+// partials[b * ncol + y] for the col_norm_blocks(N3) workgroups b, to be
+// summed with launch_reduce(partials, col_norm_blocks(N3), ncol, ncol, out)
+// (kry_rst.hip).  mu may be null (mu = 1).
+int col_norm_blocks(long long N3);
+hipError_t launch_col_norms(Storage st, const void* Z, long long ldz, const int* cols, int ncol, long long N3,
+                            const double* eps, const double* mu, double* partials, hipStream_t s);
 int rst_march_max_m();
 // Parallel-in-time form: with 1 <= L < nt, EL = E^L (m x m column-major,
 // device) and `work` of rst_march_work(m, nt, ncol, L) doubles (device),

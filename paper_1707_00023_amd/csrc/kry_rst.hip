@@ -15,8 +15,12 @@
 // u_{p+1} = E^L u_p + v_p, with E^L = e^{-L dt H} from the host; then every
 // chunk is marched again from its start, writing the residual samples.
 // The chain of dependent steps is L + P + L long instead of P L.
-// Lane r owns u_r and keeps row r of E and W (and, for r < q, of El and Wl)
-// in registers; u and a reach the other lanes by lane broadcasts.
+// Lane r owns u_r and keeps row r of E and W in registers; u and a reach
+// the other lanes by lane broadcasts.  The residual samples El u take 8
+// values of El per lane, El[r mod 8][8 (r div 8) + kk] for kk < 8: each lane
+// gathers its 8 entries of u by lane shuffles, and the 8 lane groups are
+// summed by three xor shuffles (a full row of El per lane would double the
+// registers and leave one wave per SIMD).
 #include "kry_internal.h"
 
 namespace kry {
@@ -60,12 +64,14 @@ __global__ __launch_bounds__(64) void k_rst_march(int m, int nt, int L, const do
   double* fo = OUT ? fout + (long long)col * ldf : nullptr;
   const int j0 = p * L;
   const int j1 = min(nt, j0 + L);
-  double er[kRstM], el[kRstM], wr[kRstQ], wl[kRstQ];
+  static_assert(kRstM == 8 * kRstQ, "the residual-sample layout takes 8 lane groups of q lanes");
+  double er[kRstM], el[kRstQ], wr[kRstQ], wl[kRstQ];
+  const int gbase = (r / kRstQ) * 8;  // first u entry of this lane's group
 #pragma unroll
-  for (int k = 0; k < kRstM; ++k) {
-    er[k] = (r < m && k < m) ? E[r + (long long)k * m] : 0.0;
-    el[k] = (OUT && r < kRstQ && k < m) ? El[(long long)r * m + k] : 0.0;
-  }
+  for (int k = 0; k < kRstM; ++k) er[k] = (r < m && k < m) ? E[r + (long long)k * m] : 0.0;
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk)
+    el[kk] = (OUT && gbase + kk < m) ? El[(long long)(r % kRstQ) * m + gbase + kk] : 0.0;
 #pragma unroll
   for (int l = 0; l < kRstQ; ++l) {
     wr[l] = r < m ? W[r + (long long)l * m] : 0.0;
@@ -81,20 +87,20 @@ __global__ __launch_bounds__(64) void k_rst_march(int m, int nt, int L, const do
     double av[kRstQ];
 #pragma unroll
     for (int l = 0; l < kRstQ; ++l) av[l] = bcast(acur, l);
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, t = 0.0;
+    if (OUT) {  // El u: this lane's 8 terms, then the sum over the 8 lane groups
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) t += el[kk] * __shfl(u, gbase + kk, 64);
+      t += __shfl_xor(t, 8, 64);
+      t += __shfl_xor(t, 16, 64);
+      t += __shfl_xor(t, 32, 64);
+    }
 #pragma unroll
     for (int k = 0; k < kRstM; k += 4) {
-      const double u0k = bcast(u, k), u1 = bcast(u, k + 1), u2 = bcast(u, k + 2), u3 = bcast(u, k + 3);
-      s0 += er[k] * u0k;
-      s1 += er[k + 1] * u1;
-      s2 += er[k + 2] * u2;
-      s3 += er[k + 3] * u3;
-      if (OUT) {
-        t0 += el[k] * u0k;
-        t1 += el[k + 1] * u1;
-        t2 += el[k + 2] * u2;
-        t3 += el[k + 3] * u3;
-      }
+      s0 += er[k] * bcast(u, k);
+      s1 += er[k + 1] * bcast(u, k + 1);
+      s2 += er[k + 2] * bcast(u, k + 2);
+      s3 += er[k + 3] * bcast(u, k + 3);
     }
     double sa = 0.0, ta = 0.0;
 #pragma unroll
@@ -103,7 +109,7 @@ __global__ __launch_bounds__(64) void k_rst_march(int m, int nt, int L, const do
       if (OUT) ta += wl[l] * av[l];
     }
     if (OUT && r < kRstQ) {
-      const double f = -hnext * (((t0 + t1) + (t2 + t3)) + ta);
+      const double f = -hnext * (t + ta);
       fo[(long long)j * kRstQ + r] = f;
       racc += wnode * fabs(f);
     }
@@ -245,6 +251,40 @@ __global__ __launch_bounds__(256) void k_fill_hash(T* __restrict__ p, long long 
   p[i] = T((double)h * (1.0 / 4294967296.0) - 0.5);
 }
 
+
+// Squared energy norms of many columns in one launch: partials[b ncol + y]
+// = sum over the cells of workgroup b of sum_p w_p x_p^2, x = column
+// cols[y] of Z (w: mu on the H planes, eps on the E planes; per cell the
+// products and sums of the single-column dot kernel).  grid (ceil(N3 /
+// 256), ncol), one cell per thread.
+template <typename T, bool HAS_MU>
+__global__ __launch_bounds__(256) void k_col_norms(const T* __restrict__ Z, long long ldz,
+                                                   const int* __restrict__ cols, int ncol, long long N3,
+                                                   const double* __restrict__ eps, const double* __restrict__ mu,
+                                                   double* __restrict__ partials) {
+  __shared__ double part[4];
+  const int y = blockIdx.y;
+  const T* x = Z + (long long)cols[y] * ldz;
+  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+  double s = 0.0;
+  if (c < N3) {
+    const double we = eps[c];
+    const double wh = HAS_MU ? mu[c] : 1.0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const double xv = (double)x[p * N3 + c];
+      const double xm = (p < 3 ? wh : we) * xv;
+      s += xm * xv;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) part[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[(long long)blockIdx.x * ncol + y] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
 }  // namespace
 
 hipError_t launch_fill_hash(void* p, Storage st, long long n, unsigned seed, hipStream_t s) {
@@ -253,6 +293,31 @@ hipError_t launch_fill_hash(void* p, Storage st, long long n, unsigned seed, hip
     hipLaunchKernelGGL(k_fill_hash<double>, grid, dim3(256), 0, s, (double*)p, n, seed);
   else
     hipLaunchKernelGGL(k_fill_hash<float>, grid, dim3(256), 0, s, (float*)p, n, seed);
+  return hipGetLastError();
+}
+
+int col_norm_blocks(long long N3) { return (int)((N3 + 255) / 256); }
+
+hipError_t launch_col_norms(Storage st, const void* Z, long long ldz, const int* cols, int ncol, long long N3,
+                            const double* eps, const double* mu, double* partials, hipStream_t s) {
+  if (ncol <= 0 || N3 <= 0) return hipSuccess;
+  if (ncol > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)col_norm_blocks(N3), (unsigned)ncol);
+  if (st == F64) {
+    if (mu)
+      hipLaunchKernelGGL((k_col_norms<double, true>), grid, dim3(256), 0, s, (const double*)Z, ldz, cols, ncol, N3,
+                         eps, mu, partials);
+    else
+      hipLaunchKernelGGL((k_col_norms<double, false>), grid, dim3(256), 0, s, (const double*)Z, ldz, cols, ncol,
+                         N3, eps, mu, partials);
+  } else {
+    if (mu)
+      hipLaunchKernelGGL((k_col_norms<float, true>), grid, dim3(256), 0, s, (const float*)Z, ldz, cols, ncol, N3,
+                         eps, mu, partials);
+    else
+      hipLaunchKernelGGL((k_col_norms<float, false>), grid, dim3(256), 0, s, (const float*)Z, ldz, cols, ncol, N3,
+                         eps, mu, partials);
+  }
   return hipGetLastError();
 }
 
