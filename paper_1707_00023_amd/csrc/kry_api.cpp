@@ -3450,14 +3450,19 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
   const int nc = (int)cols.size();
   const bool gpu = m <= kry::rst_march_max_m();
   const size_t ldf = (size_t)nt * q;
-  std::vector<double> f0((size_t)nc * ldf);
-  for (int k = 0; k < nc; ++k)
-    for (int j = 0; j < nt; ++j)
-      for (int i = 0; i < q; ++i) {
-        const double t = (j + gx[i]) * dt;
-        f0[(size_t)k * ldf + (size_t)j * q + i] =
-            cols[k].ca * std::sin(cols[k].w * t) + cols[k].cb * std::cos(cols[k].w * t);
-      }
+  // the sampled time functions: computed on the device for the GPU march
+  // (nc nt q samples, two trigonometric evaluations each), on the host for
+  // the host march
+  auto sample_host = [&](std::vector<double>& f0) {
+    f0.assign((size_t)nc * ldf, 0.0);
+    for (int k = 0; k < nc; ++k)
+      for (int j = 0; j < nt; ++j)
+        for (int i = 0; i < q; ++i) {
+          const double t = (j + gx[i]) * dt;
+          f0[(size_t)k * ldf + (size_t)j * q + i] =
+              cols[k].ca * std::sin(cols[k].w * t) + cols[k].cb * std::cos(cols[k].w * t);
+        }
+  };
   // device buffers: samples (2 nc ldf), packed propagators E, W, El, Wl,
   // the Gauss weights and E^L, u(T) per time function, residual integrals,
   // index map, and the chunk states of the parallel-in-time march (chunks of
@@ -3466,7 +3471,7 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
   const bool chunked = gpu && Lc < nt;
   const size_t npk = 2 * (size_t)m * m + 2 * (size_t)m * q + (size_t)q * q + q;
   const long long nwork = chunked ? kry::rst_march_work(m, nt, nc, Lc) : 0;
-  double *dF = nullptr, *dP = nullptr, *dU = nullptr, *dR = nullptr, *dWk = nullptr;
+  double *dF = nullptr, *dP = nullptr, *dU = nullptr, *dR = nullptr, *dWk = nullptr, *dSw = nullptr;
   int* dMap = nullptr;
   // pinned host staging of each restart's small transfers (propagators,
   // residual integrals, active list, output map), so they queue behind the
@@ -3480,6 +3485,7 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
     hipFree(dR);
     hipFree(dMap);
     hipFree(dWk);
+    hipFree(dSw);
     if (hpin) hipHostFree(hpin);
   }};
   if (hipHostMalloc(&hpin, sizeof(double) * (npk + nc) + sizeof(int) * 2 * (size_t)nc, hipHostMallocDefault) !=
@@ -3493,18 +3499,28 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
   int* h_act = (int*)(h_rs + nc);
   int* h_cmap = h_act + nc;
   std::vector<double> hF[2];
+  std::vector<double> sw;  // nodes and (w, ca, cb) per time function; kept until the function returns
   if (gpu) {
     if (hipMalloc(&dF, sizeof(double) * 2 * nc * ldf) != hipSuccess || hipMalloc(&dP, sizeof(double) * npk) != hipSuccess ||
         hipMalloc(&dU, sizeof(double) * (size_t)m * nc) != hipSuccess || hipMalloc(&dR, sizeof(double) * nc) != hipSuccess ||
         hipMalloc(&dMap, sizeof(int) * nc) != hipSuccess ||
+        hipMalloc(&dSw, sizeof(double) * ((size_t)q + 3 * (size_t)nc)) != hipSuccess ||
         (nwork > 0 && hipMalloc(&dWk, sizeof(double) * nwork) != hipSuccess)) {
       (void)hipGetLastError();
       return fail(c, KRY_ENOMEM, "cannot allocate the sampled sources of the restarted method");
     }
-    KRY_HIP(hipMemcpyAsync(dF, f0.data(), sizeof(double) * f0.size(), hipMemcpyHostToDevice, c->stream));
+    sw.assign((size_t)q + 3 * (size_t)nc, 0.0);
+    std::copy(gx.begin(), gx.end(), sw.begin());
+    for (int k = 0; k < nc; ++k) {
+      sw[q + 3 * (size_t)k] = cols[k].w;
+      sw[q + 3 * (size_t)k + 1] = cols[k].ca;
+      sw[q + 3 * (size_t)k + 2] = cols[k].cb;
+    }
+    KRY_HIP(hipMemcpyAsync(dSw, sw.data(), sizeof(double) * sw.size(), hipMemcpyHostToDevice, c->stream));
+    KRY_HIP(kry::launch_rst_samples(nc, nt, q, dt, dSw, dSw + q, dF, (long long)ldf, c->stream));
   } else {
-    hF[0] = f0;
-    hF[1].assign(f0.size(), 0.0);
+    sample_host(hF[0]);
+    hF[1].assign(hF[0].size(), 0.0);
   }
   const int maxcyc = c->opts.max_restarts > 0 ? c->opts.max_restarts : 100000;
   int rc = ensure_y(c, m + 1, nc);

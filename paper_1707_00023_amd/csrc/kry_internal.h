@@ -209,6 +209,11 @@ hipError_t launch_fill_hash(void* p, Storage st, long long n, unsigned seed, hip
 int col_norm_blocks(long long N3);
 hipError_t launch_col_norms(Storage st, const void* Z, long long ldz, const int* cols, int ncol, long long N3,
                             const double* eps, const double* mu, double* partials, hipStream_t s);
+// The sampled time functions of the restarted method (kry_rst.hip):
+// F[k ldf + j q + i] = ca_k sin(w_k t) + cb_k cos(w_k t), t = (j + gx[i]) dt,
+// cw[3 k .. 3 k + 2] = (w_k, ca_k, cb_k); gx (q), cw device.
+hipError_t launch_rst_samples(int nc, int nt, int q, double dt, const double* gx, const double* cw, double* F,
+                              long long ldf, hipStream_t s);
 int rst_march_max_m();
 // Parallel-in-time form: with 1 <= L < nt, EL = E^L (m x m column-major,
 // device) and `work` of rst_march_work(m, nt, ncol, L) doubles (device),

@@ -285,6 +285,24 @@ __global__ __launch_bounds__(256) void k_col_norms(const T* __restrict__ Z, long
   if (threadIdx.x == 0) partials[(long long)blockIdx.x * ncol + y] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
+
+// Sampled time functions of the restarted method: F[k ldf + j q + i] =
+// ca_k sin(w_k t) + cb_k cos(w_k t) at t = (j + gx[i]) dt, for nc functions
+// (cw = w, ca, cb of function k at 3 k), nt steps and q nodes per step.
+__global__ __launch_bounds__(256) void k_rst_samples(int nc, int nt, int q, double dt, const double* __restrict__ gx,
+                                                     const double* __restrict__ cw, double* __restrict__ F,
+                                                     long long ldf) {
+  const long long per = (long long)nt * q;
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= per * nc) return;
+  const int k = (int)(idx / per);
+  const long long r = idx - (long long)k * per;
+  const int j = (int)(r / q), i = (int)(r - (long long)j * q);
+  const double t = (j + gx[i]) * dt;
+  const double w = cw[3 * k], ca = cw[3 * k + 1], cb = cw[3 * k + 2];
+  F[(long long)k * ldf + r] = ca * sin(w * t) + cb * cos(w * t);
+}
+
 }  // namespace
 
 hipError_t launch_fill_hash(void* p, Storage st, long long n, unsigned seed, hipStream_t s) {
@@ -318,6 +336,16 @@ hipError_t launch_col_norms(Storage st, const void* Z, long long ldz, const int*
       hipLaunchKernelGGL((k_col_norms<float, false>), grid, dim3(256), 0, s, (const float*)Z, ldz, cols, ncol, N3,
                          eps, mu, partials);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_rst_samples(int nc, int nt, int q, double dt, const double* gx, const double* cw, double* F,
+                              long long ldf, hipStream_t s) {
+  if (nc <= 0 || nt <= 0 || q <= 0) return hipSuccess;
+  if (ldf < (long long)nt * q) return hipErrorInvalidValue;
+  const long long total = (long long)nc * nt * q;
+  hipLaunchKernelGGL(k_rst_samples, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, nc, nt, q, dt, gx, cw, F,
+                     ldf);
   return hipGetLastError();
 }
 
