@@ -449,11 +449,14 @@ __global__ __launch_bounds__(256) void k_gemm_cols(const T* X, int M1, const T2*
 #pragma unroll
     for (int j = 0; j < NO; ++j) acc[q][j] = 0.0;
   }
-  // one row k of a segment: acc += x_k C[k][:]
+  // one row k of a segment: acc += x_k C[k][:].  Every load and store of
+  // the sweep is marked non-temporal (nothing is reused from the caches):
+  // measured at 128^3, 5.3-5.8 TB/s against 5.1-5.2 with ordinary accesses
+  // (either hint alone gains nothing)
   auto row_update = [&](const auto* xk, int k) {
     double x[EPT];
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) x[q] = ok[q] ? (double)xk[base + 256LL * q] : 0.0;
+    for (int q = 0; q < EPT; ++q) x[q] = ok[q] ? (double)__builtin_nontemporal_load(xk + base + 256LL * q) : 0.0;
     const double2* row = reinterpret_cast<const double2*>(sC + NO * k);
 #pragma unroll
     for (int j2 = 0; j2 < NO / 2; ++j2) {
@@ -478,8 +481,8 @@ __global__ __launch_bounds__(256) void k_gemm_cols(const T* X, int M1, const T2*
     for (int j = 0; j < NO; ++j) {
       if (j < N) {
         TO* o = Out + (long long)j * ld + e;
-        const double prev = accumulate ? (double)*o : 0.0;
-        *o = TO(prev + alpha * acc[q][j]);
+        const double prev = accumulate ? (double)__builtin_nontemporal_load(o) : 0.0;
+        __builtin_nontemporal_store(TO(prev + alpha * acc[q][j]), o);
       }
     }
   }
