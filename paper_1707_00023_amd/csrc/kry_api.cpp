@@ -3541,6 +3541,21 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
       break;
     }
     const double hnext = me < m ? 0.0 : c->h_H[m + (size_t)(m - 1) * ldh];
+    // E^L = e^{-L dt H} for the carry between chunks of the GPU march, on a
+    // second host thread while the step propagators are formed (the two
+    // dense computations are independent; joined on every path below)
+    std::vector<double> Xel, Eel;
+    std::thread th_el;
+    Defer<std::function<void()>> join_el{[&]() {
+      if (th_el.joinable()) th_el.join();
+    }};
+    if (gpu && chunked) {
+      Xel.resize((size_t)me * me);
+      Eel.resize((size_t)me * me);
+      for (int jj = 0; jj < me; ++jj)
+        for (int ii = 0; ii < me; ++ii) Xel[ii + (size_t)jj * me] = -(double)Lc * dt * c->h_H[ii + (size_t)jj * ldh];
+      th_el = std::thread([&]() { kry::expm(me, Xel.data(), Eel.data()); });
+    }
     kry::rst_prepare(me, c->h_H, ldh, q, dt, gx.data(), &P);
     act.clear();
     for (int k = 0; k < nc; ++k)
@@ -3558,11 +3573,9 @@ int rst_part(kry_ctx* c, std::vector<RstColumn>& cols, double T, int nt, const s
       std::copy(P.Wl.begin(), P.Wl.end(), p + (size_t)me * me + 2 * (size_t)me * q);
       std::copy(gw.begin(), gw.end(), p + (size_t)me * me + 2 * (size_t)me * q + (size_t)q * q);
       double* pEL = p + (size_t)me * me + 2 * (size_t)me * q + (size_t)q * q + q;
-      if (chunked) {  // E^L = e^{-L dt H} for the carry between chunks
-        std::vector<double> X((size_t)me * me);
-        for (int jj = 0; jj < me; ++jj)
-          for (int ii = 0; ii < me; ++ii) X[ii + (size_t)jj * me] = -(double)Lc * dt * c->h_H[ii + (size_t)jj * ldh];
-        kry::expm(me, X.data(), pEL);
+      if (chunked) {  // E^L from the second thread
+        th_el.join();
+        std::copy(Eel.begin(), Eel.end(), pEL);
       }
       const double* dE = dP;
       const double* dW = dP + (size_t)me * me;
