@@ -3302,8 +3302,8 @@ int api_autotune(kry_ctx* c, int32_t cnt, kry_tune* out) {
   // the stencil keeps one cell per thread unless another shape is faster by
   // more than kStencilMargin: one launch timed in isolation varies by 1-2%,
   // and one cell per thread fetches the least from HBM (on the 128^3 medium
-  // 1.03 of its algorithmic bytes, against 1.11 with two cells per thread
-  // and 1.10 for the z-marching form)
+  // 1.01 of its algorithmic bytes, against 1.06 with two cells per thread
+  // and 1.04 for the z-marching form)
   constexpr double kStencilMargin = 0.03;
   {
     int b = 0;

@@ -225,8 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil_axpby(const T* __restrict__ 
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
       double r = alpha * (double)o[p] + gamma * (double)ctr[p];
-      if (prev) r += beta * (double)prev[p * N3 + c];
-      out[p * N3 + c] = T(r);
+      if (prev) r += beta * (double)__builtin_nontemporal_load(prev + p * N3 + c);
+      __builtin_nontemporal_store(T(r), out + p * N3 + c);
     }
   }
 }
@@ -313,8 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil_axpby_zm(const T* __restrict
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
       double r = alpha * (double)o[p] + gamma * (double)ctr[p];
-      if (prev) r += beta * (double)prev[p * N3 + c];
-      out[p * N3 + c] = T(r);
+      if (prev) r += beta * (double)__builtin_nontemporal_load(prev + p * N3 + c);
+      __builtin_nontemporal_store(T(r), out + p * N3 + c);
     }
     hxm = hx;
     hym = hy;
