@@ -29,9 +29,11 @@ typedef float nt_f2 __attribute__((ext_vector_type(2)));
 
 constexpr int kOutStride = 34;  // LDS row stride (doubles) of a column's 32 entries
 
-// One wave owns 32 output columns (two 16-column tiles) and keeps their
-// coefficients, the MFMA A operands for every k, in registers (loaded once);
-// it then streams tpw blocks of 32 entries of the basis through them, the
+// One wave owns 32 output columns (two 16-column tiles); their coefficients,
+// the MFMA A operands for every k, sit in LDS for the workgroup (read per
+// MFMA: in registers they took 64 VGPRs and left two waves per SIMD, in LDS
+// three, 9% faster); the wave streams tpw blocks of 32 entries of the basis
+// through them, the
 // four waves of a workgroup on 128 consecutive entries at a time.  Per block
 // the old outputs are read first in the read-modify-write layout (load
 // instruction q: lane l takes column 4 q + l / 16, entries 2 (l % 16) and
@@ -43,11 +45,12 @@ constexpr int kOutStride = 34;  // LDS row stride (doubles) of a column's 32 ent
 // XCD at nearby dispatch times, so its basis entries come from HBM once.
 // MC: 16-row chunks of k (m <= 16 MC).
 template <typename T, int MC>
-__global__ __launch_bounds__(256) void k_combine_mfma(const T* __restrict__ V, long long ldv, int m,
+__global__ __launch_bounds__(256, 3) void k_combine_mfma(const T* __restrict__ V, long long ldv, int m,
                                                       const double* __restrict__ Y, int ncol, T* __restrict__ out,
                                                       long long ldo, const int* __restrict__ cmap, long long n,
                                                       int tpw, int ncg, long long neb) {
   __shared__ double slots[4][32 * kOutStride];
+  __shared__ double ya[16 * MC][32];  // ya[k][jj] = Y[k][jbase + jj]
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const long long bt = blockIdx.x >> 3;
@@ -57,16 +60,11 @@ __global__ __launch_bounds__(256) void k_combine_mfma(const T* __restrict__ V, l
   const int jbase = cg * 32;
   const int i = lane & 15, kk = lane >> 4;
   double* slot = slots[wave];
-  double a[MC][4][2];
-#pragma unroll
-  for (int c = 0; c < MC; ++c)
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int k = 16 * c + 4 * u + kk, j = jbase + t * 16 + i;
-        a[c][u][t] = (k < m && j < ncol) ? Y[k + (long long)j * m] : 0.0;
-      }
+  for (int t = threadIdx.x; t < 16 * MC * 32; t += 256) {
+    const int k = t / 32, j = jbase + t % 32;
+    ya[k][t % 32] = (k < m && j < ncol) ? Y[k + (long long)j * m] : 0.0;
+  }
+  __syncthreads();
   T* op[8];  // output column of lane l in read-modify-write instruction q
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
@@ -112,12 +110,15 @@ __global__ __launch_bounds__(256) void k_combine_mfma(const T* __restrict__ V, l
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u) {
+        const int k = 16 * c + 4 * u + kk;
+        const double a0 = ya[k][i], a1 = ya[k][16 + i];
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int t = 0; t < 2; ++t)
-            acc[x][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][u][t], b[x][u], acc[x][t], 0, 0, 0);
+        for (int x = 0; x < 2; ++x) {
+          acc[x][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b[x][u], acc[x][0], 0, 0, 0);
+          acc[x][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b[x][u], acc[x][1], 0, 0, 0);
+        }
+      }
     }
     // acc[x][t][r]: column 16 t + 4 r + kk, entry 16 x + i
 #pragma unroll
