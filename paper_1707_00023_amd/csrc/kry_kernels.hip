@@ -1158,26 +1158,17 @@ static hipError_t combine_t(const void* V, long long ldv, int m, const double* Y
   if (out_last && ncol > CC) return hipErrorInvalidValue;
   const unsigned gx = blocks_for(g.N3);
   const unsigned g8 = (gx + 7) / 8 * 8;
-  // columns per workgroup: the smallest of 1, 2, 4, 8 that holds them all
-  // (the accumulators take 12 CC registers: 8 columns leave 4 waves per
-  // SIMD, too few loads in flight for the 1-3 columns of a single solve),
-  // else chunks of 8
-#define KRY_COMB(CCW)                                                                                   \
-  {                                                                                                     \
-    const int ncc = (ncol + (CCW) - 1) / (CCW);                                                         \
-    const size_t shm = sizeof(double) * (size_t)m * (CCW);                                              \
-    hipLaunchKernelGGL((k_combine<T, CCW>), dim3(g8 * ncc), dim3(kBlock), shm, s, (const T*)V, ldv, m, Y, \
-                       ncol, (T*)out, ldo, colmap, accumulate, (T*)out_last, g.N3, ncc, (int)gx);     \
+  if (ncol == 1) {
+    const size_t shm = sizeof(double) * (size_t)m;
+    hipLaunchKernelGGL((k_combine<T, 1>), dim3(g8), dim3(kBlock), shm, s, (const T*)V, ldv, m, Y,
+                       ncol, (T*)out, ldo, colmap, accumulate, (T*)out_last, g.N3, 1, (int)gx);
+  } else {
+    const int ncc = (ncol + CC - 1) / CC;
+    const size_t shm = sizeof(double) * (size_t)m * CC;
+    hipLaunchKernelGGL((k_combine<T, CC>), dim3(g8 * ncc), dim3(kBlock), shm, s,
+                       (const T*)V, ldv, m, Y, ncol, (T*)out, ldo, colmap, accumulate, (T*)out_last,
+                       g.N3, ncc, (int)gx);
   }
-  if (ncol == 1)
-    KRY_COMB(1)
-  else if (ncol == 2)
-    KRY_COMB(2)
-  else if (ncol <= 4)
-    KRY_COMB(4)
-  else
-    KRY_COMB(CC)
-#undef KRY_COMB
   return hipGetLastError();
 }
 
