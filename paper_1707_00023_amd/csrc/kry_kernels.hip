@@ -703,10 +703,11 @@ __global__ void k_scale(const T* __restrict__ x, const double* __restrict__ s, T
 // out_last instead, never accumulated; out_last may be one of the V_i (a
 // thread reads every V_i at its entries before writing them), so then all
 // columns must be in one workgroup row (ncol <= CC).
-// A thread owns one entry of the flat vector (consecutive threads,
-// consecutive entries: every row access is one 512-byte run per wave in
-// FP64), and every load and store is non-temporal (nothing of the sweep is
-// reused from the caches).  Measured at 128^3, m = 65, on its own: 1.14 ms
+// A thread owns EP consecutive entries of the flat vector (one in FP64, two
+// in FP32: every row access is one 512-byte run per wave), and every load
+// and store is non-temporal (nothing of the sweep is reused from the
+// caches).  The entry count is even and every column starts 64 entries
+// aligned, so the FP32 pairs are aligned.  Measured at 128^3, m = 65, on its own: 1.14 ms
 // for 3 outputs (6.2 TB/s) against 1.44 ms when a thread owned the six
 // components of a cell (six runs per row 2 MB apart, ordinary accesses),
 // 1.73 against 2.22 ms for 16 outputs.
@@ -715,6 +716,8 @@ __global__ void k_scale(const T* __restrict__ x, const double* __restrict__ s, T
 // dispatcher assigns to b mod 8 = i mod 8, at nearby dispatch times, so the
 // basis entries of the chunk come from HBM once and from that XCD's L2 for
 // the other column chunks.
+typedef float vf2 __attribute__((ext_vector_type(2)));  // FP32 pair for the non-temporal builtins
+
 template <typename T, int CC>
 __global__ __launch_bounds__(kBlock) void k_combine(const T* V, long long ldv, int m,
                                                     const double* __restrict__ Y, int ncol,
@@ -733,16 +736,30 @@ __global__ __launch_bounds__(kBlock) void k_combine(const T* V, long long ldv, i
     sY[t] = (cc < nc) ? Y[i + (long long)(c0 + cc) * m] : 0.0;
   }
   __syncthreads();
-  const long long e = ichunk * kBlock + threadIdx.x;
+  constexpr int EP = sizeof(T) == 4 ? 2 : 1;
+  const long long e = (ichunk * kBlock + threadIdx.x) * EP;
   if (e >= n) return;
-  double acc[CC];
+  double acc[EP][CC];
 #pragma unroll
-  for (int cc = 0; cc < CC; ++cc) acc[cc] = 0.0;
+  for (int q = 0; q < EP; ++q)
+#pragma unroll
+    for (int cc = 0; cc < CC; ++cc) acc[q][cc] = 0.0;
 #pragma unroll 2
   for (int i = 0; i < m; ++i) {
-    const double v = (double)__builtin_nontemporal_load(V + (long long)i * ldv + e);
+    double v[EP];
+    if constexpr (EP == 2) {
+      const vf2 x = __builtin_nontemporal_load(reinterpret_cast<const vf2*>(V + (long long)i * ldv + e));
+      v[0] = x.x;
+      v[1] = x.y;
+    } else {
+      v[0] = (double)__builtin_nontemporal_load(V + (long long)i * ldv + e);
+    }
 #pragma unroll
-    for (int cc = 0; cc < CC; ++cc) acc[cc] += v * sY[i * CC + cc];
+    for (int cc = 0; cc < CC; ++cc) {
+      const double y = sY[i * CC + cc];
+#pragma unroll
+      for (int q = 0; q < EP; ++q) acc[q][cc] += v[q] * y;
+    }
   }
 #pragma unroll
   for (int cc = 0; cc < CC; ++cc) {
@@ -750,8 +767,22 @@ __global__ __launch_bounds__(kBlock) void k_combine(const T* V, long long ldv, i
     const bool last = out_last && c0 + cc == ncol - 1;
     const int col = last ? 0 : (colmap ? colmap[c0 + cc] : (c0 + cc));
     T* o = (last ? out_last : out + (long long)col * ldo) + e;
-    const double prev = (!last && accumulate) ? (double)__builtin_nontemporal_load(o) : 0.0;
-    __builtin_nontemporal_store(T(prev + acc[cc]), o);
+    const bool acc_on = !last && accumulate;
+    if constexpr (EP == 2) {
+      vf2 r;
+      if (acc_on) {
+        const vf2 prev = __builtin_nontemporal_load(reinterpret_cast<const vf2*>(o));
+        r.x = T((double)prev.x + acc[0][cc]);
+        r.y = T((double)prev.y + acc[1][cc]);
+      } else {
+        r.x = T(acc[0][cc]);
+        r.y = T(acc[1][cc]);
+      }
+      __builtin_nontemporal_store(r, reinterpret_cast<vf2*>(o));
+    } else {
+      const double prev = acc_on ? (double)__builtin_nontemporal_load(o) : 0.0;
+      __builtin_nontemporal_store(T(prev + acc[0][cc]), o);
+    }
   }
 }
 
@@ -1148,12 +1179,16 @@ static hipError_t combine_t(const void* V, long long ldv, int m, const double* Y
                             long long ldo, const int* colmap, int accumulate, void* out_last,
                             const DevGrid& g, hipStream_t s) {
   if (m <= 0 || ncol <= 0) return hipSuccess;
-  // columns per workgroup: 1, 4, 8 or chunks of 16 (16 accumulators keep
-  // 6 waves per SIMD)
-  constexpr int CMAX = 16;
+  // columns per workgroup: 1, 4, 8 or chunks of CMAX.  FP64: chunks of 16
+  // (8 waves per SIMD; at 128^3, m = 65, 16 outputs took 1.73 ms against
+  // 2.42 ms in two chunks of 8).  FP32 (two entries per thread): chunks of
+  // 8 (at 256^3, m = 49, 16 outputs took 8.9 ms against 10.8 ms in one
+  // chunk of 16, whose 32 accumulators leave 5 waves per SIMD)
+  constexpr int CMAX = sizeof(T) == 4 ? 8 : 16;
+  constexpr int EPT = sizeof(T) == 4 ? 2 : 1;  // entries per thread
   if (out_last && ncol > CMAX) return hipErrorInvalidValue;
   const long long n = 6 * g.N3;
-  const long long gx = (n + kBlock - 1) / kBlock;
+  const long long gx = (n + kBlock * EPT - 1) / (kBlock * EPT);  // workgroups per column chunk
   const long long g8 = (gx + 7) / 8 * 8;
 #define KRY_COMB(CCW)                                                                                     \
   {                                                                                                       \
