@@ -210,10 +210,13 @@ def compare_batched(args, wl, inp, dev):
 COPY_BYTES = 1 << 30
 
 
-def precision_compare(args, wl, inp, dev):
-    """FP32 storage (FP32 stencil, FP64 reductions and small dense) against
-    an FP64 run of the same frequencies; relative 2-norm error per omega."""
-    import numpy as np
+def precision_runs(wl, inp, dev, om, method, s_step, verbose=True):
+    """All frequencies om of the workload's shared source, solved once with
+    FP32 storage (FP32 stencil, FP64 reductions and small dense) at the
+    workload's tolerance and once in FP64 at 1e-8, by the split solver
+    (Corollary 3) or the residual-restarted method; wall time of each solve
+    and the relative 2-norm error of every FP32 field against the FP64 one.
+    Returns (summary dict, solutions by name)."""
     import torch
 
     import paper_1707_00023_amd as kry
@@ -221,16 +224,14 @@ def precision_compare(args, wl, inp, dev):
 
     eps = torch.as_tensor(inp.eps, device=dev)
     sig = torch.as_tensor(inp.sigma, device=dev)
-    om = list(wl.omegas[args.omega_offset: args.omega_offset + args.n_omega])
     b = torch.as_tensor(wk.source_vector(wl, om[0], 0.0)[None, :], device=dev)
     out = {"metric": "FP32-storage error vs FP64 GPU run, per omega", "workload": wl.name,
-           "n": wl.n, "omegas": om, "T": wl.T, "krylov_dim": wl.krylov_dim}
+           "n": wl.n, "omegas": om, "T": wl.T, "krylov_dim": wl.krylov_dim, "method": method}
     ys = {}
-    out["method"] = args.method
     for name, storage, tol in (("f32", "f32", wl.tol), ("f64", "f64", 1e-8)):
         s = kry.Solver(eps, None, sig, kry.Options(storage=storage, krylov_dim=wl.krylov_dim,
-                                                   tol=tol, verbose=True, s_step=args.s_step_cli))
-        solve = s.solve_restarted if args.method == "restarted" else s.solve_multifreq
+                                                   tol=tol, verbose=verbose, s_step=s_step))
+        solve = s.solve_restarted if method == "restarted" else s.solve_multifreq
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         y = solve(om, b, wl.T)
@@ -245,7 +246,24 @@ def precision_compare(args, wl, inp, dev):
         s.close()
     err = (torch.linalg.norm(ys["f32"] - ys["f64"], dim=1) / torch.linalg.norm(ys["f64"], dim=1))
     out["rel_err_per_omega"] = [float(e) for e in err.cpu()]
+    out["speedup_f32_over_f64"] = out["f64"]["s"] / out["f32"]["s"]
+    return out, ys
+
+
+def precision_compare(args, wl, inp, dev):
+    """FP32 storage against an FP64 run of the same frequencies (see
+    precision_runs), optionally checked against one-at-a-time FP64 solves."""
+    import torch
+
+    import paper_1707_00023_amd as kry
+    import workloads as wk
+
+    om = list(wl.omegas[args.omega_offset: args.omega_offset + args.n_omega])
+    out, ys = precision_runs(wl, inp, dev, om, args.method, args.s_step_cli)
     if args.single_ref > 0:
+        eps = torch.as_tensor(inp.eps, device=dev)
+        sig = torch.as_tensor(inp.sigma, device=dev)
+        b = torch.as_tensor(wk.source_vector(wl, om[0], 0.0)[None, :], device=dev)
         # the first frequencies solved again one at a time in FP64: a check
         # of the many-shift solves of both runs
         s = kry.Solver(eps, None, sig, kry.Options(storage="f64", krylov_dim=wl.krylov_dim, tol=1e-8,
@@ -258,7 +276,6 @@ def precision_compare(args, wl, inp, dev):
             print(f"[bench] single omega {k} done", file=sys.stderr, flush=True)
         s.close()
         out["rel_err_vs_single_f64"] = ref
-    out["speedup_f32_over_f64"] = out["f64"]["s"] / out["f32"]["s"]
     print(json.dumps(out), flush=True)
 
 
@@ -376,6 +393,10 @@ def main():
                     help="s-step Arnoldi block size (default: the library binding's default)")
     ap.add_argument("--no-methods", action="store_true",
                     help="skip the one-off timings of the restarted method and source splitting")
+    ap.add_argument("--no-multi-omega", action="store_true",
+                    help="skip the one-off all-frequency runs of the 256^3 precision workload "
+                         "(FP64 and FP32 storage, restarted method) after the 128^3 steps; "
+                         "--no-methods skips them too")
     ap.add_argument("--split2-periods", type=int, default=5,
                     help="source splitting: periods of the source per subinterval")
     ap.add_argument("--stencil-planes", type=int, default=None, choices=[0, 4, 8, 16],
@@ -537,6 +558,21 @@ def main():
                            "kernels": [kry.KERNEL_CLASSES[i] for i in agg]}
     if not args.no_methods:
         out["methods"] = other_methods(solver, wl, b, per_omega, stats[-1], args)
+    if not args.no_methods and not args.no_multi_omega and args.workload == "c2":
+        # every frequency of the 256^3 precision workload (16 on one shared
+        # source), timed once in each storage type by the restarted method
+        solver.close()
+        wl5 = wk.CONFIGS["c5"]
+        om5 = list(wl5.omegas)
+        print(f"[bench] all {len(om5)} frequencies of {wl5.name}", file=sys.stderr, flush=True)
+        r5, _ = precision_runs(wl5, wk.generate(wl5), dev, om5, "restarted", args.s_step_cli, verbose=False)
+        out["all_omega_multi"] = {
+            "workload": wl5.name, "grid": f"{wl5.N}^3", "unknowns": wl5.n, "n_omega": len(om5),
+            "T": wl5.T, "krylov_dim": wl5.krylov_dim, "method": "restarted",
+            "f64": {k: r5["f64"][k] for k in ("tol", "s", "matvecs_transient", "converged")},
+            "f32": {k: r5["f32"][k] for k in ("tol", "s", "matvecs_transient", "converged")},
+            "max_rel_err_f32_vs_f64": max(r5["rel_err_per_omega"]),
+            "speedup_f32_over_f64": r5["speedup_f32_over_f64"]}
     if calib is not None:
         out["calibration_copy"] = calib
     if not args.no_cpu_baseline:
